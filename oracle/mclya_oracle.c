@@ -1,0 +1,327 @@
+/*
+ * FP64 CPU oracle for Monte-Carlo Lyman-alpha packet transport.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, plain reference that the
+ * GPU path is checked against. Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may build, load or run it; the product path
+ * never does. It shares no code, header, table or constant with the HIP
+ * library: it is written independently from the paper and from the published
+ * definition of the Philox generator.
+ *
+ * What it computes (paper: Jedamzik, Abel & Ali-Haimoud, arXiv:2312.11448):
+ *   - packets are injected at random locations (App. A, step 1), here with a
+ *     frequency drawn from the thermal (Doppler) line profile and an isotropic
+ *     direction;
+ *   - each packet streams in a straight line through a periodic grid; inside a
+ *     cell its gas-frame frequency drifts to the red by H dl / v_th (App. A,
+ *     step 4); at a cell face it changes by the bulk-velocity term of
+ *     Eq. (inout), x_new = x_old - k.(U_new - U_old) / v_th;
+ *   - along a segment the expected true-absorption depth is
+ *     kappa_c * [Phi(x_in) - Phi(x_out)], with kappa_c the mean optical depth
+ *     to true absorption of Eq. (<fnu>) evaluated with the cell's n_1s and Phi
+ *     the cumulative line profile; the absorbed part of the packet weight is
+ *     deposited into the cell as a 64-bit integer;
+ *   - a packet escapes once it has redshifted past -x_eff on the red wing
+ *     (the "lost to redshifting" outcome at the end of App. A).
+ * Weights are integers, so sum(absorbed) + escaped == w0 * npackets exactly.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC mclya_oracle.c -o libmclya_oracle.so -lm
+ * (no fast-math: every floating-point operation is plain IEEE double).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11, "Parallel random        */
+/* numbers: as easy as 1, 2, 3"). Ten rounds of two 32x32->64 multiplies,     */
+/* key schedule bumped by the Weyl constants between rounds.                  */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t mul0 = 0xD2511F53u, mul1 = 0xCD9E8D57u;
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)mul0 * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)mul1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += weyl0;
+        k1 += weyl1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1) from the top 23 bits of a word: (m + 1/2) 2^-23. Every such
+ * value is exactly representable in binary32 and binary64. */
+static double orc_uniform(uint32_t r)
+{
+    return ((double)(r >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* The eight uniforms of packet p: two Philox blocks with counter
+ * (p_lo, p_hi, s, 0), s = 0, 1, and key (seed_lo, seed_hi). */
+void orc_packet_uniforms(uint64_t seed, uint64_t p, double u[8])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint32_t s = 0; s < 2; ++s) {
+        uint32_t ctr[4] = {(uint32_t)p, (uint32_t)(p >> 32), s, 0u};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        for (int i = 0; i < 4; ++i) u[4 * s + i] = orc_uniform(r[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Emission: packets are distributed over cells in proportion to the local    */
+/* recombination source alpha_e n_e^2 (Eq. rec0; the integral of the          */
+/* footnote in Sec. III.B), with an exact integer systematic allocation.      */
+/* ------------------------------------------------------------------------- */
+
+/* q_c = floor(2^32 * s_c / s_max). Returns 0 on success, -1 for a negative or
+ * non-finite weight, -2 when every weight is zero. */
+int orc_quantize(int64_t ncells, const double *s, uint64_t *q)
+{
+    double smax = 0.0;
+    for (int64_t c = 0; c < ncells; ++c) {
+        if (!(s[c] >= 0.0) || isinf(s[c])) return -1;
+        if (s[c] > smax) smax = s[c];
+    }
+    if (smax == 0.0) return -2;
+    for (int64_t c = 0; c < ncells; ++c) {
+        double ratio = s[c] / smax;             /* one correctly rounded division */
+        q[c] = (uint64_t)floor(ratio * 4294967296.0);  /* exact scaling by 2^32 */
+    }
+    return 0;
+}
+
+/* Number of packets p in [0, N) whose systematic point t_p = floor((2p+1) Qtot / 2N)
+ * lies below Q: the odd integers o = 2p+1 with o * Qtot < 2 N Q. */
+static uint64_t orc_count_below(uint64_t Q, uint64_t Qtot, uint64_t N)
+{
+    u128 m = (u128)2 * (u128)N * (u128)Q;
+    u128 ceil_y = (m + (u128)Qtot - 1) / (u128)Qtot;  /* ceil(2 N Q / Qtot) */
+    return (uint64_t)(ceil_y / 2);
+}
+
+/* first[c] = id of the first packet emitted in cell c; first[ncells] = N. */
+int orc_allocate(int64_t ncells, const uint64_t *q, uint64_t npackets, uint64_t *first)
+{
+    uint64_t Qtot = 0;
+    for (int64_t c = 0; c < ncells; ++c) Qtot += q[c];
+    if (Qtot == 0) return -2;
+    uint64_t Q = 0;
+    for (int64_t c = 0; c < ncells; ++c) {
+        first[c] = orc_count_below(Q, Qtot, npackets);
+        Q += q[c];
+    }
+    first[ncells] = orc_count_below(Qtot, Qtot, npackets);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Transport                                                                 */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t has_vel;
+    double delta;        /* red drift of x per cell width of path (App. A step 4) */
+    double x_eff;        /* escape once x <= -x_eff */
+    uint64_t w0;         /* weight of one packet */
+    uint64_t seed;
+    int64_t max_cross;   /* crossing cap per packet */
+} orc_box;
+
+typedef struct {
+    int64_t cell0;
+    double fx, fy, fz;   /* emission position inside cell0, in [0,1) */
+    double kx, ky, kz;   /* direction */
+    double x0;           /* emission frequency, gas frame, Doppler units */
+    int64_t crossings;   /* number of (packet, cell) segments walked */
+    int64_t escaped;     /* weight that escaped */
+    int64_t absorbed;    /* weight deposited into the grid */
+    int32_t fate;        /* 0 absorbed, 1 escaped, 2 capped */
+    int32_t pad;
+} orc_packet_rec;
+
+typedef struct {
+    int64_t *cells;      /* cell of each segment */
+    int64_t *deposits;   /* integer deposit of each segment */
+    double *x_in, *x_out, *length;
+    int64_t cap, n;
+} orc_trace;
+
+/* Cumulative Doppler profile: Phi(x) = int_{-inf}^{x} exp(-y^2)/sqrt(pi) dy. */
+static double orc_Phi(double x)
+{
+    return 0.5 * erfc(-x);
+}
+
+static int64_t orc_wrap(int64_t i, int64_t n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+/* Walk one packet. Deposits go to A; returns the packet's record. */
+static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux,
+                         const double *uy, const double *uz, uint64_t p, int64_t cell0,
+                         int64_t *A, orc_packet_rec *rec, orc_trace *tr)
+{
+    const int64_t nx = b->nx, ny = b->ny, nz = b->nz;
+    double u[8];
+    orc_packet_uniforms(b->seed, p, u);
+
+    /* position: uniform inside the emission cell */
+    double f[3] = {u[0], u[1], u[2]};
+    /* direction: isotropic, mu = cos(theta) uniform in [-1,1], azimuth uniform */
+    double mu = 2.0 * u[3] - 1.0;
+    double phi = 2.0 * M_PI * u[4];
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double k[3] = {st * cos(phi), st * sin(phi), mu};
+    /* frequency: Doppler profile exp(-x^2)/sqrt(pi), a normal law of variance
+     * 1/2, by the Box-Muller transform */
+    double x = sqrt(-log(u[5])) * cos(2.0 * M_PI * u[6]);
+
+    int64_t ci[3] = {cell0 % nx, (cell0 / nx) % ny, cell0 / (nx * ny)};
+    int64_t n[3] = {nx, ny, nz};
+    int64_t w = (int64_t)b->w0;
+    int64_t ncross = 0, absorbed = 0;
+    int fate = 0;
+
+    rec->cell0 = cell0;
+    rec->fx = f[0]; rec->fy = f[1]; rec->fz = f[2];
+    rec->kx = k[0]; rec->ky = k[1]; rec->kz = k[2];
+    rec->x0 = x;
+
+    for (;;) {
+        if (x <= -b->x_eff) { fate = 1; break; }              /* redshifted out */
+        if (ncross >= b->max_cross) { fate = 2; break; }
+        int64_t c = ci[0] + nx * (ci[1] + ny * ci[2]);
+        ++ncross;
+
+        /* distance (in cell widths) to the face the ray leaves through */
+        double t[3];
+        for (int a = 0; a < 3; ++a) {
+            if (k[a] > 0.0) t[a] = (1.0 - f[a]) / k[a];
+            else if (k[a] < 0.0) t[a] = f[a] / (-k[a]);
+            else t[a] = INFINITY;
+        }
+        int axis = 0;                                        /* ties: x, then y, then z */
+        if (t[1] < t[axis]) axis = 1;
+        if (t[2] < t[axis]) axis = 2;
+        double s = t[axis];
+
+        double x_out = x - b->delta * s;                     /* Hubble drift */
+        int escaping = x_out <= -b->x_eff;
+        double dPhi = escaping ? orc_Phi(x) - orc_Phi(-b->x_eff) : orc_Phi(x) - orc_Phi(x_out);
+        double dtau = kappa[c] * dPhi;
+        int64_t d = (int64_t)rint((double)w * (-expm1(-dtau)));
+        if (d > w) d = w;
+        w -= d;
+        A[c] += d;
+        absorbed += d;
+        if (tr && tr->n < tr->cap) {
+            tr->cells[tr->n] = c; tr->deposits[tr->n] = d;
+            tr->x_in[tr->n] = x; tr->x_out[tr->n] = escaping ? -b->x_eff : x_out;
+            tr->length[tr->n] = s;
+            tr->n++;
+        } else if (tr) {
+            tr->n++;
+        }
+        if (escaping) { fate = 1; break; }
+        if (w == 0) { fate = 0; break; }
+
+        /* move to the face, then into the neighbouring cell */
+        for (int a = 0; a < 3; ++a) {
+            if (a == axis) continue;
+            double g = f[a] + k[a] * s;
+            f[a] = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+        }
+        int64_t old = c;
+        if (k[axis] > 0.0) { f[axis] = 0.0; ci[axis] = orc_wrap(ci[axis] + 1, n[axis]); }
+        else { f[axis] = 1.0; ci[axis] = orc_wrap(ci[axis] - 1, n[axis]); }
+        x = x_out;
+        if (b->has_vel) {
+            int64_t cn = ci[0] + nx * (ci[1] + ny * ci[2]);
+            double du = k[0] * (ux[cn] - ux[old]) + k[1] * (uy[cn] - uy[old]) + k[2] * (uz[cn] - uz[old]);
+            x -= du;                                          /* Eq. (inout), bulk term */
+        }
+    }
+    rec->crossings = ncross;
+    rec->escaped = (fate == 0) ? 0 : w;
+    rec->absorbed = absorbed;
+    rec->fate = fate;
+}
+
+/* Cell of packet p: the largest c with first[c] <= p. */
+static int64_t orc_find_cell(const uint64_t *first, int64_t ncells, uint64_t p)
+{
+    int64_t lo = 0, hi = ncells - 1;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo + 1) / 2;
+        if (first[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+/* Walk packets [p_begin, p_end). A (ncells) and out[4] = {escaped weight,
+ * crossings, capped packets, capped weight} are accumulated into (not reset).
+ * recs, when not NULL, receives one record per packet. Returns 0. */
+int orc_transport(const orc_box *b, const double *kappa, const double *ux, const double *uy,
+                  const double *uz, const uint64_t *first, uint64_t p_begin, uint64_t p_end,
+                  int64_t *A, int64_t out[4], orc_packet_rec *recs, int nthreads)
+{
+    const int64_t ncells = (int64_t)b->nx * b->ny * b->nz;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+    int64_t *priv = (int64_t *)calloc((size_t)nthreads * (size_t)ncells, sizeof(int64_t));
+    if (!priv) return -1;
+    int64_t esc = 0, cross = 0, capn = 0, capw = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : esc, cross, capn, capw)
+    {
+        int64_t *mine = priv + (size_t)omp_get_thread_num() * (size_t)ncells;
+#pragma omp for schedule(dynamic, 256)
+        for (uint64_t p = p_begin; p < p_end; ++p) {
+            orc_packet_rec r;
+            orc_walk_one(b, kappa, ux, uy, uz, p, orc_find_cell(first, ncells, p), mine, &r, NULL);
+            cross += r.crossings;
+            if (r.fate == 1) esc += r.escaped;
+            if (r.fate == 2) { capn += 1; capw += r.escaped; }
+            if (recs) recs[p - p_begin] = r;
+        }
+    }
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t c = 0; c < ncells; ++c) {
+        int64_t sum = 0;
+        for (int t = 0; t < nthreads; ++t) sum += priv[(size_t)t * (size_t)ncells + c];
+        A[c] += sum;
+    }
+    free(priv);
+    out[0] += esc; out[1] += cross; out[2] += capn; out[3] += capw;
+    return 0;
+}
+
+/* Walk one packet and record every segment (cell, deposit, x_in, x_out,
+ * length). A receives its deposits. Returns the number of segments; only the
+ * first `cap` are stored. */
+int64_t orc_trace_packet(const orc_box *b, const double *kappa, const double *ux,
+                         const double *uy, const double *uz, const uint64_t *first, uint64_t p,
+                         int64_t *A, orc_packet_rec *rec, int64_t *cells, int64_t *deposits,
+                         double *x_in, double *x_out, double *length, int64_t cap)
+{
+    const int64_t ncells = (int64_t)b->nx * b->ny * b->nz;
+    orc_trace tr = {cells, deposits, x_in, x_out, length, cap, 0};
+    orc_walk_one(b, kappa, ux, uy, uz, p, orc_find_cell(first, ncells, p), A, rec, &tr);
+    return tr.n;
+}

@@ -1,0 +1,184 @@
+"""ctypes glue to the oracle's C walker (test infrastructure only).
+
+Everything here is bookkeeping: promote inputs to FP64, call the C functions,
+return numpy arrays. The arithmetic lives in mclya_oracle.c and physics.py.
+"""
+import ctypes as C
+import os
+import numpy as np
+
+from . import build as _build
+from . import physics as P
+
+_lib = None
+
+
+class OrcBox(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("has_vel", C.c_int32),
+                ("delta", C.c_double), ("x_eff", C.c_double), ("w0", C.c_uint64),
+                ("seed", C.c_uint64), ("max_cross", C.c_int64)]
+
+
+REC_DTYPE = np.dtype([("cell0", np.int64), ("fx", np.float64), ("fy", np.float64),
+                      ("fz", np.float64), ("kx", np.float64), ("ky", np.float64),
+                      ("kz", np.float64), ("x0", np.float64), ("crossings", np.int64),
+                      ("escaped", np.int64), ("absorbed", np.int64), ("fate", np.int32),
+                      ("pad", np.int32)])
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = C.CDLL(path)
+        P_ = C.POINTER
+        L.orc_philox4x32_10.argtypes = [P_(C.c_uint32), P_(C.c_uint32), P_(C.c_uint32)]
+        L.orc_packet_uniforms.argtypes = [C.c_uint64, C.c_uint64, P_(C.c_double)]
+        L.orc_quantize.argtypes = [C.c_int64, P_(C.c_double), P_(C.c_uint64)]
+        L.orc_quantize.restype = C.c_int
+        L.orc_allocate.argtypes = [C.c_int64, P_(C.c_uint64), C.c_uint64, P_(C.c_uint64)]
+        L.orc_allocate.restype = C.c_int
+        L.orc_transport.argtypes = [P_(OrcBox), P_(C.c_double), P_(C.c_double), P_(C.c_double),
+                                    P_(C.c_double), P_(C.c_uint64), C.c_uint64, C.c_uint64,
+                                    P_(C.c_int64), P_(C.c_int64), C.c_void_p, C.c_int]
+        L.orc_transport.restype = C.c_int
+        L.orc_trace_packet.argtypes = [P_(OrcBox), P_(C.c_double), P_(C.c_double), P_(C.c_double),
+                                       P_(C.c_double), P_(C.c_uint64), C.c_uint64, P_(C.c_int64),
+                                       C.c_void_p, P_(C.c_int64), P_(C.c_int64), P_(C.c_double),
+                                       P_(C.c_double), P_(C.c_double), C.c_int64]
+        L.orc_trace_packet.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: 4 words of counter, 2 words of key -> 4 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def packet_uniforms(seed, p):
+    u = np.zeros(8, dtype=np.float64)
+    lib().orc_packet_uniforms(int(seed), int(p), _ptr(u, C.c_double))
+    return u
+
+
+def quantize(weights):
+    s = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    q = np.zeros(s.size, dtype=np.uint64)
+    rc = lib().orc_quantize(s.size, _ptr(s, C.c_double), _ptr(q, C.c_uint64))
+    if rc != 0:
+        raise ValueError(f"invalid emission weights (code {rc})")
+    return q
+
+
+def allocate(q, n_packets):
+    """first[c] = first packet id of cell c, first[ncells] = N."""
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    first = np.zeros(q.size + 1, dtype=np.uint64)
+    rc = lib().orc_allocate(q.size, _ptr(q, C.c_uint64), int(n_packets), _ptr(first, C.c_uint64))
+    if rc != 0:
+        raise ValueError("all emission weights are zero")
+    return first
+
+
+class Prepared:
+    """Oracle inputs of one box: FP64 fields, scalars, allocation."""
+
+    @classmethod
+    def custom(cls, shape, kappa, weights, n_packets, seed, delta, x_eff, vel=None,
+               w0=1 << 32, max_cross=1_000_000):
+        """Walk parameters given directly (no physics): for tests of the walk."""
+        self = cls.__new__(cls)
+        self.spec = None
+        self.w0 = int(w0)
+        self.n_packets = int(n_packets)
+        self.seed = int(seed)
+        self.scal = None
+        self.kappa = np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+        self.vel = None if vel is None else [np.ascontiguousarray(np.asarray(vel, dtype=np.float64).reshape(3, -1)[i]) for i in range(3)]
+        self.x_eff = float(x_eff)
+        self.q = quantize(weights)
+        self.first = allocate(self.q, self.n_packets)
+        nx, ny, nz = (int(t) for t in shape)
+        self.box = OrcBox(nx, ny, nz, 0 if self.vel is None else 1, float(delta), self.x_eff,
+                          self.w0, self.seed, int(max_cross))
+        return self
+
+    def __init__(self, spec, n_packets=None, seed=None, max_cross=1_000_000):
+        self.spec = spec
+        self.w0 = int(spec.w0)
+        self.n_packets = int(spec.n_packets if n_packets is None else n_packets)
+        self.seed = int(spec.seed if seed is None else seed)
+        self.scal = P.box_scalars(spec)
+        self.kappa = np.ascontiguousarray(P.kappa_field(spec))
+        v = P.velocity_field(spec)
+        self.vel = None if v is None else [np.ascontiguousarray(v[i]) for i in range(3)]
+        self.x_eff = P.x_eff(spec)
+        self.q = quantize(P.emission_weights(spec))
+        self.first = allocate(self.q, self.n_packets)
+        nx, ny, nz = (int(t) for t in spec.n)
+        self.box = OrcBox(nx, ny, nz, 0 if self.vel is None else 1, self.scal["delta"],
+                          self.x_eff, int(spec.w0), self.seed, int(max_cross))
+
+    @property
+    def emitted_per_cell(self):
+        return np.diff(self.first.astype(np.int64)) * self.w0
+
+    def _vp(self, i):
+        return None if self.vel is None else _ptr(self.vel[i], C.c_double)
+
+    def transport(self, p_begin=0, p_end=None, records=False, nthreads=None):
+        """Walk packets [p_begin, p_end). Returns dict(A, escaped, crossings,
+        capped, capped_weight[, records])."""
+        p_end = self.n_packets if p_end is None else int(p_end)
+        ncells = self.kappa.size
+        A = np.zeros(ncells, dtype=np.int64)
+        out = np.zeros(4, dtype=np.int64)
+        recs = np.zeros(p_end - p_begin, dtype=REC_DTYPE) if records else None
+        nt = int(nthreads or os.environ.get("ORACLE_THREADS", 0) or 0)
+        lib().orc_transport(C.byref(self.box), _ptr(self.kappa, C.c_double), self._vp(0),
+                            self._vp(1), self._vp(2), _ptr(self.first, C.c_uint64), int(p_begin),
+                            int(p_end), _ptr(A, C.c_int64), _ptr(out, C.c_int64),
+                            None if recs is None else recs.ctypes.data, nt)
+        res = dict(A=A, escaped=int(out[0]), crossings=int(out[1]), capped=int(out[2]),
+                   capped_weight=int(out[3]))
+        if records:
+            res["records"] = recs
+        return res
+
+    def trace(self, p, cap=100_000):
+        """Every segment of packet p: dict(cells, deposits, x_in, x_out, length, record)."""
+        cells = np.zeros(cap, dtype=np.int64)
+        dep = np.zeros(cap, dtype=np.int64)
+        xi = np.zeros(cap)
+        xo = np.zeros(cap)
+        ln = np.zeros(cap)
+        A = np.zeros(self.kappa.size, dtype=np.int64)
+        rec = np.zeros(1, dtype=REC_DTYPE)
+        n = lib().orc_trace_packet(C.byref(self.box), _ptr(self.kappa, C.c_double), self._vp(0),
+                                   self._vp(1), self._vp(2), _ptr(self.first, C.c_uint64), int(p),
+                                   _ptr(A, C.c_int64), rec.ctypes.data, _ptr(cells, C.c_int64),
+                                   _ptr(dep, C.c_int64), _ptr(xi, C.c_double),
+                                   _ptr(xo, C.c_double), _ptr(ln, C.c_double), cap)
+        if n > cap:
+            raise ValueError("trace longer than cap")
+        return dict(cells=cells[:n], deposits=dep[:n], x_in=xi[:n], x_out=xo[:n], length=ln[:n],
+                    record=rec[0])
+
+
+def run_box(spec, n_packets=None, seed=None, p_begin=0, p_end=None, records=False,
+            nthreads=None, max_cross=1_000_000):
+    """Full oracle run of one box: allocation, transport, conservation check."""
+    prep = Prepared(spec, n_packets, seed, max_cross)
+    res = prep.transport(p_begin, p_end, records, nthreads)
+    res["emitted"] = prep.emitted_per_cell
+    res["prepared"] = prep
+    return res
