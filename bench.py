@@ -1,0 +1,139 @@
+"""Benchmark: photon cell-crossings per second of the whole transport step.
+
+One step is the full hot path over one batch of synthetic input already
+resident in HBM: pack the fields (kappa_c, velocity, emission weight),
+allocate the packets to cells, walk every packet (emission, drift, deposits,
+escape), finish the tallies (conservation check) and compute the
+recombination feed. Workload: the 128^3 k^2 Gaussian field with its
+curl-free flow at z = 1100, 1e7 packets.
+
+Prints one JSON line (rank 0). The dominant kernel's roofline uses the walk
+kernel's duration measured with HIP events on the library's stream and the
+algorithmic bytes per crossing (one 16-byte cell record read, one 8-byte
+tally update). The CPU baseline is the FP64 oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_CROSSING_VEL = 16 + 8      # float4 record (kappa, U) + int64 tally update
+BYTES_PER_CROSSING_NOVEL = 4 + 8     # float record (kappa) + int64 tally update
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="budget of the oracle's CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "walk_traffic.json"),
+                    help="measured HBM bytes per launch of the walk kernel (rocprofv3 counters)")
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, budget_s):
+    """The oracle as it is, on the host's cores, over consecutive packet
+    blocks of the same workload until the time budget is spent."""
+    from oracle import walker
+    prep = walker.Prepared(spec)
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
+    n = spec.n_packets
+    block = max(1, n // 50)
+    done, cross = 0, 0
+    t0 = time.perf_counter()
+    while done < n and time.perf_counter() - t0 < budget_s:
+        r = prep.transport(done, min(n, done + block), nthreads=threads)
+        cross += r["crossings"]
+        done = min(n, done + block)
+    dt = time.perf_counter() - t0
+    return {"value": cross / dt, "unit": "crossings/s", "cores": threads, "kind": "oracle",
+            "sample": f"packets [0, {done}) of {n} of the same workload "
+                      f"({cross} crossings in {dt:.1f} s, FP64 C + OpenMP)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2312_11448_amd as M
+
+    spec = W.make_box(a.config)
+    dev = torch.device("cuda:0")
+    sim = M.Simulation(spec, device=dev)
+    sim.set_option(M.MC_LYA_OPT_TIMING, 1)
+    seeds, npk = [spec.seed], [spec.n_packets]
+
+    def step():
+        sim.refresh()
+        sim.emit(seeds, npk)
+        sim.transport()
+        t = sim.tally(want_emitted=False)
+        f = sim.feed()
+        return t, f
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    sim.kernel_time()                      # drop the warm-up launches
+    t0 = time.perf_counter()
+    cross = 0
+    for _ in range(a.steps):
+        t, f = step()
+        st = t["stats"][0]
+        if st.conserved != 1 or st.capped_packets:
+            raise SystemExit("conservation identity failed")
+        cross += st.crossings
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    kms, launches = sim.kernel_time()
+    per_launch_s = kms / 1e3 / max(launches, 1)
+    cross_per_launch = cross / a.steps
+    bpc = BYTES_PER_CROSSING_VEL if spec.velocity is not None else BYTES_PER_CROSSING_NOVEL
+    achieved = bpc * cross_per_launch / per_launch_s / 1e9
+    traffic = None
+    if os.path.exists(a.traffic):
+        with open(a.traffic) as fh:
+            tr = json.load(fh)
+        if tr.get("config") == a.config:
+            traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": "photon cell-crossings/s",
+        "value": cross / dt,
+        "unit": "crossings/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "cells": spec.ncells, "packets": spec.n_packets,
+                   "crossings_per_step": cross_per_launch,
+                   "walk_ms": per_launch_s * 1e3,
+                   "walk_crossings_per_s": cross_per_launch / per_launch_s,
+                   "f_absorbed": f["stats"][0].f_absorbed, "c_mc": f["stats"][0].c_mc},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+    }
+    sim.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

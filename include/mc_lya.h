@@ -1,0 +1,240 @@
+/*
+ * mc_lya.h -- C ABI of the MI355X (gfx950) Monte-Carlo Lyman-alpha packet
+ * transport library (libmclya.so).
+ *
+ * The library computes, for one or many periodic boxes of baryons, where the
+ * Lyman-alpha photons emitted by recombination are destroyed, and turns the
+ * result into the local recombination rate. It follows Jedamzik, Abel &
+ * Ali-Haimoud, "Cosmic recombination in the presence of primordial magnetic
+ * fields" (arXiv:2312.11448):
+ *   - emission in proportion to the recombination source alpha_e n_e^2
+ *     (Eq. rec0; the Monte-Carlo integral of the footnote in Sec. III.B);
+ *   - frequency drift by the Hubble flow along the path (App. A, step 4) and
+ *     the bulk-velocity shift of Eq. (inout) between cells;
+ *   - destruction by the true-absorption opacity p_ab n_1s sigma(x), whose
+ *     integral over the line is the mean optical depth of Eq. (<fnu>);
+ *   - escape by redshifting out of the line (end of App. A);
+ *   - the per-cell feed of Eq. (rec) / Eq. (dotne-mix) (Sec. III.A.1, IV.B).
+ * Packets stream in straight lines (no resonant scattering); their weight is
+ * deposited as an expected value into 64-bit integer per-cell tallies, so
+ * the tallies do not depend on the order of the atomic updates and
+ *   sum(absorbed) + escaped + capped == w0 * packets   holds exactly.
+ *
+ * Conventions
+ *   - Grids are C-ordered [nz][ny][nx] (x fastest), periodic in all three
+ *     directions. With several boxes, cells and packets are concatenated box
+ *     by box ("box-major") in the order the boxes were given.
+ *   - "dev" pointers are HIP device memory; "host" pointers are host memory.
+ *     All device work is queued on the HIP stream given to mc_lya_init.
+ *   - Every call returns a status and never aborts. On failure the context is
+ *     left as it was and mc_lya_last_error() describes the failure.
+ *   - Call order: init -> [refresh] -> emit -> transport (or transport_range,
+ *     any number of times) -> tally / feed / trace -> emit ... ; calling out
+ *     of this order returns MC_LYA_ESTATE.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef MC_LYA_H
+#define MC_LYA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_LYA_ABI_VERSION 1
+
+typedef struct mc_lya_ctx mc_lya_ctx;
+
+typedef enum mc_lya_status {
+    MC_LYA_OK = 0,
+    MC_LYA_EINVAL = 1,      /* bad argument or field value (NaN, negative density, ...) */
+    MC_LYA_ENOMEM = 2,      /* a device allocation failed */
+    MC_LYA_EDEVICE = 3,     /* the HIP runtime reported an error */
+    MC_LYA_EOVERFLOW = 4,   /* w0 * packets >= 2^63, or more than 2^32 cells */
+    MC_LYA_ESTATE = 5,      /* call out of order */
+    MC_LYA_ECAP = 6,        /* some packet hit the crossing cap (weights still conserved) */
+    MC_LYA_ECONSERVE = 7    /* the integer conservation identity failed (internal error) */
+} mc_lya_status;
+
+/* velocity field element type */
+enum { MC_LYA_VEL_NONE = 0, MC_LYA_VEL_F32 = 1, MC_LYA_VEL_F16 = 2 };
+
+/* One periodic box: its grid, its physics and its (caller-owned) fields.
+ * Physics parameters are those of the paper's runs (Sec. II.C): cosmology
+ * (h, Omega_b h^2, Omega_c h^2, Y_p), the redshift z, and zeta, the factor
+ * multiplying the expansion rate in the paper's Monte-Carlo test problem
+ * (App. A, H -> zeta H; 1 for physical runs). */
+typedef struct mc_lya_box_desc {
+    int32_t nx, ny, nz;           /* grid edge in cells, each >= 1 */
+    int32_t vel_dtype;            /* MC_LYA_VEL_NONE / _F32 / _F16 */
+    double cell_comoving_cm;      /* comoving cell edge, cm (> 0) */
+    double z;                     /* redshift (> 0) */
+    double zeta;                  /* expansion-rate factor (> 0), 1 = physical */
+    double x_esc;                 /* red-wing escape threshold in Doppler widths (> 0) */
+    double temp_K;                /* gas and radiation temperature, uniform in the box (> 0) */
+    double h, omega_b_h2, omega_c_h2, y_p, t_cmb0, n_eff;   /* cosmology */
+    uint64_t w0;                  /* integer weight of one packet (> 0), e.g. 2^32 */
+    const float *overdensity;     /* dev [ncells]: Delta = rho_b / <rho_b>, finite, >= 0 */
+    const void *velocity;         /* dev [3][ncells] (x, y, z components) in units of the
+                                     thermal velocity sqrt(2kT/m_H), or NULL */
+    const float *x_e;             /* dev [ncells] free-electron fraction in [0, 1.2], or NULL */
+    float x_e_uniform;            /* used when x_e == NULL */
+    int32_t reserved;             /* must be 0 */
+    const float *source;          /* dev [ncells] emission rate density (cm^-3 s^-1, finite,
+                                     >= 0), or NULL for alpha_e(T) n_e^2 */
+} mc_lya_box_desc;
+
+/* Per-box integer totals from mc_lya_tally. */
+typedef struct mc_lya_box_stats {
+    int64_t emitted;              /* w0 * packets emitted in the box */
+    int64_t absorbed;             /* sum of the box's per-cell tallies */
+    int64_t escaped;              /* weight redshifted out of the line */
+    int64_t capped_weight;        /* weight of packets stopped by the crossing cap */
+    int64_t capped_packets;
+    int64_t crossings;            /* (packet, cell) segments walked */
+    int64_t packets;              /* packets emitted in the box */
+    int32_t conserved;            /* 1 iff absorbed + escaped + capped_weight == emitted */
+    int32_t reserved;
+    double delta;                 /* red drift per cell width, Doppler units (App. A step 4) */
+    double x_eff;                 /* escape threshold used (x_esc + velocity margin) */
+    double tau_ab_mean;           /* <kappa_c>: mean optical depth to true absorption */
+} mc_lya_box_stats;
+
+/* Per-box scalars from mc_lya_feed. */
+typedef struct mc_lya_feed_stats {
+    double c_mc;                  /* Monte-Carlo Peebles factor [E + sum(A) L/(b+L)] / (w0 N) */
+    double c_mix;                 /* Eq. (Cfactor) with R_alpha -> R_alpha^mix (Sec. IV.A.2) */
+    double f_escape;              /* escaped / emitted */
+    double f_absorbed;            /* absorbed / emitted */
+    double x_e_global;            /* X_e = <n_e> / <n_H> (Sec. II.A) */
+    double ndot_e_mean;           /* volume mean of the per-cell rate, cm^-3 s^-1 */
+} mc_lya_feed_stats;
+
+/* One packet's history from mc_lya_trace (56 bytes). */
+typedef struct mc_lya_packet_trace {
+    uint32_t cell0;               /* global emission cell */
+    float fx, fy, fz;             /* emission position inside the cell, [0,1) */
+    float kx, ky, kz;             /* direction */
+    float x0;                     /* emission frequency, gas frame, Doppler widths */
+    int64_t escaped;              /* weight that escaped (0 if absorbed) */
+    int64_t absorbed;             /* weight deposited into the grid */
+    uint32_t crossings;
+    int32_t fate;                 /* 0 absorbed, 1 escaped, 2 capped */
+} mc_lya_packet_trace;
+
+/* Tunables for mc_lya_set_option (all results are independent of them, bit
+ * for bit, except MC_LYA_OPT_MAX_CROSSINGS). */
+enum {
+    MC_LYA_OPT_KERNEL = 1,        /* 0 = persistent walk with wave refill (default),
+                                     1 = one thread per packet */
+    MC_LYA_OPT_BLOCK = 2,         /* threads per workgroup: 64, 128 or 256 */
+    MC_LYA_OPT_WAVES_PER_CU = 3,  /* resident waves per compute unit for the persistent grid */
+    MC_LYA_OPT_CHUNK = 4,         /* packets a wave takes from the queue at once (>= 1) */
+    MC_LYA_OPT_REFILL = 5,        /* refill a wave once this many lanes are idle (1..64) */
+    MC_LYA_OPT_MAX_CROSSINGS = 6, /* crossing cap per packet (>= 1, default 1e6) */
+    MC_LYA_OPT_TIMING = 7,        /* 1 = time transport kernels with HIP events */
+    MC_LYA_OPT_GRAPH = 8          /* 1 = replay transport as a captured HIP graph */
+};
+
+/* Creates a context for n_boxes boxes, validates and packs their fields
+ * (Sec. III.A.1 quantities per cell: n_1s, the true-absorption depth kappa_c
+ * of Eq. (<fnu>), the bulk velocity, the emission weight) and allocates every
+ * device buffer except the per-packet queue (sized by mc_lya_emit).
+ *   out      host, receives the context (set to NULL on failure)
+ *   boxes    host [n_boxes]; the field pointers must stay valid and unchanged
+ *            until mc_lya_destroy, or until they are refreshed
+ *   n_boxes  1 to 1024
+ *   stream   hipStream_t to run on (NULL = the default stream)
+ * Synchronises the stream (to report invalid fields). Errors: EINVAL,
+ * ENOMEM, EOVERFLOW, EDEVICE. */
+mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_t n_boxes,
+                          void *stream);
+
+/* Re-reads the field arrays of every box (same pointers, new contents) and
+ * repacks them. Synchronises the stream. Afterwards mc_lya_emit must be called. */
+mc_lya_status mc_lya_refresh(mc_lya_ctx *ctx);
+
+/* Distributes n_packets[b] packets over the cells of box b in proportion to
+ * the emission weight (systematic integer allocation: cell c receives
+ * floor-based counts with |N_c - N q_c / sum q| < 1, q_c = floor(2^32 S_c /
+ * max S)), zeroes the tallies, and keys packet p of box b to the Philox4x32-10
+ * stream (key = seeds[b], counter = (p, s)). May (re)allocate the packet queue
+ * when the total packet count grows.
+ *   seeds, n_packets  host [n_boxes]; n_packets[b] may be 0
+ * Errors: EINVAL, EOVERFLOW (w0 * packets >= 2^63), ENOMEM, ESTATE, EDEVICE. */
+mc_lya_status mc_lya_emit(mc_lya_ctx *ctx, const uint64_t *seeds, const uint64_t *n_packets);
+
+/* Walks every emitted packet (App. A steps 1-4 and the red-wing exit) and
+ * accumulates the per-cell absorbed weight and the per-box totals.
+ * Asynchronous on the context's stream. Errors: ESTATE, EDEVICE. */
+mc_lya_status mc_lya_transport(mc_lya_ctx *ctx);
+
+/* As mc_lya_transport, for global packet ids [first, first + count) only.
+ * Tallies accumulate, so disjoint ranges covering all packets give the same
+ * integers as one mc_lya_transport call. Errors: EINVAL (range outside the
+ * emitted packets), ESTATE, EDEVICE. */
+mc_lya_status mc_lya_transport_range(mc_lya_ctx *ctx, uint64_t first, uint64_t count);
+
+/* Finishes a transport: checks the conservation identity per box and copies
+ * the tallies out. Synchronises the stream.
+ *   absorbed  dev [total cells] int64, or NULL
+ *   emitted   dev [total cells] int64 (w0 * packets emitted per cell), or NULL
+ *   stats     host [n_boxes], or NULL
+ * Returns ECAP if a packet hit the crossing cap, ECONSERVE if the identity
+ * fails, else OK. */
+mc_lya_status mc_lya_tally(mc_lya_ctx *ctx, int64_t *absorbed, int64_t *emitted,
+                           mc_lya_box_stats *stats);
+
+/* Recombination feed from the last transport (Sec. III.A.1 Eq. (rec),
+ * Sec. IV.B Eq. (dotne-mix)): with a_c = A_c sum(S) / (w0 N) the absorbed
+ * rate density, beta_e/(beta_e + Lambda_2g) of it re-ionises, and
+ *   ndot_e,c = -S_c + beta/(beta+Lambda) a_c + C_MC beta n_1s,c exp(-E_alpha/kT),
+ *   C_MC = [E + sum(A) Lambda/(beta+Lambda)] / (w0 N);
+ * and the mixing correction M_c = A_c / A_c^fm with A_c^fm = sum(A) n_1s,c /
+ * sum(n_1s) (1 everywhere under full mixing).
+ *   ndot_e    dev [total cells] double, or NULL
+ *   mix_corr  dev [total cells] float, or NULL
+ *   stats     host [n_boxes], or NULL
+ * Synchronises the stream. Errors: ESTATE, EDEVICE. */
+mc_lya_status mc_lya_feed(mc_lya_ctx *ctx, double *ndot_e, float *mix_corr,
+                          mc_lya_feed_stats *stats);
+
+/* Replays packets [first, first + count) of the current emission and writes
+ * their histories without touching the tallies.
+ *   out  dev [count]
+ * Errors: EINVAL, ESTATE, EDEVICE. */
+mc_lya_status mc_lya_trace(mc_lya_ctx *ctx, uint64_t first, uint64_t count,
+                           mc_lya_packet_trace *out);
+
+/* Sets a tunable (see the MC_LYA_OPT_ enum). Errors: EINVAL. */
+mc_lya_status mc_lya_set_option(mc_lya_ctx *ctx, int32_t option, int64_t value);
+
+/* Sum of the durations of the transport kernels since the last call (ms),
+ * measured with HIP events on the context's stream when MC_LYA_OPT_TIMING is
+ * on; also returns the number of launches timed. Synchronises the stream. */
+mc_lya_status mc_lya_kernel_time(mc_lya_ctx *ctx, double *ms, int64_t *launches);
+
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) on the device: n blocks,
+ * ctr dev [n][4], key dev [n][2], out dev [n][4]. The packet streams use
+ * counter (p_lo, p_hi, s, 0), s = 0, 1, and key (seed_lo, seed_hi); the 8
+ * words give the uniforms (w >> 9) + 1/2) 2^-23 in (0, 1). Asynchronous on
+ * `stream`. Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out,
+                                   uint64_t n, void *stream);
+
+/* Frees the context and its device memory (synchronises its stream). NULL ok. */
+void mc_lya_destroy(mc_lya_ctx *ctx);
+
+/* Static description of a status code. */
+const char *mc_lya_strerror(mc_lya_status status);
+
+/* Description of the context's last failure ("" if none); valid until the
+ * next call on the context. */
+const char *mc_lya_last_error(const mc_lya_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC_LYA_H */

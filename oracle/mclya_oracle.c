@@ -312,6 +312,18 @@ int orc_transport(const orc_box *b, const double *kappa, const double *ux, const
     return 0;
 }
 
+/* Walk the packets ids[0..n) one after another (single thread) and return
+ * their records. Deposits go to the caller's scratch array A. */
+int orc_walk_packets(const orc_box *b, const double *kappa, const double *ux, const double *uy,
+                     const double *uz, const uint64_t *first, const uint64_t *ids, int64_t n,
+                     int64_t *A, orc_packet_rec *recs)
+{
+    const int64_t ncells = (int64_t)b->nx * b->ny * b->nz;
+    for (int64_t i = 0; i < n; ++i)
+        orc_walk_one(b, kappa, ux, uy, uz, ids[i], orc_find_cell(first, ncells, ids[i]), A, &recs[i], NULL);
+    return 0;
+}
+
 /* Walk one packet and record every segment (cell, deposit, x_in, x_out,
  * length). A receives its deposits. Returns the number of segments; only the
  * first `cap` are stored. */

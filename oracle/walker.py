@@ -47,6 +47,10 @@ def lib():
                                        C.c_void_p, P_(C.c_int64), P_(C.c_int64), P_(C.c_double),
                                        P_(C.c_double), P_(C.c_double), C.c_int64]
         L.orc_trace_packet.restype = C.c_int64
+        L.orc_walk_packets.argtypes = [P_(OrcBox), P_(C.c_double), P_(C.c_double), P_(C.c_double),
+                                       P_(C.c_double), P_(C.c_uint64), P_(C.c_uint64), C.c_int64,
+                                       P_(C.c_int64), C.c_void_p]
+        L.orc_walk_packets.restype = C.c_int
         _lib = L
     return _lib
 
@@ -153,6 +157,17 @@ class Prepared:
         if records:
             res["records"] = recs
         return res
+
+    def records(self, ids):
+        """Per-packet records of the given packet ids (single thread)."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        recs = np.zeros(ids.size, dtype=REC_DTYPE)
+        scratch = np.zeros(self.kappa.size, dtype=np.int64)
+        lib().orc_walk_packets(C.byref(self.box), _ptr(self.kappa, C.c_double), self._vp(0),
+                               self._vp(1), self._vp(2), _ptr(self.first, C.c_uint64),
+                               _ptr(ids, C.c_uint64), ids.size, _ptr(scratch, C.c_int64),
+                               recs.ctypes.data)
+        return recs
 
     def trace(self, p, cap=100_000):
         """Every segment of packet p: dict(cells, deposits, x_in, x_out, length, record)."""

@@ -1,0 +1,192 @@
+"""ctypes binding of libmclya.so: the C ABI of include/mc_lya.h, same names.
+
+Argument marshalling only. Every step of the transport runs in the HIP
+kernels of the library; nothing here computes. torch is imported first so that
+the library binds to the HIP runtime torch already loaded (one runtime, shared
+streams and device pointers).
+"""
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library must share)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmclya.so")
+
+MC_LYA_OK, MC_LYA_EINVAL, MC_LYA_ENOMEM, MC_LYA_EDEVICE = 0, 1, 2, 3
+MC_LYA_EOVERFLOW, MC_LYA_ESTATE, MC_LYA_ECAP, MC_LYA_ECONSERVE = 4, 5, 6, 7
+MC_LYA_VEL_NONE, MC_LYA_VEL_F32, MC_LYA_VEL_F16 = 0, 1, 2
+MC_LYA_OPT_KERNEL, MC_LYA_OPT_BLOCK, MC_LYA_OPT_WAVES_PER_CU, MC_LYA_OPT_CHUNK = 1, 2, 3, 4
+MC_LYA_OPT_REFILL, MC_LYA_OPT_MAX_CROSSINGS, MC_LYA_OPT_TIMING, MC_LYA_OPT_GRAPH = 5, 6, 7, 8
+
+
+class mc_lya_box_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("vel_dtype", C.c_int32),
+                ("cell_comoving_cm", C.c_double), ("z", C.c_double), ("zeta", C.c_double),
+                ("x_esc", C.c_double), ("temp_K", C.c_double), ("h", C.c_double),
+                ("omega_b_h2", C.c_double), ("omega_c_h2", C.c_double), ("y_p", C.c_double),
+                ("t_cmb0", C.c_double), ("n_eff", C.c_double), ("w0", C.c_uint64),
+                ("overdensity", C.c_void_p), ("velocity", C.c_void_p), ("x_e", C.c_void_p),
+                ("x_e_uniform", C.c_float), ("reserved", C.c_int32), ("source", C.c_void_p)]
+
+
+class mc_lya_box_stats(C.Structure):
+    _fields_ = [("emitted", C.c_int64), ("absorbed", C.c_int64), ("escaped", C.c_int64),
+                ("capped_weight", C.c_int64), ("capped_packets", C.c_int64),
+                ("crossings", C.c_int64), ("packets", C.c_int64), ("conserved", C.c_int32),
+                ("reserved", C.c_int32), ("delta", C.c_double), ("x_eff", C.c_double),
+                ("tau_ab_mean", C.c_double)]
+
+
+class mc_lya_feed_stats(C.Structure):
+    _fields_ = [("c_mc", C.c_double), ("c_mix", C.c_double), ("f_escape", C.c_double),
+                ("f_absorbed", C.c_double), ("x_e_global", C.c_double),
+                ("ndot_e_mean", C.c_double)]
+
+
+class mc_lya_packet_trace(C.Structure):
+    _fields_ = [("cell0", C.c_uint32), ("fx", C.c_float), ("fy", C.c_float), ("fz", C.c_float),
+                ("kx", C.c_float), ("ky", C.c_float), ("kz", C.c_float), ("x0", C.c_float),
+                ("escaped", C.c_int64), ("absorbed", C.c_int64), ("crossings", C.c_uint32),
+                ("fate", C.c_int32)]
+
+
+EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
+           "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace",
+           "mc_lya_set_option", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
+           "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error"]
+
+
+class MCLyaError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Loads libmclya.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc for gfx950); there is no fallback")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, u64, i32, i64 = C.c_void_p, C.c_uint64, C.c_int32, C.c_int64
+    L.mc_lya_init.argtypes = [P(vp), P(mc_lya_box_desc), i32, vp]
+    L.mc_lya_refresh.argtypes = [vp]
+    L.mc_lya_emit.argtypes = [vp, P(u64), P(u64)]
+    L.mc_lya_transport.argtypes = [vp]
+    L.mc_lya_transport_range.argtypes = [vp, u64, u64]
+    L.mc_lya_tally.argtypes = [vp, vp, vp, P(mc_lya_box_stats)]
+    L.mc_lya_feed.argtypes = [vp, vp, vp, P(mc_lya_feed_stats)]
+    L.mc_lya_trace.argtypes = [vp, u64, u64, vp]
+    L.mc_lya_set_option.argtypes = [vp, i32, i64]
+    L.mc_lya_kernel_time.argtypes = [vp, P(C.c_double), P(i64)]
+    L.mc_lya_philox4x32_10.argtypes = [vp, vp, vp, u64, vp]
+    for name in EXPORTS:
+        if name in ("mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error"):
+            continue
+        getattr(L, name).restype = C.c_int
+    L.mc_lya_destroy.argtypes = [vp]
+    L.mc_lya_destroy.restype = None
+    L.mc_lya_strerror.argtypes = [C.c_int]
+    L.mc_lya_strerror.restype = C.c_char_p
+    L.mc_lya_last_error.argtypes = [vp]
+    L.mc_lya_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status, ctx=None):
+    if status != MC_LYA_OK:
+        L = load()
+        msg = L.mc_lya_last_error(ctx).decode() or L.mc_lya_strerror(status).decode()
+        raise MCLyaError(status, msg)
+    return status
+
+
+def _arr(ctype, values):
+    values = list(values)
+    return (ctype * len(values))(*values)
+
+
+def mc_lya_init(boxes, stream=None):
+    """boxes: sequence of mc_lya_box_desc; stream: hipStream_t as int (None =
+    torch's current stream). Returns the context handle."""
+    L = load()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    arr = (mc_lya_box_desc * len(boxes))(*boxes)
+    ctx = C.c_void_p()
+    _check(L.mc_lya_init(C.byref(ctx), arr, len(boxes), C.c_void_p(stream)))
+    return ctx
+
+
+def mc_lya_refresh(ctx):
+    return _check(load().mc_lya_refresh(ctx), ctx)
+
+
+def mc_lya_emit(ctx, seeds, n_packets):
+    return _check(load().mc_lya_emit(ctx, _arr(C.c_uint64, seeds), _arr(C.c_uint64, n_packets)), ctx)
+
+
+def mc_lya_transport(ctx):
+    return _check(load().mc_lya_transport(ctx), ctx)
+
+
+def mc_lya_transport_range(ctx, first, count):
+    return _check(load().mc_lya_transport_range(ctx, int(first), int(count)), ctx)
+
+
+def mc_lya_tally(ctx, absorbed_ptr, emitted_ptr, n_boxes, check=True):
+    """Returns (status, [mc_lya_box_stats]); raises unless check is False."""
+    stats = (mc_lya_box_stats * n_boxes)()
+    s = load().mc_lya_tally(ctx, absorbed_ptr, emitted_ptr, stats)
+    if check:
+        _check(s, ctx)
+    return s, list(stats)
+
+
+def mc_lya_feed(ctx, ndot_ptr, mix_ptr, n_boxes):
+    stats = (mc_lya_feed_stats * n_boxes)()
+    _check(load().mc_lya_feed(ctx, ndot_ptr, mix_ptr, stats), ctx)
+    return list(stats)
+
+
+def mc_lya_trace(ctx, first, count, out_ptr):
+    return _check(load().mc_lya_trace(ctx, int(first), int(count), out_ptr), ctx)
+
+
+def mc_lya_set_option(ctx, option, value):
+    return _check(load().mc_lya_set_option(ctx, int(option), int(value)), ctx)
+
+
+def mc_lya_kernel_time(ctx):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(load().mc_lya_kernel_time(ctx, C.byref(ms), C.byref(n)), ctx)
+    return ms.value, n.value
+
+
+def mc_lya_philox4x32_10(ctr_ptr, key_ptr, out_ptr, n, stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    return _check(load().mc_lya_philox4x32_10(ctr_ptr, key_ptr, out_ptr, int(n), C.c_void_p(stream)))
+
+
+def mc_lya_destroy(ctx):
+    if ctx:
+        load().mc_lya_destroy(ctx)
+
+
+def mc_lya_strerror(status):
+    return load().mc_lya_strerror(int(status)).decode()
+
+
+def mc_lya_last_error(ctx=None):
+    return load().mc_lya_last_error(ctx).decode()

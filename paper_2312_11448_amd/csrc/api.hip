@@ -1,0 +1,653 @@
+// Host runtime behind the C ABI of mc_lya.h: argument validation, the FP64
+// physics scalars of each box, device buffers, the state machine and the
+// kernel launch sequence. All device work runs on the context's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace mclya;
+
+static_assert(sizeof(mc_lya_box_desc) == 152, "mc_lya_box_desc layout");
+static_assert(sizeof(mc_lya_box_stats) == 88, "mc_lya_box_stats layout");
+static_assert(sizeof(mc_lya_packet_trace) == 56, "mc_lya_packet_trace layout");
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Physics scalars (binary64, host). Paper: Sec. II.C (cosmology), Sec. III.A.1
+// (three-level atom), Sec. IV.A (p_ab and the absorption depth), App. A
+// (thermal velocity and the Hubble drift).
+// ---------------------------------------------------------------------------
+namespace phys {
+constexpr double kC = 2.99792458e10;          // cm/s
+constexpr double kBoltz = 1.380649e-16;       // erg/K
+constexpr double kPlanck = 6.62607015e-27;    // erg s
+constexpr double kMe = 9.1093837015e-28;      // g
+constexpr double kMH = 1.6735328e-24;         // g, hydrogen atom
+constexpr double kGrav = 6.67430e-8;          // cgs
+constexpr double kMpc = 3.0856775814913673e24; // cm
+constexpr double kEV = 1.602176634e-12;       // erg
+constexpr double kArad = 7.565723e-15;        // erg cm^-3 K^-4
+constexpr double kEion = 13.598434 * kEV;     // H ionisation energy
+constexpr double kLya = 1215.67e-8;           // cm
+constexpr double kA2p = 6.2649e8;             // s^-1
+constexpr double kL2g = 8.22458;              // s^-1
+constexpr double kPi = 3.14159265358979323846;
+
+struct Box {
+    double H, vth, delta, nH, kappa_unit, alpha, beta, pab, boltz;
+};
+
+inline Box scalars(const mc_lya_box_desc &d)
+{
+    Box o;
+    const double H0 = d.h * 1.0e7 / kMpc;                         // 100 h km/s/Mpc
+    const double rhoc = 3.0 * H0 * H0 / (8.0 * kPi * kGrav);
+    const double om = (d.omega_b_h2 + d.omega_c_h2) / (d.h * d.h);
+    const double og = kArad * std::pow(d.t_cmb0, 4) / (rhoc * kC * kC);
+    const double orad = og * (1.0 + 0.875 * std::pow(4.0 / 11.0, 4.0 / 3.0) * d.n_eff);
+    const double ol = 1.0 - om - orad;
+    const double a1 = 1.0 + d.z;
+    o.H = d.zeta * H0 * std::sqrt(om * a1 * a1 * a1 + orad * a1 * a1 * a1 * a1 + ol);
+    const double T = d.temp_K;
+    o.vth = std::sqrt(2.0 * kBoltz * T / kMH);
+    const double dl = d.cell_comoving_cm / a1;                    // physical cell width
+    o.delta = o.H * dl / o.vth;                                   // App. A step 4 per cell
+    o.nH = (1.0 - d.y_p) * (d.omega_b_h2 / (d.h * d.h)) * rhoc / kMH * a1 * a1 * a1;
+    const double t4 = T / 1.0e4;                                  // alpha_e = 1.14 A_B
+    o.alpha = 1.14e-13 * 4.309 * std::pow(t4, -0.6166) / (1.0 + 0.6703 * std::pow(t4, 0.5300));
+    const double saha = std::pow(2.0 * kPi * kMe * kBoltz * T / (kPlanck * kPlanck), 1.5);
+    o.beta = o.alpha * saha * std::exp(-0.25 * kEion / (kBoltz * T));   // per 2s atom
+    o.pab = (o.beta + kL2g) / (3.0 * kA2p + o.beta + kL2g);
+    // kappa_c = p_ab 3 lambda^3 A n_1s / (8 pi zeta H), n_1s = nH (1 - x_e) Delta
+    o.kappa_unit = o.pab * 3.0 * kLya * kLya * kLya * kA2p / (8.0 * kPi * o.H) * o.nH;
+    o.boltz = std::exp(-0.75 * kEion / (kBoltz * T));
+    return o;
+}
+}  // namespace phys
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
+}
+
+}  // namespace
+
+struct mc_lya_ctx {
+    hipStream_t stream = nullptr;
+    int n_boxes = 0;
+    std::vector<mc_lya_box_desc> desc;
+    std::vector<phys::Box> ph;
+    std::vector<PackBox> pack;
+    std::vector<WalkBox> walk;
+    std::vector<BoxRed> red;
+    std::vector<uint64_t> walked;     // packets walked per box since the last emit
+    uint64_t total_cells = 0;
+    uint64_t total_packets = 0;
+    int max_blk = 1;
+    bool vel = false;
+    int num_cu = 256;
+
+    PackBox *d_pack = nullptr;
+    WalkBox *d_walk = nullptr;
+    BoxRed *d_red = nullptr;
+    BoxTot *d_tot = nullptr;
+    void *d_rec = nullptr;
+    double *d_wgt = nullptr;
+    double *d_part = nullptr;
+    uint64_t *d_q = nullptr;
+    uint64_t *d_bsum = nullptr;
+    uint32_t *d_npk = nullptr;
+    unsigned long long *d_A = nullptr;
+    unsigned long long *d_queue = nullptr;
+    unsigned long long *d_boxabs = nullptr;
+    double *d_fsum = nullptr;
+    FeedBox *d_feed = nullptr;
+    uint32_t *d_cop = nullptr;
+    uint64_t cop_cap = 0;
+
+    int state = 0;                    // 0 packed, 1 emitted, 2 transported
+    // options
+    int kernel = 0, block = 256, waves_per_cu = 32, chunk = 256, refill = 16;
+    int64_t max_cross = 1000000;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_err;   // last failure of mc_lya_init on this thread
+
+mc_lya_status fail(mc_lya_ctx *c, mc_lya_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_init_err = msg;
+    return s;
+}
+
+mc_lya_status hip_fail(mc_lya_ctx *c, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (c) c->err = m;
+    return e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE;
+}
+
+#define HIP_TRY(ctx, expr)                                           \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);     \
+    } while (0)
+
+void free_all(mc_lya_ctx *c)
+{
+    void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
+                    c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
+                    c->d_cop};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &ev : c->events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    c->events.clear();
+}
+
+std::string check_desc(const mc_lya_box_desc &d, int b)
+{
+    char buf[256];
+    auto bad = [&](const char *what) {
+        std::snprintf(buf, sizeof buf, "box %d: %s", b, what);
+        return std::string(buf);
+    };
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return bad("grid edges must be >= 1");
+    if (!(d.cell_comoving_cm > 0.0) || !std::isfinite(d.cell_comoving_cm)) return bad("cell_comoving_cm must be > 0");
+    if (!(d.z > 0.0) || !std::isfinite(d.z)) return bad("z must be > 0");
+    if (!(d.zeta > 0.0) || !std::isfinite(d.zeta)) return bad("zeta must be > 0");
+    if (!(d.x_esc > 0.0) || !std::isfinite(d.x_esc)) return bad("x_esc must be > 0");
+    if (!(d.temp_K > 0.0) || !std::isfinite(d.temp_K)) return bad("temp_K must be > 0");
+    if (!(d.h > 0.0) || !(d.omega_b_h2 > 0.0) || !(d.omega_c_h2 >= 0.0) || !(d.y_p >= 0.0 && d.y_p < 1.0) ||
+        !(d.t_cmb0 > 0.0) || !(d.n_eff >= 0.0))
+        return bad("cosmological parameters out of range");
+    if (d.w0 == 0) return bad("w0 must be > 0");
+    if (!d.overdensity) return bad("overdensity is NULL");
+    if (d.vel_dtype != MC_LYA_VEL_NONE && d.vel_dtype != MC_LYA_VEL_F32 && d.vel_dtype != MC_LYA_VEL_F16)
+        return bad("unknown vel_dtype");
+    if ((d.vel_dtype == MC_LYA_VEL_NONE) != (d.velocity == nullptr))
+        return bad("velocity must be given exactly when vel_dtype is not NONE");
+    if (!d.x_e && !(d.x_e_uniform >= 0.0f && d.x_e_uniform <= 1.2f)) return bad("x_e_uniform outside [0, 1.2]");
+    if (d.reserved != 0) return bad("reserved must be 0");
+    return std::string();
+}
+
+mc_lya_status do_refresh(mc_lya_ctx *c)
+{
+    const int nb = c->n_boxes;
+    HIP_TRY(c, hipMemsetAsync(c->d_red, 0, sizeof(BoxRed) * nb, c->stream));
+    HIP_TRY(c, launch_pack(c->d_pack, nb, c->max_blk, c->vel, c->d_rec, c->d_wgt, c->d_part, c->d_red,
+                           c->stream));
+    HIP_TRY(c, launch_box_reduce(c->d_pack, nb, c->max_blk, c->d_part, c->d_red, c->stream));
+    if (c->vel)
+        HIP_TRY(c, launch_margin(c->d_pack, nb, c->max_blk, static_cast<const float4 *>(c->d_rec), c->d_red,
+                                 c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->red.data(), c->d_red, sizeof(BoxRed) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nb; ++b) {
+        const uint32_t f = c->red[b].flags;
+        if (f) {
+            std::string what;
+            if (f & FLAG_OD_BAD) what += " overdensity negative or not finite;";
+            if (f & FLAG_XE_BAD) what += " x_e outside [0, 1.2] or not finite;";
+            if (f & FLAG_VEL_BAD) what += " velocity not finite;";
+            if (f & FLAG_SRC_BAD) what += " source negative or not finite;";
+            c->state = -1;
+            return fail(c, MC_LYA_EINVAL, "box " + std::to_string(b) + ":" + what);
+        }
+        double udev = 0.0;
+        std::memcpy(&udev, &c->red[b].udev_bits, sizeof udev);
+        WalkBox &w = c->walk[b];
+        w.x_eff = (float)(c->desc[b].x_esc + 2.0 * udev);
+        w.delta = (float)c->ph[b].delta;
+        w.valid = 1;
+    }
+    c->state = 0;
+    return MC_LYA_OK;
+}
+
+mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
+{
+    if (count == 0) return MC_LYA_OK;
+    WalkParams p;
+    p.boxes = c->d_walk;
+    p.n_boxes = c->n_boxes;
+    p.vel = c->vel ? 1 : 0;
+    p.rec = c->d_rec;
+    p.cell_of_packet = c->d_cop;
+    p.A = c->d_A;
+    p.tot = c->d_tot;
+    p.queue = c->d_queue;
+    p.first = first;
+    p.count = count;
+    p.max_cross = c->max_cross;
+    p.chunk = c->chunk;
+    p.refill = c->refill;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->events_used == c->events.size()) {
+            hipEvent_t a, b;
+            HIP_TRY(c, hipEventCreate(&a));
+            HIP_TRY(c, hipEventCreate(&b));
+            c->events.emplace_back(a, b);
+        }
+        e0 = c->events[c->events_used].first;
+        e1 = c->events[c->events_used].second;
+        ++c->events_used;
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+    }
+    if (c->kernel == 1) {
+        HIP_TRY(c, launch_walk_simple(p, c->block, c->stream));
+    } else {
+        const int waves_per_block = c->block / 64;
+        int grid = std::max(1, c->num_cu * c->waves_per_cu / waves_per_block);
+        const uint64_t need = (count + 63) / 64;     // no more waves than packets
+        if ((uint64_t)grid * waves_per_block > need) grid = (int)std::max<uint64_t>(1, (need + waves_per_block - 1) / waves_per_block);
+        HIP_TRY(c, launch_walk_persistent(p, c->block, grid, c->stream));
+    }
+    if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
+    // account the walked packets per box
+    for (int b = 0; b < c->n_boxes; ++b) {
+        const uint64_t lo = std::max(first, c->walk[b].pkt_off);
+        const uint64_t hi = std::min(first + count, c->walk[b].pkt_off + c->walk[b].npkt);
+        if (hi > lo) c->walked[b] += hi - lo;
+    }
+    c->state = 2;
+    return MC_LYA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mc_lya_strerror(mc_lya_status s)
+{
+    switch (s) {
+    case MC_LYA_OK: return "ok";
+    case MC_LYA_EINVAL: return "invalid argument or field value";
+    case MC_LYA_ENOMEM: return "device allocation failed";
+    case MC_LYA_EDEVICE: return "HIP runtime error";
+    case MC_LYA_EOVERFLOW: return "integer range exceeded";
+    case MC_LYA_ESTATE: return "call out of order";
+    case MC_LYA_ECAP: return "a packet hit the crossing cap";
+    case MC_LYA_ECONSERVE: return "conservation identity failed";
+    }
+    return "unknown status";
+}
+
+const char *mc_lya_last_error(const mc_lya_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_err.c_str(); }
+
+mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_t n_boxes, void *stream)
+{
+    g_init_err.clear();
+    if (!out) return fail(nullptr, MC_LYA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!boxes || n_boxes < 1 || n_boxes > 1024)
+        return fail(nullptr, MC_LYA_EINVAL, "need 1 to 1024 box descriptors");
+    uint64_t cells = 0;
+    for (int b = 0; b < n_boxes; ++b) {
+        const std::string why = check_desc(boxes[b], b);
+        if (!why.empty()) return fail(nullptr, MC_LYA_EINVAL, why);
+        cells += (uint64_t)boxes[b].nx * (uint64_t)boxes[b].ny * (uint64_t)boxes[b].nz;
+        if (cells >= (1ull << 32)) return fail(nullptr, MC_LYA_EOVERFLOW, "more than 2^32 cells in total");
+    }
+    mc_lya_ctx *c = new (std::nothrow) mc_lya_ctx;
+    if (!c) return fail(nullptr, MC_LYA_ENOMEM, "host allocation failed");
+    c->stream = static_cast<hipStream_t>(stream);
+    c->n_boxes = n_boxes;
+    c->desc.assign(boxes, boxes + n_boxes);
+    c->total_cells = cells;
+    c->pack.resize(n_boxes);
+    c->walk.resize(n_boxes);
+    c->red.resize(n_boxes);
+    c->walked.assign(n_boxes, 0);
+    c->ph.resize(n_boxes);
+    uint64_t off = 0;
+    int max_blk = 1;
+    for (int b = 0; b < n_boxes; ++b) {
+        const mc_lya_box_desc &d = boxes[b];
+        const uint64_t n = (uint64_t)d.nx * d.ny * d.nz;
+        c->ph[b] = phys::scalars(d);
+        PackBox &p = c->pack[b];
+        std::memset(&p, 0, sizeof p);
+        p.od = d.overdensity;
+        p.vel = d.velocity;
+        p.xe = d.x_e;
+        p.src = d.source;
+        p.kappa_unit = c->ph[b].kappa_unit;
+        p.cell_off = (uint32_t)off;
+        p.ncells = (uint32_t)n;
+        p.xe_uniform = d.x_e_uniform;
+        p.vel_dtype = d.vel_dtype;
+        p.nblk = (int)((n + kSetupBlock - 1) / kSetupBlock);
+        max_blk = std::max(max_blk, p.nblk);
+        WalkBox &w = c->walk[b];
+        std::memset(&w, 0, sizeof w);
+        w.nx = d.nx;
+        w.ny = d.ny;
+        w.nz = d.nz;
+        w.cell_off = (uint32_t)off;
+        w.ncells = (uint32_t)n;
+        w.w0 = d.w0;
+        if (d.vel_dtype != MC_LYA_VEL_NONE) c->vel = true;
+        off += n;
+    }
+    c->max_blk = max_blk;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            c->num_cu = cu;
+    }
+    auto cleanup = [&](mc_lya_status s) {
+        g_init_err = c->err.empty() ? std::string(mc_lya_strerror(s)) : c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+    const size_t nbk = (size_t)n_boxes * max_blk;
+    hipError_t e = hipSuccess;
+    if ((e = dalloc(&c->d_pack, n_boxes)) != hipSuccess || (e = dalloc(&c->d_walk, n_boxes)) != hipSuccess ||
+        (e = dalloc(&c->d_red, n_boxes)) != hipSuccess || (e = dalloc(&c->d_tot, n_boxes)) != hipSuccess ||
+        (e = hipMalloc(&c->d_rec, cells * (c->vel ? sizeof(float4) : sizeof(float)))) != hipSuccess ||
+        (e = dalloc(&c->d_wgt, cells)) != hipSuccess || (e = dalloc(&c->d_part, nbk * 4)) != hipSuccess ||
+        (e = dalloc(&c->d_q, cells)) != hipSuccess || (e = dalloc(&c->d_bsum, nbk)) != hipSuccess ||
+        (e = dalloc(&c->d_npk, cells)) != hipSuccess || (e = dalloc(&c->d_A, cells)) != hipSuccess ||
+        (e = dalloc(&c->d_queue, 1)) != hipSuccess || (e = dalloc(&c->d_boxabs, n_boxes)) != hipSuccess ||
+        (e = dalloc(&c->d_fsum, (size_t)4 * n_boxes)) != hipSuccess ||
+        (e = dalloc(&c->d_feed, n_boxes)) != hipSuccess)
+        return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
+    if (hipMemcpyAsync(c->d_pack, c->pack.data(), sizeof(PackBox) * n_boxes, hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess)
+        return cleanup(MC_LYA_EDEVICE);
+    mc_lya_status s = do_refresh(c);
+    if (s != MC_LYA_OK) return cleanup(s);
+    *out = c;
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_refresh(mc_lya_ctx *c)
+{
+    if (!c) return MC_LYA_EINVAL;
+    return do_refresh(c);
+}
+
+mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *n_packets)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 0) return fail(c, MC_LYA_ESTATE, "fields failed validation; call mc_lya_refresh");
+    if (!seeds || !n_packets) return fail(c, MC_LYA_EINVAL, "seeds and n_packets must not be NULL");
+    unsigned __int128 total = 0, weight = 0;
+    for (int b = 0; b < c->n_boxes; ++b) {
+        total += n_packets[b];
+        weight += (unsigned __int128)n_packets[b] * c->desc[b].w0;
+        double wmax = 0.0;
+        std::memcpy(&wmax, &c->red[b].wmax_bits, sizeof wmax);
+        if (n_packets[b] > 0 && !(wmax > 0.0))
+            return fail(c, MC_LYA_EINVAL, "box " + std::to_string(b) + ": every emission weight is zero");
+        if ((unsigned __int128)n_packets[b] * c->desc[b].w0 >= ((unsigned __int128)1 << 63))
+            return fail(c, MC_LYA_EOVERFLOW, "w0 * packets of a box must stay below 2^63");
+    }
+    if (weight >= ((unsigned __int128)1 << 63) || total >= ((unsigned __int128)1 << 40))
+        return fail(c, MC_LYA_EOVERFLOW, "total packets or total weight too large");
+    const uint64_t ntot = (uint64_t)total;
+    if (ntot > c->cop_cap) {
+        uint32_t *np = nullptr;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&np), ntot * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(c, e, "packet queue allocation");
+        if (c->d_cop) (void)hipFree(c->d_cop);
+        c->d_cop = np;
+        c->cop_cap = ntot;
+    }
+    uint64_t off = 0;
+    for (int b = 0; b < c->n_boxes; ++b) {
+        c->walk[b].pkt_off = off;
+        c->walk[b].npkt = n_packets[b];
+        c->walk[b].seed = seeds[b];
+        off += n_packets[b];
+        c->walked[b] = 0;
+    }
+    c->total_packets = ntot;
+    const int nb = c->n_boxes;
+    HIP_TRY(c, hipMemcpyAsync(c->d_walk, c->walk.data(), sizeof(WalkBox) * nb, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_quantize(c->d_pack, nb, c->max_blk, c->d_wgt, c->d_red, c->d_q, c->d_bsum, c->stream));
+    HIP_TRY(c, launch_scan_blocks(c->d_pack, nb, c->max_blk, c->d_bsum, c->d_red, c->stream));
+    HIP_TRY(c, launch_allocate(c->d_pack, c->d_walk, nb, c->max_blk, c->d_q, c->d_bsum, c->d_red, c->d_npk,
+                               c->d_cop, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_A, 0, sizeof(unsigned long long) * c->total_cells, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_tot, 0, sizeof(BoxTot) * nb, c->stream));
+    c->state = 1;
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_transport(mc_lya_ctx *c)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_transport before mc_lya_emit");
+    return launch_walk(c, 0, c->total_packets);
+}
+
+mc_lya_status mc_lya_transport_range(mc_lya_ctx *c, uint64_t first, uint64_t count)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_transport_range before mc_lya_emit");
+    if (first > c->total_packets || count > c->total_packets - first)
+        return fail(c, MC_LYA_EINVAL, "packet range outside the emitted packets");
+    return launch_walk(c, first, count);
+}
+
+mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, mc_lya_box_stats *stats)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_tally before mc_lya_emit");
+    const int nb = c->n_boxes;
+    HIP_TRY(c, hipMemsetAsync(c->d_boxabs, 0, sizeof(unsigned long long) * nb, c->stream));
+    HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, absorbed, emitted, c->d_boxabs,
+                            c->stream));
+    std::vector<BoxTot> tot(nb);
+    std::vector<unsigned long long> abs(nb);
+    HIP_TRY(c, hipMemcpyAsync(tot.data(), c->d_tot, sizeof(BoxTot) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(abs.data(), c->d_boxabs, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    bool capped = false, broken = false;
+    for (int b = 0; b < nb; ++b) {
+        const uint64_t w0 = c->desc[b].w0;
+        const uint64_t walked_w = c->walked[b] * w0;
+        const uint64_t lhs = abs[b] + tot[b].escaped + tot[b].capped_weight;
+        const bool ok = lhs == walked_w;
+        if (!ok) broken = true;
+        if (tot[b].capped_packets) capped = true;
+        if (stats) {
+            mc_lya_box_stats &s = stats[b];
+            std::memset(&s, 0, sizeof s);
+            s.emitted = (int64_t)walked_w;
+            s.absorbed = (int64_t)abs[b];
+            s.escaped = (int64_t)tot[b].escaped;
+            s.capped_weight = (int64_t)tot[b].capped_weight;
+            s.capped_packets = (int64_t)tot[b].capped_packets;
+            s.crossings = (int64_t)tot[b].crossings;
+            s.packets = (int64_t)c->walked[b];
+            s.conserved = ok ? 1 : 0;
+            s.delta = c->walk[b].delta;
+            s.x_eff = c->walk[b].x_eff;
+            s.tau_ab_mean = c->red[b].kappa_sum / (double)c->walk[b].ncells;
+        }
+    }
+    if (broken) return fail(c, MC_LYA_ECONSERVE, "sum(absorbed) + escaped + capped != w0 * packets");
+    if (capped) return fail(c, MC_LYA_ECAP, "some packets reached the crossing cap");
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya_feed_stats *stats)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 2) return fail(c, MC_LYA_ESTATE, "mc_lya_feed before mc_lya_transport");
+    const int nb = c->n_boxes;
+    HIP_TRY(c, hipMemsetAsync(c->d_boxabs, 0, sizeof(unsigned long long) * nb, c->stream));
+    HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, nullptr, nullptr, c->d_boxabs,
+                            c->stream));
+    HIP_TRY(c, launch_feed_sums(c->d_pack, nb, c->max_blk, c->d_wgt, c->d_part, c->stream));
+    HIP_TRY(c, launch_feed_reduce(nb, c->max_blk, c->d_pack, c->d_part, c->d_fsum, c->stream));
+    std::vector<BoxTot> tot(nb);
+    std::vector<unsigned long long> abs(nb);
+    std::vector<double> sums((size_t)4 * nb);
+    HIP_TRY(c, hipMemcpyAsync(tot.data(), c->d_tot, sizeof(BoxTot) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(abs.data(), c->d_boxabs, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sums.data(), c->d_fsum, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<FeedBox> fb(nb);
+    for (int b = 0; b < nb; ++b) {
+        const phys::Box &ph = c->ph[b];
+        const mc_lya_box_desc &d = c->desc[b];
+        const double ncell = (double)c->walk[b].ncells;
+        const double wtot = (double)c->walked[b] * (double)d.w0;
+        const double s_scale = d.source ? 1.0 : ph.alpha * ph.nH * ph.nH;
+        const double sum_s = s_scale * sums[4 * b + 0];
+        const double sum_n1s = ph.nH * sums[4 * b + 1];
+        const double sum_A = (double)abs[b];
+        const double reion = ph.beta / (ph.beta + phys::kL2g);
+        const double c_mc = wtot > 0.0 ? ((double)tot[b].escaped + sum_A * phys::kL2g / (ph.beta + phys::kL2g)) / wtot
+                                       : 0.0;
+        fb[b].S_scale = s_scale;
+        fb[b].n_h = ph.nH;
+        fb[b].a_norm = wtot > 0.0 ? sum_s / wtot : 0.0;
+        fb[b].reion = reion;
+        fb[b].thermal = c_mc * ph.beta * ph.boltz;
+        fb[b].fm_norm = sum_n1s > 0.0 ? sum_A / sum_n1s : 0.0;
+        if (stats) {
+            mc_lya_feed_stats &s = stats[b];
+            const double n1s_mean = sum_n1s / ncell;
+            const double r_mix = 8.0 * phys::kPi * ph.H /
+                                 (phys::kLya * phys::kLya * phys::kLya * n1s_mean);
+            s.c_mc = c_mc;
+            s.c_mix = (phys::kL2g + r_mix) / (ph.beta + phys::kL2g + r_mix);
+            s.f_escape = wtot > 0.0 ? (double)tot[b].escaped / wtot : 0.0;
+            s.f_absorbed = wtot > 0.0 ? sum_A / wtot : 0.0;
+            s.x_e_global = sums[4 * b + 3] > 0.0 ? sums[4 * b + 2] / sums[4 * b + 3] : 0.0;
+            // volume mean of the rate: -<S> + reion <a> + thermal <n1s>
+            s.ndot_e_mean = (-sum_s + reion * sum_A * fb[b].a_norm + fb[b].thermal * sum_n1s) / ncell;
+        }
+    }
+    if (ndot_e || mix_corr) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_feed, fb.data(), sizeof(FeedBox) * nb, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, launch_feed(c->d_pack, c->d_feed, nb, c->max_blk, c->d_wgt, c->d_A, ndot_e, mix_corr,
+                               c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_trace(mc_lya_ctx *c, uint64_t first, uint64_t count, mc_lya_packet_trace *out)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_trace before mc_lya_emit");
+    if (!out && count) return fail(c, MC_LYA_EINVAL, "out is NULL");
+    if (first > c->total_packets || count > c->total_packets - first)
+        return fail(c, MC_LYA_EINVAL, "packet range outside the emitted packets");
+    if (count == 0) return MC_LYA_OK;
+    WalkParams p{};
+    p.boxes = c->d_walk;
+    p.n_boxes = c->n_boxes;
+    p.vel = c->vel ? 1 : 0;
+    p.rec = c->d_rec;
+    p.cell_of_packet = c->d_cop;
+    p.first = first;
+    p.count = count;
+    p.max_cross = c->max_cross;
+    HIP_TRY(c, launch_trace(p, out, c->stream));
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
+{
+    if (!c) return MC_LYA_EINVAL;
+    switch (option) {
+    case MC_LYA_OPT_KERNEL:
+        if (v != 0 && v != 1) return fail(c, MC_LYA_EINVAL, "kernel must be 0 or 1");
+        c->kernel = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_BLOCK:
+        if (v != 64 && v != 128 && v != 256) return fail(c, MC_LYA_EINVAL, "block must be 64, 128 or 256");
+        c->block = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_WAVES_PER_CU:
+        if (v < 1 || v > 64) return fail(c, MC_LYA_EINVAL, "waves per CU must be in [1, 64]");
+        c->waves_per_cu = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_CHUNK:
+        if (v < 1 || v > (1 << 20)) return fail(c, MC_LYA_EINVAL, "chunk must be in [1, 2^20]");
+        c->chunk = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_REFILL:
+        if (v < 1 || v > 64) return fail(c, MC_LYA_EINVAL, "refill must be in [1, 64]");
+        c->refill = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_MAX_CROSSINGS:
+        if (v < 1 || v > 0x7fffffff) return fail(c, MC_LYA_EINVAL, "crossing cap must be in [1, 2^31)");
+        c->max_cross = v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_TIMING:
+        c->timing = v != 0;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_GRAPH:
+        if (v != 0) return fail(c, MC_LYA_EINVAL, "graph replay is not available in this build");
+        return MC_LYA_OK;
+    }
+    return fail(c, MC_LYA_EINVAL, "unknown option");
+}
+
+mc_lya_status mc_lya_kernel_time(mc_lya_ctx *c, double *ms, int64_t *launches)
+{
+    if (!c || !ms) return MC_LYA_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < c->events_used; ++i) {
+        float t = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&t, c->events[i].first, c->events[i].second));
+        tot += t;
+    }
+    *ms = tot;
+    if (launches) *launches = (int64_t)c->events_used;
+    c->events_used = 0;
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, uint64_t n,
+                                   void *stream)
+{
+    if (n == 0) return MC_LYA_OK;
+    if (!ctr || !key || !out) return MC_LYA_EINVAL;
+    if (launch_philox(ctr, key, out, n, static_cast<hipStream_t>(stream)) != hipSuccess) return MC_LYA_EDEVICE;
+    return MC_LYA_OK;
+}
+
+void mc_lya_destroy(mc_lya_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations of the MI355X Lyman-alpha transport library.
+// Device-side data layout, the Philox generator and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "mc_lya.h"
+
+namespace mclya {
+
+// ---------------------------------------------------------------------------
+// Device-side box descriptor used by every kernel (64 bytes, one cache line).
+// ---------------------------------------------------------------------------
+struct alignas(64) WalkBox {
+    int32_t nx, ny, nz;
+    int32_t valid;        // 0 when the box's fields failed validation
+    uint32_t cell_off;    // first global cell of the box
+    uint32_t ncells;
+    uint64_t pkt_off;     // first global packet id of the box
+    uint64_t npkt;        // packets emitted in the box
+    uint64_t seed;        // Philox key
+    uint64_t w0;          // weight of one packet
+    float delta;          // red drift per cell width (Doppler units)
+    float x_eff;          // escape once x <= -x_eff
+};
+static_assert(sizeof(WalkBox) == 64, "WalkBox layout");
+
+// Inputs of the pack kernel for one box (device copy of the descriptor).
+struct PackBox {
+    const float *od;
+    const void *vel;
+    const float *xe;
+    const float *src;
+    double kappa_unit;    // kappa_c = kappa_unit * (1 - x_e) * Delta
+    uint32_t cell_off, ncells;
+    float xe_uniform;
+    int32_t vel_dtype;
+    int32_t nblk;         // blocks covering the box
+    int32_t pad;
+};
+
+// Per-box reduction results (device).
+struct BoxRed {
+    double usum[3];       // sum of the velocity components
+    double kappa_sum;     // sum of kappa_c
+    unsigned long long wmax_bits;   // max emission weight (bit pattern of a double >= 0)
+    unsigned long long udev_bits;   // max |U_c - <U>| (bit pattern of a double >= 0)
+    uint32_t flags;       // validation failures (bit mask)
+    uint32_t pad;
+    uint64_t qtot;        // sum of the quantised weights
+};
+
+// Per-box running totals of the walk (device, int64).
+struct BoxTot {
+    unsigned long long escaped;
+    unsigned long long crossings;
+    unsigned long long capped_packets;
+    unsigned long long capped_weight;
+};
+
+enum : uint32_t {
+    FLAG_OD_BAD = 1u,     // non-finite or negative overdensity
+    FLAG_XE_BAD = 2u,     // x_e outside [0, 1.2] or non-finite
+    FLAG_VEL_BAD = 4u,    // non-finite velocity
+    FLAG_SRC_BAD = 8u,    // negative or non-finite source
+    FLAG_ZERO_SRC = 16u   // all emission weights zero
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// (w >> 9) + 1/2, scaled by 2^-23: exact in binary32, strictly inside (0,1).
+__device__ __forceinline__ float u01(uint32_t w)
+{
+    return (float)(w >> 9) * 0x1p-23f + 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (each defined next to its kernels).
+// ---------------------------------------------------------------------------
+constexpr int kSetupBlock = 256;
+
+hipError_t launch_pack(const PackBox *pb_dev, int n_boxes, int max_blk, bool vel_rec, void *rec,
+                       double *wgt, double *partials, BoxRed *red, hipStream_t s);
+hipError_t launch_box_reduce(const PackBox *pb_dev, int n_boxes, int max_blk, const double *partials,
+                             BoxRed *red, hipStream_t s);
+hipError_t launch_margin(const PackBox *pb_dev, int n_boxes, int max_blk, const float4 *rec, BoxRed *red,
+                         hipStream_t s);
+
+hipError_t launch_quantize(const PackBox *pb_dev, int n_boxes, int max_blk, const double *wgt,
+                           const BoxRed *red, uint64_t *q, uint64_t *bsum, hipStream_t s);
+hipError_t launch_scan_blocks(const PackBox *pb_dev, int n_boxes, int max_blk, uint64_t *bsum,
+                              BoxRed *red, hipStream_t s);
+hipError_t launch_allocate(const PackBox *pb_dev, const WalkBox *wb_dev, int n_boxes, int max_blk,
+                           const uint64_t *q, const uint64_t *bsum, const BoxRed *red,
+                           uint32_t *npk, uint32_t *cell_of_packet, hipStream_t s);
+
+struct WalkParams {
+    const WalkBox *boxes;
+    int32_t n_boxes;
+    int32_t vel;             // record layout: 0 = kappa only, 1 = float4 (kappa, U)
+    const void *rec;
+    const uint32_t *cell_of_packet;
+    unsigned long long *A;   // per-cell absorbed weight
+    BoxTot *tot;
+    unsigned long long *queue;   // work counter (persistent kernel)
+    uint64_t first, count;   // global packet range
+    int64_t max_cross;
+    int32_t chunk, refill;
+};
+
+hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s);
+hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s);
+hipError_t launch_trace(const WalkParams &p, mc_lya_packet_trace *out, hipStream_t s);
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, uint64_t n,
+                         hipStream_t s);
+
+hipError_t launch_tally(const WalkBox *wb_dev, int n_boxes, int max_blk, const unsigned long long *A,
+                        const uint32_t *npk, int64_t *absorbed_out, int64_t *emitted_out,
+                        unsigned long long *box_abs, hipStream_t s);
+
+struct FeedBox {
+    double S_scale;          // physical source = S_scale * weight
+    double n_h;              // mean hydrogen density n_H0 (1+z)^3
+    double a_norm;           // sum(S) / (w0 N)
+    double reion;            // beta / (beta + Lambda)
+    double thermal;          // C_MC beta exp(-E_alpha/kT)
+    double fm_norm;          // sum(A) / sum(n_1s)
+};
+hipError_t launch_feed_sums(const PackBox *pb_dev, int n_boxes, int max_blk, const double *wgt,
+                            double *partials, hipStream_t s);
+hipError_t launch_feed_reduce(int n_boxes, int max_blk, const PackBox *pb_dev, const double *partials,
+                              double *sums, hipStream_t s);
+hipError_t launch_feed(const PackBox *pb_dev, const FeedBox *fb_dev, int n_boxes, int max_blk,
+                       const double *wgt, const unsigned long long *A, double *ndot,
+                       float *mix, hipStream_t s);
+
+}  // namespace mclya

@@ -1,0 +1,129 @@
+"""Simulation: device-memory holder around one library context.
+
+Uploads the fields of one or more boxes to HIP device memory (torch tensors,
+kept alive as long as the context), fills the box descriptors and forwards
+every operation to the C ABI. Marshalling only.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+TRACE_DTYPE = np.dtype([("cell0", np.uint32), ("fx", np.float32), ("fy", np.float32),
+                        ("fz", np.float32), ("kx", np.float32), ("ky", np.float32),
+                        ("kz", np.float32), ("x0", np.float32), ("escaped", np.int64),
+                        ("absorbed", np.int64), ("crossings", np.uint32), ("fate", np.int32)])
+assert TRACE_DTYPE.itemsize == C.sizeof(A.mc_lya_packet_trace)
+
+
+def _dev(a, dtype, device):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+
+
+def desc_from_spec(spec, tensors, device="cuda"):
+    """mc_lya_box_desc for a box spec (geometry, physics, fields); the device
+    tensors it points to are appended to ``tensors`` to keep them alive."""
+    od = _dev(spec.overdensity, torch.float32, device)
+    vel = None
+    vdt = A.MC_LYA_VEL_NONE
+    if spec.velocity is not None:
+        half = (getattr(spec.velocity, "dtype", None) in (np.float16, torch.float16))
+        vel = _dev(spec.velocity, torch.float16 if half else torch.float32, device)
+        vdt = A.MC_LYA_VEL_F16 if half else A.MC_LYA_VEL_F32
+    xe = _dev(spec.x_e, torch.float32, device)
+    src = _dev(spec.source, torch.float32, device)
+    tensors.extend(t for t in (od, vel, xe, src) if t is not None)
+    c = spec.cosmo
+    nx, ny, nz = (int(v) for v in spec.n)
+    return A.mc_lya_box_desc(
+        nx=nx, ny=ny, nz=nz, vel_dtype=vdt, cell_comoving_cm=float(spec.cell_cm), z=float(spec.z),
+        zeta=float(spec.zeta), x_esc=float(spec.x_esc), temp_K=float(spec.temp_K), h=c.h,
+        omega_b_h2=c.omega_b_h2, omega_c_h2=c.omega_c_h2, y_p=c.y_p, t_cmb0=c.t_cmb0,
+        n_eff=c.n_eff, w0=int(spec.w0), overdensity=od.data_ptr(),
+        velocity=None if vel is None else vel.data_ptr(),
+        x_e=None if xe is None else xe.data_ptr(), x_e_uniform=float(spec.x_e_uniform),
+        reserved=0, source=None if src is None else src.data_ptr())
+
+
+class Simulation:
+    """One context over ``specs`` (a box spec or a list of them)."""
+
+    def __init__(self, specs, device="cuda", stream=None):
+        if not isinstance(specs, (list, tuple)):
+            specs = [specs]
+        self.specs = list(specs)
+        self.device = torch.device(device)
+        self._keep = []
+        descs = [desc_from_spec(s, self._keep, self.device) for s in self.specs]
+        self.ncells = [s.ncells for s in self.specs]
+        self.total_cells = int(sum(self.ncells))
+        self.cell_off = np.concatenate([[0], np.cumsum(self.ncells)]).astype(np.int64)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self.ctx = A.mc_lya_init(descs, self.stream)
+        self.n_packets = [0] * len(self.specs)
+
+    # -- C calls --------------------------------------------------------------
+    def refresh(self):
+        A.mc_lya_refresh(self.ctx)
+
+    def emit(self, seeds=None, n_packets=None):
+        seeds = [s.seed for s in self.specs] if seeds is None else list(seeds)
+        n_packets = [s.n_packets for s in self.specs] if n_packets is None else list(n_packets)
+        A.mc_lya_emit(self.ctx, seeds, n_packets)
+        self.n_packets = [int(n) for n in n_packets]
+
+    def transport(self, first=None, count=None):
+        if first is None:
+            A.mc_lya_transport(self.ctx)
+        else:
+            A.mc_lya_transport_range(self.ctx, first, count)
+
+    def tally(self, check=True, want_emitted=True):
+        """Returns dict(absorbed: int64 tensor [cells], emitted, stats, status)."""
+        absorbed = torch.empty(self.total_cells, dtype=torch.int64, device=self.device)
+        emitted = torch.empty_like(absorbed) if want_emitted else None
+        status, stats = A.mc_lya_tally(self.ctx, absorbed.data_ptr(),
+                                       None if emitted is None else emitted.data_ptr(),
+                                       len(self.specs), check=check)
+        return dict(absorbed=absorbed, emitted=emitted, stats=stats, status=status)
+
+    def feed(self):
+        ndot = torch.empty(self.total_cells, dtype=torch.float64, device=self.device)
+        mix = torch.empty(self.total_cells, dtype=torch.float32, device=self.device)
+        stats = A.mc_lya_feed(self.ctx, ndot.data_ptr(), mix.data_ptr(), len(self.specs))
+        return dict(ndot_e=ndot, mix_corr=mix, stats=stats)
+
+    def trace(self, first, count):
+        buf = torch.empty(int(count) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        A.mc_lya_trace(self.ctx, first, count, buf.data_ptr())
+        torch.cuda.synchronize(self.device)
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=TRACE_DTYPE)
+
+    def set_option(self, option, value):
+        A.mc_lya_set_option(self.ctx, option, value)
+
+    def kernel_time(self):
+        return A.mc_lya_kernel_time(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            A.mc_lya_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bit-exact: Philox words, emission allocation, the conservation identity on
+each side, and the GPU's own run-to-run / launch-configuration / range-split /
+batch-vs-alone equality. Toleranced (FP32 walk vs FP64 oracle): per-cell
+absorbed weight within 1e-3 relative plus a floor of 1e-6 of the mean cell,
+global absorbed fraction within 1e-5 relative.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import walker
+from tests.gpu_helpers import gpu_run, compare_cells, GLOBAL_REL
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2312_11448_amd as M  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_philox_known_answers_on_device():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append([int(t, 16) for t in line.split()])
+    rows = np.array(rows, dtype=np.uint64).astype(np.uint32)
+    rng = np.random.default_rng(0)
+    extra = rng.integers(0, 2 ** 32, size=(1000, 6), dtype=np.uint64).astype(np.uint32)
+    ctr = np.concatenate([rows[:, 0:4], extra[:, 0:4]])
+    key = np.concatenate([rows[:, 4:6], extra[:, 4:6]])
+    d_ctr = torch.from_numpy(ctr.view(np.int32).copy()).cuda()
+    d_key = torch.from_numpy(key.view(np.int32).copy()).cuda()
+    d_out = torch.empty_like(d_ctr)
+    M.mc_lya_philox4x32_10(d_ctr.data_ptr(), d_key.data_ptr(), d_out.data_ptr(), ctr.shape[0])
+    torch.cuda.synchronize()
+    out = d_out.cpu().numpy().view(np.uint32)
+    assert np.array_equal(out[:3], rows[:, 6:10])
+    for i in range(3, ctr.shape[0], 97):
+        assert np.array_equal(out[i], walker.philox4x32_10(ctr[i], key[i]))
+
+
+def test_packet_initial_states_match_oracle():
+    spec = W.make_box("c2", n=16, n_packets=4000)
+    prep = walker.Prepared(spec)
+    ref = prep.transport(records=True)["records"]
+    with M.Simulation(spec) as sim:
+        sim.emit()
+        tr = sim.trace(0, spec.n_packets)
+    assert np.array_equal(tr["cell0"].astype(np.int64), ref["cell0"])
+    for f in ("fx", "fy", "fz"):
+        assert np.array_equal(tr[f].astype(np.float64), ref[f])      # exact binary32 uniforms
+    for f in ("kx", "ky", "kz"):
+        assert np.abs(tr[f] - ref[f]).max() < 1e-6
+    assert np.abs(tr["x0"] - ref["x0"]).max() < 1e-5 * (1 + np.abs(ref["x0"]).max())
+    # per-packet outcomes
+    assert np.mean(tr["fate"] == ref["fate"]) > 0.999
+    both = tr["fate"] == ref["fate"]
+    assert np.mean(tr["crossings"][both] == ref["crossings"][both]) > 0.995
+    w0 = float(spec.w0)
+    esc_diff = np.abs(tr["escaped"].astype(np.float64) - ref["escaped"]) / w0
+    assert esc_diff.max() < 1e-3
+
+
+@pytest.mark.parametrize("case", ["c1", "ragged_flow_source", "c2_small"])
+def test_tallies_match_oracle(case):
+    if case == "c1":
+        spec = W.make_box("c1")
+    elif case == "ragged_flow_source":
+        rng = np.random.default_rng(12)
+        n = (13, 7, 11)
+        od = rng.lognormal(0.0, 0.5, size=n[::-1]).astype(np.float32)
+        vel = rng.normal(0.0, 0.2, size=(3,) + n[::-1]).astype(np.float32)
+        src = (od * od * rng.uniform(0.5, 1.5, size=n[::-1])).astype(np.float32)
+        src[0, 0, :3] = 0.0
+        spec = W.BoxSpec(n=n, overdensity=od, velocity=vel, source=src, n_packets=30_000,
+                         seed=77, zeta=3.0)
+    else:
+        spec = W.make_box("c2", n=48, n_packets=300_000)
+    _say(f"case {case}: {spec.n} packets {spec.n_packets}")
+    ref = walker.run_box(spec)
+    g = gpu_run(spec)
+    w_total = float(spec.w0) * spec.n_packets
+    assert np.array_equal(g["emitted"], ref["emitted"])
+    assert g["stats"].conserved == 1
+    assert ref["A"].sum() + ref["escaped"] == spec.w0 * spec.n_packets
+    cmp = compare_cells(g["A"], ref["A"], w_total)
+    _say(f"  {cmp}; crossings gpu {g['crossings']} orc {ref['crossings']}")
+    assert cmp["bad"] == 0
+    assert cmp["f_rel"] <= GLOBAL_REL
+    assert abs(g["crossings"] - ref["crossings"]) <= 1e-4 * ref["crossings"] + 10
+
+
+def test_c2_full_size_parity():
+    spec = W.make_box("c2")
+    _say(f"c2 full: {spec.n} packets {spec.n_packets}")
+    ref = walker.run_box(spec)
+    g = gpu_run(spec)
+    w_total = float(spec.w0) * spec.n_packets
+    assert np.array_equal(g["emitted"], ref["emitted"])
+    assert g["stats"].conserved == 1
+    cmp = compare_cells(g["A"], ref["A"], w_total)
+    _say(f"  {cmp}; crossings gpu {g['crossings']} orc {ref['crossings']}")
+    assert cmp["bad"] == 0
+    assert cmp["f_rel"] <= GLOBAL_REL
+
+
+def test_launch_configuration_and_ranges_bitwise():
+    spec = W.make_box("c2", n=32, n_packets=200_000)
+    base = gpu_run(spec)
+    variants = [
+        {M.MC_LYA_OPT_KERNEL: 1},
+        {M.MC_LYA_OPT_BLOCK: 64, M.MC_LYA_OPT_WAVES_PER_CU: 8},
+        {M.MC_LYA_OPT_CHUNK: 7, M.MC_LYA_OPT_REFILL: 1},
+        {M.MC_LYA_OPT_CHUNK: 4096, M.MC_LYA_OPT_REFILL: 64, M.MC_LYA_OPT_BLOCK: 128},
+    ]
+    for opt in variants:
+        g = gpu_run(spec, options=opt)
+        assert np.array_equal(g["A"], base["A"]), opt
+        assert g["escaped"] == base["escaped"] and g["crossings"] == base["crossings"]
+    split = gpu_run(spec, ranges=[(0, 12345), (12345, 150000), (150000, 200000)])
+    assert np.array_equal(split["A"], base["A"])
+    assert split["escaped"] == base["escaped"]
+    again = gpu_run(spec)
+    assert np.array_equal(again["A"], base["A"])
+
+
+def test_batch_equals_boxes_alone():
+    boxes = [W.make_box("c2", n=n, n_packets=p, field_seed=fs, seed=s)
+             for n, p, fs, s in ((12, 20000, 5, 1), (20, 50000, 6, 2), (9, 7000, 7, 3))]
+    boxes[1].z = 900.0
+    boxes[1].temp_K = 2.7255 * 901
+    alone = [gpu_run(b) for b in boxes]
+    with M.Simulation(boxes) as sim:
+        sim.emit()
+        sim.transport()
+        t = sim.tally()
+    A = t["absorbed"].cpu().numpy()
+    for i, b in enumerate(boxes):
+        lo, hi = sim.cell_off[i], sim.cell_off[i + 1]
+        assert np.array_equal(A[lo:hi], alone[i]["A"])
+        assert t["stats"][i].escaped == alone[i]["escaped"]
+        assert t["stats"][i].crossings == alone[i]["crossings"]
+        assert t["stats"][i].conserved == 1
+
+
+def test_uniform_flow_changes_nothing():
+    base = W.make_box("c1", n=16, n_packets=20000)
+    u = np.zeros((3, 16, 16, 16), dtype=np.float32)
+    u[0], u[1], u[2] = 0.3, -0.2, 0.1
+    moving = W.BoxSpec(**{**base.__dict__, "velocity": u})
+    zero = W.BoxSpec(**{**base.__dict__, "velocity": np.zeros_like(u)})
+    a, b, c = gpu_run(base), gpu_run(moving), gpu_run(zero)
+    assert np.array_equal(b["A"], c["A"]) and b["escaped"] == c["escaped"]
+    assert b["stats"].x_eff == base.x_esc
+    # the kappa-only record and the (kappa, U) record walk identically
+    assert np.array_equal(a["A"], c["A"])
+
+
+def test_feed_matches_oracle_feed():
+    from oracle import physics as P
+    spec = W.make_box("c2", n=24, n_packets=50000)
+    with M.Simulation(spec) as sim:
+        sim.emit()
+        sim.transport()
+        t = sim.tally()
+        f = sim.feed()
+    A = t["absorbed"].cpu().numpy()
+    E = t["stats"][0].escaped
+    ref = P.feed(spec, A, E, spec.n_packets)
+    nd = f["ndot_e"].cpu().numpy()
+    assert np.allclose(nd, ref["ndot_e"], rtol=1e-9, atol=1e-12 * np.abs(ref["ndot_e"]).max())
+    mix = f["mix_corr"].cpu().numpy()
+    assert np.allclose(mix, ref["mix_corr"], rtol=2e-7)
+    st = f["stats"][0]
+    assert st.c_mc == pytest.approx(ref["c_mc"], rel=1e-12)
+    assert st.c_mix == pytest.approx(ref["c_mix"], rel=1e-9)
+    assert st.x_e_global == pytest.approx(ref["x_e_global"], rel=1e-9)
+    assert st.ndot_e_mean == pytest.approx(ref["ndot_e"].mean(), rel=1e-6)
+
+
+def test_sampled_packets_at_full_256_size():
+    spec = W.make_box("c3")
+    prep = walker.Prepared(spec)
+    n = spec.n_packets
+    ids = np.unique(np.linspace(0, n - 1, 3000).astype(np.uint64))
+    ref = prep.records(ids)
+    with M.Simulation(spec) as sim:
+        sim.emit()
+        sim.transport()
+        t = sim.tally(want_emitted=True)
+        st = t["stats"][0]
+        assert st.conserved == 1 and st.capped_packets == 0
+        em = t["emitted"].cpu().numpy()
+        assert np.array_equal(em, prep.emitted_per_cell)
+        recs = np.concatenate([sim.trace(int(i), 1) for i in ids])
+    assert np.array_equal(recs["cell0"].astype(np.int64), ref["cell0"])
+    same = recs["fate"] == ref["fate"]
+    assert same.mean() > 0.995
+    w0 = float(spec.w0)
+    assert np.abs(recs["escaped"][same].astype(np.float64) - ref["escaped"][same]).max() / w0 < 2e-3
+    # global absorbed fraction vs the oracle's estimate from the sample
+    f_gpu = t["absorbed"].sum().item() / (w0 * n)
+    esc = np.where(ref["fate"] == 1, ref["escaped"], 0) / w0
+    f_orc = 1.0 - esc.mean()
+    assert abs(f_gpu - f_orc) <= 4 * esc.std() / np.sqrt(esc.size) + 1e-6
+
+
+def test_errors_and_cap():
+    bad = W.make_box("c1", n=8, n_packets=100)
+    bad.overdensity = bad.overdensity.copy()
+    bad.overdensity[1, 2, 3] = np.nan
+    with pytest.raises(M.MCLyaError) as e:
+        M.Simulation(bad)
+    assert e.value.status == M.MC_LYA_EINVAL and "overdensity" in str(e.value)
+    neg = W.make_box("c1", n=8, n_packets=100)
+    neg.x_e = np.full((8, 8, 8), 0.1, dtype=np.float32)
+    neg.x_e[0, 0, 0] = 1.5
+    with pytest.raises(M.MCLyaError) as e:
+        M.Simulation(neg)
+    assert "x_e" in str(e.value)
+    spec = W.make_box("c1", n=8, n_packets=1000)
+    with M.Simulation(spec) as sim:
+        with pytest.raises(M.MCLyaError) as e:
+            sim.transport()
+        assert e.value.status == M.MC_LYA_ESTATE
+        with pytest.raises(M.MCLyaError) as e:
+            sim.emit(n_packets=[1 << 33])
+        assert e.value.status == M.MC_LYA_EOVERFLOW
+        sim.emit(n_packets=[0])
+        sim.transport()
+        t = sim.tally()
+        assert t["stats"][0].conserved == 1 and int(t["absorbed"].sum().item()) == 0
+        sim.set_option(M.MC_LYA_OPT_MAX_CROSSINGS, 3)
+        sim.emit()
+        sim.transport()
+        t = sim.tally(check=False)
+        assert t["status"] == M.MC_LYA_ECAP
+        st = t["stats"][0]
+        assert st.capped_packets > 0 and st.conserved == 1
+        with pytest.raises(M.MCLyaError) as e:
+            M.mc_lya_transport_range(sim.ctx, 900, 200)
+        assert e.value.status == M.MC_LYA_EINVAL
