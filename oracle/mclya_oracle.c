@@ -226,6 +226,9 @@ static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux
         double x_out = x - b->delta * s;                     /* Hubble drift */
         int escaping = x_out <= -b->x_eff;
         double dPhi = escaping ? orc_Phi(x) - orc_Phi(-b->x_eff) : orc_Phi(x) - orc_Phi(x_out);
+        /* Phi is non-decreasing: a negative difference of two rounded values
+         * (a segment far shorter than a cell) is rounding, not absorption */
+        if (dPhi < 0.0) dPhi = 0.0;
         double dtau = kappa[c] * dPhi;
         int64_t d = (int64_t)rint((double)w * (-expm1(-dtau)));
         if (d > w) d = w;

@@ -258,7 +258,10 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
         HIP_TRY(c, launch_walk_simple(p, c->block, c->stream));
     } else {
         const int waves_per_block = c->block / 64;
-        int grid = std::max(1, c->num_cu * c->waves_per_cu / waves_per_block);
+        // never more workgroups than can be resident at once
+        const int resident = persistent_blocks_per_cu(c->vel, c->block);
+        const int per_cu = std::max(1, std::min(c->waves_per_cu / waves_per_block, resident));
+        int grid = c->num_cu * per_cu;
         const uint64_t need = (count + 63) / 64;     // no more waves than packets
         if ((uint64_t)grid * waves_per_block > need) grid = (int)std::max<uint64_t>(1, (need + waves_per_block - 1) / waves_per_block);
         HIP_TRY(c, launch_walk_persistent(p, c->block, grid, c->stream));

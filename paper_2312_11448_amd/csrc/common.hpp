@@ -131,6 +131,7 @@ struct WalkParams {
 
 hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s);
 hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s);
+int persistent_blocks_per_cu(bool vel, int block);   // resident workgroups per CU
 hipError_t launch_trace(const WalkParams &p, mc_lya_packet_trace *out, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, uint64_t n,
                          hipStream_t s);

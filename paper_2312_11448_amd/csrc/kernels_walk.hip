@@ -18,14 +18,18 @@
 namespace mclya {
 namespace {
 
-constexpr float kFar = 3.0e38f;   // face distance along an axis the ray does not move on
+constexpr double kFar = 1.0e300;   // face distance along an axis the ray does not move on
 
+// Ray geometry (direction, position inside the cell, face distances) is kept
+// in binary64: over paths of hundreds of cells binary32 directions drift by
+// ~1e-5 cell, enough to clip a different cell corner than an exact ray. The
+// line-profile arithmetic (drift, Phi, deposit) is binary32.
 struct Lane {
     int32_t ix, iy, iz;
     uint32_t c;          // global cell
-    float fx, fy, fz;    // position inside the cell, [0,1]
-    float kx, ky, kz;    // direction
-    float rx, ry, rz;    // 1/|k| per axis
+    double fx, fy, fz;   // position inside the cell, [0,1]
+    double kx, ky, kz;   // direction
+    double rx, ry, rz;   // 1/|k| per axis
     float x;             // gas-frame frequency, Doppler widths
     float kap;           // kappa of the current cell
     float ux, uy, uz;    // bulk velocity of the current cell (Doppler units)
@@ -74,20 +78,20 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
     L.iy = (int32_t)(rest % (uint32_t)B.ny);
     L.iz = (int32_t)(rest / (uint32_t)B.ny);
     L.c = gcell;
-    L.fx = u01(a[0]);
-    L.fy = u01(a[1]);
-    L.fz = u01(a[2]);
-    const float mu = 2.0f * u01(a[3]) - 1.0f;          // exact
-    float sp, cp;
-    sincospif(2.0f * u01(b[0]), &sp, &cp);              // azimuth 2 pi u
-    const float st = sqrtf((1.0f - mu) * (1.0f + mu));
+    L.fx = (double)u01(a[0]);
+    L.fy = (double)u01(a[1]);
+    L.fz = (double)u01(a[2]);
+    const double mu = 2.0 * (double)u01(a[3]) - 1.0;   // exact
+    double sp, cp;
+    sincospi(2.0 * (double)u01(b[0]), &sp, &cp);         // azimuth 2 pi u
+    const double st = sqrt((1.0 - mu) * (1.0 + mu));
     L.kx = st * cp;
     L.ky = st * sp;
     L.kz = mu;
-    L.rx = L.kx != 0.0f ? 1.0f / fabsf(L.kx) : kFar;
-    L.ry = L.ky != 0.0f ? 1.0f / fabsf(L.ky) : kFar;
-    L.rz = L.kz != 0.0f ? 1.0f / fabsf(L.kz) : kFar;
-    L.x = sqrtf(-logf(u01(b[1]))) * cospif(2.0f * u01(b[2]));
+    L.rx = L.kx != 0.0 ? 1.0 / fabs(L.kx) : kFar;
+    L.ry = L.ky != 0.0 ? 1.0 / fabs(L.ky) : kFar;
+    L.rz = L.kz != 0.0 ? 1.0 / fabs(L.kz) : kFar;
+    L.x = (float)(sqrt(-log((double)u01(b[1]))) * cospi(2.0 * (double)u01(b[2])));
     L.w = B.w0;
     L.ncross = 0;
     load_cell<VEL>(L, rec);
@@ -96,10 +100,12 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
 // Phi(hi) - Phi(lo) for hi > lo, Phi(x) = erfc(-x)/2, written with the
 // complementary function on the side where it is small so that the
 // difference does not cancel.
+// Clamped at 0: Phi is non-decreasing, but two rounded erfc values of nearly
+// equal arguments (a sliver segment at a cell corner) can come out reversed.
 __device__ __forceinline__ float delta_phi(float hi, float lo)
 {
-    if (lo >= 0.0f) return 0.5f * (erfcf(lo) - erfcf(hi));
-    return 0.5f * (erfcf(-hi) - erfcf(-lo));
+    const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(hi)) : 0.5f * (erfcf(-hi) - erfcf(-lo));
+    return fmaxf(d, 0.0f);
 }
 
 enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3 };
@@ -115,16 +121,16 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec,
     ++L.ncross;
 
     // distance to the face the ray leaves through (ties: x, then y, then z)
-    const float tx = (L.kx > 0.0f ? 1.0f - L.fx : L.fx) * L.rx;
-    const float ty = (L.ky > 0.0f ? 1.0f - L.fy : L.fy) * L.ry;
-    const float tz = (L.kz > 0.0f ? 1.0f - L.fz : L.fz) * L.rz;
+    const double tx = (L.kx > 0.0 ? 1.0 - L.fx : L.fx) * L.rx;
+    const double ty = (L.ky > 0.0 ? 1.0 - L.fy : L.fy) * L.ry;
+    const double tz = (L.kz > 0.0 ? 1.0 - L.fz : L.fz) * L.rz;
     int axis = 0;
-    float s = tx;
+    double s = tx;
     if (ty < s) { axis = 1; s = ty; }
     if (tz < s) { axis = 2; s = tz; }
 
     // Hubble drift across the segment; the last one stops at -x_eff
-    const float xo = fmaf(-L.delta, s, L.x);
+    const float xo = fmaf(-L.delta, (float)s, L.x);
     const bool esc = xo <= -L.xeff;
     const float dphi = delta_phi(L.x, esc ? -L.xeff : xo);
     const float dtau = L.kap * dphi;
@@ -138,21 +144,18 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec,
     if (L.w == 0) return kAbsorbed;
 
     // move to the face and into the neighbour (periodic)
-    const float gx = fminf(fmaxf(fmaf(L.kx, s, L.fx), 0.0f), 1.0f);
-    const float gy = fminf(fmaxf(fmaf(L.ky, s, L.fy), 0.0f), 1.0f);
-    const float gz = fminf(fmaxf(fmaf(L.kz, s, L.fz), 0.0f), 1.0f);
-    L.fx = gx;
-    L.fy = gy;
-    L.fz = gz;
+    L.fx = fmin(fmax(fma(L.kx, s, L.fx), 0.0), 1.0);
+    L.fy = fmin(fmax(fma(L.ky, s, L.fy), 0.0), 1.0);
+    L.fz = fmin(fmax(fma(L.kz, s, L.fz), 0.0), 1.0);
     if (axis == 0) {
-        if (L.kx > 0.0f) { L.fx = 0.0f; L.ix = (L.ix + 1 == L.nx) ? 0 : L.ix + 1; }
-        else { L.fx = 1.0f; L.ix = (L.ix == 0) ? L.nx - 1 : L.ix - 1; }
+        if (L.kx > 0.0) { L.fx = 0.0; L.ix = (L.ix + 1 == L.nx) ? 0 : L.ix + 1; }
+        else { L.fx = 1.0; L.ix = (L.ix == 0) ? L.nx - 1 : L.ix - 1; }
     } else if (axis == 1) {
-        if (L.ky > 0.0f) { L.fy = 0.0f; L.iy = (L.iy + 1 == L.ny) ? 0 : L.iy + 1; }
-        else { L.fy = 1.0f; L.iy = (L.iy == 0) ? L.ny - 1 : L.iy - 1; }
+        if (L.ky > 0.0) { L.fy = 0.0; L.iy = (L.iy + 1 == L.ny) ? 0 : L.iy + 1; }
+        else { L.fy = 1.0; L.iy = (L.iy == 0) ? L.ny - 1 : L.iy - 1; }
     } else {
-        if (L.kz > 0.0f) { L.fz = 0.0f; L.iz = (L.iz + 1 == L.nz) ? 0 : L.iz + 1; }
-        else { L.fz = 1.0f; L.iz = (L.iz == 0) ? L.nz - 1 : L.iz - 1; }
+        if (L.kz > 0.0) { L.fz = 0.0; L.iz = (L.iz + 1 == L.nz) ? 0 : L.iz + 1; }
+        else { L.fz = 1.0; L.iz = (L.iz == 0) ? L.nz - 1 : L.iz - 1; }
     }
     L.c = L.coff + (uint32_t)L.ix + (uint32_t)L.nx * ((uint32_t)L.iy + (uint32_t)L.ny * (uint32_t)L.iz);
     L.x = xo;
@@ -160,7 +163,9 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec,
         const float ux = L.ux, uy = L.uy, uz = L.uz;
         load_cell<VEL>(L, rec);
         // Eq. (inout), bulk term: x_new = x_old - k.(U_new - U_old)
-        L.x = xo - (L.kx * (L.ux - ux) + L.ky * (L.uy - uy) + L.kz * (L.uz - uz));
+        const float du = (float)(L.kx * (double)(L.ux - ux) + L.ky * (double)(L.uy - uy) +
+                                 L.kz * (double)(L.uz - uz));
+        L.x = xo - du;
     } else {
         load_cell<VEL>(L, rec);
     }
@@ -343,12 +348,12 @@ __global__ __launch_bounds__(256) void trace_kernel(WalkParams P, mc_lya_packet_
     init_packet<VEL>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec);
     mc_lya_packet_trace t;
     t.cell0 = L.c;
-    t.fx = L.fx;
-    t.fy = L.fy;
-    t.fz = L.fz;
-    t.kx = L.kx;
-    t.ky = L.ky;
-    t.kz = L.kz;
+    t.fx = (float)L.fx;
+    t.fy = (float)L.fy;
+    t.fz = (float)L.fz;
+    t.kx = (float)L.kx;
+    t.ky = (float)L.ky;
+    t.kz = (float)L.kz;
     t.x0 = L.x;
     uint64_t dep = 0;
     int fate;
@@ -375,6 +380,15 @@ __global__ void philox_kernel(const uint32_t *__restrict__ ctr, const uint32_t *
 __global__ void reset_queue_kernel(unsigned long long *q) { *q = 0ull; }
 
 }  // namespace
+
+int persistent_blocks_per_cu(bool vel, int block)
+{
+    int n = 0;
+    const size_t lds = sizeof(WalkBox);
+    hipError_t e = vel ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<true>, block, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<false>, block, lds);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
 
 hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s)
 {

@@ -235,3 +235,14 @@ def test_drift_per_cell_from_friedmann_light_travel():
     dnu_over_nu = da / a1
     drift_per_cm = dnu_over_nu / (sc["v_th"] / P.C_LIGHT) / chi
     assert sc["delta"] == pytest.approx(drift_per_cm * spec.cell_cm, rel=1e-5)
+
+
+def test_deposits_never_negative():
+    """Phi is non-decreasing, so no segment, however short, deposits a negative
+    weight; the packet weight never grows."""
+    import workloads as W
+    spec = W.make_box("c2", n=24, n_packets=400)
+    prep = walker.Prepared(spec)
+    for p in range(400):
+        t = prep.trace(p)
+        assert (t["deposits"] >= 0).all()
