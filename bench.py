@@ -37,7 +37,22 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "walk_traffic.json"),
                     help="measured HBM bytes per launch of the walk kernel (rocprofv3 counters)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain elementwise copy of MIB MiB (float32 negation, "
+                         "reads and writes MIB MiB) five times, to scale byte counters")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "neg", "bytes_read": n * 4, "bytes_written": n * 4,
+                      "launches": 5}), flush=True)
 
 
 def cpu_baseline(spec, budget_s):
@@ -62,6 +77,9 @@ def cpu_baseline(spec, budget_s):
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -134,7 +134,9 @@ enum {
     MC_LYA_OPT_REFILL = 5,        /* refill a wave once this many lanes are idle (1..64) */
     MC_LYA_OPT_MAX_CROSSINGS = 6, /* crossing cap per packet (>= 1, default 1e6) */
     MC_LYA_OPT_TIMING = 7,        /* 1 = time transport kernels with HIP events */
-    MC_LYA_OPT_GRAPH = 8          /* 1 = replay transport as a captured HIP graph */
+    MC_LYA_OPT_GRAPH = 8,         /* 1 = replay transport as a captured HIP graph */
+    MC_LYA_OPT_QUEUES = 9         /* parts the packet range is split into for the persistent
+                                     walk (1..64, default 8: one grid slab per XCD) */
 };
 
 /* Creates a context for n_boxes boxes, validates and packs their fields

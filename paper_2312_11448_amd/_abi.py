@@ -18,6 +18,7 @@ MC_LYA_EOVERFLOW, MC_LYA_ESTATE, MC_LYA_ECAP, MC_LYA_ECONSERVE = 4, 5, 6, 7
 MC_LYA_VEL_NONE, MC_LYA_VEL_F32, MC_LYA_VEL_F16 = 0, 1, 2
 MC_LYA_OPT_KERNEL, MC_LYA_OPT_BLOCK, MC_LYA_OPT_WAVES_PER_CU, MC_LYA_OPT_CHUNK = 1, 2, 3, 4
 MC_LYA_OPT_REFILL, MC_LYA_OPT_MAX_CROSSINGS, MC_LYA_OPT_TIMING, MC_LYA_OPT_GRAPH = 5, 6, 7, 8
+MC_LYA_OPT_QUEUES = 9
 
 
 class mc_lya_box_desc(C.Structure):

@@ -114,10 +114,24 @@ struct mc_lya_ctx {
     FeedBox *d_feed = nullptr;
     uint32_t *d_cop = nullptr;
     uint64_t cop_cap = 0;
+    uint64_t *d_pfirst = nullptr;
+
+    // tile-decomposed walk
+    std::vector<TileInfo> tiles;
+    std::vector<int4> box_tiles;
+    TileInfo *d_tiles = nullptr;
+    int4 *d_box_tiles = nullptr;
+    uint32_t *d_tbase[2] = {nullptr, nullptr};
+    uint32_t *d_tcount[2] = {nullptr, nullptr};
+    PState *d_state[2] = {nullptr, nullptr};
+    uint32_t *d_dest[2] = {nullptr, nullptr};
+    unsigned long long *d_gen = nullptr;     // [0] bump allocator, [1] exits of the generation
+    uint64_t state_cap = 0;
+    int64_t generations = 0;                 // generations run by the last tiled transport
 
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
-    int kernel = 0, block = 256, waves_per_cu = 32, chunk = 256, refill = 16;
+    int kernel = 2, block = 256, waves_per_cu = 32, chunk = 256, refill = 16, nqueues = 8;
     int64_t max_cross = 1000000;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -153,7 +167,9 @@ void free_all(mc_lya_ctx *c)
 {
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop};
+                    c->d_cop, c->d_pfirst, c->d_tiles, c->d_box_tiles, c->d_tbase[0], c->d_tbase[1],
+                    c->d_tcount[0], c->d_tcount[1], c->d_state[0], c->d_state[1], c->d_dest[0],
+                    c->d_dest[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &ev : c->events) {
@@ -224,6 +240,142 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
     return MC_LYA_OK;
 }
 
+// Tiles of kTileEdge^3 cells per box (the last ones along an axis may be
+// thinner), with their distinct periodic face neighbours.
+void build_tiles(mc_lya_ctx *c)
+{
+    const int TE = kTileEdge;
+    c->tiles.clear();
+    c->box_tiles.clear();
+    for (int b = 0; b < c->n_boxes; ++b) {
+        const mc_lya_box_desc &d = c->desc[b];
+        const int nt[3] = {(d.nx + TE - 1) / TE, (d.ny + TE - 1) / TE, (d.nz + TE - 1) / TE};
+        const int off = (int)c->tiles.size();
+        c->box_tiles.push_back(make_int4(off, nt[0], nt[1], nt[2]));
+        const int n[3] = {d.nx, d.ny, d.nz};
+        for (int tz = 0; tz < nt[2]; ++tz)
+            for (int ty = 0; ty < nt[1]; ++ty)
+                for (int tx = 0; tx < nt[0]; ++tx) {
+                    TileInfo t;
+                    std::memset(&t, 0, sizeof t);
+                    t.box = b;
+                    const int tc[3] = {tx, ty, tz};
+                    int o[3], e[3];
+                    for (int a = 0; a < 3; ++a) {
+                        o[a] = tc[a] * TE;
+                        e[a] = std::min(TE, n[a] - o[a]);
+                    }
+                    t.ox = o[0];
+                    t.oy = o[1];
+                    t.oz = o[2];
+                    t.sx = e[0];
+                    t.sy = e[1];
+                    t.sz = e[2];
+                    const int self = off + tx + nt[0] * (ty + nt[1] * tz);
+                    for (int a = 0; a < 3; ++a) {
+                        if (nt[a] == 1) continue;       // the tile spans the axis: wraps onto itself
+                        for (int dir = -1; dir <= 1; dir += 2) {
+                            int q[3] = {tx, ty, tz};
+                            q[a] = (q[a] + dir + nt[a]) % nt[a];
+                            const int id = off + q[0] + nt[0] * (q[1] + nt[1] * q[2]);
+                            bool seen = id == self;
+                            for (int k = 0; k < t.nnbr; ++k) seen = seen || t.nbr[k] == id;
+                            if (!seen) t.nbr[t.nnbr++] = id;
+                        }
+                    }
+                    c->tiles.push_back(t);
+                }
+    }
+}
+
+constexpr uint64_t kTiledBatch = 1ull << 25;   // packets per tiled batch (state buffers of ~3.9 GB)
+
+mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
+{
+    const uint64_t cap = std::max<uint64_t>(1, std::min(packets, kTiledBatch));
+    if (cap <= c->state_cap) return MC_LYA_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 2; ++i) {
+        if (c->d_state[i]) (void)hipFree(c->d_state[i]);
+        if (c->d_dest[i]) (void)hipFree(c->d_dest[i]);
+        c->d_state[i] = nullptr;
+        c->d_dest[i] = nullptr;
+    }
+    c->state_cap = 0;
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(c, dalloc(&c->d_state[i], cap));
+        HIP_TRY(c, dalloc(&c->d_dest[i], cap));
+    }
+    c->state_cap = cap;
+    return MC_LYA_OK;
+}
+
+mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
+{
+    *e1 = nullptr;
+    if (!c->timing) return MC_LYA_OK;
+    if (c->events_used == c->events.size()) {
+        hipEvent_t a, b;
+        HIP_TRY(c, hipEventCreate(&a));
+        HIP_TRY(c, hipEventCreate(&b));
+        c->events.emplace_back(a, b);
+    }
+    HIP_TRY(c, hipEventRecord(c->events[c->events_used].first, c->stream));
+    *e1 = c->events[c->events_used].second;
+    ++c->events_used;
+    return MC_LYA_OK;
+}
+
+mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
+{
+    TileParams p;
+    std::memset(&p, 0, sizeof p);
+    p.boxes = c->d_walk;
+    p.tiles = c->d_tiles;
+    p.box_tiles = c->d_box_tiles;
+    p.rec = c->d_rec;
+    p.npk = c->d_npk;
+    p.pfirst = c->d_pfirst;
+    p.A = c->d_A;
+    p.tot = c->d_tot;
+    p.bump = c->d_gen;
+    p.exits = c->d_gen + 1;
+    p.max_cross = (uint32_t)c->max_cross;
+    p.ntiles = (int)c->tiles.size();
+    p.chunk = 64;
+    c->generations = 0;
+    for (uint64_t done = 0; done < count;) {
+        const uint64_t n = std::min(count - done, c->state_cap);
+        p.first = first + done;
+        p.count = n;
+        int cur = 0;
+        for (int64_t gen = 0;; ++gen) {
+            p.in_state = c->d_state[cur ^ 1];
+            p.in_dest = c->d_dest[cur ^ 1];
+            p.in_base = c->d_tbase[cur ^ 1];
+            p.in_count = c->d_tcount[cur ^ 1];
+            p.out_state = c->d_state[cur];
+            p.out_dest = c->d_dest[cur];
+            p.out_base = c->d_tbase[cur];
+            p.out_count = c->d_tcount[cur];
+            hipEvent_t e1;
+            mc_lya_status st = timed_begin(c, &e1);
+            if (st != MC_LYA_OK) return st;
+            HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->stream));
+            if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+            ++c->generations;
+            unsigned long long exits = 0;
+            HIP_TRY(c, hipMemcpyAsync(&exits, c->d_gen + 1, sizeof exits, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (exits == 0) break;
+            if (gen > c->max_cross) return fail(c, MC_LYA_EDEVICE, "tiled walk did not drain");
+            cur ^= 1;
+        }
+        done += n;
+    }
+    return MC_LYA_OK;
+}
+
 mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
 {
     if (count == 0) return MC_LYA_OK;
@@ -241,6 +393,18 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
     p.max_cross = c->max_cross;
     p.chunk = c->chunk;
     p.refill = c->refill;
+    p.nqueues = c->nqueues;
+    if (c->kernel == 2) {
+        mc_lya_status st = walk_tiled(c, first, count);
+        if (st != MC_LYA_OK) return st;
+        for (int b = 0; b < c->n_boxes; ++b) {
+            const uint64_t lo = std::max(first, c->walk[b].pkt_off);
+            const uint64_t hi = std::min(first + count, c->walk[b].pkt_off + c->walk[b].npkt);
+            if (hi > lo) c->walked[b] += hi - lo;
+        }
+        c->state = 2;
+        return MC_LYA_OK;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if (c->events_used == c->events.size()) {
@@ -374,10 +538,23 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         (e = dalloc(&c->d_wgt, cells)) != hipSuccess || (e = dalloc(&c->d_part, nbk * 4)) != hipSuccess ||
         (e = dalloc(&c->d_q, cells)) != hipSuccess || (e = dalloc(&c->d_bsum, nbk)) != hipSuccess ||
         (e = dalloc(&c->d_npk, cells)) != hipSuccess || (e = dalloc(&c->d_A, cells)) != hipSuccess ||
-        (e = dalloc(&c->d_queue, 1)) != hipSuccess || (e = dalloc(&c->d_boxabs, n_boxes)) != hipSuccess ||
+        (e = dalloc(&c->d_queue, kMaxQueues)) != hipSuccess || (e = dalloc(&c->d_boxabs, n_boxes)) != hipSuccess ||
         (e = dalloc(&c->d_fsum, (size_t)4 * n_boxes)) != hipSuccess ||
-        (e = dalloc(&c->d_feed, n_boxes)) != hipSuccess)
+        (e = dalloc(&c->d_feed, n_boxes)) != hipSuccess || (e = dalloc(&c->d_pfirst, cells)) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
+    build_tiles(c);
+    const size_t nt = c->tiles.size();
+    if ((e = dalloc(&c->d_tiles, nt)) != hipSuccess || (e = dalloc(&c->d_box_tiles, (size_t)n_boxes)) != hipSuccess ||
+        (e = dalloc(&c->d_tbase[0], nt)) != hipSuccess || (e = dalloc(&c->d_tbase[1], nt)) != hipSuccess ||
+        (e = dalloc(&c->d_tcount[0], nt)) != hipSuccess || (e = dalloc(&c->d_tcount[1], nt)) != hipSuccess ||
+        (e = dalloc(&c->d_gen, 2)) != hipSuccess)
+        return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
+    if (hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(TileInfo) * nt, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_box_tiles, c->box_tiles.data(), sizeof(int4) * n_boxes, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_tcount[0], 0, sizeof(uint32_t) * nt, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_tcount[1], 0, sizeof(uint32_t) * nt, c->stream) != hipSuccess)
+        return cleanup(MC_LYA_EDEVICE);
     if (hipMemcpyAsync(c->d_pack, c->pack.data(), sizeof(PackBox) * n_boxes, hipMemcpyHostToDevice, c->stream) !=
         hipSuccess)
         return cleanup(MC_LYA_EDEVICE);
@@ -435,7 +612,11 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *
     HIP_TRY(c, launch_quantize(c->d_pack, nb, c->max_blk, c->d_wgt, c->d_red, c->d_q, c->d_bsum, c->stream));
     HIP_TRY(c, launch_scan_blocks(c->d_pack, nb, c->max_blk, c->d_bsum, c->d_red, c->stream));
     HIP_TRY(c, launch_allocate(c->d_pack, c->d_walk, nb, c->max_blk, c->d_q, c->d_bsum, c->d_red, c->d_npk,
-                               c->d_cop, c->stream));
+                               c->d_pfirst, c->d_cop, c->stream));
+    if (c->kernel == 2) {
+        mc_lya_status st = ensure_tile_buffers(c, ntot);
+        if (st != MC_LYA_OK) return st;
+    }
     HIP_TRY(c, hipMemsetAsync(c->d_A, 0, sizeof(unsigned long long) * c->total_cells, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_tot, 0, sizeof(BoxTot) * nb, c->stream));
     c->state = 1;
@@ -587,7 +768,11 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     if (!c) return MC_LYA_EINVAL;
     switch (option) {
     case MC_LYA_OPT_KERNEL:
-        if (v != 0 && v != 1) return fail(c, MC_LYA_EINVAL, "kernel must be 0 or 1");
+        if (v < 0 || v > 2) return fail(c, MC_LYA_EINVAL, "kernel must be 0, 1 or 2");
+        if (v == 2 && c->state >= 1) {
+            mc_lya_status st = ensure_tile_buffers(c, c->total_packets);
+            if (st != MC_LYA_OK) return st;
+        }
         c->kernel = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_BLOCK:
@@ -609,6 +794,10 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     case MC_LYA_OPT_MAX_CROSSINGS:
         if (v < 1 || v > 0x7fffffff) return fail(c, MC_LYA_EINVAL, "crossing cap must be in [1, 2^31)");
         c->max_cross = v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_QUEUES:
+        if (v < 1 || v > kMaxQueues) return fail(c, MC_LYA_EINVAL, "queues must be in [1, 64]");
+        c->nqueues = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_TIMING:
         c->timing = v != 0;

@@ -113,7 +113,7 @@ hipError_t launch_scan_blocks(const PackBox *pb_dev, int n_boxes, int max_blk, u
                               BoxRed *red, hipStream_t s);
 hipError_t launch_allocate(const PackBox *pb_dev, const WalkBox *wb_dev, int n_boxes, int max_blk,
                            const uint64_t *q, const uint64_t *bsum, const BoxRed *red,
-                           uint32_t *npk, uint32_t *cell_of_packet, hipStream_t s);
+                           uint32_t *npk, uint64_t *pfirst, uint32_t *cell_of_packet, hipStream_t s);
 
 struct WalkParams {
     const WalkBox *boxes;
@@ -123,11 +123,62 @@ struct WalkParams {
     const uint32_t *cell_of_packet;
     unsigned long long *A;   // per-cell absorbed weight
     BoxTot *tot;
-    unsigned long long *queue;   // work counter (persistent kernel)
+    unsigned long long *queue;   // work counters, one per part of the range (persistent kernel)
     uint64_t first, count;   // global packet range
     int64_t max_cross;
     int32_t chunk, refill;
+    int32_t nqueues;         // parts of the packet range (1..kMaxQueues)
 };
+constexpr int kMaxQueues = 64;
+
+// ---- tile-decomposed walk -------------------------------------------------
+constexpr int kTileEdge = 16;          // cells per tile edge (tiles of 16^3 cells)
+
+struct TileInfo {
+    int32_t box;
+    int32_t ox, oy, oz;      // origin (cell coordinates in the box)
+    int32_t sx, sy, sz;      // extent (cells)
+    int32_t nnbr;            // distinct face-neighbour tiles other than itself (0..6)
+    int32_t nbr[6];
+    int32_t pad[2];
+};
+static_assert(sizeof(TileInfo) == 64, "TileInfo layout");
+
+// A packet standing on the face between two tiles (112 bytes).
+struct alignas(16) PState {
+    double tmx, tmy, tmz, tdx, tdy, tdz, t;
+    uint64_t w;
+    float x, kx, ky, kz;     // pre-jump frequency and direction
+    float ux, uy, uz;        // velocity of the cell it leaves
+    uint32_t cell;           // cell it enters (global)
+    uint32_t ncross;
+    int32_t ix, iy, iz;      // coordinates of that cell
+};
+static_assert(sizeof(PState) == 112, "PState layout");
+
+struct TileParams {
+    const WalkBox *boxes;
+    const TileInfo *tiles;
+    const int4 *box_tiles;   // per box: first tile, tiles along x, y, z
+    const void *rec;
+    const uint32_t *npk;     // packets per cell
+    const uint64_t *pfirst;  // global id of each cell's first packet
+    unsigned long long *A;
+    BoxTot *tot;
+    const PState *in_state;
+    const uint32_t *in_dest, *in_base, *in_count;
+    PState *out_state;
+    uint32_t *out_dest, *out_base, *out_count;
+    unsigned long long *bump;    // allocator of the exit buffer
+    unsigned long long *exits;   // packets written out this generation
+    uint64_t first, count;   // packet range
+    uint32_t max_cross;
+    int32_t ntiles;
+    int32_t chunk;
+    int32_t pad;
+};
+
+hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s);
 
 hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s);
 hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s);

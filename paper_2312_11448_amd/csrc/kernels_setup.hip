@@ -268,6 +268,7 @@ __global__ __launch_bounds__(B) void allocate_kernel(const PackBox *__restrict__
                                                      const uint64_t *__restrict__ bsum,
                                                      const BoxRed *__restrict__ red,
                                                      uint32_t *__restrict__ npk,
+                                                     uint64_t *__restrict__ pfirst,
                                                      uint32_t *__restrict__ cop, int max_blk)
 {
     __shared__ uint64_t lds[kWaves];
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(B) void allocate_kernel(const PackBox *__restrict__
     const uint64_t qtot = red[b].qtot;
     if (n == 0 || qtot == 0) {
         npk[g] = 0;
+        pfirst[g] = wbs[b].pkt_off;
         return;
     }
     const uint64_t Q = bsum[(size_t)b * max_blk + blockIdx.x] + inc - v;
@@ -291,6 +293,7 @@ __global__ __launch_bounds__(B) void allocate_kernel(const PackBox *__restrict__
     const uint64_t next = count_below(Q + v, qtot, n);
     const uint32_t cnt = (uint32_t)(next - first);
     npk[g] = cnt;
+    pfirst[g] = wbs[b].pkt_off + first;
     uint32_t *dst = cop + wbs[b].pkt_off + first;
     for (uint32_t k = 0; k < cnt; ++k) dst[k] = (uint32_t)g;
 }
@@ -344,10 +347,10 @@ hipError_t launch_scan_blocks(const PackBox *pb_dev, int n_boxes, int max_blk, u
 
 hipError_t launch_allocate(const PackBox *pb_dev, const WalkBox *wb_dev, int n_boxes, int max_blk,
                            const uint64_t *q, const uint64_t *bsum, const BoxRed *red, uint32_t *npk,
-                           uint32_t *cell_of_packet, hipStream_t s)
+                           uint64_t *pfirst, uint32_t *cell_of_packet, hipStream_t s)
 {
     hipLaunchKernelGGL(allocate_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, pb_dev, wb_dev, q, bsum, red,
-                       npk, cell_of_packet, max_blk);
+                       npk, pfirst, cell_of_packet, max_blk);
     return hipGetLastError();
 }
 

@@ -1,0 +1,365 @@
+// Tile-decomposed walk.
+//
+// Device-scope 64-bit atomics run at a fixed ~2.4e10 operations/s on this
+// chip whatever the cache residency, while a packet deposits into one cell per
+// crossing. So the grid is cut into tiles of kTileEdge^3 cells and the walk
+// proceeds in generations: in each generation one workgroup owns one tile,
+// walks every packet that is inside it, deposits into a tally in LDS (LDS
+// atomics), and at the end adds that tally to the device tallies with plain
+// read-modify-write (no other workgroup touches the tile's cells in that
+// generation). A packet that leaves the tile is written, standing on the face
+// with its pre-jump frequency, to the tile's exit region; in the next
+// generation the neighbouring tile pulls it and applies the face jump.
+//
+// The per-packet arithmetic is walk_core's, so the integer tallies are the
+// same bits as those of the other drivers.
+#include "walk_core.hpp"
+
+namespace mclya {
+namespace {
+
+constexpr int TE = kTileEdge;
+constexpr int TC = TE * TE * TE;
+constexpr int BLK = 256;
+constexpr int kWaves = BLK / 64;
+
+struct TileSink {
+    unsigned long long *tally;   // LDS, one entry per cell of the tile
+    int32_t ox, oy, oz, sx, sy, sz;
+    __device__ __forceinline__ bool inside(int32_t jx, int32_t jy, int32_t jz) const
+    {
+        return (uint32_t)(jx - ox) < (uint32_t)sx && (uint32_t)(jy - oy) < (uint32_t)sy &&
+               (uint32_t)(jz - oz) < (uint32_t)sz;
+    }
+    __device__ __forceinline__ void deposit(const Lane &L, uint64_t d) const
+    {
+        const int lc = (L.ix - ox) + sx * ((L.iy - oy) + sy * (L.iz - oz));
+        atomicAdd(&tally[lc], (unsigned long long)d);
+    }
+};
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void save_state(PState &o, const Lane &L)
+{
+    o.tmx = L.tmx;
+    o.tmy = L.tmy;
+    o.tmz = L.tmz;
+    o.tdx = L.tdx;
+    o.tdy = L.tdy;
+    o.tdz = L.tdz;
+    o.t = L.t;
+    o.w = L.w;
+    o.x = L.x;
+    o.kx = L.kx;
+    o.ky = L.ky;
+    o.kz = L.kz;
+    o.ux = L.ux;
+    o.uy = L.uy;
+    o.uz = L.uz;
+    o.cell = L.c;
+    o.ncross = L.ncross;
+    o.ix = L.ix;
+    o.iy = L.iy;
+    o.iz = L.iz;
+}
+
+__device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkBox &B)
+{
+    L.tmx = o.tmx;
+    L.tmy = o.tmy;
+    L.tmz = o.tmz;
+    L.tdx = o.tdx;
+    L.tdy = o.tdy;
+    L.tdz = o.tdz;
+    L.t = o.t;
+    L.w = o.w;
+    L.x = o.x;
+    L.kx = o.kx;
+    L.ky = o.ky;
+    L.kz = o.kz;
+    L.ux = o.ux;
+    L.uy = o.uy;
+    L.uz = o.uz;
+    L.c = o.cell;
+    L.ncross = o.ncross;
+    L.ix = o.ix;
+    L.iy = o.iy;
+    L.iz = o.iz;
+    L.nx = B.nx;
+    L.ny = B.ny;
+    L.nz = B.nz;
+    L.coff = B.cell_off;
+    L.delta = B.delta;
+    L.xeff = B.x_eff;
+}
+
+// One generation. GEN0: the tile's input is the packets emitted in its cells
+// (within the requested packet range); otherwise it is the packets its face
+// neighbours wrote out in the previous generation with this tile as target.
+template <bool VEL, bool GEN0>
+__global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
+{
+    __shared__ unsigned long long tally[TC];
+    __shared__ uint32_t pre[GEN0 ? TC + 1 : 8];   // GEN0: cell prefix of packet counts; else region prefix
+    __shared__ uint32_t src[8];                    // region bases (previous generation)
+    __shared__ uint32_t s_tsum[BLK];
+    __shared__ uint32_t s_next, s_exit, s_total, s_base;
+    __shared__ unsigned long long s_red[kWaves][4];
+
+    const int T = blockIdx.x;
+    const TileInfo ti = P.tiles[T];
+    const WalkBox B = P.boxes[ti.box];
+    const int ncell = ti.sx * ti.sy * ti.sz;
+    const int tid = threadIdx.x;
+    const uint32_t lane = __lane_id();
+    const uint64_t r_lo = P.first, r_hi = P.first + P.count;
+
+    // ---- input ----------------------------------------------------------
+    uint32_t n_in = 0;
+    if (GEN0) {
+        // packet counts of the tile's cells, clipped to the range, scanned
+        constexpr int PER = TC / BLK;
+        uint32_t cnt[PER];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int lc = tid * PER + k;
+            uint32_t c = 0;
+            if (lc < ncell) {
+                const int lx = lc % ti.sx, ly = (lc / ti.sx) % ti.sy, lz = lc / (ti.sx * ti.sy);
+                const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                                    (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+                const uint64_t pf = P.pfirst[gc];
+                const uint64_t lo = pf > r_lo ? pf : r_lo;
+                const uint64_t pe = pf + P.npk[gc];
+                const uint64_t hi = pe < r_hi ? pe : r_hi;
+                c = hi > lo ? (uint32_t)(hi - lo) : 0u;
+            }
+            cnt[k] = c;
+            sum += c;
+        }
+        s_tsum[tid] = sum;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (int i = 0; i < BLK; ++i) {
+                const uint32_t v = s_tsum[i];
+                s_tsum[i] = run;
+                run += v;
+            }
+            s_total = run;
+        }
+        __syncthreads();
+        uint32_t run = s_tsum[tid];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int lc = tid * PER + k;
+            if (lc < ncell) pre[lc] = run;
+            run += cnt[k];
+        }
+        if (tid == 0) pre[ncell] = s_total;
+        n_in = s_total;
+    } else {
+        if (tid == 0) {
+            uint32_t run = 0;
+            const int32_t *nbr = P.tiles[T].nbr;
+            for (int k = 0; k < ti.nnbr; ++k) {
+                pre[k] = run;
+                src[k] = P.in_base[nbr[k]];
+                run += P.in_count[nbr[k]];
+            }
+            pre[ti.nnbr] = run;
+            s_total = run;
+        }
+        __syncthreads();
+        n_in = s_total;
+    }
+    // packets this tile will take: all of n_in for GEN0, the matching entries otherwise
+    uint32_t n_pk = n_in;
+    if (!GEN0) {
+        uint32_t m = 0;
+        for (uint32_t j = tid; j < n_in; j += BLK) {
+            int k = 0;
+            while (k + 1 < ti.nnbr && pre[k + 1] <= j) ++k;
+            m += P.in_dest[src[k] + (j - pre[k])] == (uint32_t)T ? 1u : 0u;
+        }
+        m = wave_sum(m);
+        __syncthreads();
+        if (lane == 0) s_tsum[tid >> 6] = m;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kWaves; ++w) t += s_tsum[w];
+            s_total = t;
+        }
+        __syncthreads();
+        n_pk = s_total;
+    }
+    if (n_pk == 0) {
+        if (tid == 0) {
+            P.out_base[T] = 0;
+            P.out_count[T] = 0;
+        }
+        return;
+    }
+    for (int lc = tid; lc < ncell; lc += BLK) tally[lc] = 0ull;
+    if (tid == 0) {
+        s_next = 0;
+        s_exit = 0;
+        s_base = (uint32_t)atomicAdd(P.bump, (unsigned long long)n_pk);
+    }
+    __syncthreads();
+
+    // ---- walk -------------------------------------------------------------
+    const TileSink sink{tally, ti.ox, ti.oy, ti.oz, ti.sx, ti.sy, ti.sz};
+    const int4 bt = P.box_tiles[ti.box];          // tile offset and tile counts of the box
+    Lane L;
+    bool alive = false, more = true;
+    uint32_t cur = 0, end = 0;
+    uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0;
+    const uint32_t chunk = (uint32_t)P.chunk;
+    for (;;) {
+        uint64_t idle = __ballot(!alive);
+        while (idle && more) {
+            if (cur >= end) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_next, chunk);
+                base = uniform_u32(__shfl(base, 0, 64));
+                if (base >= n_in) {
+                    more = false;
+                    break;
+                }
+                cur = base;
+                end = base + chunk < n_in ? base + chunk : n_in;
+            }
+            const uint32_t take = min((uint32_t)__popcll(idle), end - cur);
+            const uint32_t r = rank_in(idle);
+            if (!alive && r < take) {
+                const uint32_t j = cur + r;
+                if (GEN0) {
+                    int lo = 0, hi = ncell - 1;             // largest cell with pre <= j
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                    }
+                    const int lx = lo % ti.sx, ly = (lo / ti.sx) % ti.sy, lz = lo / (ti.sx * ti.sy);
+                    const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                                        (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+                    const uint64_t pf = P.pfirst[gc];
+                    const uint64_t gp = (pf > r_lo ? pf : r_lo) + (j - pre[lo]);
+                    init_packet<VEL>(L, B, gp - B.pkt_off, gc, P.rec);
+                    alive = true;
+                } else {
+                    int k = 0;
+                    while (k + 1 < ti.nnbr && pre[k + 1] <= j) ++k;
+                    const uint32_t g = src[k] + (j - pre[k]);
+                    if (P.in_dest[g] == (uint32_t)T) {
+                        load_state(L, P.in_state[g], B);
+                        finish_entry<VEL>(L, load_rec<VEL>(P.rec, L.c));
+                        alive = true;
+                    }
+                }
+            }
+            cur += take;
+            idle = __ballot(!alive);
+        }
+        if (!__ballot(alive)) {
+            if (!more) break;
+            continue;
+        }
+        if (alive) {
+            uint64_t dep = 0;
+            const int fate = walk_step<VEL>(L, P.rec, sink, P.max_cross, dep);
+            if (fate == kExit) {
+                const uint32_t slot = atomicAdd(&s_exit, 1u);
+                const uint32_t g = s_base + slot;
+                save_state(P.out_state[g], L);
+                const int32_t tx = L.ix / TE, ty = L.iy / TE, tz = L.iz / TE;
+                P.out_dest[g] = (uint32_t)bt.x + (uint32_t)tx + (uint32_t)bt.y * ((uint32_t)ty + (uint32_t)bt.z * (uint32_t)tz);
+                alive = false;
+            } else if (fate != kAlive) {
+                a_cross += L.ncross;
+                a_esc += fate == kEscaped ? L.w : 0;
+                a_capn += fate == kCapped ? 1 : 0;
+                a_capw += fate == kCapped ? L.w : 0;
+                alive = false;
+            }
+        }
+    }
+
+    // ---- finish: tally, totals, exits --------------------------------------
+    a_esc = wave_sum(a_esc);
+    a_cross = wave_sum(a_cross);
+    a_capn = wave_sum(a_capn);
+    a_capw = wave_sum(a_capw);
+    if (lane == 0) {
+        s_red[tid >> 6][0] = a_esc;
+        s_red[tid >> 6][1] = a_cross;
+        s_red[tid >> 6][2] = a_capn;
+        s_red[tid >> 6][3] = a_capw;
+    }
+    __syncthreads();
+    for (int lc = tid; lc < ncell; lc += BLK) {
+        const unsigned long long v = tally[lc];
+        if (v) {
+            const int lx = lc % ti.sx, ly = (lc / ti.sx) % ti.sy, lz = lc / (ti.sx * ti.sy);
+            const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                                (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+            P.A[gc] += v;    // this workgroup alone owns these cells in this generation
+        }
+    }
+    if (tid < 4) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWaves; ++w) t += s_red[w][tid];
+        if (t) {
+            unsigned long long *dst = tid == 0 ? &P.tot[ti.box].escaped
+                                   : tid == 1 ? &P.tot[ti.box].crossings
+                                   : tid == 2 ? &P.tot[ti.box].capped_packets
+                                              : &P.tot[ti.box].capped_weight;
+            atomicAdd(dst, t);
+        }
+    }
+    if (tid == 0) {
+        P.out_base[T] = s_base;
+        P.out_count[T] = s_exit;
+        if (s_exit) atomicAdd(P.exits, (unsigned long long)s_exit);
+    }
+}
+
+__global__ void reset_counters_kernel(unsigned long long *a, unsigned long long *b)
+{
+    *a = 0ull;
+    *b = 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(1), 0, s, p.bump, p.exits);
+    const dim3 grid((unsigned)p.ntiles), block(BLK);
+    if (gen0) {
+        if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, true>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((tile_walk_kernel<false, true>), grid, block, 0, s, p);
+    } else {
+        if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, false>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((tile_walk_kernel<false, false>), grid, block, 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mclya

@@ -13,164 +13,10 @@
 //   walk_simple      one thread per packet (reference driver, same results).
 // Both produce bit-identical integer tallies: each packet's arithmetic does
 // not depend on the driver, and integer additions commute.
-#include "common.hpp"
+#include "walk_core.hpp"
 
 namespace mclya {
 namespace {
-
-constexpr double kFar = 1.0e300;   // face distance along an axis the ray does not move on
-
-// Ray geometry (direction, position inside the cell, face distances) is kept
-// in binary64: over paths of hundreds of cells binary32 directions drift by
-// ~1e-5 cell, enough to clip a different cell corner than an exact ray. The
-// line-profile arithmetic (drift, Phi, deposit) is binary32.
-struct Lane {
-    int32_t ix, iy, iz;
-    uint32_t c;          // global cell
-    double fx, fy, fz;   // position inside the cell, [0,1]
-    double kx, ky, kz;   // direction
-    double rx, ry, rz;   // 1/|k| per axis
-    float x;             // gas-frame frequency, Doppler widths
-    float kap;           // kappa of the current cell
-    float ux, uy, uz;    // bulk velocity of the current cell (Doppler units)
-    uint64_t w;          // remaining weight
-    uint32_t ncross;
-    int32_t nx, ny, nz;
-    uint32_t coff;
-    float delta, xeff;
-};
-
-template <bool VEL>
-__device__ __forceinline__ void load_cell(Lane &L, const void *__restrict__ rec)
-{
-    if (VEL) {
-        const float4 r = static_cast<const float4 *>(rec)[L.c];
-        L.kap = r.x;
-        L.ux = r.y;
-        L.uy = r.z;
-        L.uz = r.w;
-    } else {
-        L.kap = static_cast<const float *>(rec)[L.c];
-    }
-}
-
-// Emission of packet p (box-local id) in global cell gcell: position uniform
-// in the cell, isotropic direction, frequency from the Doppler profile
-// exp(-x^2)/sqrt(pi) by the Box-Muller transform.
-template <bool VEL>
-__device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t p, uint32_t gcell,
-                                            const void *__restrict__ rec)
-{
-    const uint32_t k0 = (uint32_t)B.seed, k1 = (uint32_t)(B.seed >> 32);
-    uint32_t a[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, 0u};
-    uint32_t b[4] = {(uint32_t)p, (uint32_t)(p >> 32), 1u, 0u};
-    philox4x32_10(a, k0, k1);
-    philox4x32_10(b, k0, k1);
-    L.nx = B.nx;
-    L.ny = B.ny;
-    L.nz = B.nz;
-    L.coff = B.cell_off;
-    L.delta = B.delta;
-    L.xeff = B.x_eff;
-    const uint32_t local = gcell - B.cell_off;
-    L.ix = (int32_t)(local % (uint32_t)B.nx);
-    const uint32_t rest = local / (uint32_t)B.nx;
-    L.iy = (int32_t)(rest % (uint32_t)B.ny);
-    L.iz = (int32_t)(rest / (uint32_t)B.ny);
-    L.c = gcell;
-    L.fx = (double)u01(a[0]);
-    L.fy = (double)u01(a[1]);
-    L.fz = (double)u01(a[2]);
-    const double mu = 2.0 * (double)u01(a[3]) - 1.0;   // exact
-    double sp, cp;
-    sincospi(2.0 * (double)u01(b[0]), &sp, &cp);         // azimuth 2 pi u
-    const double st = sqrt((1.0 - mu) * (1.0 + mu));
-    L.kx = st * cp;
-    L.ky = st * sp;
-    L.kz = mu;
-    L.rx = L.kx != 0.0 ? 1.0 / fabs(L.kx) : kFar;
-    L.ry = L.ky != 0.0 ? 1.0 / fabs(L.ky) : kFar;
-    L.rz = L.kz != 0.0 ? 1.0 / fabs(L.kz) : kFar;
-    L.x = (float)(sqrt(-log((double)u01(b[1]))) * cospi(2.0 * (double)u01(b[2])));
-    L.w = B.w0;
-    L.ncross = 0;
-    load_cell<VEL>(L, rec);
-}
-
-// Phi(hi) - Phi(lo) for hi > lo, Phi(x) = erfc(-x)/2, written with the
-// complementary function on the side where it is small so that the
-// difference does not cancel.
-// Clamped at 0: Phi is non-decreasing, but two rounded erfc values of nearly
-// equal arguments (a sliver segment at a cell corner) can come out reversed.
-__device__ __forceinline__ float delta_phi(float hi, float lo)
-{
-    const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(hi)) : 0.5f * (erfcf(-hi) - erfcf(-lo));
-    return fmaxf(d, 0.0f);
-}
-
-enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3 };
-
-// One (packet, cell) segment. Returns kAlive, or the packet's fate.
-template <bool VEL, bool TALLY>
-__device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec,
-                                         unsigned long long *__restrict__ A, uint32_t max_cross,
-                                         uint64_t &deposited)
-{
-    if (L.x <= -L.xeff) return kEscaped;            // redshifted out of the line
-    if (L.ncross >= max_cross) return kCapped;
-    ++L.ncross;
-
-    // distance to the face the ray leaves through (ties: x, then y, then z)
-    const double tx = (L.kx > 0.0 ? 1.0 - L.fx : L.fx) * L.rx;
-    const double ty = (L.ky > 0.0 ? 1.0 - L.fy : L.fy) * L.ry;
-    const double tz = (L.kz > 0.0 ? 1.0 - L.fz : L.fz) * L.rz;
-    int axis = 0;
-    double s = tx;
-    if (ty < s) { axis = 1; s = ty; }
-    if (tz < s) { axis = 2; s = tz; }
-
-    // Hubble drift across the segment; the last one stops at -x_eff
-    const float xo = fmaf(-L.delta, (float)s, L.x);
-    const bool esc = xo <= -L.xeff;
-    const float dphi = delta_phi(L.x, esc ? -L.xeff : xo);
-    const float dtau = L.kap * dphi;
-    const float pabs = -expm1f(-dtau);
-    uint64_t d = (uint64_t)rintf((float)L.w * pabs);
-    if (d > L.w) d = L.w;
-    L.w -= d;
-    deposited += d;
-    if (TALLY && d) atomicAdd(&A[L.c], (unsigned long long)d);
-    if (esc) return kEscaped;
-    if (L.w == 0) return kAbsorbed;
-
-    // move to the face and into the neighbour (periodic)
-    L.fx = fmin(fmax(fma(L.kx, s, L.fx), 0.0), 1.0);
-    L.fy = fmin(fmax(fma(L.ky, s, L.fy), 0.0), 1.0);
-    L.fz = fmin(fmax(fma(L.kz, s, L.fz), 0.0), 1.0);
-    if (axis == 0) {
-        if (L.kx > 0.0) { L.fx = 0.0; L.ix = (L.ix + 1 == L.nx) ? 0 : L.ix + 1; }
-        else { L.fx = 1.0; L.ix = (L.ix == 0) ? L.nx - 1 : L.ix - 1; }
-    } else if (axis == 1) {
-        if (L.ky > 0.0) { L.fy = 0.0; L.iy = (L.iy + 1 == L.ny) ? 0 : L.iy + 1; }
-        else { L.fy = 1.0; L.iy = (L.iy == 0) ? L.ny - 1 : L.iy - 1; }
-    } else {
-        if (L.kz > 0.0) { L.fz = 0.0; L.iz = (L.iz + 1 == L.nz) ? 0 : L.iz + 1; }
-        else { L.fz = 1.0; L.iz = (L.iz == 0) ? L.nz - 1 : L.iz - 1; }
-    }
-    L.c = L.coff + (uint32_t)L.ix + (uint32_t)L.nx * ((uint32_t)L.iy + (uint32_t)L.ny * (uint32_t)L.iz);
-    L.x = xo;
-    if (VEL) {
-        const float ux = L.ux, uy = L.uy, uz = L.uz;
-        load_cell<VEL>(L, rec);
-        // Eq. (inout), bulk term: x_new = x_old - k.(U_new - U_old)
-        const float du = (float)(L.kx * (double)(L.ux - ux) + L.ky * (double)(L.uy - uy) +
-                                 L.kz * (double)(L.uz - uz));
-        L.x = xo - du;
-    } else {
-        load_cell<VEL>(L, rec);
-    }
-    return kAlive;
-}
 
 // ---- wave helpers --------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -191,6 +37,14 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 __device__ __forceinline__ uint64_t bcast_u64(uint64_t v, int src)
 {
     return __shfl(v, src, 64);
+}
+
+// Tells the compiler a wave-uniform value is uniform (scalar registers).
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Per-lane per-box totals, flushed with one atomic per box per wave.
@@ -226,8 +80,9 @@ __device__ __forceinline__ void flush(Acc &a, bool give, BoxTot *__restrict__ to
 __device__ __forceinline__ void account(Acc &a, const Lane &L, int fate)
 {
     a.cross += L.ncross;
-    if (fate == kEscaped) a.esc += L.w;
-    if (fate == kCapped) { a.capn += 1; a.capw += L.w; }
+    a.esc += fate == kEscaped ? L.w : 0;
+    a.capn += fate == kCapped ? 1 : 0;
+    a.capw += fate == kCapped ? L.w : 0;
 }
 
 // Box of a global packet id (boxes sorted by packet offset).
@@ -258,20 +113,33 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
     uint64_t cur = 0, end = 0;        // wave-uniform: current block of packet ids
     const uint32_t refill = (uint32_t)P.refill;
     const uint64_t chunk = (uint64_t)P.chunk;
+    // The packet range is split into nq contiguous parts (packet ids follow
+    // the cell order, so each part is a slab of the grid). Workgroups are
+    // dispatched round-robin over the chip's XCDs, so workgroup g starts on
+    // part g % nq and moves on to the next part when its own is drained:
+    // each XCD's L2 mostly sees one slab.
+    const uint32_t nq = (uint32_t)P.nqueues;
+    uint32_t part = blockIdx.x % nq, tried = 0;
 
     for (;;) {
         uint64_t idle = __ballot(!alive);
         if (more && (uint32_t)__popcll(idle) >= refill) {
             while (idle && more) {
                 if (cur >= end) {
+                    const uint64_t lo = P.count * part / nq, hi = P.count * (part + 1) / nq;
                     uint64_t base = 0;
-                    if (lane == 0) base = atomicAdd(P.queue, (unsigned long long)chunk);
-                    base = bcast_u64(base, 0);
-                    if (base >= P.count) { more = false; break; }
+                    if (lane == 0) base = atomicAdd(&P.queue[part], (unsigned long long)chunk);
+                    base = lo + bcast_u64(base, 0);
+                    base = uniform_u64(base);
+                    if (base >= hi) {
+                        if (++tried >= nq) { more = false; break; }
+                        part = part + 1 == nq ? 0 : part + 1;
+                        continue;
+                    }
                     cur = base;
-                    end = base + chunk < P.count ? base + chunk : P.count;
+                    end = base + chunk < hi ? base + chunk : hi;
                 }
-                const uint64_t n_idle = (uint64_t)__popcll(idle);
+        const uint64_t n_idle = (uint64_t)__popcll(idle);
                 const uint64_t take = n_idle < end - cur ? n_idle : end - cur;
                 const uint32_t r = rank_in(idle);
                 const bool fresh = !alive && (uint64_t)r < take;
@@ -299,7 +167,7 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
         }
         if (alive) {
             uint64_t dep = 0;
-            const int fate = walk_step<VEL, true>(L, P.rec, P.A, max_cross, dep);
+            const int fate = walk_step<VEL>(L, P.rec, GlobalSink{P.A}, max_cross, dep);
             if (fate != kAlive) {
                 account(acc, L, fate);
                 alive = false;
@@ -328,7 +196,7 @@ __global__ __launch_bounds__(256) void walk_simple_kernel(WalkParams P)
         uint64_t dep = 0;
         int fate;
         do {
-            fate = walk_step<VEL, true>(L, P.rec, P.A, (uint32_t)P.max_cross, dep);
+            fate = walk_step<VEL>(L, P.rec, GlobalSink{P.A}, (uint32_t)P.max_cross, dep);
         } while (fate == kAlive);
         account(acc, L, fate);
     }
@@ -345,20 +213,21 @@ __global__ __launch_bounds__(256) void trace_kernel(WalkParams P, mc_lya_packet_
     const int nb = P.n_boxes == 1 ? 0 : box_of(P.boxes, P.n_boxes, gp);
     const WalkBox B = P.boxes[nb];
     Lane L;
-    init_packet<VEL>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec);
+    float f0[3];
+    init_packet<VEL>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec, f0);
     mc_lya_packet_trace t;
     t.cell0 = L.c;
-    t.fx = (float)L.fx;
-    t.fy = (float)L.fy;
-    t.fz = (float)L.fz;
-    t.kx = (float)L.kx;
-    t.ky = (float)L.ky;
-    t.kz = (float)L.kz;
+    t.fx = f0[0];
+    t.fy = f0[1];
+    t.fz = f0[2];
+    t.kx = L.kx;
+    t.ky = L.ky;
+    t.kz = L.kz;
     t.x0 = L.x;
     uint64_t dep = 0;
     int fate;
     do {
-        fate = walk_step<VEL, false>(L, P.rec, nullptr, (uint32_t)P.max_cross, dep);
+        fate = walk_step<VEL>(L, P.rec, NullSink{}, (uint32_t)P.max_cross, dep);
     } while (fate == kAlive);
     t.escaped = fate == kAbsorbed ? 0 : (int64_t)L.w;
     t.absorbed = (int64_t)dep;
@@ -377,7 +246,10 @@ __global__ void philox_kernel(const uint32_t *__restrict__ ctr, const uint32_t *
     for (int j = 0; j < 4; ++j) out[4 * i + j] = c[j];
 }
 
-__global__ void reset_queue_kernel(unsigned long long *q) { *q = 0ull; }
+__global__ void reset_queue_kernel(unsigned long long *q, int n)
+{
+    if ((int)threadIdx.x < n) q[threadIdx.x] = 0ull;
+}
 
 }  // namespace
 
@@ -392,7 +264,7 @@ int persistent_blocks_per_cu(bool vel, int block)
 
 hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, p.queue);
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, p.queue, (int)p.nqueues);
     const size_t lds = sizeof(WalkBox) * (size_t)p.n_boxes;
     if (p.vel)
         hipLaunchKernelGGL(walk_persistent_kernel<true>, dim3((unsigned)grid), dim3((unsigned)block), lds, s, p);

@@ -1,0 +1,234 @@
+// Per-packet arithmetic of the Lyman-alpha walk, shared by every driver:
+// emission (App. A step 1), the straight-line cell walk with the Hubble drift
+// (App. A step 4), the bulk-velocity shift of Eq. (inout) at faces, the
+// expected-value deposit of the true absorption (kappa_c times the swept part
+// of the profile, the depth of Eq. (<fnu>)) and escape by redshifting (end of
+// App. A). Drivers differ only in where deposits go and which cells they own,
+// so every driver produces the same integers.
+#pragma once
+
+#include "common.hpp"
+
+namespace mclya {
+
+constexpr double kFar = 1.0e300;   // face distance along an axis the ray does not move on
+
+// Ray geometry is kept in binary64: over paths of hundreds of cells binary32
+// directions drift by ~1e-5 cell, enough to clip a different cell corner than
+// an exact ray. The walk is incremental (Amanatides & Woo): tm[a] is the path
+// length from the emission point to the next face on axis a, td[a] = 1/|k_a|
+// the length between two faces, t the length walked so far. The line-profile
+// arithmetic (drift, swept profile, deposit) is binary32.
+struct Lane {
+    int32_t ix, iy, iz;
+    uint32_t c;          // global cell
+    double tmx, tmy, tmz;
+    double tdx, tdy, tdz;
+    double t;
+    float kx, ky, kz;    // direction (binary32: velocity terms only)
+    float x;             // gas-frame frequency, Doppler widths
+    float kap;           // kappa of the current cell
+    float ux, uy, uz;    // bulk velocity of the current cell (Doppler units)
+    uint64_t w;          // remaining weight
+    uint32_t ncross;
+    int32_t nx, ny, nz;
+    uint32_t coff;
+    float delta, xeff;
+};
+
+struct Rec {
+    float kap, ux, uy, uz;
+};
+
+template <bool VEL>
+__device__ __forceinline__ Rec load_rec(const void *__restrict__ rec, uint32_t c)
+{
+    Rec r;
+    if (VEL) {
+        const float4 v = static_cast<const float4 *>(rec)[c];
+        r.kap = v.x;
+        r.ux = v.y;
+        r.uy = v.z;
+        r.uz = v.w;
+    } else {
+        r.kap = static_cast<const float *>(rec)[c];
+        r.ux = r.uy = r.uz = 0.0f;
+    }
+    return r;
+}
+
+// Emission of packet p (box-local id) in global cell gcell: position uniform
+// in the cell, isotropic direction, frequency from the Doppler profile
+// exp(-x^2)/sqrt(pi) by the Box-Muller transform. Optionally returns the
+// initial state (position inside the cell and direction) for traces.
+template <bool VEL>
+__device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t p, uint32_t gcell,
+                                            const void *__restrict__ rec, float *state = nullptr)
+{
+    const uint32_t k0 = (uint32_t)B.seed, k1 = (uint32_t)(B.seed >> 32);
+    uint32_t a[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, 0u};
+    uint32_t b[4] = {(uint32_t)p, (uint32_t)(p >> 32), 1u, 0u};
+    philox4x32_10(a, k0, k1);
+    philox4x32_10(b, k0, k1);
+    L.nx = B.nx;
+    L.ny = B.ny;
+    L.nz = B.nz;
+    L.coff = B.cell_off;
+    L.delta = B.delta;
+    L.xeff = B.x_eff;
+    const uint32_t local = gcell - B.cell_off;
+    L.ix = (int32_t)(local % (uint32_t)B.nx);
+    const uint32_t rest = local / (uint32_t)B.nx;
+    L.iy = (int32_t)(rest % (uint32_t)B.ny);
+    L.iz = (int32_t)(rest / (uint32_t)B.ny);
+    L.c = gcell;
+    const double fx = (double)u01(a[0]), fy = (double)u01(a[1]), fz = (double)u01(a[2]);
+    const double mu = 2.0 * (double)u01(a[3]) - 1.0;   // exact
+    double sp, cp;
+    sincospi(2.0 * (double)u01(b[0]), &sp, &cp);         // azimuth 2 pi u
+    const double st = sqrt((1.0 - mu) * (1.0 + mu));
+    const double kx = st * cp, ky = st * sp, kz = mu;
+    L.tdx = kx != 0.0 ? 1.0 / fabs(kx) : kFar;
+    L.tdy = ky != 0.0 ? 1.0 / fabs(ky) : kFar;
+    L.tdz = kz != 0.0 ? 1.0 / fabs(kz) : kFar;
+    L.tmx = kx != 0.0 ? (kx > 0.0 ? 1.0 - fx : fx) * L.tdx : kFar;
+    L.tmy = ky != 0.0 ? (ky > 0.0 ? 1.0 - fy : fy) * L.tdy : kFar;
+    L.tmz = kz != 0.0 ? (kz > 0.0 ? 1.0 - fz : fz) * L.tdz : kFar;
+    L.t = 0.0;
+    L.kx = (float)kx;
+    L.ky = (float)ky;
+    L.kz = (float)kz;
+    L.x = sqrtf(-logf(u01(b[1]))) * cospif(2.0f * u01(b[2]));
+    L.w = B.w0;
+    L.ncross = 0;
+    const Rec r = load_rec<VEL>(rec, gcell);
+    L.kap = r.kap;
+    L.ux = r.ux;
+    L.uy = r.uy;
+    L.uz = r.uz;
+    if (state) {
+        state[0] = (float)fx;
+        state[1] = (float)fy;
+        state[2] = (float)fz;
+    }
+}
+
+// Swept profile mass Phi(x) - Phi(x - dx) for dx > 0, Phi the cumulative
+// Doppler profile. Segments are short (dx = delta * length, a few hundredths
+// of a Doppler width for the paper's cells), so the integral of
+// exp(-y^2)/sqrt(pi) over the segment is taken by 3-point Gauss-Legendre
+// (relative error < 5e-8 for dx <= 0.05, < 3e-6 for dx <= 0.1); longer
+// segments use the difference of complementary error functions, each taken
+// where it is small. Never negative.
+__device__ __forceinline__ float swept_profile(float x, float dx)
+{
+    if (dx <= 0.1f) {
+        const float h = 0.5f * dx;
+        const float m = x - h;
+        const float a = h * 0.7745966692414834f;          // sqrt(3/5)
+        const float y0 = m - a, y2 = m + a;
+        const float e0 = __expf(-y0 * y0), e1 = __expf(-m * m), e2 = __expf(-y2 * y2);
+        // (5 e0 + 8 e1 + 5 e2) / 9 * h / sqrt(pi)
+        return h * 0.06268937721449021f * (5.0f * (e0 + e2) + 8.0f * e1);
+    }
+    const float lo = x - dx;
+    const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(x)) : 0.5f * (erfcf(-x) - erfcf(-lo));
+    return fmaxf(d, 0.0f);
+}
+
+// 1 - exp(-tau) for tau >= 0 without cancellation.
+__device__ __forceinline__ float one_minus_exp(float tau)
+{
+    if (tau < 0.1f)
+        return tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f -
+                                                 tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
+    return 1.0f - __expf(-tau);
+}
+
+// Entering a cell: the bulk term of Eq. (inout), x_new = x_old - k.(U_new -
+// U_old), then the new cell's opacity and velocity.
+template <bool VEL>
+__device__ __forceinline__ void finish_entry(Lane &L, const Rec &nr)
+{
+    if (VEL) {
+        const float du = L.kx * (nr.ux - L.ux) + L.ky * (nr.uy - L.uy) + L.kz * (nr.uz - L.uz);
+        L.x = L.x - du;
+        L.ux = nr.ux;
+        L.uy = nr.uy;
+        L.uz = nr.uz;
+    }
+    L.kap = nr.kap;
+}
+
+// Deposits go straight to the per-cell int64 tallies in device memory.
+struct GlobalSink {
+    unsigned long long *A;
+    __device__ __forceinline__ void deposit(const Lane &L, uint64_t d) const
+    {
+        atomicAdd(&A[L.c], (unsigned long long)d);
+    }
+    __device__ __forceinline__ bool inside(int32_t, int32_t, int32_t) const { return true; }
+};
+
+// Histories only: nothing is tallied.
+struct NullSink {
+    __device__ __forceinline__ void deposit(const Lane &, uint64_t) const {}
+    __device__ __forceinline__ bool inside(int32_t, int32_t, int32_t) const { return true; }
+};
+
+enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
+
+// One (packet, cell) segment. Returns kAlive, or the packet's fate, or kExit
+// when the next cell is outside the sink's region: the packet then stands on
+// the face with its pre-jump frequency and the old cell's velocity, and the
+// region that owns the new cell applies the jump (finish_entry).
+template <bool VEL, class Sink>
+__device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, const Sink &sink,
+                                         uint32_t max_cross, uint64_t &deposited)
+{
+    if (L.x <= -L.xeff) return kEscaped;            // redshifted out of the line
+    if (L.ncross >= max_cross) return kCapped;
+    ++L.ncross;
+
+    // next face (ties: x, then y, then z) and the neighbour behind it
+    int axis = 0;
+    double tn = L.tmx;
+    if (L.tmy < tn) { axis = 1; tn = L.tmy; }
+    if (L.tmz < tn) { axis = 2; tn = L.tmz; }
+    int32_t jx = L.ix, jy = L.iy, jz = L.iz;
+    if (axis == 0) jx = L.kx > 0.0f ? (jx + 1 == L.nx ? 0 : jx + 1) : (jx == 0 ? L.nx - 1 : jx - 1);
+    else if (axis == 1) jy = L.ky > 0.0f ? (jy + 1 == L.ny ? 0 : jy + 1) : (jy == 0 ? L.ny - 1 : jy - 1);
+    else jz = L.kz > 0.0f ? (jz + 1 == L.nz ? 0 : jz + 1) : (jz == 0 ? L.nz - 1 : jz - 1);
+    const uint32_t cn = L.coff + (uint32_t)jx + (uint32_t)L.nx * ((uint32_t)jy + (uint32_t)L.ny * (uint32_t)jz);
+    const bool stay = sink.inside(jx, jy, jz);
+    const Rec nr = load_rec<VEL>(rec, cn);           // in flight during the profile arithmetic
+
+    // Hubble drift across the segment; the last one stops at -x_eff
+    const float s = (float)(tn - L.t);
+    const float xo = fmaf(-L.delta, s, L.x);
+    const bool esc = xo <= -L.xeff;
+    const float dphi = swept_profile(L.x, esc ? L.x + L.xeff : L.delta * s);
+    const float pabs = one_minus_exp(L.kap * dphi);
+    uint64_t d = (uint64_t)rintf((float)L.w * pabs);
+    if (d > L.w) d = L.w;
+    L.w -= d;
+    deposited += d;
+    if (d) sink.deposit(L, d);
+    if (esc) return kEscaped;
+    if (L.w == 0) return kAbsorbed;
+
+    // cross the face
+    L.t = tn;
+    if (axis == 0) L.tmx += L.tdx;
+    else if (axis == 1) L.tmy += L.tdy;
+    else L.tmz += L.tdz;
+    L.ix = jx;
+    L.iy = jy;
+    L.iz = jz;
+    L.c = cn;
+    L.x = xo;
+    if (!stay) return kExit;
+    finish_entry<VEL>(L, nr);
+    return kAlive;
+}
+}  // namespace mclya

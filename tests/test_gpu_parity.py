@@ -128,8 +128,10 @@ def test_launch_configuration_and_ranges_bitwise():
     base = gpu_run(spec)
     variants = [
         {M.MC_LYA_OPT_KERNEL: 1},
+        {M.MC_LYA_OPT_KERNEL: 0},
         {M.MC_LYA_OPT_BLOCK: 64, M.MC_LYA_OPT_WAVES_PER_CU: 8},
-        {M.MC_LYA_OPT_CHUNK: 7, M.MC_LYA_OPT_REFILL: 1},
+        {M.MC_LYA_OPT_CHUNK: 7, M.MC_LYA_OPT_REFILL: 1, M.MC_LYA_OPT_QUEUES: 1},
+        {M.MC_LYA_OPT_QUEUES: 64, M.MC_LYA_OPT_CHUNK: 1},
         {M.MC_LYA_OPT_CHUNK: 4096, M.MC_LYA_OPT_REFILL: 64, M.MC_LYA_OPT_BLOCK: 128},
     ]
     for opt in variants:
@@ -259,3 +261,22 @@ def test_errors_and_cap():
         with pytest.raises(M.MCLyaError) as e:
             M.mc_lya_transport_range(sim.ctx, 900, 200)
         assert e.value.status == M.MC_LYA_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (9, 9, 9), (20, 33, 17), (48, 16, 40), (5, 70, 3)])
+def test_tiled_walk_equals_global_walk(shape):
+    """The tile-decomposed walk (LDS tallies, packets handed between tiles)
+    gives the same integers as the walk with device-wide atomics: tiles that
+    span an axis and wrap onto themselves, thin last tiles, two tiles along an
+    axis (one neighbour on both sides)."""
+    rng = np.random.default_rng(sum(shape))
+    od = rng.lognormal(0.0, 0.6, size=shape[::-1]).astype(np.float32)
+    vel = rng.normal(0.0, 0.15, size=(3,) + shape[::-1]).astype(np.float32)
+    spec = W.BoxSpec(n=shape, overdensity=od, velocity=vel, n_packets=60_000, seed=5)
+    ref = gpu_run(spec, options={M.MC_LYA_OPT_KERNEL: 0})
+    for opts in ({M.MC_LYA_OPT_KERNEL: 2}, ):
+        g = gpu_run(spec, options=opts)
+        assert np.array_equal(g["A"], ref["A"])
+        assert g["escaped"] == ref["escaped"] and g["crossings"] == ref["crossings"]
+    part = gpu_run(spec, options={M.MC_LYA_OPT_KERNEL: 2}, ranges=[(0, 17), (17, 31000), (31000, 60000)])
+    assert np.array_equal(part["A"], ref["A"])
