@@ -116,10 +116,12 @@ def main():
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
     kms, launches = sim.kernel_time()
-    per_launch_s = kms / 1e3 / max(launches, 1)
-    cross_per_launch = cross / a.steps
+    # the walk of one step may be several launches (one per tile generation):
+    # time and bytes are both taken per step
+    walk_s = kms / 1e3 / a.steps
+    cross_per_step = cross / a.steps
     bpc = BYTES_PER_CROSSING_VEL if spec.velocity is not None else BYTES_PER_CROSSING_NOVEL
-    achieved = bpc * cross_per_launch / per_launch_s / 1e9
+    achieved = bpc * cross_per_step / walk_s / 1e9
     traffic = None
     if os.path.exists(a.traffic):
         with open(a.traffic) as fh:
@@ -140,9 +142,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": spec.name, "cells": spec.ncells, "packets": spec.n_packets,
-                   "crossings_per_step": cross_per_launch,
-                   "walk_ms": per_launch_s * 1e3,
-                   "walk_crossings_per_s": cross_per_launch / per_launch_s,
+                   "crossings_per_step": cross_per_step,
+                   "walk_ms": walk_s * 1e3,
+                   "walk_launches_per_step": launches / a.steps,
+                   "walk_crossings_per_s": cross_per_step / walk_s,
                    "f_absorbed": f["stats"][0].f_absorbed, "c_mc": f["stats"][0].c_mc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},

@@ -74,7 +74,7 @@ typedef struct mc_lya_box_desc {
     double x_esc;                 /* red-wing escape threshold in Doppler widths (> 0) */
     double temp_K;                /* gas and radiation temperature, uniform in the box (> 0) */
     double h, omega_b_h2, omega_c_h2, y_p, t_cmb0, n_eff;   /* cosmology */
-    uint64_t w0;                  /* integer weight of one packet (> 0), e.g. 2^32 */
+    uint64_t w0;                  /* integer weight of one packet, 1 <= w0 < 2^32 (e.g. 2^31) */
     const float *overdensity;     /* dev [ncells]: Delta = rho_b / <rho_b>, finite, >= 0 */
     const void *velocity;         /* dev [3][ncells] (x, y, z components) in units of the
                                      thermal velocity sqrt(2kT/m_H), or NULL */
@@ -126,12 +126,17 @@ typedef struct mc_lya_packet_trace {
 /* Tunables for mc_lya_set_option (all results are independent of them, bit
  * for bit, except MC_LYA_OPT_MAX_CROSSINGS). */
 enum {
-    MC_LYA_OPT_KERNEL = 1,        /* 0 = persistent walk with wave refill (default),
-                                     1 = one thread per packet */
+    MC_LYA_OPT_KERNEL = 1,        /* 0 = persistent walk with wave refill and device
+                                     atomics, 1 = one thread per packet,
+                                     2 = tile-decomposed walk (default): 16^3-cell
+                                     tiles, tallies in LDS, packets handed between
+                                     tiles once per generation */
     MC_LYA_OPT_BLOCK = 2,         /* threads per workgroup: 64, 128 or 256 */
     MC_LYA_OPT_WAVES_PER_CU = 3,  /* resident waves per compute unit for the persistent grid */
-    MC_LYA_OPT_CHUNK = 4,         /* packets a wave takes from the queue at once (>= 1) */
-    MC_LYA_OPT_REFILL = 5,        /* refill a wave once this many lanes are idle (1..64) */
+    MC_LYA_OPT_CHUNK = 4,         /* packets a wave takes from the queue at once (>= 1;
+                                     the tiled walk uses min(chunk, 1024) per workgroup) */
+    MC_LYA_OPT_REFILL = 5,        /* refill a wave once this many lanes are idle (1..64;
+                                     kernels 0 and 2) */
     MC_LYA_OPT_MAX_CROSSINGS = 6, /* crossing cap per packet (>= 1, default 1e6) */
     MC_LYA_OPT_TIMING = 7,        /* 1 = time transport kernels with HIP events */
     MC_LYA_OPT_GRAPH = 8,         /* 1 = replay transport as a captured HIP graph */
@@ -169,7 +174,10 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *ctx, const uint64_t *seeds, const uint64_t
 
 /* Walks every emitted packet (App. A steps 1-4 and the red-wing exit) and
  * accumulates the per-cell absorbed weight and the per-box totals.
- * Asynchronous on the context's stream. Errors: ESTATE, EDEVICE. */
+ * Asynchronous on the context's stream, except that the tiled walk (kernel 2)
+ * reads one device counter back after every 16 generations to learn whether
+ * packets are still in flight (a stream synchronisation per 16 launches).
+ * Errors: ESTATE, EDEVICE. */
 mc_lya_status mc_lya_transport(mc_lya_ctx *ctx);
 
 /* As mc_lya_transport, for global packet ids [first, first + count) only.

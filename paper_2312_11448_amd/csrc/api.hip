@@ -118,16 +118,14 @@ struct mc_lya_ctx {
 
     // tile-decomposed walk
     std::vector<TileInfo> tiles;
-    std::vector<int4> box_tiles;
     TileInfo *d_tiles = nullptr;
-    int4 *d_box_tiles = nullptr;
-    uint32_t *d_tbase[2] = {nullptr, nullptr};
-    uint32_t *d_tcount[2] = {nullptr, nullptr};
+    TileExits *d_texits[2] = {nullptr, nullptr};
     PState *d_state[2] = {nullptr, nullptr};
-    uint32_t *d_dest[2] = {nullptr, nullptr};
-    unsigned long long *d_gen = nullptr;     // [0] bump allocator, [1] exits of the generation
+    uint8_t *d_face[2] = {nullptr, nullptr};
+    uint32_t *d_idx[2] = {nullptr, nullptr};
+    unsigned long long *d_gen = nullptr;     // per generation: bump allocator, exits
     uint64_t state_cap = 0;
-    int64_t generations = 0;                 // generations run by the last tiled transport
+    int64_t generations = 0;                 // generations launched by the last tiled transport
 
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
@@ -167,9 +165,8 @@ void free_all(mc_lya_ctx *c)
 {
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_tiles, c->d_box_tiles, c->d_tbase[0], c->d_tbase[1],
-                    c->d_tcount[0], c->d_tcount[1], c->d_state[0], c->d_state[1], c->d_dest[0],
-                    c->d_dest[1], c->d_gen};
+                    c->d_cop, c->d_pfirst, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &ev : c->events) {
@@ -195,7 +192,7 @@ std::string check_desc(const mc_lya_box_desc &d, int b)
     if (!(d.h > 0.0) || !(d.omega_b_h2 > 0.0) || !(d.omega_c_h2 >= 0.0) || !(d.y_p >= 0.0 && d.y_p < 1.0) ||
         !(d.t_cmb0 > 0.0) || !(d.n_eff >= 0.0))
         return bad("cosmological parameters out of range");
-    if (d.w0 == 0) return bad("w0 must be > 0");
+    if (d.w0 == 0 || d.w0 >= (1ull << 32)) return bad("w0 must be in [1, 2^32)");
     if (!d.overdensity) return bad("overdensity is NULL");
     if (d.vel_dtype != MC_LYA_VEL_NONE && d.vel_dtype != MC_LYA_VEL_F32 && d.vel_dtype != MC_LYA_VEL_F16)
         return bad("unknown vel_dtype");
@@ -241,17 +238,17 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
 }
 
 // Tiles of kTileEdge^3 cells per box (the last ones along an axis may be
-// thinner), with their distinct periodic face neighbours.
+// thinner). For each tile, the exit lists it pulls: for each of its six faces
+// whose neighbour is another tile, that neighbour's list through the
+// opposite face (a tile that spans an axis wraps onto itself there).
 void build_tiles(mc_lya_ctx *c)
 {
     const int TE = kTileEdge;
     c->tiles.clear();
-    c->box_tiles.clear();
     for (int b = 0; b < c->n_boxes; ++b) {
         const mc_lya_box_desc &d = c->desc[b];
         const int nt[3] = {(d.nx + TE - 1) / TE, (d.ny + TE - 1) / TE, (d.nz + TE - 1) / TE};
         const int off = (int)c->tiles.size();
-        c->box_tiles.push_back(make_int4(off, nt[0], nt[1], nt[2]));
         const int n[3] = {d.nx, d.ny, d.nz};
         for (int tz = 0; tz < nt[2]; ++tz)
             for (int ty = 0; ty < nt[1]; ++ty)
@@ -271,16 +268,16 @@ void build_tiles(mc_lya_ctx *c)
                     t.sx = e[0];
                     t.sy = e[1];
                     t.sz = e[2];
-                    const int self = off + tx + nt[0] * (ty + nt[1] * tz);
                     for (int a = 0; a < 3; ++a) {
-                        if (nt[a] == 1) continue;       // the tile spans the axis: wraps onto itself
+                        if (nt[a] == 1) continue;
                         for (int dir = -1; dir <= 1; dir += 2) {
                             int q[3] = {tx, ty, tz};
                             q[a] = (q[a] + dir + nt[a]) % nt[a];
-                            const int id = off + q[0] + nt[0] * (q[1] + nt[1] * q[2]);
-                            bool seen = id == self;
-                            for (int k = 0; k < t.nnbr; ++k) seen = seen || t.nbr[k] == id;
-                            if (!seen) t.nbr[t.nnbr++] = id;
+                            // the neighbour on side dir sends what leaves it through the opposite face
+                            const int face = 2 * a + (dir < 0 ? 1 : 0);
+                            t.src_tile[t.nsrc] = off + q[0] + nt[0] * (q[1] + nt[1] * q[2]);
+                            t.src_faces |= (uint32_t)face << (4 * t.nsrc);
+                            ++t.nsrc;
                         }
                     }
                     c->tiles.push_back(t);
@@ -289,6 +286,7 @@ void build_tiles(mc_lya_ctx *c)
 }
 
 constexpr uint64_t kTiledBatch = 1ull << 25;   // packets per tiled batch (state buffers of ~3.9 GB)
+constexpr int kGenRound = 16;                  // generations queued between two checks
 
 mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
 {
@@ -297,14 +295,17 @@ mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < 2; ++i) {
         if (c->d_state[i]) (void)hipFree(c->d_state[i]);
-        if (c->d_dest[i]) (void)hipFree(c->d_dest[i]);
+        if (c->d_face[i]) (void)hipFree(c->d_face[i]);
+        if (c->d_idx[i]) (void)hipFree(c->d_idx[i]);
         c->d_state[i] = nullptr;
-        c->d_dest[i] = nullptr;
+        c->d_face[i] = nullptr;
+        c->d_idx[i] = nullptr;
     }
     c->state_cap = 0;
     for (int i = 0; i < 2; ++i) {
         HIP_TRY(c, dalloc(&c->d_state[i], cap));
-        HIP_TRY(c, dalloc(&c->d_dest[i], cap));
+        HIP_TRY(c, dalloc(&c->d_face[i], cap));
+        HIP_TRY(c, dalloc(&c->d_idx[i], cap));
     }
     c->state_cap = cap;
     return MC_LYA_OK;
@@ -326,50 +327,57 @@ mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
     return MC_LYA_OK;
 }
 
+// Generations are queued in rounds without waiting; a generation whose
+// predecessor moved nothing returns at once. After each round the host reads
+// the last generation's exit count: zero means every packet has finished.
 mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
 {
     TileParams p;
     std::memset(&p, 0, sizeof p);
     p.boxes = c->d_walk;
     p.tiles = c->d_tiles;
-    p.box_tiles = c->d_box_tiles;
     p.rec = c->d_rec;
     p.npk = c->d_npk;
     p.pfirst = c->d_pfirst;
     p.A = c->d_A;
     p.tot = c->d_tot;
-    p.bump = c->d_gen;
-    p.exits = c->d_gen + 1;
     p.max_cross = (uint32_t)c->max_cross;
     p.ntiles = (int)c->tiles.size();
-    p.chunk = 64;
+    p.chunk = std::min(c->chunk, 1024);
+    p.refill = c->refill;
     c->generations = 0;
     for (uint64_t done = 0; done < count;) {
         const uint64_t n = std::min(count - done, c->state_cap);
         p.first = first + done;
         p.count = n;
-        int cur = 0;
-        for (int64_t gen = 0;; ++gen) {
-            p.in_state = c->d_state[cur ^ 1];
-            p.in_dest = c->d_dest[cur ^ 1];
-            p.in_base = c->d_tbase[cur ^ 1];
-            p.in_count = c->d_tcount[cur ^ 1];
-            p.out_state = c->d_state[cur];
-            p.out_dest = c->d_dest[cur];
-            p.out_base = c->d_tbase[cur];
-            p.out_count = c->d_tcount[cur];
-            hipEvent_t e1;
-            mc_lya_status st = timed_begin(c, &e1);
-            if (st != MC_LYA_OK) return st;
-            HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->stream));
-            if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
-            ++c->generations;
+        HIP_TRY(c, launch_zero_counters(c->d_gen, 2 * kMaxGenerations, c->stream));
+        int gen = 0;
+        for (;;) {
+            for (int r = 0; r < kGenRound && gen < kMaxGenerations; ++r, ++gen) {
+                const int cur = gen & 1, prev = cur ^ 1;
+                p.in_state = c->d_state[prev];
+                p.in_idx = c->d_idx[prev];
+                p.in_exits = c->d_texits[prev];
+                p.out_state = c->d_state[cur];
+                p.out_face = c->d_face[cur];
+                p.out_idx = c->d_idx[cur];
+                p.out_exits = c->d_texits[cur];
+                p.bump = c->d_gen + 2 * gen;
+                p.exits = c->d_gen + 2 * gen + 1;
+                p.prev_exits = gen > 0 ? c->d_gen + 2 * (gen - 1) + 1 : c->d_gen + 1;
+                hipEvent_t e1;
+                mc_lya_status st = timed_begin(c, &e1);
+                if (st != MC_LYA_OK) return st;
+                HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->stream));
+                if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+                ++c->generations;
+            }
             unsigned long long exits = 0;
-            HIP_TRY(c, hipMemcpyAsync(&exits, c->d_gen + 1, sizeof exits, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(&exits, c->d_gen + 2 * (gen - 1) + 1, sizeof exits, hipMemcpyDeviceToHost,
+                                      c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             if (exits == 0) break;
-            if (gen > c->max_cross) return fail(c, MC_LYA_EDEVICE, "tiled walk did not drain");
-            cur ^= 1;
+            if (gen >= kMaxGenerations) return fail(c, MC_LYA_EDEVICE, "tiled walk did not drain");
         }
         done += n;
     }
@@ -544,19 +552,13 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
     build_tiles(c);
     const size_t nt = c->tiles.size();
-    if ((e = dalloc(&c->d_tiles, nt)) != hipSuccess || (e = dalloc(&c->d_box_tiles, (size_t)n_boxes)) != hipSuccess ||
-        (e = dalloc(&c->d_tbase[0], nt)) != hipSuccess || (e = dalloc(&c->d_tbase[1], nt)) != hipSuccess ||
-        (e = dalloc(&c->d_tcount[0], nt)) != hipSuccess || (e = dalloc(&c->d_tcount[1], nt)) != hipSuccess ||
-        (e = dalloc(&c->d_gen, 2)) != hipSuccess)
+    if ((e = dalloc(&c->d_tiles, nt)) != hipSuccess || (e = dalloc(&c->d_texits[0], nt)) != hipSuccess ||
+        (e = dalloc(&c->d_texits[1], nt)) != hipSuccess || (e = dalloc(&c->d_gen, 2 * kMaxGenerations)) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
-    if (hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(TileInfo) * nt, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->d_box_tiles, c->box_tiles.data(), sizeof(int4) * n_boxes, hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess ||
-        hipMemsetAsync(c->d_tcount[0], 0, sizeof(uint32_t) * nt, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->d_tcount[1], 0, sizeof(uint32_t) * nt, c->stream) != hipSuccess)
-        return cleanup(MC_LYA_EDEVICE);
-    if (hipMemcpyAsync(c->d_pack, c->pack.data(), sizeof(PackBox) * n_boxes, hipMemcpyHostToDevice, c->stream) !=
-        hipSuccess)
+    if (hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(TileInfo) * nt, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->d_pack, c->pack.data(), sizeof(PackBox) * n_boxes, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess)
         return cleanup(MC_LYA_EDEVICE);
     mc_lya_status s = do_refresh(c);
     if (s != MC_LYA_OK) return cleanup(s);

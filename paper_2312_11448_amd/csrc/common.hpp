@@ -138,16 +138,18 @@ struct TileInfo {
     int32_t box;
     int32_t ox, oy, oz;      // origin (cell coordinates in the box)
     int32_t sx, sy, sz;      // extent (cells)
-    int32_t nnbr;            // distinct face-neighbour tiles other than itself (0..6)
-    int32_t nbr[6];
-    int32_t pad[2];
+    int32_t nsrc;            // exit lists this tile pulls from (0..6)
+    int32_t src_tile[6];     // tile whose exits through face src_face[k] enter this tile
+    uint32_t src_faces;      // 4 bits per source: the face (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z)
+    int32_t pad;
 };
 static_assert(sizeof(TileInfo) == 64, "TileInfo layout");
 
 // A packet standing on the face between two tiles (112 bytes).
 struct alignas(16) PState {
     double tmx, tmy, tmz, tdx, tdy, tdz, t;
-    uint64_t w;
+    uint32_t w;
+    uint32_t pad;
     float x, kx, ky, kz;     // pre-jump frequency and direction
     float ux, uy, uz;        // velocity of the cell it leaves
     uint32_t cell;           // cell it enters (global)
@@ -156,29 +158,42 @@ struct alignas(16) PState {
 };
 static_assert(sizeof(PState) == 112, "PState layout");
 
+// Exit lists of one tile in one generation: states in [base, base + off[6]),
+// and the states that left through face f are idx[base + off[f] .. base + off[f+1]).
+struct TileExits {
+    uint32_t base;
+    uint32_t off[7];
+};
+
+constexpr int kMaxGenerations = 4096;  // per transport batch (packets cross at most one tile per generation)
+
 struct TileParams {
     const WalkBox *boxes;
     const TileInfo *tiles;
-    const int4 *box_tiles;   // per box: first tile, tiles along x, y, z
     const void *rec;
     const uint32_t *npk;     // packets per cell
     const uint64_t *pfirst;  // global id of each cell's first packet
     unsigned long long *A;
     BoxTot *tot;
     const PState *in_state;
-    const uint32_t *in_dest, *in_base, *in_count;
+    const uint32_t *in_idx;
+    const TileExits *in_exits;
     PState *out_state;
-    uint32_t *out_dest, *out_base, *out_count;
-    unsigned long long *bump;    // allocator of the exit buffer
+    uint8_t *out_face;
+    uint32_t *out_idx;
+    TileExits *out_exits;
+    unsigned long long *bump;    // allocator of this generation's exit buffer
     unsigned long long *exits;   // packets written out this generation
+    const unsigned long long *prev_exits;   // packets written out by the previous generation
     uint64_t first, count;   // packet range
     uint32_t max_cross;
     int32_t ntiles;
     int32_t chunk;
-    int32_t pad;
+    int32_t refill;          // refill a wave once this many lanes are idle
 };
 
 hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s);
+hipError_t launch_zero_counters(unsigned long long *c, int n, hipStream_t s);
 
 hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s);
 hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s);

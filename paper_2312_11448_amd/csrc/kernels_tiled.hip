@@ -8,8 +8,9 @@
 // atomics), and at the end adds that tally to the device tallies with plain
 // read-modify-write (no other workgroup touches the tile's cells in that
 // generation). A packet that leaves the tile is written, standing on the face
-// with its pre-jump frequency, to the tile's exit region; in the next
-// generation the neighbouring tile pulls it and applies the face jump.
+// with its pre-jump frequency, to the tile's exit region, and the region is
+// indexed by face; in the next generation each tile pulls exactly the face
+// lists that point at it and applies the face jump.
 //
 // The per-packet arithmetic is walk_core's, so the integer tallies are the
 // same bits as those of the other drivers.
@@ -20,21 +21,45 @@ namespace {
 
 constexpr int TE = kTileEdge;
 constexpr int TC = TE * TE * TE;
-constexpr int BLK = 256;
+constexpr int BLK = 1024;          // 16 waves per tile
 constexpr int kWaves = BLK / 64;
 
+// Deposits and opacity/velocity records of the cells of one tile, both in LDS.
+template <bool VEL>
 struct TileSink {
-    unsigned long long *tally;   // LDS, one entry per cell of the tile
+    unsigned long long *tally;
+    const float4 *rec4;          // VEL: (kappa, U) per cell
+    const float *reck;           // !VEL: kappa per cell
     int32_t ox, oy, oz, sx, sy, sz;
+    __device__ __forceinline__ int local(int32_t ix, int32_t iy, int32_t iz) const
+    {
+        return (ix - ox) + sx * ((iy - oy) + sy * (iz - oz));
+    }
     __device__ __forceinline__ bool inside(int32_t jx, int32_t jy, int32_t jz) const
     {
-        return (uint32_t)(jx - ox) < (uint32_t)sx && (uint32_t)(jy - oy) < (uint32_t)sy &&
-               (uint32_t)(jz - oz) < (uint32_t)sz;
+        return ((uint32_t)(jx - ox) < (uint32_t)sx) & ((uint32_t)(jy - oy) < (uint32_t)sy) &
+               ((uint32_t)(jz - oz) < (uint32_t)sz);
     }
-    __device__ __forceinline__ void deposit(const Lane &L, uint64_t d) const
+    __device__ __forceinline__ void deposit(const Lane &L, uint32_t d) const
     {
-        const int lc = (L.ix - ox) + sx * ((L.iy - oy) + sy * (L.iz - oz));
-        atomicAdd(&tally[lc], (unsigned long long)d);
+        atomicAdd(&tally[local(L.ix, L.iy, L.iz)], (unsigned long long)d);
+    }
+    template <bool V>
+    __device__ __forceinline__ Rec fetch(const void *, uint32_t, int32_t jx, int32_t jy, int32_t jz, bool stay) const
+    {
+        Rec r;
+        const int lc = stay ? local(jx, jy, jz) : 0;    // leaving: the record is not used
+        if (V) {
+            const float4 v = rec4[lc];
+            r.kap = v.x;
+            r.ux = v.y;
+            r.uy = v.z;
+            r.uz = v.w;
+        } else {
+            r.kap = reck[lc];
+            r.ux = r.uy = r.uz = 0.0f;
+        }
+        return r;
     }
 };
 
@@ -108,23 +133,27 @@ __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkB
 }
 
 // One generation. GEN0: the tile's input is the packets emitted in its cells
-// (within the requested packet range); otherwise it is the packets its face
-// neighbours wrote out in the previous generation with this tile as target.
+// (within the requested packet range); otherwise it is the face lists of the
+// previous generation that point at this tile.
 template <bool VEL, bool GEN0>
 __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
 {
     __shared__ unsigned long long tally[TC];
-    __shared__ uint32_t pre[GEN0 ? TC + 1 : 8];   // GEN0: cell prefix of packet counts; else region prefix
-    __shared__ uint32_t src[8];                    // region bases (previous generation)
-    __shared__ uint32_t s_tsum[BLK];
+    __shared__ float4 srec4[VEL ? TC : 1];
+    __shared__ float sreck[VEL ? 1 : TC];
+    __shared__ uint32_t pre[GEN0 ? TC + 1 : 8];   // GEN0: cell prefix of packet counts; else list prefix
+    __shared__ uint32_t lst[8];                    // pull: first index of each source list
+    __shared__ uint32_t s_tsum[kWaves];
     __shared__ uint32_t s_next, s_exit, s_total, s_base;
+    __shared__ uint32_t s_fcnt[8], s_fcur[8];
     __shared__ unsigned long long s_red[kWaves][4];
 
     const int T = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (!GEN0 && *P.prev_exits == 0) return;       // the walk has drained: nothing moves any more
     const TileInfo ti = P.tiles[T];
     const WalkBox B = P.boxes[ti.box];
     const int ncell = ti.sx * ti.sy * ti.sz;
-    const int tid = threadIdx.x;
     const uint32_t lane = __lane_id();
     const uint64_t r_lo = P.first, r_hi = P.first + P.count;
 
@@ -152,19 +181,26 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             cnt[k] = c;
             sum += c;
         }
-        s_tsum[tid] = sum;
+        // block exclusive scan of the per-thread sums
+        uint32_t inc = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if ((int)lane >= off) inc += o;
+        }
+        if (lane == 63) s_tsum[tid >> 6] = inc;
         __syncthreads();
         if (tid == 0) {
             uint32_t run = 0;
-            for (int i = 0; i < BLK; ++i) {
-                const uint32_t v = s_tsum[i];
-                s_tsum[i] = run;
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t v = s_tsum[w];
+                s_tsum[w] = run;
                 run += v;
             }
             s_total = run;
         }
         __syncthreads();
-        uint32_t run = s_tsum[tid];
+        uint32_t run = s_tsum[tid >> 6] + inc - sum;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int lc = tid * PER + k;
@@ -172,68 +208,61 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             run += cnt[k];
         }
         if (tid == 0) pre[ncell] = s_total;
-        n_in = s_total;
     } else {
         if (tid == 0) {
             uint32_t run = 0;
-            const int32_t *nbr = P.tiles[T].nbr;
-            for (int k = 0; k < ti.nnbr; ++k) {
+            const int32_t *src = P.tiles[T].src_tile;
+            for (int k = 0; k < ti.nsrc; ++k) {
+                const int f = (int)((ti.src_faces >> (4 * k)) & 15u);
+                const TileExits &e = P.in_exits[src[k]];
                 pre[k] = run;
-                src[k] = P.in_base[nbr[k]];
-                run += P.in_count[nbr[k]];
+                lst[k] = e.base + e.off[f];
+                run += e.off[f + 1] - e.off[f];
             }
-            pre[ti.nnbr] = run;
+            pre[ti.nsrc] = run;
             s_total = run;
         }
         __syncthreads();
-        n_in = s_total;
     }
-    // packets this tile will take: all of n_in for GEN0, the matching entries otherwise
-    uint32_t n_pk = n_in;
-    if (!GEN0) {
-        uint32_t m = 0;
-        for (uint32_t j = tid; j < n_in; j += BLK) {
-            int k = 0;
-            while (k + 1 < ti.nnbr && pre[k + 1] <= j) ++k;
-            m += P.in_dest[src[k] + (j - pre[k])] == (uint32_t)T ? 1u : 0u;
-        }
-        m = wave_sum(m);
-        __syncthreads();
-        if (lane == 0) s_tsum[tid >> 6] = m;
-        __syncthreads();
+    n_in = s_total;
+    if (n_in == 0) {
         if (tid == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kWaves; ++w) t += s_tsum[w];
-            s_total = t;
-        }
-        __syncthreads();
-        n_pk = s_total;
-    }
-    if (n_pk == 0) {
-        if (tid == 0) {
-            P.out_base[T] = 0;
-            P.out_count[T] = 0;
+            TileExits e;
+            e.base = 0;
+            for (int f = 0; f < 7; ++f) e.off[f] = 0;
+            P.out_exits[T] = e;
         }
         return;
     }
-    for (int lc = tid; lc < ncell; lc += BLK) tally[lc] = 0ull;
+    for (int lc = tid; lc < ncell; lc += BLK) {
+        tally[lc] = 0ull;
+        const int lx = lc % ti.sx, ly = (lc / ti.sx) % ti.sy, lz = lc / (ti.sx * ti.sy);
+        const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                            (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+        if (VEL) srec4[lc] = static_cast<const float4 *>(P.rec)[gc];
+        else sreck[lc] = static_cast<const float *>(P.rec)[gc];
+    }
     if (tid == 0) {
         s_next = 0;
         s_exit = 0;
-        s_base = (uint32_t)atomicAdd(P.bump, (unsigned long long)n_pk);
+        s_base = (uint32_t)atomicAdd(P.bump, (unsigned long long)n_in);
     }
+    if (tid < 8) s_fcnt[tid] = 0;
     __syncthreads();
 
     // ---- walk -------------------------------------------------------------
-    const TileSink sink{tally, ti.ox, ti.oy, ti.oz, ti.sx, ti.sy, ti.sz};
-    const int4 bt = P.box_tiles[ti.box];          // tile offset and tile counts of the box
+    const TileSink<VEL> sink{tally, srec4, sreck, ti.ox, ti.oy, ti.oz, ti.sx, ti.sy, ti.sz};
     Lane L;
     bool alive = false, more = true;
     uint32_t cur = 0, end = 0;
     uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0;
     const uint32_t chunk = (uint32_t)P.chunk;
+    const uint32_t refill = (uint32_t)P.refill;
     for (;;) {
         uint64_t idle = __ballot(!alive);
+        // refilling stalls the whole wave on the new packets' loads: wait until
+        // enough lanes are idle (or all are)
+        if ((uint32_t)__popcll(idle) < refill && idle != ~0ull) idle = 0;
         while (idle && more) {
             if (cur >= end) {
                 uint32_t base = 0;
@@ -262,17 +291,14 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
                     const uint64_t pf = P.pfirst[gc];
                     const uint64_t gp = (pf > r_lo ? pf : r_lo) + (j - pre[lo]);
                     init_packet<VEL>(L, B, gp - B.pkt_off, gc, P.rec);
-                    alive = true;
                 } else {
                     int k = 0;
-                    while (k + 1 < ti.nnbr && pre[k + 1] <= j) ++k;
-                    const uint32_t g = src[k] + (j - pre[k]);
-                    if (P.in_dest[g] == (uint32_t)T) {
-                        load_state(L, P.in_state[g], B);
-                        finish_entry<VEL>(L, load_rec<VEL>(P.rec, L.c));
-                        alive = true;
-                    }
+                    while (k + 1 < ti.nsrc && pre[k + 1] <= j) ++k;
+                    const uint32_t g = P.in_idx[lst[k] + (j - pre[k])];
+                    load_state(L, P.in_state[g], B);
+                    finish_entry<VEL>(L, sink.template fetch<VEL>(P.rec, L.c, L.ix, L.iy, L.iz, true));
                 }
+                alive = true;
             }
             cur += take;
             idle = __ballot(!alive);
@@ -288,8 +314,13 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
                 const uint32_t slot = atomicAdd(&s_exit, 1u);
                 const uint32_t g = s_base + slot;
                 save_state(P.out_state[g], L);
-                const int32_t tx = L.ix / TE, ty = L.iy / TE, tz = L.iz / TE;
-                P.out_dest[g] = (uint32_t)bt.x + (uint32_t)tx + (uint32_t)bt.y * ((uint32_t)ty + (uint32_t)bt.z * (uint32_t)tz);
+                // the face it left through: the one coordinate now outside the tile
+                uint32_t f;
+                if ((uint32_t)(L.ix - ti.ox) >= (uint32_t)ti.sx) f = L.kx > 0.0f ? 1u : 0u;
+                else if ((uint32_t)(L.iy - ti.oy) >= (uint32_t)ti.sy) f = L.ky > 0.0f ? 3u : 2u;
+                else f = L.kz > 0.0f ? 5u : 4u;
+                P.out_face[g] = (uint8_t)f;
+                atomicAdd(&s_fcnt[f], 1u);
                 alive = false;
             } else if (fate != kAlive) {
                 a_cross += L.ncross;
@@ -301,7 +332,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
     }
 
-    // ---- finish: tally, totals, exits --------------------------------------
+    // ---- finish: tally, totals, face lists of the exits ----------------------
     a_esc = wave_sum(a_esc);
     a_cross = wave_sum(a_cross);
     a_capn = wave_sum(a_capn);
@@ -312,6 +343,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         s_red[tid >> 6][2] = a_capn;
         s_red[tid >> 6][3] = a_capw;
     }
+    __threadfence_block();
     __syncthreads();
     for (int lc = tid; lc < ncell; lc += BLK) {
         const unsigned long long v = tally[lc];
@@ -333,24 +365,38 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             atomicAdd(dst, t);
         }
     }
+    const uint32_t n_exit = s_exit;
     if (tid == 0) {
-        P.out_base[T] = s_base;
-        P.out_count[T] = s_exit;
-        if (s_exit) atomicAdd(P.exits, (unsigned long long)s_exit);
+        TileExits e;
+        e.base = s_base;
+        uint32_t run = 0;
+        for (int f = 0; f < 6; ++f) {
+            e.off[f] = run;
+            s_fcur[f] = run;
+            run += s_fcnt[f];
+        }
+        e.off[6] = run;
+        P.out_exits[T] = e;
+        if (n_exit) atomicAdd(P.exits, (unsigned long long)n_exit);
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < n_exit; k += BLK) {
+        const uint32_t g = s_base + k;
+        const uint32_t pos = atomicAdd(&s_fcur[P.out_face[g]], 1u);
+        P.out_idx[s_base + pos] = g;
     }
 }
 
-__global__ void reset_counters_kernel(unsigned long long *a, unsigned long long *b)
+__global__ void zero_counters_kernel(unsigned long long *c, int n)
 {
-    *a = 0ull;
-    *b = 0ull;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0ull;
 }
 
 }  // namespace
 
 hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(1), 0, s, p.bump, p.exits);
     const dim3 grid((unsigned)p.ntiles), block(BLK);
     if (gen0) {
         if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, true>), grid, block, 0, s, p);
@@ -359,6 +405,12 @@ hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipS
         if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, false>), grid, block, 0, s, p);
         else hipLaunchKernelGGL((tile_walk_kernel<false, false>), grid, block, 0, s, p);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(unsigned long long *c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_counters_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, n);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ struct Lane {
     float x;             // gas-frame frequency, Doppler widths
     float kap;           // kappa of the current cell
     float ux, uy, uz;    // bulk velocity of the current cell (Doppler units)
-    uint64_t w;          // remaining weight
+    uint32_t w;          // remaining weight (w0 < 2^32)
     uint32_t ncross;
     int32_t nx, ny, nz;
     uint32_t coff;
@@ -99,7 +99,7 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
     L.ky = (float)ky;
     L.kz = (float)kz;
     L.x = sqrtf(-logf(u01(b[1]))) * cospif(2.0f * u01(b[2]));
-    L.w = B.w0;
+    L.w = (uint32_t)B.w0;
     L.ncross = 0;
     const Rec r = load_rec<VEL>(rec, gcell);
     L.kap = r.kap;
@@ -136,13 +136,21 @@ __device__ __forceinline__ float swept_profile(float x, float dx)
     return fmaxf(d, 0.0f);
 }
 
-// 1 - exp(-tau) for tau >= 0 without cancellation.
+// 1 - exp(-tau) for tau >= 0 without cancellation (series below 0.1).
 __device__ __forceinline__ float one_minus_exp(float tau)
 {
-    if (tau < 0.1f)
-        return tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f -
-                                                 tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
-    return 1.0f - __expf(-tau);
+    const float series = tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f -
+                                              tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
+    const float direct = 1.0f - __expf(-tau);
+    return tau < 0.1f ? series : direct;
+}
+
+// k . (U_new - U_old) in thermal units: the frequency shift of Eq. (inout)
+// at a face. One expression, shared by every place that applies the jump, so
+// that the rounding is the same wherever the face is crossed.
+__device__ __forceinline__ float bulk_jump(const Lane &L, const Rec &nr)
+{
+    return L.kx * (nr.ux - L.ux) + L.ky * (nr.uy - L.uy) + L.kz * (nr.uz - L.uz);
 }
 
 // Entering a cell: the bulk term of Eq. (inout), x_new = x_old - k.(U_new -
@@ -151,8 +159,7 @@ template <bool VEL>
 __device__ __forceinline__ void finish_entry(Lane &L, const Rec &nr)
 {
     if (VEL) {
-        const float du = L.kx * (nr.ux - L.ux) + L.ky * (nr.uy - L.uy) + L.kz * (nr.uz - L.uz);
-        L.x = L.x - du;
+        L.x = L.x - bulk_jump(L, nr);
         L.ux = nr.ux;
         L.uy = nr.uy;
         L.uz = nr.uz;
@@ -163,17 +170,29 @@ __device__ __forceinline__ void finish_entry(Lane &L, const Rec &nr)
 // Deposits go straight to the per-cell int64 tallies in device memory.
 struct GlobalSink {
     unsigned long long *A;
-    __device__ __forceinline__ void deposit(const Lane &L, uint64_t d) const
+    __device__ __forceinline__ void deposit(const Lane &L, uint32_t d) const
     {
         atomicAdd(&A[L.c], (unsigned long long)d);
     }
     __device__ __forceinline__ bool inside(int32_t, int32_t, int32_t) const { return true; }
+    template <bool VEL>
+    __device__ __forceinline__ Rec fetch(const void *__restrict__ rec, uint32_t cn, int32_t, int32_t, int32_t,
+                                         bool) const
+    {
+        return load_rec<VEL>(rec, cn);
+    }
 };
 
 // Histories only: nothing is tallied.
 struct NullSink {
-    __device__ __forceinline__ void deposit(const Lane &, uint64_t) const {}
+    __device__ __forceinline__ void deposit(const Lane &, uint32_t) const {}
     __device__ __forceinline__ bool inside(int32_t, int32_t, int32_t) const { return true; }
+    template <bool VEL>
+    __device__ __forceinline__ Rec fetch(const void *__restrict__ rec, uint32_t cn, int32_t, int32_t, int32_t,
+                                         bool) const
+    {
+        return load_rec<VEL>(rec, cn);
+    }
 };
 
 enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
@@ -182,26 +201,38 @@ enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
 // when the next cell is outside the sink's region: the packet then stands on
 // the face with its pre-jump frequency and the old cell's velocity, and the
 // region that owns the new cell applies the jump (finish_entry).
+//
+// Written as straight-line code with one exit: the fate is a value, the
+// deposit is predicated, and the state always advances to the next cell
+// (harmless for a packet that has finished, whose weight and crossing count
+// are left as they were). Early returns would make the compiler copy the
+// whole lane state on every path.
 template <bool VEL, class Sink>
 __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, const Sink &sink,
                                          uint32_t max_cross, uint64_t &deposited)
 {
-    if (L.x <= -L.xeff) return kEscaped;            // redshifted out of the line
-    if (L.ncross >= max_cross) return kCapped;
-    ++L.ncross;
+    const bool gone = L.x <= -L.xeff;                     // redshifted out of the line
+    const bool capped = !gone && L.ncross >= max_cross;
+    const bool walk = !gone && !capped;
 
     // next face (ties: x, then y, then z) and the neighbour behind it
-    int axis = 0;
-    double tn = L.tmx;
-    if (L.tmy < tn) { axis = 1; tn = L.tmy; }
-    if (L.tmz < tn) { axis = 2; tn = L.tmz; }
-    int32_t jx = L.ix, jy = L.iy, jz = L.iz;
-    if (axis == 0) jx = L.kx > 0.0f ? (jx + 1 == L.nx ? 0 : jx + 1) : (jx == 0 ? L.nx - 1 : jx - 1);
-    else if (axis == 1) jy = L.ky > 0.0f ? (jy + 1 == L.ny ? 0 : jy + 1) : (jy == 0 ? L.ny - 1 : jy - 1);
-    else jz = L.kz > 0.0f ? (jz + 1 == L.nz ? 0 : jz + 1) : (jz == 0 ? L.nz - 1 : jz - 1);
+    const bool bx = L.tmx <= L.tmy && L.tmx <= L.tmz;
+    const bool by = !bx && L.tmy <= L.tmz;
+    const bool bz = !bx && !by;
+    const double tn = fmin(fmin(L.tmx, L.tmy), L.tmz);   // (a value, not a choice of field)
+    // only the coordinate on the chosen axis moves, by one cell (periodic);
+    // sums of field-or-zero terms: a choice between fields would make the
+    // compiler address the lane state in memory
+    const int32_t ci = (bx ? L.ix : 0) + (by ? L.iy : 0) + (bz ? L.iz : 0);
+    const int32_t ni = (bx ? L.nx : 0) + (by ? L.ny : 0) + (bz ? L.nz : 0);
+    const bool up = (bx & (L.kx > 0.0f)) | (by & (L.ky > 0.0f)) | (bz & (L.kz > 0.0f));
+    int32_t mi = ci + (up ? 1 : -1);
+    mi = mi == ni ? 0 : mi;
+    mi = mi < 0 ? ni - 1 : mi;
+    const int32_t jx = bx ? mi : L.ix, jy = by ? mi : L.iy, jz = bz ? mi : L.iz;
     const uint32_t cn = L.coff + (uint32_t)jx + (uint32_t)L.nx * ((uint32_t)jy + (uint32_t)L.ny * (uint32_t)jz);
     const bool stay = sink.inside(jx, jy, jz);
-    const Rec nr = load_rec<VEL>(rec, cn);           // in flight during the profile arithmetic
+    const Rec nr = sink.template fetch<VEL>(rec, cn, jx, jy, jz, stay);   // in flight during the profile arithmetic
 
     // Hubble drift across the segment; the last one stops at -x_eff
     const float s = (float)(tn - L.t);
@@ -209,26 +240,38 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     const bool esc = xo <= -L.xeff;
     const float dphi = swept_profile(L.x, esc ? L.x + L.xeff : L.delta * s);
     const float pabs = one_minus_exp(L.kap * dphi);
-    uint64_t d = (uint64_t)rintf((float)L.w * pabs);
-    if (d > L.w) d = L.w;
+    const uint32_t d = walk ? min((uint32_t)rintf((float)L.w * pabs), L.w) : 0u;
+    if (d) sink.deposit(L, d);
     L.w -= d;
     deposited += d;
-    if (d) sink.deposit(L, d);
-    if (esc) return kEscaped;
-    if (L.w == 0) return kAbsorbed;
+    L.ncross += walk ? 1u : 0u;
+    const int fate = gone ? kEscaped
+                   : capped ? kCapped
+                   : esc ? kEscaped
+                   : L.w == 0 ? kAbsorbed
+                   : stay ? kAlive : kExit;
 
     // cross the face
     L.t = tn;
-    if (axis == 0) L.tmx += L.tdx;
-    else if (axis == 1) L.tmy += L.tdy;
-    else L.tmz += L.tdz;
+    L.tmx = bx ? L.tmx + L.tdx : L.tmx;
+    L.tmy = by ? L.tmy + L.tdy : L.tmy;
+    L.tmz = bz ? L.tmz + L.tdz : L.tmz;
     L.ix = jx;
     L.iy = jy;
     L.iz = jz;
     L.c = cn;
-    L.x = xo;
-    if (!stay) return kExit;
-    finish_entry<VEL>(L, nr);
-    return kAlive;
+    // entering a cell owned by the same region: the bulk term of Eq. (inout)
+    // and the new cell's opacity; leaving it: keep the pre-jump frequency
+    if (VEL) {
+        L.x = stay ? xo - bulk_jump(L, nr) : xo;
+        L.ux = stay ? nr.ux : L.ux;
+        L.uy = stay ? nr.uy : L.uy;
+        L.uz = stay ? nr.uz : L.uz;
+    } else {
+        L.x = xo;
+    }
+    L.kap = stay ? nr.kap : L.kap;
+    return fate;
 }
+
 }  // namespace mclya

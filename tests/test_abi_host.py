@@ -51,14 +51,14 @@ def test_status_strings():
 def _desc(M, **kw):
     d = dict(nx=4, ny=4, nz=4, vel_dtype=0, cell_comoving_cm=2.9e20, z=1100.0, zeta=1.0,
              x_esc=6.0, temp_K=3000.0, h=0.67, omega_b_h2=0.0224, omega_c_h2=0.12, y_p=0.24,
-             t_cmb0=2.7255, n_eff=3.046, w0=1 << 32, overdensity=0x1000, velocity=None,
+             t_cmb0=2.7255, n_eff=3.046, w0=1 << 31, overdensity=0x1000, velocity=None,
              x_e=None, x_e_uniform=0.1, reserved=0, source=None)
     d.update(kw)
     return M.mc_lya_box_desc(**d)
 
 
 @pytest.mark.parametrize("bad,msg", [(dict(nx=0), "grid"), (dict(z=-1.0), "z must"),
-                                     (dict(zeta=0.0), "zeta"), (dict(w0=0), "w0"),
+                                     (dict(zeta=0.0), "zeta"), (dict(w0=0), "w0"), (dict(w0=1 << 32), "w0"),
                                      (dict(overdensity=None), "overdensity"),
                                      (dict(vel_dtype=1), "velocity"),
                                      (dict(x_e_uniform=1.5), "x_e_uniform"),

@@ -213,7 +213,7 @@ def test_escape_margin_is_final():
     for p in range(64):
         t = prep.trace(p)
         rec = t["record"]
-        esc_orc = (rec["escaped"] if rec["fate"] == 1 else 0) / W0
+        esc_orc = (rec["escaped"] if rec["fate"] == 1 else 0) / prep.w0
         dep, esc = brute.march(rec, prep.kappa, v, (n, n, n), prep.scal["delta"],
                                prep.x_eff + 8.0, 2e-4)
         worst = max(worst, abs(esc - esc_orc))

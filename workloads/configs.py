@@ -41,7 +41,7 @@ class BoxSpec:
     zeta: float = 1.0
     x_esc: float = 6.0
     cell_cm: float = DEFAULT_CELL_CM
-    w0: int = 1 << 32
+    w0: int = 1 << 31
     cosmo: CosmoParams = field(default_factory=CosmoParams)
     n_packets: int = 0
     seed: int = 1
