@@ -114,6 +114,7 @@ struct mc_lya_ctx {
     FeedBox *d_feed = nullptr;
     uint32_t *d_cop = nullptr;
     uint64_t cop_cap = 0;
+    bool cop_valid = false;      // d_cop holds the cells of the current emission
     uint64_t *d_pfirst = nullptr;
 
     // tile-decomposed walk
@@ -212,7 +213,7 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
     HIP_TRY(c, launch_box_reduce(c->d_pack, nb, c->max_blk, c->d_part, c->d_red, c->stream));
     if (c->vel)
         HIP_TRY(c, launch_margin(c->d_pack, nb, c->max_blk, static_cast<const float4 *>(c->d_rec), c->d_red,
-                                 c->stream));
+                                 c->d_part, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->red.data(), c->d_red, sizeof(BoxRed) * nb, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int b = 0; b < nb; ++b) {
@@ -384,6 +385,27 @@ mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
     return MC_LYA_OK;
 }
 
+// The per-packet cell list, built on first use after an emission (the
+// persistent, per-packet and trace kernels take packets by id).
+mc_lya_status ensure_cell_of_packet(mc_lya_ctx *c)
+{
+    if (c->cop_valid) return MC_LYA_OK;
+    const uint64_t ntot = c->total_packets;
+    if (ntot > c->cop_cap) {
+        uint32_t *np = nullptr;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&np), ntot * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(c, e, "packet queue allocation");
+        if (c->d_cop) (void)hipFree(c->d_cop);
+        c->d_cop = np;
+        c->cop_cap = ntot;
+    }
+    if (ntot) HIP_TRY(c, launch_cell_of_packet(c->d_pack, c->n_boxes, c->max_blk, c->d_npk, c->d_pfirst, c->d_cop,
+                                               c->stream));
+    c->cop_valid = true;
+    return MC_LYA_OK;
+}
+
 mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
 {
     if (count == 0) return MC_LYA_OK;
@@ -412,6 +434,11 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
         }
         c->state = 2;
         return MC_LYA_OK;
+    }
+    {
+        mc_lya_status st = ensure_cell_of_packet(c);
+        if (st != MC_LYA_OK) return st;
+        p.cell_of_packet = c->d_cop;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -543,7 +570,7 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
     if ((e = dalloc(&c->d_pack, n_boxes)) != hipSuccess || (e = dalloc(&c->d_walk, n_boxes)) != hipSuccess ||
         (e = dalloc(&c->d_red, n_boxes)) != hipSuccess || (e = dalloc(&c->d_tot, n_boxes)) != hipSuccess ||
         (e = hipMalloc(&c->d_rec, cells * (c->vel ? sizeof(float4) : sizeof(float)))) != hipSuccess ||
-        (e = dalloc(&c->d_wgt, cells)) != hipSuccess || (e = dalloc(&c->d_part, nbk * 4)) != hipSuccess ||
+        (e = dalloc(&c->d_wgt, cells)) != hipSuccess || (e = dalloc(&c->d_part, nbk * kPartStride)) != hipSuccess ||
         (e = dalloc(&c->d_q, cells)) != hipSuccess || (e = dalloc(&c->d_bsum, nbk)) != hipSuccess ||
         (e = dalloc(&c->d_npk, cells)) != hipSuccess || (e = dalloc(&c->d_A, cells)) != hipSuccess ||
         (e = dalloc(&c->d_queue, kMaxQueues)) != hipSuccess || (e = dalloc(&c->d_boxabs, n_boxes)) != hipSuccess ||
@@ -591,15 +618,6 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *
     if (weight >= ((unsigned __int128)1 << 63) || total >= ((unsigned __int128)1 << 40))
         return fail(c, MC_LYA_EOVERFLOW, "total packets or total weight too large");
     const uint64_t ntot = (uint64_t)total;
-    if (ntot > c->cop_cap) {
-        uint32_t *np = nullptr;
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&np), ntot * sizeof(uint32_t));
-        if (e != hipSuccess) return hip_fail(c, e, "packet queue allocation");
-        if (c->d_cop) (void)hipFree(c->d_cop);
-        c->d_cop = np;
-        c->cop_cap = ntot;
-    }
     uint64_t off = 0;
     for (int b = 0; b < c->n_boxes; ++b) {
         c->walk[b].pkt_off = off;
@@ -614,7 +632,8 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *
     HIP_TRY(c, launch_quantize(c->d_pack, nb, c->max_blk, c->d_wgt, c->d_red, c->d_q, c->d_bsum, c->stream));
     HIP_TRY(c, launch_scan_blocks(c->d_pack, nb, c->max_blk, c->d_bsum, c->d_red, c->stream));
     HIP_TRY(c, launch_allocate(c->d_pack, c->d_walk, nb, c->max_blk, c->d_q, c->d_bsum, c->d_red, c->d_npk,
-                               c->d_pfirst, c->d_cop, c->stream));
+                               c->d_pfirst, c->stream));
+    c->cop_valid = false;
     if (c->kernel == 2) {
         mc_lya_status st = ensure_tile_buffers(c, ntot);
         if (st != MC_LYA_OK) return st;
@@ -646,9 +665,8 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, m
     if (!c) return MC_LYA_EINVAL;
     if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_tally before mc_lya_emit");
     const int nb = c->n_boxes;
-    HIP_TRY(c, hipMemsetAsync(c->d_boxabs, 0, sizeof(unsigned long long) * nb, c->stream));
-    HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, absorbed, emitted, c->d_boxabs,
-                            c->stream));
+    HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, absorbed, emitted, c->d_part,
+                            c->d_boxabs, c->stream));
     std::vector<BoxTot> tot(nb);
     std::vector<unsigned long long> abs(nb);
     HIP_TRY(c, hipMemcpyAsync(tot.data(), c->d_tot, sizeof(BoxTot) * nb, hipMemcpyDeviceToHost, c->stream));
@@ -689,9 +707,8 @@ mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya
     if (!c) return MC_LYA_EINVAL;
     if (c->state < 2) return fail(c, MC_LYA_ESTATE, "mc_lya_feed before mc_lya_transport");
     const int nb = c->n_boxes;
-    HIP_TRY(c, hipMemsetAsync(c->d_boxabs, 0, sizeof(unsigned long long) * nb, c->stream));
-    HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, nullptr, nullptr, c->d_boxabs,
-                            c->stream));
+    HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, nullptr, nullptr, c->d_part,
+                            c->d_boxabs, c->stream));
     HIP_TRY(c, launch_feed_sums(c->d_pack, nb, c->max_blk, c->d_wgt, c->d_part, c->stream));
     HIP_TRY(c, launch_feed_reduce(nb, c->max_blk, c->d_pack, c->d_part, c->d_fsum, c->stream));
     std::vector<BoxTot> tot(nb);
@@ -752,6 +769,10 @@ mc_lya_status mc_lya_trace(mc_lya_ctx *c, uint64_t first, uint64_t count, mc_lya
     if (first > c->total_packets || count > c->total_packets - first)
         return fail(c, MC_LYA_EINVAL, "packet range outside the emitted packets");
     if (count == 0) return MC_LYA_OK;
+    {
+        mc_lya_status st = ensure_cell_of_packet(c);
+        if (st != MC_LYA_OK) return st;
+    }
     WalkParams p{};
     p.boxes = c->d_walk;
     p.n_boxes = c->n_boxes;

@@ -99,13 +99,19 @@ __device__ __forceinline__ float u01(uint32_t w)
 // Launchers (each defined next to its kernels).
 // ---------------------------------------------------------------------------
 constexpr int kSetupBlock = 256;
+// Per-block partial results of the setup and tally kernels, kPartStride
+// doubles per (box, block): [0..3] sums (pack, then feed), [4] the block's
+// largest emission weight, [5] its largest |U - <U>|, [6] its absorbed-weight
+// sum (uint64 bits). Reduced per box by one-block kernels; no same-address
+// atomics, which serialise at the cache.
+constexpr int kPartStride = 8;
 
 hipError_t launch_pack(const PackBox *pb_dev, int n_boxes, int max_blk, bool vel_rec, void *rec,
                        double *wgt, double *partials, BoxRed *red, hipStream_t s);
 hipError_t launch_box_reduce(const PackBox *pb_dev, int n_boxes, int max_blk, const double *partials,
                              BoxRed *red, hipStream_t s);
 hipError_t launch_margin(const PackBox *pb_dev, int n_boxes, int max_blk, const float4 *rec, BoxRed *red,
-                         hipStream_t s);
+                         double *partials, hipStream_t s);
 
 hipError_t launch_quantize(const PackBox *pb_dev, int n_boxes, int max_blk, const double *wgt,
                            const BoxRed *red, uint64_t *q, uint64_t *bsum, hipStream_t s);
@@ -113,7 +119,9 @@ hipError_t launch_scan_blocks(const PackBox *pb_dev, int n_boxes, int max_blk, u
                               BoxRed *red, hipStream_t s);
 hipError_t launch_allocate(const PackBox *pb_dev, const WalkBox *wb_dev, int n_boxes, int max_blk,
                            const uint64_t *q, const uint64_t *bsum, const BoxRed *red,
-                           uint32_t *npk, uint64_t *pfirst, uint32_t *cell_of_packet, hipStream_t s);
+                           uint32_t *npk, uint64_t *pfirst, hipStream_t s);
+hipError_t launch_cell_of_packet(const PackBox *pb_dev, int n_boxes, int max_blk, const uint32_t *npk,
+                                 const uint64_t *pfirst, uint32_t *cell_of_packet, hipStream_t s);
 
 struct WalkParams {
     const WalkBox *boxes;
@@ -204,7 +212,7 @@ hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out
 
 hipError_t launch_tally(const WalkBox *wb_dev, int n_boxes, int max_blk, const unsigned long long *A,
                         const uint32_t *npk, int64_t *absorbed_out, int64_t *emitted_out,
-                        unsigned long long *box_abs, hipStream_t s);
+                        double *partials, unsigned long long *box_abs, hipStream_t s);
 
 struct FeedBox {
     double S_scale;          // physical source = S_scale * weight

@@ -52,6 +52,21 @@ __device__ __forceinline__ T block_sum(T v, T *lds)
     return t;
 }
 
+// Block maximum (order independent). Result valid in thread 0.
+__device__ __forceinline__ double block_max(double v, double *lds)
+{
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kWaves; ++w) t = fmax(t, lds[w]);
+    }
+    return t;
+}
+
 // Inclusive scan of a 64-bit value across the block; also returns the block
 // total through *total (all threads).
 __device__ __forceinline__ uint64_t block_inclusive_scan(uint64_t v, uint64_t *lds, uint64_t *total)
@@ -136,19 +151,17 @@ __global__ __launch_bounds__(B) void pack_kernel(const PackBox *__restrict__ pbs
     const double sy = block_sum(uy, lds);
     const double sz = block_sum(uz, lds);
     const double sk = block_sum(ks, lds);
-    // order-independent reductions
-    double wm = wave_max(w);
-    uint32_t fl = wave_or(flags);
-    if ((threadIdx.x & 63) == 0) {
-        if (fl) atomicOr(&red[b].flags, fl);
-        atomicMax(&red[b].wmax_bits, (unsigned long long)__double_as_longlong(wm));
-    }
+    const double wm = block_max(w, lds);
+    // validation failures are rare: an atomic only where one is found
+    const uint32_t fl = wave_or(flags);
+    if ((threadIdx.x & 63) == 0 && fl) atomicOr(&red[b].flags, fl);
     if (threadIdx.x == 0) {
-        double *p = partials + ((size_t)b * max_blk + blockIdx.x) * 4;
+        double *p = partials + ((size_t)b * max_blk + blockIdx.x) * kPartStride;
         p[0] = sx;
         p[1] = sy;
         p[2] = sz;
         p[3] = sk;
+        p[4] = wm;
     }
 }
 
@@ -161,26 +174,33 @@ __global__ __launch_bounds__(B) void box_reduce_kernel(const PackBox *__restrict
     const int b = blockIdx.x;
     const int nblk = pbs[b].nblk;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double wm = 0.0;
     for (int k = threadIdx.x; k < nblk; k += B) {
-        const double *p = partials + ((size_t)b * max_blk + k) * 4;
+        const double *p = partials + ((size_t)b * max_blk + k) * kPartStride;
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] += p[j];
+        wm = fmax(wm, p[4]);
     }
     double tot[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) tot[j] = block_sum(acc[j], lds);
+    wm = block_max(wm, lds);
     if (threadIdx.x == 0) {
         red[b].usum[0] = tot[0];
         red[b].usum[1] = tot[1];
         red[b].usum[2] = tot[2];
         red[b].kappa_sum = tot[3];
+        red[b].wmax_bits = (unsigned long long)__double_as_longlong(wm);
     }
 }
 
-// max_c |U_c - <U>| per box (order independent).
+// max_c |U_c - <U>| per box (order independent): block maxima, then one
+// block per box.
 __global__ __launch_bounds__(B) void margin_kernel(const PackBox *__restrict__ pbs,
-                                                   const float4 *__restrict__ rec, BoxRed *red)
+                                                   const float4 *__restrict__ rec, const BoxRed *red,
+                                                   double *__restrict__ partials, int max_blk)
 {
+    __shared__ double lds[kWaves];
     const int b = blockIdx.y;
     const PackBox pb = pbs[b];
     if ((int)blockIdx.x >= pb.nblk) return;
@@ -194,9 +214,21 @@ __global__ __launch_bounds__(B) void margin_kernel(const PackBox *__restrict__ p
         const double dx = (double)r.y - mx, dy = (double)r.z - my, dz = (double)r.w - mz;
         dev = sqrt(dx * dx + dy * dy + dz * dz);
     }
-    dev = wave_max(dev);
-    if ((threadIdx.x & 63) == 0)
-        atomicMax(&red[b].udev_bits, (unsigned long long)__double_as_longlong(dev));
+    dev = block_max(dev, lds);
+    if (threadIdx.x == 0) partials[((size_t)b * max_blk + blockIdx.x) * kPartStride + 5] = dev;
+}
+
+__global__ __launch_bounds__(B) void margin_reduce_kernel(const PackBox *__restrict__ pbs,
+                                                          const double *__restrict__ partials, BoxRed *red,
+                                                          int max_blk)
+{
+    __shared__ double lds[kWaves];
+    const int b = blockIdx.x;
+    const int nblk = pbs[b].nblk;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += B) m = fmax(m, partials[((size_t)b * max_blk + k) * kPartStride + 5]);
+    m = block_max(m, lds);
+    if (threadIdx.x == 0) red[b].udev_bits = (unsigned long long)__double_as_longlong(m);
 }
 
 // -------------------------------------------------------------------------
@@ -260,16 +292,14 @@ __device__ __forceinline__ uint64_t count_below(uint64_t Q, uint64_t qtot, uint6
     return (uint64_t)(c >> 1);
 }
 
-// Allocation: each cell learns its first packet id and count and writes its
-// global cell index into the packet queue.
+// Allocation: each cell learns its first packet id and its count.
 __global__ __launch_bounds__(B) void allocate_kernel(const PackBox *__restrict__ pbs,
                                                      const WalkBox *__restrict__ wbs,
                                                      const uint64_t *__restrict__ q,
                                                      const uint64_t *__restrict__ bsum,
                                                      const BoxRed *__restrict__ red,
                                                      uint32_t *__restrict__ npk,
-                                                     uint64_t *__restrict__ pfirst,
-                                                     uint32_t *__restrict__ cop, int max_blk)
+                                                     uint64_t *__restrict__ pfirst, int max_blk)
 {
     __shared__ uint64_t lds[kWaves];
     const int b = blockIdx.y;
@@ -294,7 +324,23 @@ __global__ __launch_bounds__(B) void allocate_kernel(const PackBox *__restrict__
     const uint32_t cnt = (uint32_t)(next - first);
     npk[g] = cnt;
     pfirst[g] = wbs[b].pkt_off + first;
-    uint32_t *dst = cop + wbs[b].pkt_off + first;
+}
+
+// The cell of every packet id (for the walks that take packets by id rather
+// than by cell): cell g writes its index over its packet range.
+__global__ __launch_bounds__(B) void cell_of_packet_kernel(const PackBox *__restrict__ pbs,
+                                                           const uint32_t *__restrict__ npk,
+                                                           const uint64_t *__restrict__ pfirst,
+                                                           uint32_t *__restrict__ cop)
+{
+    const int b = blockIdx.y;
+    const PackBox pb = pbs[b];
+    if ((int)blockIdx.x >= pb.nblk) return;
+    const uint32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= pb.ncells) return;
+    const size_t g = (size_t)pb.cell_off + i;
+    const uint32_t cnt = npk[g];
+    uint32_t *dst = cop + pfirst[g];
     for (uint32_t k = 0; k < cnt; ++k) dst[k] = (uint32_t)g;
 }
 
@@ -323,9 +369,12 @@ hipError_t launch_box_reduce(const PackBox *pb_dev, int n_boxes, int max_blk, co
 }
 
 hipError_t launch_margin(const PackBox *pb_dev, int n_boxes, int max_blk, const float4 *rec, BoxRed *red,
-                         hipStream_t s)
+                         double *partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(margin_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, pb_dev, rec, red);
+    hipLaunchKernelGGL(margin_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, pb_dev, rec, red, partials,
+                       max_blk);
+    hipLaunchKernelGGL(margin_reduce_kernel, dim3((unsigned)n_boxes), dim3(B), 0, s, pb_dev, partials, red,
+                       max_blk);
     return hipGetLastError();
 }
 
@@ -347,10 +396,18 @@ hipError_t launch_scan_blocks(const PackBox *pb_dev, int n_boxes, int max_blk, u
 
 hipError_t launch_allocate(const PackBox *pb_dev, const WalkBox *wb_dev, int n_boxes, int max_blk,
                            const uint64_t *q, const uint64_t *bsum, const BoxRed *red, uint32_t *npk,
-                           uint64_t *pfirst, uint32_t *cell_of_packet, hipStream_t s)
+                           uint64_t *pfirst, hipStream_t s)
 {
     hipLaunchKernelGGL(allocate_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, pb_dev, wb_dev, q, bsum, red,
-                       npk, pfirst, cell_of_packet, max_blk);
+                       npk, pfirst, max_blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_of_packet(const PackBox *pb_dev, int n_boxes, int max_blk, const uint32_t *npk,
+                                 const uint64_t *pfirst, uint32_t *cell_of_packet, hipStream_t s)
+{
+    hipLaunchKernelGGL(cell_of_packet_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, pb_dev, npk, pfirst,
+                       cell_of_packet);
     return hipGetLastError();
 }
 

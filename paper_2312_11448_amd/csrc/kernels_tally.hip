@@ -40,7 +40,7 @@ __global__ __launch_bounds__(B) void tally_kernel(const WalkBox *__restrict__ wb
                                                   const uint32_t *__restrict__ npk,
                                                   int64_t *__restrict__ absorbed_out,
                                                   int64_t *__restrict__ emitted_out,
-                                                  unsigned long long *box_abs)
+                                                  double *__restrict__ partials, int max_blk)
 {
     __shared__ unsigned long long lds[kWaves];
     const int b = blockIdx.y;
@@ -55,7 +55,23 @@ __global__ __launch_bounds__(B) void tally_kernel(const WalkBox *__restrict__ wb
         if (emitted_out) emitted_out[g] = (int64_t)((uint64_t)npk[g] * wb.w0);
     }
     const unsigned long long s = block_sum(a, lds);
-    if (threadIdx.x == 0 && s) atomicAdd(&box_abs[b], s);
+    if (threadIdx.x == 0)
+        reinterpret_cast<unsigned long long *>(partials)[((size_t)b * max_blk + blockIdx.x) * kPartStride + 6] = s;
+}
+
+// One block per box: the integer sum of the block sums (exact in any order).
+__global__ __launch_bounds__(B) void tally_reduce_kernel(const WalkBox *__restrict__ wbs,
+                                                         const double *__restrict__ partials,
+                                                         unsigned long long *__restrict__ box_abs, int max_blk)
+{
+    __shared__ unsigned long long lds[kWaves];
+    const int b = blockIdx.x;
+    const uint32_t nblk = (wbs[b].ncells + B - 1) / B;
+    const unsigned long long *p = reinterpret_cast<const unsigned long long *>(partials);
+    unsigned long long a = 0;
+    for (uint32_t k = threadIdx.x; k < nblk; k += B) a += p[((size_t)b * max_blk + k) * kPartStride + 6];
+    a = block_sum(a, lds);
+    if (threadIdx.x == 0) box_abs[b] = a;
 }
 
 // Per block: sum of weights, of (1 - x_e) Delta, of x_e Delta and of Delta.
@@ -82,7 +98,7 @@ __global__ __launch_bounds__(B) void feed_sums_kernel(const PackBox *__restrict_
     const double t2 = block_sum(s2, lds);
     const double t3 = block_sum(s3, lds);
     if (threadIdx.x == 0) {
-        double *p = partials + ((size_t)b * max_blk + blockIdx.x) * 4;
+        double *p = partials + ((size_t)b * max_blk + blockIdx.x) * kPartStride;
         p[0] = t0;
         p[1] = t1;
         p[2] = t2;
@@ -100,7 +116,7 @@ __global__ __launch_bounds__(B) void reduce4_kernel(const PackBox *__restrict__ 
     const int nblk = pbs[b].nblk;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < nblk; k += B) {
-        const double *p = partials + ((size_t)b * max_blk + k) * 4;
+        const double *p = partials + ((size_t)b * max_blk + k) * kPartStride;
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] += p[j];
     }
@@ -143,10 +159,12 @@ inline dim3 grid2(int max_blk, int n_boxes) { return dim3((unsigned)max_blk, (un
 
 hipError_t launch_tally(const WalkBox *wb_dev, int n_boxes, int max_blk, const unsigned long long *A,
                         const uint32_t *npk, int64_t *absorbed_out, int64_t *emitted_out,
-                        unsigned long long *box_abs, hipStream_t s)
+                        double *partials, unsigned long long *box_abs, hipStream_t s)
 {
     hipLaunchKernelGGL(tally_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, wb_dev, A, npk, absorbed_out,
-                       emitted_out, box_abs);
+                       emitted_out, partials, max_blk);
+    hipLaunchKernelGGL(tally_reduce_kernel, dim3((unsigned)n_boxes), dim3(B), 0, s, wb_dev, partials, box_abs,
+                       max_blk);
     return hipGetLastError();
 }
 
