@@ -13,6 +13,8 @@ algorithmic bytes per crossing (one 16-byte cell record read, one 8-byte
 tally update). The CPU baseline is the FP64 oracle on a bounded sample.
 """
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +26,19 @@ sys.path.insert(0, ROOT)
 BYTES_PER_CROSSING_VEL = 16 + 8      # float4 record (kappa, U) + int64 tally update
 BYTES_PER_CROSSING_NOVEL = 4 + 8     # float record (kappa) + int64 tally update
 HBM_PEAK_GBS = 8000.0
+# the sources of the dominant kernel (the tiled walk): stored byte counters are
+# only reported while these are unchanged
+WALK_SOURCES = ("paper_2312_11448_amd/csrc/walk_core.hpp", "paper_2312_11448_amd/csrc/kernels_tiled.hip",
+                "paper_2312_11448_amd/csrc/common.hpp")
+WALK_KERNEL = "tile_walk_kernel"
+
+
+def walk_source_hash():
+    h = hashlib.sha256()
+    for rel in WALK_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -40,7 +55,48 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy of MIB MiB (float32 negation, "
                          "reads and writes MIB MiB) five times, to scale byte counters")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
+                    help="only turn four rocprofv3 counter_collection.csv files (FETCH_SIZE and WRITE_SIZE "
+                         "of the benchmark, then of --calibrate-copy) into the walk's HBM bytes per launch, "
+                         "written to --traffic")
+    ap.add_argument("--calibration-mib", type=int, default=1024)
     return ap.parse_args()
+
+
+def _counter_rows(path, counter):
+    with open(path, newline="") as fh:
+        return [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+
+
+def summarize_counters(a):
+    """HBM bytes per walk launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for a copy of known size."""
+    f_csv, w_csv, cf_csv, cw_csv = a.summarize_counters
+    known = a.calibration_mib * (1 << 20)
+    scale = {}
+    for name, path, counter in (("fetch", cf_csv, "FETCH_SIZE"), ("write", cw_csv, "WRITE_SIZE")):
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in _counter_rows(path, counter)
+                if "neg_kernel" in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit(f"no copy-kernel rows in {path}")
+        scale[name] = known / (sum(vals) / len(vals))
+    per = {}
+    launches = {}
+    for name, path, counter in (("fetch", f_csv, "FETCH_SIZE"), ("write", w_csv, "WRITE_SIZE")):
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in _counter_rows(path, counter)
+                if WALK_KERNEL in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit(f"no {WALK_KERNEL} rows in {path}")
+        per[name] = scale[name] * sum(vals) / len(vals)
+        launches[name] = len(vals)
+    out = {"config": a.config, "kernel": WALK_KERNEL, "launches": launches,
+           "fetch_scale": scale["fetch"], "write_scale": scale["write"],
+           "fetch_bytes_per_launch": per["fetch"], "write_bytes_per_launch": per["write"],
+           "bytes_per_launch": per["fetch"] + per["write"], "source_sha256": walk_source_hash()}
+    with open(a.traffic, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out), flush=True)
 
 
 def calibrate_copy(mib):
@@ -79,6 +135,9 @@ def main():
     a = parse()
     if a.calibrate_copy:
         calibrate_copy(a.calibrate_copy)
+        return
+    if a.summarize_counters:
+        summarize_counters(a)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -126,7 +185,7 @@ def main():
     if os.path.exists(a.traffic):
         with open(a.traffic) as fh:
             tr = json.load(fh)
-        if tr.get("config") == a.config:
+        if tr.get("config") == a.config and tr.get("source_sha256") == walk_source_hash():
             traffic = tr.get("bytes_per_launch")
     out = {
         "metric": "photon cell-crossings/s",
@@ -145,6 +204,8 @@ def main():
                    "crossings_per_step": cross_per_step,
                    "walk_ms": walk_s * 1e3,
                    "walk_launches_per_step": launches / a.steps,
+                   "walk_launch_avg_us": kms * 1e3 / max(1, launches),
+                   "walk_alg_bytes_per_launch": bpc * cross / max(1, launches),
                    "walk_crossings_per_s": cross_per_step / walk_s,
                    "f_absorbed": f["stats"][0].f_absorbed, "c_mc": f["stats"][0].c_mc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
