@@ -139,9 +139,21 @@ enum {
                                      kernels 0 and 2) */
     MC_LYA_OPT_MAX_CROSSINGS = 6, /* crossing cap per packet (>= 1, default 1e6) */
     MC_LYA_OPT_TIMING = 7,        /* 1 = time transport kernels with HIP events */
-    MC_LYA_OPT_GRAPH = 8,         /* 1 = replay transport as a captured HIP graph */
-    MC_LYA_OPT_QUEUES = 9         /* parts the packet range is split into for the persistent
+    MC_LYA_OPT_GRAPH = 8,         /* 1 = a whole-emission mc_lya_transport replays a captured
+                                     HIP graph of its kernels (recaptured when options, packet
+                                     count or buffers change; tiled emissions larger than the
+                                     packet-state buffers, 2^25 packets, and
+                                     mc_lya_transport_range stay eager) */
+    MC_LYA_OPT_QUEUES = 9,        /* parts the packet range is split into for the persistent
                                      walk (1..64, default 8: one grid slab per XCD) */
+    MC_LYA_OPT_TILE_SHARE = 10,   /* kernel 2: a box is walked by tiles when it has at least 8
+                                     tiles and its estimated crossings per tile are at most
+                                     this percentage of the emission's crossings per compute
+                                     unit (default 100); other boxes take the persistent walk.
+                                     0 = no box tiled, 1000000 = every box tiled */
+    MC_LYA_OPT_GRAPH_GENS = 11    /* tile generations inside a captured transport graph
+                                     (16..4096, default 64); a replay that needs more
+                                     continues eagerly and the next capture takes enough */
 };
 
 /* Creates a context for n_boxes boxes, validates and packs their fields
@@ -220,9 +232,35 @@ mc_lya_status mc_lya_trace(mc_lya_ctx *ctx, uint64_t first, uint64_t count,
 /* Sets a tunable (see the MC_LYA_OPT_ enum). Errors: EINVAL. */
 mc_lya_status mc_lya_set_option(mc_lya_ctx *ctx, int32_t option, int64_t value);
 
+/* Result of mc_lya_autotune: the options chosen and the transport times. */
+typedef struct mc_lya_tune_result {
+    int64_t kernel;               /* MC_LYA_OPT_KERNEL */
+    int64_t tile_share;           /* MC_LYA_OPT_TILE_SHARE */
+    int64_t block;                /* MC_LYA_OPT_BLOCK */
+    int64_t waves_per_cu;         /* MC_LYA_OPT_WAVES_PER_CU */
+    int64_t chunk;                /* MC_LYA_OPT_CHUNK */
+    int64_t refill;               /* MC_LYA_OPT_REFILL */
+    double best_ms;               /* fastest transport of the current emission, ms */
+    double start_ms;              /* the same with the options set before the call, ms */
+    int32_t trials;               /* option sets timed */
+    int32_t reserved;
+} mc_lya_tune_result;
+
+/* Times a fixed list of option sets (the current one first; the tiled and
+ * persistent walks at several tile shares, chunk, refill, block and resident
+ * wave counts) on full transports of the current emission, `reps` timed runs
+ * each after one warm-up run, and keeps the fastest. Transport results do not
+ * depend on these options (bit for bit), so tuning changes speed only. Leaves
+ * the context as after mc_lya_emit (tallies zero), ready for mc_lya_transport.
+ * Costs about (reps + 1) x 12 transports. result: host, or NULL.
+ * Synchronises the stream. Errors: EINVAL (reps outside [1, 100]), ESTATE
+ * (before mc_lya_emit), EDEVICE. */
+mc_lya_status mc_lya_autotune(mc_lya_ctx *ctx, int32_t reps, mc_lya_tune_result *result);
+
 /* Sum of the durations of the transport kernels since the last call (ms),
  * measured with HIP events on the context's stream when MC_LYA_OPT_TIMING is
- * on; also returns the number of launches timed. Synchronises the stream. */
+ * on; also returns the number of launches timed (a graph replay counts as
+ * one). Synchronises the stream. */
 mc_lya_status mc_lya_kernel_time(mc_lya_ctx *ctx, double *ms, int64_t *launches);
 
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) on the device: n blocks,

@@ -19,6 +19,8 @@ MC_LYA_VEL_NONE, MC_LYA_VEL_F32, MC_LYA_VEL_F16 = 0, 1, 2
 MC_LYA_OPT_KERNEL, MC_LYA_OPT_BLOCK, MC_LYA_OPT_WAVES_PER_CU, MC_LYA_OPT_CHUNK = 1, 2, 3, 4
 MC_LYA_OPT_REFILL, MC_LYA_OPT_MAX_CROSSINGS, MC_LYA_OPT_TIMING, MC_LYA_OPT_GRAPH = 5, 6, 7, 8
 MC_LYA_OPT_QUEUES = 9
+MC_LYA_OPT_TILE_SHARE = 10
+MC_LYA_OPT_GRAPH_GENS = 11
 
 
 class mc_lya_box_desc(C.Structure):
@@ -52,9 +54,16 @@ class mc_lya_packet_trace(C.Structure):
                 ("fate", C.c_int32)]
 
 
+class mc_lya_tune_result(C.Structure):
+    _fields_ = [("kernel", C.c_int64), ("tile_share", C.c_int64), ("block", C.c_int64),
+                ("waves_per_cu", C.c_int64), ("chunk", C.c_int64), ("refill", C.c_int64),
+                ("best_ms", C.c_double), ("start_ms", C.c_double), ("trials", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace",
-           "mc_lya_set_option", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
+           "mc_lya_set_option", "mc_lya_autotune", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error"]
 
 
@@ -87,6 +96,7 @@ def load():
     L.mc_lya_feed.argtypes = [vp, vp, vp, P(mc_lya_feed_stats)]
     L.mc_lya_trace.argtypes = [vp, u64, u64, vp]
     L.mc_lya_set_option.argtypes = [vp, i32, i64]
+    L.mc_lya_autotune.argtypes = [vp, i32, P(mc_lya_tune_result)]
     L.mc_lya_kernel_time.argtypes = [vp, P(C.c_double), P(i64)]
     L.mc_lya_philox4x32_10.argtypes = [vp, vp, vp, u64, vp]
     for name in EXPORTS:
@@ -165,6 +175,12 @@ def mc_lya_trace(ctx, first, count, out_ptr):
 
 def mc_lya_set_option(ctx, option, value):
     return _check(load().mc_lya_set_option(ctx, int(option), int(value)), ctx)
+
+
+def mc_lya_autotune(ctx, reps=1):
+    r = mc_lya_tune_result()
+    _check(load().mc_lya_autotune(ctx, int(reps), C.byref(r)), ctx)
+    return r
 
 
 def mc_lya_kernel_time(ctx):

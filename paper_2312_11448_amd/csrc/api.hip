@@ -16,6 +16,7 @@ using namespace mclya;
 static_assert(sizeof(mc_lya_box_desc) == 152, "mc_lya_box_desc layout");
 static_assert(sizeof(mc_lya_box_stats) == 88, "mc_lya_box_stats layout");
 static_assert(sizeof(mc_lya_packet_trace) == 56, "mc_lya_packet_trace layout");
+static_assert(sizeof(mc_lya_tune_result) == 72, "mc_lya_tune_result layout");
 
 namespace {
 
@@ -127,6 +128,18 @@ struct mc_lya_ctx {
     unsigned long long *d_gen = nullptr;     // per generation: bump allocator, exits
     uint64_t state_cap = 0;
     int64_t generations = 0;                 // generations launched by the last tiled transport
+    std::vector<uint8_t> tiled;              // per box: walked by tiles (1) or by the persistent walk (0)
+    std::vector<double> cpp;                 // per box: estimated crossings per packet (set by refresh)
+    std::vector<uint64_t> seg_host;          // packet segments of the persistent part: starts, then ids
+    uint64_t *d_seg = nullptr;               // [2 (n_boxes + 1)]
+    int tile_share = 100;
+    // captured transport (MC_LYA_OPT_GRAPH)
+    bool graph = false;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;        // private stream the graph is captured on
+    std::vector<uint64_t> graph_key;
+    int graph_gens = 64;                     // tile generations inside the graph
+    uint64_t epoch = 0;                      // bumped whenever a buffer a graph reads is reallocated
 
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
@@ -164,9 +177,13 @@ mc_lya_status hip_fail(mc_lya_ctx *c, hipError_t e, const char *what)
 
 void free_all(mc_lya_ctx *c)
 {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -204,6 +221,39 @@ std::string check_desc(const mc_lya_box_desc &d, int b)
     return std::string();
 }
 
+// Expected crossings per packet in a homogeneous box with opacity kappa per
+// unit Phi, drift delta per cell, escape at -x_eff and packet weight w0. A
+// packet emitted at x0 walks until its weight rounds to zero, once
+// kappa (Phi(x0) - Phi(x)) exceeds ln(2 w0), or until x = -x_eff; that is
+// (x0 - x_end) / delta cells. Only used to balance work between the walks.
+double crossings_per_packet(double kappa, double delta, double x_eff, double w0)
+{
+    if (!(delta > 0.0)) return 1.0;
+    auto Phi = [](double x) { return 0.5 * std::erfc(-x); };
+    const double need = kappa > 0.0 ? std::log(2.0 * w0) / kappa : 1e300;
+    const double floor_phi = Phi(-x_eff);
+    const int n = 64;
+    const double lo = -x_eff, hi = 6.0;
+    double sum = 0.0, norm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double x0 = lo + (hi - lo) * (i + 0.5) / n;
+        const double target = Phi(x0) - need;
+        double xe = -x_eff;
+        if (target > floor_phi) {
+            double a = -x_eff, b = x0;
+            for (int it = 0; it < 40; ++it) {
+                const double m = 0.5 * (a + b);
+                if (Phi(m) < target) a = m; else b = m;
+            }
+            xe = 0.5 * (a + b);
+        }
+        const double wgt = std::exp(-x0 * x0);
+        sum += wgt * (x0 - xe) / delta;
+        norm += wgt;
+    }
+    return 1.0 + sum / norm;
+}
+
 mc_lya_status do_refresh(mc_lya_ctx *c)
 {
     const int nb = c->n_boxes;
@@ -233,6 +283,7 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
         w.x_eff = (float)(c->desc[b].x_esc + 2.0 * udev);
         w.delta = (float)c->ph[b].delta;
         w.valid = 1;
+        c->cpp[b] = crossings_per_packet(c->red[b].kappa_sum / (double)w.ncells, w.delta, w.x_eff, (double)w.w0);
     }
     c->state = 0;
     return MC_LYA_OK;
@@ -247,6 +298,7 @@ void build_tiles(mc_lya_ctx *c)
     const int TE = kTileEdge;
     c->tiles.clear();
     for (int b = 0; b < c->n_boxes; ++b) {
+        if (!c->tiled[b]) continue;
         const mc_lya_box_desc &d = c->desc[b];
         const int nt[3] = {(d.nx + TE - 1) / TE, (d.ny + TE - 1) / TE, (d.nz + TE - 1) / TE};
         const int off = (int)c->tiles.size();
@@ -286,6 +338,47 @@ void build_tiles(mc_lya_ctx *c)
     }
 }
 
+int tiles_of_box(const mc_lya_box_desc &d)
+{
+    const int TE = kTileEdge;
+    return ((d.nx + TE - 1) / TE) * ((d.ny + TE - 1) / TE) * ((d.nz + TE - 1) / TE);
+}
+
+constexpr int kMinTiles = 8;              // fewer tiles than this never pays
+constexpr int kAllTiled = 1000000;        // tile_share at or above this: every box is tiled
+
+// Which boxes the tiled walk takes: those whose estimated work per tile is at
+// most tile_share % of one compute unit's fair share of the whole emission
+// (a tile is walked by one workgroup, so a box with few tiles and many long
+// walks would hold the whole launch); the rest go to the persistent walk.
+// Rebuilds and uploads the tile table when the choice changes.
+mc_lya_status classify_boxes(mc_lya_ctx *c)
+{
+    const int nb = c->n_boxes;
+    std::vector<double> cost(nb, 0.0);
+    double total = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        cost[b] = (double)c->walk[b].npkt * c->cpp[b];
+        total += cost[b];
+    }
+    const double fair = total / std::max(1, c->num_cu);
+    std::vector<uint8_t> m(nb, 0);
+    for (int b = 0; b < nb; ++b) {
+        const int nt = tiles_of_box(c->desc[b]);
+        if (c->tile_share >= kAllTiled) m[b] = 1;
+        else if (c->tile_share > 0)
+            m[b] = nt >= kMinTiles && cost[b] / nt <= 0.01 * c->tile_share * fair ? 1 : 0;
+    }
+    if (m == c->tiled) return MC_LYA_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
+    c->tiled = m;
+    build_tiles(c);
+    if (!c->tiles.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(TileInfo) * c->tiles.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    return MC_LYA_OK;
+}
+
 constexpr uint64_t kTiledBatch = 1ull << 25;   // packets per tiled batch (state buffers of ~3.9 GB)
 constexpr int kGenRound = 16;                  // generations queued between two checks
 
@@ -309,9 +402,12 @@ mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
         HIP_TRY(c, dalloc(&c->d_idx[i], cap));
     }
     c->state_cap = cap;
+    ++c->epoch;
     return MC_LYA_OK;
 }
 
+// Times the work enqueued between timed_begin and timed_end with a pair of
+// HIP events on the context's stream (when MC_LYA_OPT_TIMING is on).
 mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
 {
     *e1 = nullptr;
@@ -328,10 +424,13 @@ mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
     return MC_LYA_OK;
 }
 
-// Generations are queued in rounds without waiting; a generation whose
-// predecessor moved nothing returns at once. After each round the host reads
-// the last generation's exit count: zero means every packet has finished.
-mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
+mc_lya_status timed_end(mc_lya_ctx *c, hipEvent_t e1)
+{
+    if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+    return MC_LYA_OK;
+}
+
+TileParams tile_params(mc_lya_ctx *c, uint64_t first, uint64_t n)
 {
     TileParams p;
     std::memset(&p, 0, sizeof p);
@@ -346,40 +445,83 @@ mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
     p.ntiles = (int)c->tiles.size();
     p.chunk = std::min(c->chunk, 1024);
     p.refill = c->refill;
-    c->generations = 0;
+    p.first = first;
+    p.count = n;
+    return p;
+}
+
+// Enqueues tile generations [g0, g1) (buffers ping-pong by parity; the
+// per-generation counters were zeroed at generation 0). timed: one event pair
+// per launch (not while a graph is being captured).
+mc_lya_status enqueue_generations(mc_lya_ctx *c, TileParams &p, int g0, int g1, bool timed)
+{
+    for (int gen = g0; gen < g1; ++gen) {
+        const int cur = gen & 1, prev = cur ^ 1;
+        p.in_state = c->d_state[prev];
+        p.in_idx = c->d_idx[prev];
+        p.in_exits = c->d_texits[prev];
+        p.out_state = c->d_state[cur];
+        p.out_face = c->d_face[cur];
+        p.out_idx = c->d_idx[cur];
+        p.out_exits = c->d_texits[cur];
+        p.bump = c->d_gen + 2 * gen;
+        p.exits = c->d_gen + 2 * gen + 1;
+        p.prev_exits = gen > 0 ? c->d_gen + 2 * (gen - 1) + 1 : c->d_gen + 1;
+        hipEvent_t e1 = nullptr;
+        if (timed) {
+            mc_lya_status st = timed_begin(c, &e1);
+            if (st != MC_LYA_OK) return st;
+        }
+        HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->stream));
+        if (timed) {
+            mc_lya_status st = timed_end(c, e1);
+            if (st != MC_LYA_OK) return st;
+        }
+        ++c->generations;
+    }
+    return MC_LYA_OK;
+}
+
+// Packets still crossing tiles after generation gen - 1 (synchronises).
+mc_lya_status exits_after(mc_lya_ctx *c, int gen, unsigned long long *exits)
+{
+    HIP_TRY(c, hipMemcpyAsync(exits, c->d_gen + 2 * (gen - 1) + 1, sizeof *exits, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MC_LYA_OK;
+}
+
+// Continues a tiled batch from generation gen in rounds of kGenRound, reading
+// the exit count after each round, until no packet is left crossing.
+mc_lya_status drain_generations(mc_lya_ctx *c, TileParams &p, int gen)
+{
+    for (;;) {
+        unsigned long long exits = 0;
+        mc_lya_status st = exits_after(c, gen, &exits);
+        if (st != MC_LYA_OK) return st;
+        if (exits == 0) return MC_LYA_OK;
+        if (gen >= kMaxGenerations) return fail(c, MC_LYA_EDEVICE, "tiled walk did not drain");
+        const int g1 = std::min(gen + kGenRound, kMaxGenerations);
+        st = enqueue_generations(c, p, gen, g1, true);
+        if (st != MC_LYA_OK) return st;
+        gen = g1;
+    }
+}
+
+// Generations are queued in rounds without waiting; a generation whose
+// predecessor moved nothing returns at once. After each round the host reads
+// the last generation's exit count: zero means every packet has finished.
+// Emissions larger than the packet-state buffers walk in batches.
+mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
+{
     for (uint64_t done = 0; done < count;) {
         const uint64_t n = std::min(count - done, c->state_cap);
-        p.first = first + done;
-        p.count = n;
+        TileParams p = tile_params(c, first + done, n);
         HIP_TRY(c, launch_zero_counters(c->d_gen, 2 * kMaxGenerations, c->stream));
-        int gen = 0;
-        for (;;) {
-            for (int r = 0; r < kGenRound && gen < kMaxGenerations; ++r, ++gen) {
-                const int cur = gen & 1, prev = cur ^ 1;
-                p.in_state = c->d_state[prev];
-                p.in_idx = c->d_idx[prev];
-                p.in_exits = c->d_texits[prev];
-                p.out_state = c->d_state[cur];
-                p.out_face = c->d_face[cur];
-                p.out_idx = c->d_idx[cur];
-                p.out_exits = c->d_texits[cur];
-                p.bump = c->d_gen + 2 * gen;
-                p.exits = c->d_gen + 2 * gen + 1;
-                p.prev_exits = gen > 0 ? c->d_gen + 2 * (gen - 1) + 1 : c->d_gen + 1;
-                hipEvent_t e1;
-                mc_lya_status st = timed_begin(c, &e1);
-                if (st != MC_LYA_OK) return st;
-                HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->stream));
-                if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
-                ++c->generations;
-            }
-            unsigned long long exits = 0;
-            HIP_TRY(c, hipMemcpyAsync(&exits, c->d_gen + 2 * (gen - 1) + 1, sizeof exits, hipMemcpyDeviceToHost,
-                                      c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            if (exits == 0) break;
-            if (gen >= kMaxGenerations) return fail(c, MC_LYA_EDEVICE, "tiled walk did not drain");
-        }
+        const int g1 = std::min(kGenRound, kMaxGenerations);
+        mc_lya_status st = enqueue_generations(c, p, 0, g1, true);
+        if (st == MC_LYA_OK) st = drain_generations(c, p, g1);
+        if (st != MC_LYA_OK) return st;
         done += n;
     }
     return MC_LYA_OK;
@@ -399,6 +541,7 @@ mc_lya_status ensure_cell_of_packet(mc_lya_ctx *c)
         if (c->d_cop) (void)hipFree(c->d_cop);
         c->d_cop = np;
         c->cop_cap = ntot;
+        ++c->epoch;
     }
     if (ntot) HIP_TRY(c, launch_cell_of_packet(c->d_pack, c->n_boxes, c->max_blk, c->d_npk, c->d_pfirst, c->d_cop,
                                                c->stream));
@@ -406,15 +549,26 @@ mc_lya_status ensure_cell_of_packet(mc_lya_ctx *c)
     return MC_LYA_OK;
 }
 
-mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
+mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed);
+
+// Everything a transport of [first, first + count) needs before its kernels
+// are enqueued: the tiled / persistent split of the boxes, the packet-state
+// buffers, the per-packet cell list and the packet segments of the
+// persistent part (all in device memory, so a captured graph can replay the
+// kernels alone).
+struct WalkPlan {
+    bool tiled = false;     // tiled generations over [first, first + count)
+    bool global = false;    // persistent / per-packet walk over p
+    WalkParams p{};
+};
+
+mc_lya_status plan_walk(mc_lya_ctx *c, uint64_t first, uint64_t count, WalkPlan *w)
 {
-    if (count == 0) return MC_LYA_OK;
-    WalkParams p;
+    WalkParams &p = w->p;
     p.boxes = c->d_walk;
     p.n_boxes = c->n_boxes;
     p.vel = c->vel ? 1 : 0;
     p.rec = c->d_rec;
-    p.cell_of_packet = c->d_cop;
     p.A = c->d_A;
     p.tot = c->d_tot;
     p.queue = c->d_queue;
@@ -424,34 +578,171 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
     p.chunk = c->chunk;
     p.refill = c->refill;
     p.nqueues = c->nqueues;
+    p.n_seg = 0;
+    w->global = true;
     if (c->kernel == 2) {
-        mc_lya_status st = walk_tiled(c, first, count);
+        // tiled boxes by tiles; the others, if any, by the persistent walk
+        // over their packet segments inside [first, first + count)
+        mc_lya_status st = classify_boxes(c);
         if (st != MC_LYA_OK) return st;
+        w->tiled = !c->tiles.empty();
+        if (w->tiled) {
+            st = ensure_tile_buffers(c, c->total_packets);
+            if (st != MC_LYA_OK) return st;
+        }
+        std::vector<uint64_t> starts, ids;
+        uint64_t n = 0;
         for (int b = 0; b < c->n_boxes; ++b) {
+            if (c->tiled[b]) continue;
             const uint64_t lo = std::max(first, c->walk[b].pkt_off);
             const uint64_t hi = std::min(first + count, c->walk[b].pkt_off + c->walk[b].npkt);
-            if (hi > lo) c->walked[b] += hi - lo;
+            if (hi <= lo) continue;
+            starts.push_back(n);
+            ids.push_back(lo);
+            n += hi - lo;
         }
-        c->state = 2;
-        return MC_LYA_OK;
+        w->global = n > 0;
+        if (w->global) {
+            std::vector<uint64_t> segs = starts;
+            segs.insert(segs.end(), ids.begin(), ids.end());
+            if (segs != c->seg_host) {
+                HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous segments may still be in flight
+                c->seg_host = segs;
+                HIP_TRY(c, hipMemcpyAsync(c->d_seg, c->seg_host.data(), sizeof(uint64_t) * segs.size(),
+                                          hipMemcpyHostToDevice, c->stream));
+            }
+            const size_t k = starts.size();
+            p.n_seg = (int32_t)k;
+            p.seg_start = c->d_seg;
+            p.seg_id = c->d_seg + k;
+            p.count = n;
+        }
     }
-    {
+    if (w->global) {
         mc_lya_status st = ensure_cell_of_packet(c);
         if (st != MC_LYA_OK) return st;
         p.cell_of_packet = c->d_cop;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-        if (c->events_used == c->events.size()) {
-            hipEvent_t a, b;
-            HIP_TRY(c, hipEventCreate(&a));
-            HIP_TRY(c, hipEventCreate(&b));
-            c->events.emplace_back(a, b);
+    return MC_LYA_OK;
+}
+
+void account_walked(mc_lya_ctx *c, uint64_t first, uint64_t count)
+{
+    for (int b = 0; b < c->n_boxes; ++b) {
+        const uint64_t lo = std::max(first, c->walk[b].pkt_off);
+        const uint64_t hi = std::min(first + count, c->walk[b].pkt_off + c->walk[b].npkt);
+        if (hi > lo) c->walked[b] += hi - lo;
+    }
+    c->state = 2;
+}
+
+void drop_graph(mc_lya_ctx *c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    c->graph_key.clear();
+}
+
+// What a captured transport depends on: any change means a new capture.
+std::vector<uint64_t> graph_key(mc_lya_ctx *c, const WalkPlan &w, int budget)
+{
+    std::vector<uint64_t> k = {(uint64_t)c->kernel, (uint64_t)c->block, (uint64_t)c->waves_per_cu,
+                               (uint64_t)c->chunk, (uint64_t)c->refill, (uint64_t)c->nqueues,
+                               (uint64_t)c->max_cross, c->total_packets, c->state_cap, (uint64_t)budget,
+                               (uint64_t)w.tiled, (uint64_t)w.global, (uint64_t)c->tiles.size(),
+                               (uint64_t)(uintptr_t)c->d_state[0], (uint64_t)(uintptr_t)c->d_cop,
+                               (uint64_t)w.p.n_seg, w.p.count, c->epoch};
+    k.insert(k.end(), c->tiled.begin(), c->tiled.end());
+    return k;
+}
+
+// The whole transport as one captured HIP graph (zeroing the generation
+// counters, `budget` tile generations, the persistent walk), replayed;
+// generations beyond the budget, if any packet still crosses tiles, run
+// eagerly after the replay, and the next capture takes a larger budget.
+mc_lya_status transport_graph(mc_lya_ctx *c, WalkPlan &w)
+{
+    const int budget = w.tiled ? std::max(kGenRound, std::min(c->graph_gens, kMaxGenerations)) : 0;
+    const std::vector<uint64_t> key = graph_key(c, w, budget);
+    TileParams tp = tile_params(c, 0, c->total_packets);
+    if (key != c->graph_key) {
+        drop_graph(c);
+        // capture on a private stream (the context's stream may be the null
+        // stream, which cannot be captured); the graph is launched on the
+        // context's stream
+        if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        const hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            c->stream = user;
+            return hip_fail(c, e, "hipStreamBeginCapture");
         }
-        e0 = c->events[c->events_used].first;
-        e1 = c->events[c->events_used].second;
-        ++c->events_used;
-        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        const int64_t gens = c->generations;
+        if (w.tiled) {
+            e = launch_zero_counters(c->d_gen, 2 * kMaxGenerations, c->stream);
+            if (e == hipSuccess && enqueue_generations(c, tp, 0, budget, false) != MC_LYA_OK) e = hipErrorUnknown;
+        }
+        c->generations = gens;
+        if (e == hipSuccess && w.global && launch_global_walk(c, w.p, false) != MC_LYA_OK) e = hipErrorUnknown;
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        c->stream = user;
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph_exec = nullptr;
+            return hip_fail(c, e, "capturing the transport graph");
+        }
+        c->graph_key = key;
+    }
+    hipEvent_t e1 = nullptr;
+    mc_lya_status st = timed_begin(c, &e1);
+    if (st != MC_LYA_OK) return st;
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+    st = timed_end(c, e1);
+    if (st != MC_LYA_OK) return st;
+    c->generations = budget;
+    if (w.tiled) {
+        st = drain_generations(c, tp, budget);
+        if (st != MC_LYA_OK) return st;
+        // ran out of captured generations: the next capture takes what this
+        // emission needed plus one round of slack (empty generations return
+        // at once)
+        if (c->generations > budget) c->graph_gens = (int)std::min<int64_t>(c->generations + kGenRound, kMaxGenerations);
+    }
+    return MC_LYA_OK;
+}
+
+mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
+{
+    if (count == 0) return MC_LYA_OK;
+    WalkPlan w;
+    mc_lya_status st = plan_walk(c, first, count, &w);
+    if (st != MC_LYA_OK) return st;
+    c->generations = 0;
+    const bool whole = first == 0 && count == c->total_packets;
+    if (c->graph && whole && (!w.tiled || c->total_packets <= c->state_cap)) {
+        st = transport_graph(c, w);
+    } else {
+        if (w.tiled) st = walk_tiled(c, first, count);
+        if (st == MC_LYA_OK && w.global) st = launch_global_walk(c, w.p, true);
+    }
+    if (st != MC_LYA_OK) return st;
+    account_walked(c, first, count);
+    return MC_LYA_OK;
+}
+
+// The persistent (kernel 0 and the untiled part of kernel 2) or per-packet
+// (kernel 1) walk over p.count packets.
+mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed)
+{
+    const uint64_t count = p.count;
+    hipEvent_t e1 = nullptr;
+    if (timed) {
+        mc_lya_status st = timed_begin(c, &e1);
+        if (st != MC_LYA_OK) return st;
     }
     if (c->kernel == 1) {
         HIP_TRY(c, launch_walk_simple(p, c->block, c->stream));
@@ -465,14 +756,7 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
         if ((uint64_t)grid * waves_per_block > need) grid = (int)std::max<uint64_t>(1, (need + waves_per_block - 1) / waves_per_block);
         HIP_TRY(c, launch_walk_persistent(p, c->block, grid, c->stream));
     }
-    if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
-    // account the walked packets per box
-    for (int b = 0; b < c->n_boxes; ++b) {
-        const uint64_t lo = std::max(first, c->walk[b].pkt_off);
-        const uint64_t hi = std::min(first + count, c->walk[b].pkt_off + c->walk[b].npkt);
-        if (hi > lo) c->walked[b] += hi - lo;
-    }
-    c->state = 2;
+    if (timed) return timed_end(c, e1);
     return MC_LYA_OK;
 }
 
@@ -575,8 +859,11 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         (e = dalloc(&c->d_npk, cells)) != hipSuccess || (e = dalloc(&c->d_A, cells)) != hipSuccess ||
         (e = dalloc(&c->d_queue, kMaxQueues)) != hipSuccess || (e = dalloc(&c->d_boxabs, n_boxes)) != hipSuccess ||
         (e = dalloc(&c->d_fsum, (size_t)4 * n_boxes)) != hipSuccess ||
-        (e = dalloc(&c->d_feed, n_boxes)) != hipSuccess || (e = dalloc(&c->d_pfirst, cells)) != hipSuccess)
+        (e = dalloc(&c->d_feed, n_boxes)) != hipSuccess || (e = dalloc(&c->d_pfirst, cells)) != hipSuccess ||
+        (e = dalloc(&c->d_seg, 2 * ((size_t)n_boxes + 1))) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
+    c->cpp.assign(n_boxes, 1.0);
+    c->tiled.assign(n_boxes, 1);         // the tile table starts with every box; emit narrows it
     build_tiles(c);
     const size_t nt = c->tiles.size();
     if ((e = dalloc(&c->d_tiles, nt)) != hipSuccess || (e = dalloc(&c->d_texits[0], nt)) != hipSuccess ||
@@ -634,10 +921,6 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *
     HIP_TRY(c, launch_allocate(c->d_pack, c->d_walk, nb, c->max_blk, c->d_q, c->d_bsum, c->d_red, c->d_npk,
                                c->d_pfirst, c->stream));
     c->cop_valid = false;
-    if (c->kernel == 2) {
-        mc_lya_status st = ensure_tile_buffers(c, ntot);
-        if (st != MC_LYA_OK) return st;
-    }
     HIP_TRY(c, hipMemsetAsync(c->d_A, 0, sizeof(unsigned long long) * c->total_cells, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_tot, 0, sizeof(BoxTot) * nb, c->stream));
     c->state = 1;
@@ -792,10 +1075,6 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     switch (option) {
     case MC_LYA_OPT_KERNEL:
         if (v < 0 || v > 2) return fail(c, MC_LYA_EINVAL, "kernel must be 0, 1 or 2");
-        if (v == 2 && c->state >= 1) {
-            mc_lya_status st = ensure_tile_buffers(c, c->total_packets);
-            if (st != MC_LYA_OK) return st;
-        }
         c->kernel = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_BLOCK:
@@ -825,11 +1104,114 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     case MC_LYA_OPT_TIMING:
         c->timing = v != 0;
         return MC_LYA_OK;
+    case MC_LYA_OPT_TILE_SHARE:
+        if (v < 0 || v > kAllTiled) return fail(c, MC_LYA_EINVAL, "tile share must be in [0, 1000000]");
+        c->tile_share = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_GRAPH_GENS:
+        if (v < kGenRound || v > kMaxGenerations)
+            return fail(c, MC_LYA_EINVAL, "graph generations must be in [16, 4096]");
+        c->graph_gens = (int)v;
+        return MC_LYA_OK;
     case MC_LYA_OPT_GRAPH:
-        if (v != 0) return fail(c, MC_LYA_EINVAL, "graph replay is not available in this build");
+        if (v != 0 && v != 1) return fail(c, MC_LYA_EINVAL, "graph must be 0 or 1");
+        c->graph = v == 1;
         return MC_LYA_OK;
     }
     return fail(c, MC_LYA_EINVAL, "unknown option");
+}
+
+mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *result)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_autotune before mc_lya_emit");
+    if (reps < 1 || reps > 100) return fail(c, MC_LYA_EINVAL, "reps must be in [1, 100]");
+    struct Opts {
+        int kernel, share, block, waves, chunk, refill;
+        bool operator==(const Opts &o) const
+        {
+            return kernel == o.kernel && share == o.share && block == o.block && waves == o.waves &&
+                   chunk == o.chunk && refill == o.refill;
+        }
+    };
+    const Opts start{c->kernel, c->tile_share, c->block, c->waves_per_cu, c->chunk, c->refill};
+    std::vector<Opts> cand = {start};
+    const Opts fixed[] = {
+        {2, 100, 256, 32, 256, 16}, {2, 50, 256, 32, 256, 16}, {2, 25, 256, 32, 256, 16},
+        {2, 100, 256, 32, 256, 8},  {2, 100, 256, 32, 256, 32}, {2, 100, 256, 32, 64, 16},
+        {0, 100, 256, 32, 256, 16}, {0, 100, 256, 16, 256, 16}, {0, 100, 256, 32, 64, 16},
+        {0, 100, 256, 32, 256, 32}, {0, 100, 128, 32, 256, 16},
+    };
+    for (const Opts &o : fixed)
+        if (std::find(cand.begin(), cand.end(), o) == cand.end()) cand.push_back(o);
+    const bool timing = c->timing;
+    c->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto finish = [&](mc_lya_status st) {
+        c->timing = timing;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return st;
+    };
+    auto reset = [&]() -> mc_lya_status {
+        HIP_TRY(c, hipMemsetAsync(c->d_A, 0, sizeof(unsigned long long) * c->total_cells, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->d_tot, 0, sizeof(BoxTot) * c->n_boxes, c->stream));
+        std::fill(c->walked.begin(), c->walked.end(), 0);
+        c->state = 1;
+        return MC_LYA_OK;
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return finish(fail(c, MC_LYA_EDEVICE, "event creation"));
+    double best = 1e300, first_ms = 0.0;
+    Opts pick = start;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        const Opts &o = cand[i];
+        c->kernel = o.kernel;
+        c->tile_share = o.share;
+        c->block = o.block;
+        c->waves_per_cu = o.waves;
+        c->chunk = o.chunk;
+        c->refill = o.refill;
+        double t_min = 1e300;
+        for (int r = 0; r <= reps; ++r) {      // the first run warms up (captures, allocations)
+            mc_lya_status st = reset();
+            if (st != MC_LYA_OK) return finish(st);
+            if (hipEventRecord(e0, c->stream) != hipSuccess) return finish(fail(c, MC_LYA_EDEVICE, "event"));
+            st = launch_walk(c, 0, c->total_packets);
+            if (st != MC_LYA_OK) return finish(st);
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return finish(fail(c, MC_LYA_EDEVICE, "event"));
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return finish(fail(c, MC_LYA_EDEVICE, "event"));
+            if (r > 0) t_min = std::min(t_min, (double)ms);
+        }
+        if (i == 0) first_ms = t_min;
+        if (t_min < best) {
+            best = t_min;
+            pick = o;
+        }
+    }
+    c->kernel = pick.kernel;
+    c->tile_share = pick.share;
+    c->block = pick.block;
+    c->waves_per_cu = pick.waves;
+    c->chunk = pick.chunk;
+    c->refill = pick.refill;
+    mc_lya_status st = reset();
+    if (st != MC_LYA_OK) return finish(st);
+    if (result) {
+        result->kernel = pick.kernel;
+        result->tile_share = pick.share;
+        result->block = pick.block;
+        result->waves_per_cu = pick.waves;
+        result->chunk = pick.chunk;
+        result->refill = pick.refill;
+        result->best_ms = best;
+        result->start_ms = first_ms;
+        result->trials = (int32_t)cand.size();
+        result->reserved = 0;
+    }
+    return finish(MC_LYA_OK);
 }
 
 mc_lya_status mc_lya_kernel_time(mc_lya_ctx *c, double *ms, int64_t *launches)

@@ -136,6 +136,12 @@ struct WalkParams {
     int64_t max_cross;
     int32_t chunk, refill;
     int32_t nqueues;         // parts of the packet range (1..kMaxQueues)
+    // optional: the range [0, count) is a concatenation of n_seg global packet
+    // segments; segment k starts at index seg_start[k] (ascending, seg_start[0]
+    // = 0) and global id seg_id[k]. n_seg = 0: packet i is global id first + i.
+    int32_t n_seg;
+    const uint64_t *seg_start;
+    const uint64_t *seg_id;
 };
 constexpr int kMaxQueues = 64;
 

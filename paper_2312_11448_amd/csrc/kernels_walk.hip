@@ -96,6 +96,18 @@ __device__ __forceinline__ int box_of(const WalkBox *boxes, int n_boxes, uint64_
     return lo;
 }
 
+// Global packet id of index i of the walked range.
+__device__ __forceinline__ uint64_t packet_id(const WalkParams &P, uint64_t i)
+{
+    if (P.n_seg == 0) return P.first + i;
+    int lo = 0, hi = P.n_seg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.seg_start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return P.seg_id[lo] + (i - P.seg_start[lo]);
+}
+
 // ---- persistent driver ---------------------------------------------------
 template <bool VEL>
 __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
@@ -146,7 +158,7 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
                 uint64_t gp = 0;
                 int nb = acc.box;
                 if (fresh) {
-                    gp = P.first + cur + r;
+                    gp = packet_id(P, cur + r);
                     nb = P.n_boxes == 1 ? 0 : box_of(sbox, P.n_boxes, gp);
                 }
                 const bool change = fresh && nb != acc.box;
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(256) void walk_simple_kernel(WalkParams P)
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Acc acc{-1, 0, 0, 0, 0};
     if (i < P.count) {
-        const uint64_t gp = P.first + i;
+        const uint64_t gp = packet_id(P, i);
         const int nb = P.n_boxes == 1 ? 0 : box_of(sbox, P.n_boxes, gp);
         const WalkBox &B = sbox[nb];
         Lane L;

@@ -108,6 +108,11 @@ class Simulation:
     def set_option(self, option, value):
         A.mc_lya_set_option(self.ctx, option, value)
 
+    def autotune(self, reps=1):
+        """Times the built-in option sets on the current emission, keeps the
+        fastest; the context is left as after emit. Returns the result struct."""
+        return A.mc_lya_autotune(self.ctx, reps)
+
     def kernel_time(self):
         return A.mc_lya_kernel_time(self.ctx)
 

@@ -25,6 +25,7 @@ if not torch.cuda.is_available():
 import paper_2312_11448_amd as M  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ALL_TILED = 1_000_000            # MC_LYA_OPT_TILE_SHARE value that tiles every box
 
 
 def _say(msg):
@@ -129,6 +130,8 @@ def test_launch_configuration_and_ranges_bitwise():
     variants = [
         {M.MC_LYA_OPT_KERNEL: 1},
         {M.MC_LYA_OPT_KERNEL: 0},
+        {M.MC_LYA_OPT_KERNEL: 2, M.MC_LYA_OPT_TILE_SHARE: ALL_TILED},
+        {M.MC_LYA_OPT_KERNEL: 2, M.MC_LYA_OPT_TILE_SHARE: 0},
         {M.MC_LYA_OPT_BLOCK: 64, M.MC_LYA_OPT_WAVES_PER_CU: 8},
         {M.MC_LYA_OPT_CHUNK: 7, M.MC_LYA_OPT_REFILL: 1, M.MC_LYA_OPT_QUEUES: 1},
         {M.MC_LYA_OPT_QUEUES: 64, M.MC_LYA_OPT_CHUNK: 1},
@@ -274,9 +277,109 @@ def test_tiled_walk_equals_global_walk(shape):
     vel = rng.normal(0.0, 0.15, size=(3,) + shape[::-1]).astype(np.float32)
     spec = W.BoxSpec(n=shape, overdensity=od, velocity=vel, n_packets=60_000, seed=5)
     ref = gpu_run(spec, options={M.MC_LYA_OPT_KERNEL: 0})
-    for opts in ({M.MC_LYA_OPT_KERNEL: 2}, ):
-        g = gpu_run(spec, options=opts)
-        assert np.array_equal(g["A"], ref["A"])
-        assert g["escaped"] == ref["escaped"] and g["crossings"] == ref["crossings"]
-    part = gpu_run(spec, options={M.MC_LYA_OPT_KERNEL: 2}, ranges=[(0, 17), (17, 31000), (31000, 60000)])
+    tiled = {M.MC_LYA_OPT_KERNEL: 2, M.MC_LYA_OPT_TILE_SHARE: ALL_TILED}
+    g = gpu_run(spec, options=tiled)
+    assert np.array_equal(g["A"], ref["A"])
+    assert g["escaped"] == ref["escaped"] and g["crossings"] == ref["crossings"]
+    part = gpu_run(spec, options=tiled, ranges=[(0, 17), (17, 31000), (31000, 60000)])
     assert np.array_equal(part["A"], ref["A"])
+
+
+def _batch_run(boxes, options, ranges=None):
+    with M.Simulation(boxes) as sim:
+        sim.set_option(M.MC_LYA_OPT_TIMING, 1)
+        for k, v in options.items():
+            sim.set_option(k, v)
+        sim.emit()
+        if ranges is None:
+            sim.transport()
+        else:
+            for a, b in ranges:
+                sim.transport(a, b - a)
+        t = sim.tally()
+        _, launches = sim.kernel_time()
+        return (t["absorbed"].cpu().numpy(), [(s.escaped, s.crossings, s.conserved) for s in t["stats"]],
+                launches)
+
+
+def test_mixed_tiled_and_persistent_batch():
+    """Kernel 2 on a batch walks boxes with enough tiles by tiles and a box
+    with a single, crowded tile by the persistent walk, in the same
+    transport; the integers equal those of either walk alone, also over
+    packet ranges that cut through boxes."""
+    boxes = [W.make_box("c2", n=64, n_packets=20_000, field_seed=11, seed=1),
+             W.make_box("c2", n=16, n_packets=100_000, field_seed=12, seed=2),
+             W.make_box("c2", n=40, n_packets=5_000, field_seed=13, seed=3)]
+    ref_A, ref_s, _ = _batch_run(boxes, {M.MC_LYA_OPT_KERNEL: 0})
+    assert all(c == 1 for _, _, c in ref_s)
+    tiled_A, tiled_s, n_tiled = _batch_run(boxes, {M.MC_LYA_OPT_TILE_SHARE: ALL_TILED})
+    mixed_A, mixed_s, n_mixed = _batch_run(boxes, {})
+    # all-tiled: whole rounds of 16 generations; mixed: the same plus one persistent launch
+    assert n_tiled % 16 == 0 and n_mixed % 16 == 1
+    assert np.array_equal(tiled_A, ref_A) and tiled_s == ref_s
+    assert np.array_equal(mixed_A, ref_A) and mixed_s == ref_s
+    split_A, split_s, _ = _batch_run(boxes, {}, ranges=[(0, 15_000), (15_000, 118_000), (118_000, 125_000)])
+    assert np.array_equal(split_A, ref_A) and split_s == ref_s
+
+
+def _low_z_box(n, packets, seed):
+    """A box at z = 830: small opacity, packets walk hundreds of cells."""
+    b = W.make_box("c2", n=n, n_packets=packets, field_seed=20 + seed, seed=seed)
+    b.z = 830.0
+    b.temp_K = 2.7255 * 831.0
+    return b
+
+
+def test_graph_replay_equals_eager():
+    """MC_LYA_OPT_GRAPH: the captured transport (tile generations plus the
+    persistent walk of the untiled box), replayed over several emissions with
+    eager work in between, gives the eager integers every time; a replay that
+    needs more generations than were captured finishes eagerly and the next
+    capture takes enough."""
+    boxes = [W.make_box("c2", n=64, n_packets=20_000, field_seed=11, seed=1),
+             W.make_box("c2", n=16, n_packets=100_000, field_seed=12, seed=2),
+             _low_z_box(40, 5_000, 3)]
+    seeds_list = [[1, 2, 3], [7, 8, 9], [1, 2, 3]]
+    eager = []
+    for seeds in seeds_list[:2]:
+        with M.Simulation(boxes) as sim:
+            sim.emit(seeds)
+            sim.transport()
+            t = sim.tally()
+            eager.append((t["absorbed"].cpu().numpy(), [(s.escaped, s.crossings) for s in t["stats"]]))
+    eager.append(eager[0])
+    with M.Simulation(boxes) as sim:
+        sim.set_option(M.MC_LYA_OPT_GRAPH, 1)
+        sim.set_option(M.MC_LYA_OPT_GRAPH_GENS, 16)
+        sim.set_option(M.MC_LYA_OPT_TIMING, 1)
+        launches = []
+        for seeds, (ref_A, ref_s) in zip(seeds_list, eager):
+            sim.emit(seeds)
+            sim.transport()
+            t = sim.tally()
+            launches.append(sim.kernel_time()[1])
+            assert np.array_equal(t["absorbed"].cpu().numpy(), ref_A)
+            assert [(s.escaped, s.crossings) for s in t["stats"]] == ref_s
+            assert all(s.conserved == 1 for s in t["stats"])
+        _say(f"  launches per transport (graph replay + eager rounds): {launches}")
+        # the first replay ran out of captured generations; later ones did not
+        assert launches[0] > 1 and launches[1] == 1 and launches[2] == 1
+
+
+def test_autotune_changes_speed_only():
+    boxes = [W.make_box("c2", n=48, n_packets=60_000, field_seed=31, seed=4),
+             _low_z_box(24, 20_000, 5)]
+    with M.Simulation(boxes) as sim:
+        sim.emit()
+        sim.transport()
+        ref = sim.tally()
+        sim.emit()
+        r = sim.autotune(1)
+        _say(f"  tuned: kernel {r.kernel} share {r.tile_share} block {r.block} waves {r.waves_per_cu} "
+             f"chunk {r.chunk} refill {r.refill}: {r.best_ms:.3f} ms (start {r.start_ms:.3f} ms, "
+             f"{r.trials} trials)")
+        assert r.trials >= 11 and r.best_ms <= r.start_ms
+        sim.transport()
+        t = sim.tally()
+        assert np.array_equal(t["absorbed"].cpu().numpy(), ref["absorbed"].cpu().numpy())
+        assert [s.escaped for s in t["stats"]] == [s.escaped for s in ref["stats"]]
