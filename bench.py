@@ -46,7 +46,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "batch"],
+                    help="c2: the 128^3 workload (default); batch: 64 uneven boxes in one context")
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=None,
+                    help="replay each transport as a captured HIP graph (default 0)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the walk options on the first emission, before the warm-up")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,24 +116,45 @@ def calibrate_copy(mib):
                       "launches": 5}), flush=True)
 
 
-def cpu_baseline(spec, budget_s):
-    """The oracle as it is, on the host's cores, over consecutive packet
-    blocks of the same workload until the time budget is spent."""
+def workload_name(config, specs):
+    if config == "batch":
+        return (f"batch of {len(specs)} boxes, N ~ U{{16..96}}, z ~ U[800, 1400], k^2 GRF rms ~ U[0.2, 2] "
+                f"+ curl-free flow (rms 0.1 v_th), T = T0 (1+z), x_e = 0.1, "
+                f"{specs[0].n_packets:.0e} packets per box")
+    return specs[0].name
+
+
+def cpu_baseline(specs, budget_s):
+    """The oracle as it is, on the host's cores, over packet blocks of the same
+    workload (one fiftieth of a box's packets per block, boxes in turn) until
+    the time budget of oracle transport is spent."""
     from oracle import walker
-    prep = walker.Prepared(spec)
     threads = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
-    n = spec.n_packets
-    block = max(1, n // 50)
-    done, cross = 0, 0
-    t0 = time.perf_counter()
-    while done < n and time.perf_counter() - t0 < budget_s:
-        r = prep.transport(done, min(n, done + block), nthreads=threads)
-        cross += r["crossings"]
-        done = min(n, done + block)
-    dt = time.perf_counter() - t0
-    return {"value": cross / dt, "unit": "crossings/s", "cores": threads, "kind": "oracle",
-            "sample": f"packets [0, {done}) of {n} of the same workload "
-                      f"({cross} crossings in {dt:.1f} s, FP64 C + OpenMP)"}
+    preps = [None] * len(specs)
+    done = [0] * len(specs)
+    cross, spent, blocks = 0, 0.0, 0
+    while spent < budget_s and any(d < s.n_packets for d, s in zip(done, specs)):
+        for i, spec in enumerate(specs):
+            n = spec.n_packets
+            if done[i] >= n or spent >= budget_s:
+                continue
+            if preps[i] is None:
+                preps[i] = walker.Prepared(spec)
+            block = max(1, n // 50)
+            t0 = time.perf_counter()
+            r = preps[i].transport(done[i], min(n, done[i] + block), nthreads=threads)
+            spent += time.perf_counter() - t0
+            cross += r["crossings"]
+            done[i] = min(n, done[i] + block)
+            blocks += 1
+    walked = sum(done)
+    total = sum(s.n_packets for s in specs)
+    where = (f"packets [0, {done[0]}) of {total}" if len(specs) == 1 else
+             f"{blocks} blocks of 1/50 of a box's packets over {sum(d > 0 for d in done)} of "
+             f"{len(specs)} boxes ({walked} of {total} packets)")
+    return {"value": cross / spent, "unit": "crossings/s", "cores": threads, "kind": "oracle",
+            "sample": f"{where} of the same workload ({cross} crossings in {spent:.1f} s of oracle "
+                      f"transport, FP64 C + OpenMP)"}
 
 
 def main():
@@ -146,11 +172,20 @@ def main():
     import workloads as W
     import paper_2312_11448_amd as M
 
-    spec = W.make_box(a.config)
+    specs = W.batch_specs() if a.config == "batch" else [W.make_box(a.config)]
     dev = torch.device("cuda:0")
-    sim = M.Simulation(spec, device=dev)
+    sim = M.Simulation(specs, device=dev)
     sim.set_option(M.MC_LYA_OPT_TIMING, 1)
-    seeds, npk = [spec.seed], [spec.n_packets]
+    graph = a.graph if a.graph is not None else 0
+    sim.set_option(M.MC_LYA_OPT_GRAPH, graph)
+    seeds, npk = [s.seed for s in specs], [s.n_packets for s in specs]
+    tuned = None
+    if a.autotune:
+        sim.emit(seeds, npk)
+        r = sim.autotune(1)
+        tuned = {"kernel": r.kernel, "tile_share": r.tile_share, "block": r.block,
+                 "waves_per_cu": r.waves_per_cu, "chunk": r.chunk, "refill": r.refill,
+                 "transport_ms": r.best_ms, "default_ms": r.start_ms}
 
     def step():
         sim.refresh()
@@ -168,10 +203,10 @@ def main():
     cross = 0
     for _ in range(a.steps):
         t, f = step()
-        st = t["stats"][0]
-        if st.conserved != 1 or st.capped_packets:
-            raise SystemExit("conservation identity failed")
-        cross += st.crossings
+        for st in t["stats"]:
+            if st.conserved != 1 or st.capped_packets:
+                raise SystemExit("conservation identity failed")
+            cross += st.crossings
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
     kms, launches = sim.kernel_time()
@@ -179,7 +214,7 @@ def main():
     # time and bytes are both taken per step
     walk_s = kms / 1e3 / a.steps
     cross_per_step = cross / a.steps
-    bpc = BYTES_PER_CROSSING_VEL if spec.velocity is not None else BYTES_PER_CROSSING_NOVEL
+    bpc = BYTES_PER_CROSSING_VEL if specs[0].velocity is not None else BYTES_PER_CROSSING_NOVEL
     achieved = bpc * cross_per_step / walk_s / 1e9
     traffic = None
     if os.path.exists(a.traffic):
@@ -200,7 +235,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": spec.name, "cells": spec.ncells, "packets": spec.n_packets,
+        "config": {"workload": workload_name(a.config, specs), "cells": sum(x.ncells for x in specs),
+                   "packets": sum(npk), "graph": graph, "autotuned": tuned,
                    "crossings_per_step": cross_per_step,
                    "walk_ms": walk_s * 1e3,
                    "walk_launches_per_step": launches / a.steps,
@@ -213,7 +249,7 @@ def main():
     }
     sim.close()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(specs, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
