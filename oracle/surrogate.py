@@ -1,0 +1,149 @@
+"""FP64 oracle of the per-cell surrogate for the Lyman-alpha mixing correction.
+
+TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the benchmark's
+CPU-baseline leg use this module. It is written independently of the HIP
+library.
+
+What is approximated. The Monte Carlo gives, per cell, the absorbed weight A_c
+and from it the mixing correction M_c = A_c / A_c^fm, with A_c^fm the
+absorption the cell would receive under full mixing (absorptions spread like
+n_1s, Sec. IV.B, Eq. (dotne-mix)). M = 1 everywhere is full mixing; local
+absorption (short mixing length, Sec. III.B, Fig. MCtravel) makes M follow the
+local emission. The surrogate regresses y = ln M_c on eight local features of
+the cell with a small multilayer perceptron, so that the correction can be
+evaluated without the transport.
+
+Features, per cell c of a periodic box (all plain definitions):
+  0  ln Delta_c
+  1  mean of Delta over the 3x3x3 cells centred on c
+  2  variance of Delta over the same 27 cells (mean of squared deviations)
+  3  div U at c by central differences, (U_x[i+1] - U_x[i-1]) / 2 + (y) + (z),
+     in thermal velocities per cell (0 without a flow)
+  4  ln(T / 3000 K)
+  5  x_e at c
+  6  z / 1000 - 1.1
+  7  0 (padding)
+
+Network: 8 -> 64 -> 64 -> 1 with SiLU activations, silu(z) = z / (1 + e^-z).
+Parameters are one flat vector of 4801 numbers:
+  W1 [64][8] at 0, b1 [64] at 512, W2 [64][64] at 576, b2 [64] at 4672,
+  w3 [64] at 4736, b3 at 4800;  row-major [out][in].
+Loss: weighted mean squared error sum_i w_i (y_i - t_i)^2 / sum_i w_i.
+Optimiser: Adam (Kingma & Ba 2015, Algorithm 1) with bias correction.
+"""
+import numpy as np
+
+N_FEAT = 8
+HIDDEN = 64
+OFF_W1, OFF_B1, OFF_W2, OFF_B2, OFF_W3, OFF_B3 = 0, 512, 576, 4672, 4736, 4800
+N_PARAMS = 4801
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+# --- features ----------------------------------------------------------------
+def features(overdensity, velocity=None, x_e=0.1, temp_K=3000.0, z=1100.0):
+    """[cells, 8] features of a box; arrays are [z][y][x] (velocity [3][z][y][x])."""
+    od = _f64(overdensity)
+    nz, ny, nx = od.shape
+    s = np.zeros_like(od)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                s += np.roll(od, (dz, dy, dx), axis=(0, 1, 2))
+    mean = s / 27.0
+    ss = np.zeros_like(od)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                d = np.roll(od, (dz, dy, dx), axis=(0, 1, 2)) - mean
+                ss += d * d
+    var = ss / 27.0
+    div = np.zeros_like(od)
+    if velocity is not None:
+        v = _f64(velocity)
+        # component a varies along array axis 2 - a (x is the last axis);
+        # roll by -1 brings cell i+1 to position i
+        for a in range(3):
+            ax = 2 - a
+            div += 0.5 * (np.roll(v[a], -1, axis=ax) - np.roll(v[a], 1, axis=ax))
+    xe = _f64(x_e) * np.ones_like(od) if np.ndim(x_e) == 0 else _f64(x_e).reshape(od.shape)
+    f = np.zeros((od.size, N_FEAT))
+    f[:, 0] = np.log(od).reshape(-1)
+    f[:, 1] = mean.reshape(-1)
+    f[:, 2] = var.reshape(-1)
+    f[:, 3] = div.reshape(-1)
+    f[:, 4] = np.log(temp_K / 3000.0)
+    f[:, 5] = xe.reshape(-1)
+    f[:, 6] = z / 1000.0 - 1.1
+    return f
+
+
+# --- network -----------------------------------------------------------------
+def unpack(params):
+    p = _f64(params)
+    W1 = p[OFF_W1:OFF_B1].reshape(HIDDEN, N_FEAT)
+    b1 = p[OFF_B1:OFF_W2]
+    W2 = p[OFF_W2:OFF_B2].reshape(HIDDEN, HIDDEN)
+    b2 = p[OFF_B2:OFF_W3]
+    w3 = p[OFF_W3:OFF_B3]
+    b3 = p[OFF_B3]
+    return W1, b1, W2, b2, w3, b3
+
+
+def pack(W1, b1, W2, b2, w3, b3):
+    return np.concatenate([_f64(W1).reshape(-1), _f64(b1), _f64(W2).reshape(-1), _f64(b2), _f64(w3),
+                           [float(b3)]])
+
+
+def silu(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def silu_grad(z):
+    s = 1.0 / (1.0 + np.exp(-z))
+    return s * (1.0 + z * (1.0 - s))
+
+
+def forward(params, X):
+    """y [n] and the intermediate values of the network on features X [n, 8]."""
+    W1, b1, W2, b2, w3, b3 = unpack(params)
+    X = _f64(X)
+    z1 = X @ W1.T + b1
+    h1 = silu(z1)
+    z2 = h1 @ W2.T + b2
+    h2 = silu(z2)
+    y = h2 @ w3 + b3
+    return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def loss_and_grad(params, X, t, w):
+    """Weighted MSE and its gradient with respect to the 4801 parameters
+    (the chain rule written out layer by layer)."""
+    W1, b1, W2, b2, w3, b3 = unpack(params)
+    y, c = forward(params, X)
+    w = _f64(w)
+    sw = w.sum()
+    r = y - _f64(t)
+    L = float((w * r * r).sum() / sw)
+    gy = 2.0 * w * r / sw                       # dL/dy
+    gw3 = c["h2"].T @ gy
+    gb3 = gy.sum()
+    gz2 = np.outer(gy, w3) * silu_grad(c["z2"])
+    gW2 = gz2.T @ c["h1"]
+    gb2 = gz2.sum(axis=0)
+    gz1 = (gz2 @ W2) * silu_grad(c["z1"])
+    gW1 = gz1.T @ c["X"]
+    gb1 = gz1.sum(axis=0)
+    return L, pack(gW1, gb1, gW2, gb2, gw3, gb3)
+
+
+def adam_step(params, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (step counts from 1); returns new (params, m, v)."""
+    m = beta1 * _f64(m) + (1.0 - beta1) * _f64(g)
+    v = beta2 * _f64(v) + (1.0 - beta2) * _f64(g) * _f64(g)
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return _f64(params) - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -1,0 +1,171 @@
+"""Pins of the surrogate oracle (features, network, loss gradient, Adam)
+against closed forms, finite differences and hand-built networks."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+
+def _sine_box(n, amp, axis):
+    """Delta = 1 + amp sin(2 pi i / n) along one array axis."""
+    i = np.arange(n)
+    prof = 1.0 + amp * np.sin(2.0 * np.pi * i / n)
+    shape = [1, 1, 1]
+    shape[axis] = n
+    return np.broadcast_to(prof.reshape(shape), (n, n, n)).copy(), prof
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_neighbourhood_mean_and_variance_closed_form(axis):
+    """For Delta varying along one axis as 1 + a sin(theta), the 27 cells hold
+    the three values at theta - h, theta, theta + h nine times each:
+    mean = 1 + a sin(theta)(1 + 2 cos h)/3 and the variance is the spread of
+    those three values."""
+    n, a = 16, 0.4
+    od, _ = _sine_box(n, a, axis)
+    f = S.features(od)
+    h = 2.0 * math.pi / n
+    theta = 2.0 * math.pi * np.arange(n) / n
+    mean = 1.0 + a * np.sin(theta) * (1.0 + 2.0 * math.cos(h)) / 3.0
+    vals = np.stack([a * np.sin(theta - h), a * np.sin(theta), a * np.sin(theta + h)])
+    var = (vals ** 2).mean(axis=0) - vals.mean(axis=0) ** 2
+    idx = [0, 0, 0]
+    got_m, got_v = [], []
+    for i in range(n):
+        idx[axis] = i
+        c = (idx[0] * n + idx[1]) * n + idx[2]
+        got_m.append(f[c, 1])
+        got_v.append(f[c, 2])
+    assert np.allclose(got_m, mean, rtol=0, atol=1e-13)
+    assert np.allclose(got_v, var, rtol=0, atol=1e-13)
+    assert np.allclose(np.exp(f[:, 0]), od.reshape(-1), rtol=1e-14)
+
+
+@pytest.mark.parametrize("comp", [0, 1, 2])
+def test_divergence_central_difference_closed_form(comp):
+    """U_comp = b sin(2 pi k / n) along its own coordinate k: the central
+    difference is b cos(theta) sin(h); components along other axes add nothing."""
+    n, b = 12, 0.3
+    od = np.ones((n, n, n))
+    vel = np.zeros((3, n, n, n))
+    i = np.arange(n)
+    prof = b * np.sin(2.0 * np.pi * i / n)
+    axis = 2 - comp                 # x is the last array axis
+    shape = [1, 1, 1]
+    shape[axis] = n
+    vel[comp] = np.broadcast_to(prof.reshape(shape), (n, n, n))
+    # a transverse component (varies across its own direction) has no divergence
+    other = (comp + 1) % 3
+    vel[other] = np.broadcast_to(prof.reshape(shape), (n, n, n))
+    f = S.features(od, vel)
+    h = 2.0 * math.pi / n
+    want = b * np.cos(2.0 * math.pi * i / n) * math.sin(h)
+    idx = [0, 0, 0]
+    for k in range(n):
+        idx[axis] = k
+        c = (idx[0] * n + idx[1]) * n + idx[2]
+        assert abs(f[c, 3] - want[k]) < 1e-14
+
+
+def test_scalar_features():
+    od = np.full((4, 4, 4), 2.0)
+    f = S.features(od, None, x_e=0.25, temp_K=3000.0 * math.e, z=800.0)
+    assert np.allclose(f[:, 0], math.log(2.0)) and np.allclose(f[:, 1], 2.0) and np.allclose(f[:, 2], 0.0)
+    assert np.allclose(f[:, 3], 0.0) and np.allclose(f[:, 4], 1.0) and np.allclose(f[:, 5], 0.25)
+    assert np.allclose(f[:, 6], -0.3) and np.allclose(f[:, 7], 0.0)
+
+
+def _random_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, S.N_PARAMS) * np.concatenate(
+        [np.full(512, 1 / math.sqrt(8)), np.full(64, 0.1), np.full(4096, 1 / 8.0), np.full(64, 0.1),
+         np.full(64, 1 / 8.0), [0.1]])
+
+
+def test_hand_built_network():
+    """Only W1[0][0] = W2[0][0] = w3[0] = 1: y = silu(silu(x0)) + b3, with
+    silu(z) = z / (1 + e^-z) evaluated from its definition."""
+    W1 = np.zeros((64, 8)); W1[0, 0] = 1.0
+    W2 = np.zeros((64, 64)); W2[0, 0] = 1.0
+    w3 = np.zeros(64); w3[0] = 1.0
+    p = S.pack(W1, np.zeros(64), W2, np.zeros(64), w3, 0.5)
+    X = np.zeros((5, 8)); X[:, 0] = [-3.0, -0.5, 0.0, 0.7, 4.0]
+    y, _ = S.forward(p, X)
+    sil = lambda z: z / (1.0 + math.exp(-z))
+    want = [sil(sil(x)) + 0.5 for x in X[:, 0]]
+    assert np.allclose(y, want, rtol=0, atol=1e-15)
+    # a hidden unit whose pre-activation is the same for every input adds a
+    # constant: silu(b) through w3
+    b1 = np.zeros(64); b1[5] = 2.0
+    W2b = W2.copy(); W2b[7, 5] = 1.0
+    w3b = w3.copy(); w3b[7] = -1.0
+    y2, _ = S.forward(S.pack(W1, b1, W2b, np.zeros(64), w3b, 0.5), X)
+    assert np.allclose(y2 - y, -sil(sil(2.0)), atol=1e-15)
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    p = _random_params(1)
+    X = rng.normal(size=(40, 8))
+    t = rng.normal(size=40)
+    w = rng.uniform(0.1, 2.0, size=40)
+    L, g = S.loss_and_grad(p, X, t, w)
+    idx = np.concatenate([rng.choice(512, 12, replace=False), 512 + rng.choice(64, 6, replace=False),
+                          576 + rng.choice(4096, 20, replace=False), 4672 + rng.choice(64, 6, replace=False),
+                          4736 + rng.choice(64, 6, replace=False), [4800]])
+    for i in idx:
+        e = np.zeros_like(p)
+        step = 1e-6 * max(1.0, abs(p[i]))
+        e[i] = step
+        Lp, _ = S.loss_and_grad(p + e, X, t, w)
+        Lm, _ = S.loss_and_grad(p - e, X, t, w)
+        fd = (Lp - Lm) / (2 * step)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_loss_is_weighted_mean_and_scale_free():
+    rng = np.random.default_rng(4)
+    p = _random_params(2)
+    X = rng.normal(size=(30, 8))
+    t = rng.normal(size=30)
+    w = rng.uniform(0.0, 1.0, size=30)
+    L1, g1 = S.loss_and_grad(p, X, t, w)
+    L2, g2 = S.loss_and_grad(p, X, t, 7.5 * w)
+    assert abs(L1 - L2) < 1e-14 * L1 and np.allclose(g1, g2, rtol=1e-12, atol=1e-15)
+    y, _ = S.forward(p, X)
+    # equal weights: the plain mean of squared residuals
+    L3, _ = S.loss_and_grad(p, X, t, np.ones(30))
+    assert abs(L3 - np.mean((y - t) ** 2)) < 1e-13
+
+
+def test_adam_constant_gradient_moves_by_lr():
+    """With bias correction and a constant gradient g, m_hat = g and
+    v_hat = g^2 at every step, so each parameter moves by
+    -lr g / (|g| + eps) per step (Kingma & Ba 2015, Sec. 2)."""
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=50)
+    p = rng.normal(size=50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    lr, eps = 1e-3, 1e-8
+    p0 = p.copy()
+    for step in range(1, 6):
+        p, m, v = S.adam_step(p, m, v, g, step, lr, 0.9, 0.999, eps)
+        want = p0 - step * lr * g / (np.abs(g) + eps)
+        assert np.allclose(p, want, rtol=0, atol=1e-15 * step + 1e-16)
+
+
+def test_adam_reaches_minimum_of_quadratic():
+    """On f(x) = sum a_i (x_i - c_i)^2 / 2 Adam converges to c."""
+    rng = np.random.default_rng(6)
+    a = rng.uniform(0.5, 3.0, 20)
+    c = rng.normal(size=20)
+    x = np.zeros(20)
+    m = np.zeros(20)
+    v = np.zeros(20)
+    for step in range(1, 4001):
+        lr = 0.05 if step < 2000 else 0.005
+        x, m, v = S.adam_step(x, m, v, a * (x - c), step, lr)
+    assert np.max(np.abs(x - c)) < 1e-3
