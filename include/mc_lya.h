@@ -271,6 +271,89 @@ mc_lya_status mc_lya_kernel_time(mc_lya_ctx *ctx, double *ms, int64_t *launches)
 mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                                    uint64_t n, void *stream);
 
+/* ---- mixing-correction surrogate ------------------------------------------
+ * A per-cell regression of y = ln M_c, the log of the mixing correction that
+ * mc_lya_feed returns (M_c = A_c / A_c^fm, Sec. IV.B, Eq. (dotne-mix); M = 1
+ * is full mixing), on eight local features, so that the correction can be
+ * evaluated without a transport. The network is 8 -> 64 -> 64 -> 1 with SiLU
+ * activations (silu(z) = z / (1 + e^-z)); its parameters are one float vector
+ * of MC_LYA_MLP_PARAMS numbers: W1 [64][8] at 0, b1 [64] at 512, W2 [64][64]
+ * at 576, b2 [64] at 4672, w3 [64] at 4736, b3 at 4800 (row-major
+ * [out][in]). */
+#define MC_LYA_MLP_PARAMS 4801
+#define MC_LYA_MLP_FEATURES 8
+
+/* Features of every cell of every box, from the fields given to mc_lya_init
+ * (they must still be alive):
+ *   0 ln Delta_c, 1 mean and 2 variance (mean squared deviation) of Delta over
+ *   the 3x3x3 cells around c (periodic), 3 div U by central differences in
+ *   thermal velocities per cell (0 without a flow), 4 ln(T / 3000 K), 5 x_e,
+ *   6 z / 1000 - 1.1, 7 zero.
+ *   out  dev [total cells][8] float, box-major, x fastest
+ * Asynchronous on the context's stream. Errors: EINVAL, ESTATE, EDEVICE. */
+mc_lya_status mc_lya_features(mc_lya_ctx *ctx, float *out);
+
+typedef struct mc_lya_mlp mc_lya_mlp;
+
+/* Adam hyper-parameters (Kingma & Ba 2015, Algorithm 1, bias-corrected). */
+typedef struct mc_lya_adam {
+    float lr, beta1, beta2, eps;
+} mc_lya_adam;
+
+/* Creates a network with the given parameters (host [MC_LYA_MLP_PARAMS],
+ * copied) and zero Adam moments, on the current device; all its work goes on
+ * `stream` (a hipStream_t, or NULL). Allocates about 20 MB (parameters, Adam
+ * moments, the gradient workspace). On failure *out = NULL and
+ * mc_lya_mlp_last_error(NULL) tells why. Errors: EINVAL (NULL or non-finite
+ * parameters), ENOMEM, EDEVICE. */
+mc_lya_status mc_lya_mlp_create(mc_lya_mlp **out, const float *params, void *stream);
+
+/* Copies the current parameters out. params: host [MC_LYA_MLP_PARAMS].
+ * Synchronises. Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_mlp_get_params(mc_lya_mlp *mlp, float *params);
+
+/* Sets the training envelope: host [8] lower and upper bounds per feature
+ * (lo <= hi), or both NULL to clear it. mc_lya_mlp_forward flags cells whose
+ * features fall outside it, for which the Monte Carlo should be used instead.
+ * Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_mlp_set_envelope(mc_lya_mlp *mlp, const float *lo, const float *hi);
+
+/* Inference: y = network(features) for n cells, on the matrix cores with
+ * BF16 weights and activations and FP32 accumulation (biases, activations and
+ * the last layer in FP32).
+ *   features  dev [n][8] float
+ *   y         dev [n] float
+ *   outside   dev [n] uint8 (1 = some feature outside the envelope), or NULL
+ *   n_outside host, or NULL: number of such cells (then synchronises)
+ * Asynchronous otherwise. Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_mlp_forward(mc_lya_mlp *mlp, const float *features, uint64_t n, float *y,
+                                 uint8_t *outside, uint64_t *n_outside);
+
+/* The weighted mean squared error L = sum w_i (y_i - t_i)^2 / sum w_i over n
+ * cells and its gradient with respect to the parameters, in FP32 (cells are
+ * summed in a fixed order: the result is reproducible bit for bit).
+ *   features dev [n][8], targets dev [n], weights dev [n] (>= 0, not all 0)
+ *   grad     host [MC_LYA_MLP_PARAMS], or NULL;  loss host, or NULL
+ * Synchronises. Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_mlp_gradient(mc_lya_mlp *mlp, const float *features, const float *targets,
+                                  const float *weights, uint64_t n, float *grad, float *loss);
+
+/* One training step: the gradient as in mc_lya_mlp_gradient, then one Adam
+ * update of the parameters (the step count starts at 1 and is kept by the
+ * object). loss: host (the loss before the update; then synchronises), or
+ * NULL (asynchronous). Errors: EINVAL (bad hyper-parameters, no cells),
+ * EDEVICE. */
+mc_lya_status mc_lya_mlp_train_step(mc_lya_mlp *mlp, const float *features, const float *targets,
+                                    const float *weights, uint64_t n, const mc_lya_adam *hp,
+                                    float *loss);
+
+/* Frees the network (synchronises its stream). NULL ok. */
+void mc_lya_mlp_destroy(mc_lya_mlp *mlp);
+
+/* Description of the network's last failure, or with NULL of the last failed
+ * mc_lya_mlp_create on this thread. */
+const char *mc_lya_mlp_last_error(const mc_lya_mlp *mlp);
+
 /* Frees the context and its device memory (synchronises its stream). NULL ok. */
 void mc_lya_destroy(mc_lya_ctx *ctx);
 

@@ -7,3 +7,4 @@ holds the device arrays (torch tensors) that the calls read and write.
 from ._abi import *  # noqa: F401,F403
 from ._abi import load, MCLyaError, LIB_PATH  # noqa: F401
 from .sim import Simulation, desc_from_spec  # noqa: F401
+from .mlp import Mlp  # noqa: F401

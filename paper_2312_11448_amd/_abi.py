@@ -64,7 +64,16 @@ class mc_lya_tune_result(C.Structure):
 EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace",
            "mc_lya_set_option", "mc_lya_autotune", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
-           "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error"]
+           "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
+           "mc_lya_features", "mc_lya_mlp_create", "mc_lya_mlp_get_params", "mc_lya_mlp_set_envelope",
+           "mc_lya_mlp_forward", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_destroy",
+           "mc_lya_mlp_last_error"]
+MC_LYA_MLP_PARAMS = 4801
+MC_LYA_MLP_FEATURES = 8
+
+
+class mc_lya_adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class MCLyaError(RuntimeError):
@@ -100,7 +109,8 @@ def load():
     L.mc_lya_kernel_time.argtypes = [vp, P(C.c_double), P(i64)]
     L.mc_lya_philox4x32_10.argtypes = [vp, vp, vp, u64, vp]
     for name in EXPORTS:
-        if name in ("mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error"):
+        if name in ("mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error", "mc_lya_mlp_destroy",
+                    "mc_lya_mlp_last_error"):
             continue
         getattr(L, name).restype = C.c_int
     L.mc_lya_destroy.argtypes = [vp]
@@ -109,6 +119,18 @@ def load():
     L.mc_lya_strerror.restype = C.c_char_p
     L.mc_lya_last_error.argtypes = [vp]
     L.mc_lya_last_error.restype = C.c_char_p
+    fp = P(C.c_float)
+    L.mc_lya_features.argtypes = [vp, vp]
+    L.mc_lya_mlp_create.argtypes = [P(vp), fp, vp]
+    L.mc_lya_mlp_get_params.argtypes = [vp, fp]
+    L.mc_lya_mlp_set_envelope.argtypes = [vp, fp, fp]
+    L.mc_lya_mlp_forward.argtypes = [vp, vp, u64, vp, vp, P(u64)]
+    L.mc_lya_mlp_gradient.argtypes = [vp, vp, vp, vp, u64, fp, fp]
+    L.mc_lya_mlp_train_step.argtypes = [vp, vp, vp, vp, u64, P(mc_lya_adam), fp]
+    L.mc_lya_mlp_destroy.argtypes = [vp]
+    L.mc_lya_mlp_destroy.restype = None
+    L.mc_lya_mlp_last_error.argtypes = [vp]
+    L.mc_lya_mlp_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -207,3 +229,66 @@ def mc_lya_strerror(status):
 
 def mc_lya_last_error(ctx=None):
     return load().mc_lya_last_error(ctx).decode()
+
+
+# ---- mixing-correction surrogate --------------------------------------------
+def mc_lya_features(ctx, out_ptr):
+    return _check(load().mc_lya_features(ctx, out_ptr), ctx)
+
+
+def _check_mlp(status, mlp=None):
+    if status != MC_LYA_OK:
+        L = load()
+        msg = L.mc_lya_mlp_last_error(mlp).decode() or L.mc_lya_strerror(status).decode()
+        raise MCLyaError(status, msg)
+    return status
+
+
+def mc_lya_mlp_create(params, stream=None):
+    """params: sequence of MC_LYA_MLP_PARAMS floats; returns the handle."""
+    L = load()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    arr = (C.c_float * MC_LYA_MLP_PARAMS)(*[float(x) for x in params])
+    h = C.c_void_p()
+    _check_mlp(L.mc_lya_mlp_create(C.byref(h), arr, C.c_void_p(stream)))
+    return h
+
+
+def mc_lya_mlp_get_params(mlp):
+    arr = (C.c_float * MC_LYA_MLP_PARAMS)()
+    _check_mlp(load().mc_lya_mlp_get_params(mlp, arr), mlp)
+    return list(arr)
+
+
+def mc_lya_mlp_set_envelope(mlp, lo, hi):
+    if lo is None:
+        return _check_mlp(load().mc_lya_mlp_set_envelope(mlp, None, None), mlp)
+    return _check_mlp(load().mc_lya_mlp_set_envelope(mlp, _arr(C.c_float, lo), _arr(C.c_float, hi)), mlp)
+
+
+def mc_lya_mlp_forward(mlp, feat_ptr, n, y_ptr, outside_ptr=None, count=False):
+    c = C.c_uint64()
+    _check_mlp(load().mc_lya_mlp_forward(mlp, feat_ptr, int(n), y_ptr, outside_ptr,
+                                         C.byref(c) if count else None), mlp)
+    return c.value if count else None
+
+
+def mc_lya_mlp_gradient(mlp, feat_ptr, t_ptr, w_ptr, n):
+    g = (C.c_float * MC_LYA_MLP_PARAMS)()
+    loss = C.c_float()
+    _check_mlp(load().mc_lya_mlp_gradient(mlp, feat_ptr, t_ptr, w_ptr, int(n), g, C.byref(loss)), mlp)
+    return list(g), loss.value
+
+
+def mc_lya_mlp_train_step(mlp, feat_ptr, t_ptr, w_ptr, n, lr, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=False):
+    hp = mc_lya_adam(lr, beta1, beta2, eps)
+    loss = C.c_float()
+    _check_mlp(load().mc_lya_mlp_train_step(mlp, feat_ptr, t_ptr, w_ptr, int(n), C.byref(hp),
+                                            C.byref(loss) if want_loss else None), mlp)
+    return loss.value if want_loss else None
+
+
+def mc_lya_mlp_destroy(mlp):
+    if mlp:
+        load().mc_lya_mlp_destroy(mlp)

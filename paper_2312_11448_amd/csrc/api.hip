@@ -131,6 +131,8 @@ struct mc_lya_ctx {
     std::vector<uint8_t> tiled;              // per box: walked by tiles (1) or by the persistent walk (0)
     std::vector<double> cpp;                 // per box: estimated crossings per packet (set by refresh)
     std::vector<uint64_t> seg_host;          // packet segments of the persistent part: starts, then ids
+    std::vector<FeatBox> featbox;            // surrogate features: per-box inputs
+    FeatBox *d_featbox = nullptr;
     uint64_t *d_seg = nullptr;               // [2 (n_boxes + 1)]
     int tile_share = 100;
     // captured transport (MC_LYA_OPT_GRAPH)
@@ -183,7 +185,7 @@ void free_all(mc_lya_ctx *c)
     c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_seg, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -982,6 +984,41 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, m
     }
     if (broken) return fail(c, MC_LYA_ECONSERVE, "sum(absorbed) + escaped + capped != w0 * packets");
     if (capped) return fail(c, MC_LYA_ECAP, "some packets reached the crossing cap");
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (!out) return fail(c, MC_LYA_EINVAL, "out is NULL");
+    if (c->state < 0) return fail(c, MC_LYA_ESTATE, "fields failed validation; call mc_lya_refresh");
+    const int nb = c->n_boxes;
+    if (!c->d_featbox) {
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&c->d_featbox), sizeof(FeatBox) * nb);
+        if (e != hipSuccess) return hip_fail(c, e, "feature table allocation");
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
+    c->featbox.resize(nb);
+    for (int b = 0; b < nb; ++b) {
+        const mc_lya_box_desc &d = c->desc[b];
+        FeatBox &f = c->featbox[b];
+        std::memset(&f, 0, sizeof f);
+        f.nx = d.nx;
+        f.ny = d.ny;
+        f.nz = d.nz;
+        f.cell_off = c->pack[b].cell_off;
+        f.ncells = c->pack[b].ncells;
+        f.vel_dtype = d.vel_dtype;
+        f.od = d.overdensity;
+        f.vel = d.velocity;
+        f.xe = d.x_e;
+        f.xe_uniform = d.x_e_uniform;
+        f.ln_t = (float)std::log(d.temp_K / 3000.0);
+        f.z_feat = (float)(d.z / 1000.0 - 1.1);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_featbox, c->featbox.data(), sizeof(FeatBox) * nb, hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, launch_features(c->d_featbox, nb, c->max_blk, out, c->stream));
     return MC_LYA_OK;
 }
 

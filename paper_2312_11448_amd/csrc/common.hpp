@@ -236,4 +236,37 @@ hipError_t launch_feed(const PackBox *pb_dev, const FeedBox *fb_dev, int n_boxes
                        const double *wgt, const unsigned long long *A, double *ndot,
                        float *mix, hipStream_t s);
 
+// ---- mixing-correction surrogate ----------------------------------------------
+// Per-box inputs of the feature kernel.
+struct FeatBox {
+    int32_t nx, ny, nz;
+    uint32_t cell_off, ncells;
+    int32_t vel_dtype;
+    const float *od;
+    const void *vel;
+    const float *xe;
+    float xe_uniform;
+    float ln_t;              // ln(T / 3000 K)
+    float z_feat;            // z / 1000 - 1.1
+    float pad;
+};
+
+constexpr int kMlpParams = 4801;         // 8-64-64-1 network
+constexpr int kMlpPartStride = 4808;     // floats per block of gradient partial sums (params, sum w r^2, sum w)
+constexpr int kMlpGradBlocks = 1024;     // blocks of the gradient kernel
+
+struct MlpAdam {
+    float lr, beta1, beta2, eps;
+    float bc1, bc2;          // 1 - beta1^t, 1 - beta2^t
+};
+
+hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, float *out, hipStream_t s);
+hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, float *y, uint8_t *outside,
+                              const float *lo, const float *hi, unsigned long long *n_out, int grid,
+                              hipStream_t s);
+hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
+                               float *partial, int blocks, float *grad, hipStream_t s);
+hipError_t launch_mlp_normalise(float *grad, hipStream_t s);
+hipError_t launch_mlp_adam(float *params, float *m, float *v, float *grad, const MlpAdam &a, hipStream_t s);
+
 }  // namespace mclya

@@ -1,0 +1,62 @@
+"""Binding of the mixing-correction surrogate network (argument marshalling
+only; the network runs in the HIP library)."""
+import torch
+
+from . import _abi as A
+
+
+class Mlp:
+    """The 8-64-64-1 SiLU network on one device and stream."""
+
+    def __init__(self, params, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self.h = A.mc_lya_mlp_create([float(x) for x in params], self.stream)
+
+    def params(self):
+        return A.mc_lya_mlp_get_params(self.h)
+
+    def set_envelope(self, lo, hi):
+        A.mc_lya_mlp_set_envelope(self.h, lo, hi)
+
+    def forward(self, features, outside=False, count=False):
+        """features: float32 [n, 8] contiguous tensor on the device. Returns y
+        (and the uint8 outside-envelope flags, and their count, if asked)."""
+        f = features.contiguous()
+        n = f.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=self.device)
+        flags = torch.empty(n, dtype=torch.uint8, device=self.device) if outside else None
+        c = A.mc_lya_mlp_forward(self.h, f.data_ptr(), n, y.data_ptr(),
+                                 flags.data_ptr() if flags is not None else None, count)
+        out = [y]
+        if outside:
+            out.append(flags)
+        if count:
+            out.append(c)
+        return out[0] if len(out) == 1 else tuple(out)
+
+    def gradient(self, features, targets, weights):
+        """(gradient [4801] as a list, loss) of the weighted MSE."""
+        return A.mc_lya_mlp_gradient(self.h, features.contiguous().data_ptr(), targets.contiguous().data_ptr(),
+                                     weights.contiguous().data_ptr(), features.shape[0])
+
+    def train_step(self, features, targets, weights, lr, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=False):
+        return A.mc_lya_mlp_train_step(self.h, features.data_ptr(), targets.data_ptr(), weights.data_ptr(),
+                                       features.shape[0], lr, beta1, beta2, eps, want_loss)
+
+    def close(self):
+        if self.h:
+            A.mc_lya_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -99,6 +99,12 @@ class Simulation:
         stats = A.mc_lya_feed(self.ctx, ndot.data_ptr(), mix.data_ptr(), len(self.specs))
         return dict(ndot_e=ndot, mix_corr=mix, stats=stats)
 
+    def features(self):
+        """Surrogate features of every cell: float32 tensor [cells, 8]."""
+        out = torch.empty((self.total_cells, A.MC_LYA_MLP_FEATURES), dtype=torch.float32, device=self.device)
+        A.mc_lya_features(self.ctx, out.data_ptr())
+        return out
+
     def trace(self, first, count):
         buf = torch.empty(int(count) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
         A.mc_lya_trace(self.ctx, first, count, buf.data_ptr())

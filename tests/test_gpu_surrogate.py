@@ -1,0 +1,219 @@
+"""GPU parity of the mixing-correction surrogate (through the C ABI) against
+the FP64 oracle: features, BF16 matrix-core inference, FP32 gradient and
+Adam, the envelope flags.
+
+Tolerances (derived from the arithmetic):
+* features: FP32 sums of at most 27 terms, |error| <= 27 * 2^-24 * sum|terms|
+  per sum; tested as 1e-5 of each feature's natural scale;
+* inference rounds W1, W2, the features and the layer-1 activations to BF16
+  (relative error <= 2^-9 each); first-order propagation through SiLU
+  (|silu'| <= 1.1) gives, per cell,
+    |dy| <= 1.1 sum_m |w3_m| (sum_k |W2_mk| (1.1 e_k + 2^-8 |h1_k|)),
+    e_k = 2^-8 sum_j |W1_kj| |x_j|,
+  and the test allows 1.5 times that plus 1e-5;
+* gradient: FP32 per-cell arithmetic and a two-level FP32 sum over cells,
+  tested as max|g_gpu - g_orc| <= 1e-4 max|g_orc|; loss to 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import surrogate as WS
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2312_11448_amd as M  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _box_features_oracle(spec):
+    return S.features(spec.overdensity, spec.velocity, np.float32(spec.x_e_uniform), spec.temp_K, spec.z)
+
+
+@pytest.mark.parametrize("shape,vel", [((24, 24, 24), True), ((9, 13, 7), True), ((16, 8, 5), False)])
+def test_features_match_oracle(shape, vel):
+    rng = np.random.default_rng(sum(shape))
+    od = rng.lognormal(0.0, 0.7, size=shape[::-1]).astype(np.float32)
+    v = rng.normal(0.0, 0.2, size=(3,) + shape[::-1]).astype(np.float32) if vel else None
+    spec = W.BoxSpec(n=shape, overdensity=od, velocity=v, z=950.0, temp_K=2.7255 * 951, n_packets=1)
+    with M.Simulation(spec) as sim:
+        f = sim.features().cpu().numpy().astype(np.float64)
+    ref = _box_features_oracle(spec)
+    scale = np.array([1.0, ref[:, 1].max(), ref[:, 1].max() ** 2, 0.2 if vel else 1.0, 1.0, 1.0, 1.0, 1.0])
+    err = np.abs(f - ref) / scale
+    _say(f"  worst feature error / scale: {err.max(axis=0)}")
+    assert err.max() <= 1e-5
+
+
+def test_features_of_a_batch_are_per_box():
+    boxes = [W.make_box("c2", n=12, field_seed=3), W.make_box("c1", n=10)]
+    boxes[1].z = 1250.0
+    with M.Simulation(boxes) as sim:
+        f = sim.features().cpu().numpy().astype(np.float64)
+    off = 0
+    for b in boxes:
+        ref = _box_features_oracle(b)
+        assert np.abs(f[off:off + b.ncells] - ref).max() <= 1e-5 * max(1.0, ref[:, 1].max() ** 2)
+        off += b.ncells
+
+
+def _test_params(seed, scale=1.0):
+    p = WS.initial_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    p[512:576] = rng.normal(0.0, 0.3, 64)          # non-zero biases exercise the bias layout
+    p[4672:4736] = rng.normal(0.0, 0.3, 64)
+    p[4800] = 0.25
+    return (p * scale).astype(np.float32)
+
+
+def _forward_bound(p, X):
+    W1, b1, W2, b2, w3, b3 = S.unpack(p)
+    _, c = S.forward(p, X)
+    e1 = 2.0 ** -8 * (np.abs(X) @ np.abs(W1).T)
+    dz2 = (1.1 * e1 + 2.0 ** -8 * np.abs(c["h1"])) @ np.abs(W2).T
+    return 1.1 * (dz2 @ np.abs(w3))
+
+
+def _forward_sigma(p, X):
+    """Standard deviation of the same first-order error when every BF16
+    rounding is an independent error of standard deviation 2^-9/sqrt(3)
+    relative (uniform within half an ulp): the worst case above adds all
+    terms with one sign, this adds their squares."""
+    W1, b1, W2, b2, w3, b3 = S.unpack(p)
+    _, c = S.forward(p, X)
+    u2 = (2.0 ** -9) ** 2 / 3.0
+    v1 = 2.0 * u2 * ((X * X) @ (W1 * W1).T)                  # W1 and x rounded
+    v2 = (1.21 * v1 + 2.0 * u2 * c["h1"] ** 2) @ (W2 * W2).T  # through SiLU; W2 and h1 rounded
+    return np.sqrt(1.21 * (v2 @ (w3 * w3)))
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 1000, 65537])
+def test_forward_matches_oracle_within_bf16_bound(n):
+    rng = np.random.default_rng(n)
+    X = rng.normal(0.0, 1.0, size=(n, 8)).astype(np.float32)
+    X[:, 7] = 0.0
+    p = _test_params(7, 1.5)
+    with M.Mlp(p) as mlp:
+        y = mlp.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    ref, _ = S.forward(p.astype(np.float64), X.astype(np.float64))
+    bound = 1.5 * _forward_bound(p.astype(np.float64), X.astype(np.float64)) + 1e-5
+    sigma = _forward_sigma(p.astype(np.float64), X.astype(np.float64))
+    ratio = np.abs(y - ref) / bound
+    z = np.abs(y - ref) / (sigma + 1e-6)
+    _say(f"  n={n}: max |dy| {np.abs(y - ref).max():.3e}, max |dy|/bound {ratio.max():.3f}, "
+         f"max |dy|/sigma {z.max():.2f}, rms |dy|/sigma {np.sqrt(np.mean(z * z)):.2f}")
+    assert np.all(ratio <= 1.0)
+    # and statistically: no cell beyond 7 sigma, the RMS near one sigma
+    assert z.max() <= 7.0 and np.sqrt(np.mean(z * z)) <= 2.0
+
+
+def test_forward_sampled_at_256cube_size():
+    """The inference launch of the 256^3 box (16.7 M cells): sampled cells
+    against the oracle, and the flags of an envelope against plain float32
+    comparisons (bit-exact)."""
+    spec = W.make_box("c3", n_packets=1)
+    with M.Simulation(spec) as sim:
+        feats = sim.features()
+    idx = np.random.default_rng(1).choice(spec.ncells, 4000, replace=False)
+    X = feats[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    ref_f = _box_features_oracle(spec)[idx]
+    assert np.abs(X - ref_f).max() <= 1e-5 * max(1.0, ref_f[:, 1].max() ** 2)
+    p = _test_params(11)
+    lo = np.quantile(X, 0.02, axis=0).astype(np.float32)
+    hi = np.quantile(X, 0.98, axis=0).astype(np.float32)
+    lo[4:] = -1.0
+    hi[4:] = 1.0
+    with M.Mlp(p) as mlp:
+        mlp.set_envelope(lo, hi)
+        y, flags, count = mlp.forward(feats, outside=True, count=True)
+    y = y.cpu().numpy()[idx].astype(np.float64)
+    ref, _ = S.forward(p.astype(np.float64), X)
+    bound = 1.5 * _forward_bound(p.astype(np.float64), X) + 1e-5
+    assert np.all(np.abs(y - ref) <= bound)
+    f32 = feats.cpu().numpy()
+    want = np.any((f32 < lo) | (f32 > hi), axis=1)
+    got = flags.cpu().numpy().astype(bool)
+    assert np.array_equal(got, want) and count == int(want.sum())
+    _say(f"  {count} of {spec.ncells} cells outside the envelope")
+
+
+def _train_data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0.0, 1.0, size=(n, 8))
+    X[:, 7] = 0.0
+    t = np.tanh(X[:, 0]) + 0.3 * X[:, 1] * X[:, 2] - 0.2 * X[:, 3]
+    w = rng.uniform(0.0, 2.0, size=n)
+    return X.astype(np.float32), t.astype(np.float32), w.astype(np.float32)
+
+
+def test_gradient_matches_oracle():
+    X, t, w = _train_data(20000, 3)
+    p = _test_params(5)
+    with M.Mlp(p) as mlp:
+        g, loss = mlp.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda(), torch.from_numpy(w).cuda())
+        g2, loss2 = mlp.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda(), torch.from_numpy(w).cuda())
+    g = np.array(g)
+    L, gref = S.loss_and_grad(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64), w.astype(np.float64))
+    _say(f"  loss gpu {loss:.7g} orc {L:.7g}; max |dg| / max |g| = {np.abs(g - gref).max() / np.abs(gref).max():.2e}")
+    assert abs(loss - L) <= 1e-5 * L
+    assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max()
+    assert np.array_equal(g, np.array(g2)) and loss == loss2      # fixed summation order
+
+
+def test_adam_steps_match_oracle():
+    """One step: the oracle's Adam on the oracle's gradient; coordinates with
+    a clear gradient move by the same amount (Adam's first step is about
+    -lr sign(g)). Thirty steps: the same loss trajectory; two runs identical."""
+    X, t, w = _train_data(8192, 4)
+    p = _test_params(6)
+    lr = 1e-3
+    Xd, td, wd = (torch.from_numpy(a).cuda() for a in (X, t, w))
+    with M.Mlp(p) as mlp:
+        mlp.train_step(Xd, td, wd, lr)
+        p1 = np.array(mlp.params(), dtype=np.float64)
+    X64, t64, w64 = X.astype(np.float64), t.astype(np.float64), w.astype(np.float64)
+    _, g = S.loss_and_grad(p.astype(np.float64), X64, t64, w64)
+    q, _, _ = S.adam_step(p.astype(np.float64), np.zeros_like(g), np.zeros_like(g), g, 1, lr)
+    clear = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.abs(p1 - q)[clear].max() <= 1e-2 * lr + 1e-6
+    assert np.abs(p1 - q).max() <= 2 * lr + 1e-6
+    runs = []
+    for _ in range(2):
+        losses = []
+        with M.Mlp(p) as mlp:
+            for _s in range(30):
+                losses.append(mlp.train_step(Xd, td, wd, lr, want_loss=True))
+            runs.append((losses, mlp.params()))
+    assert runs[0] == runs[1]
+    pq, m, v = p.astype(np.float64), np.zeros(S.N_PARAMS), np.zeros(S.N_PARAMS)
+    ref_losses = []
+    for s in range(1, 31):
+        L, g = S.loss_and_grad(pq, X64, t64, w64)
+        ref_losses.append(L)
+        pq, m, v = S.adam_step(pq, m, v, g, s, lr)
+    rel = np.abs(np.array(runs[0][0]) - np.array(ref_losses)) / np.array(ref_losses)
+    _say(f"  loss {ref_losses[0]:.4f} -> {ref_losses[-1]:.4f}; max relative gap {rel.max():.2e}")
+    assert ref_losses[-1] < 0.9 * ref_losses[0]
+    assert rel.max() <= 1e-3
+
+
+def test_mlp_errors():
+    with pytest.raises(M.MCLyaError):
+        M.Mlp([float("nan")] * 4801)
+    with M.Mlp(_test_params(1)) as mlp:
+        X = torch.zeros((4, 8), device="cuda")
+        with pytest.raises(M.MCLyaError):
+            mlp.set_envelope([1.0] * 8, [0.0] * 8)
+        with pytest.raises(M.MCLyaError):
+            mlp.gradient(X, torch.zeros(4, device="cuda"), torch.zeros(4, device="cuda"))
+        with pytest.raises(M.MCLyaError):
+            mlp.train_step(X, torch.zeros(4, device="cuda"), torch.ones(4, device="cuda"), lr=-1.0)
+        assert mlp.forward(X[:0]).numel() == 0
