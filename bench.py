@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "batch"],
-                    help="c2: the 128^3 workload (default); batch: 64 uneven boxes in one context")
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "batch", "surrogate"],
+                    help="c2: the 128^3 workload (default); batch: 64 uneven boxes in one context; "
+                         "surrogate: train the mixing-correction network on Monte-Carlo boxes, evaluate it "
+                         "on held-out boxes and time its inference on the 256^3 box")
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--graph", type=int, choices=[0, 1], default=None,
                     help="replay each transport as a captured HIP graph (default 0)")
     ap.add_argument("--autotune", action="store_true",
@@ -157,6 +160,73 @@ def cpu_baseline(specs, budget_s):
                       f"transport, FP64 C + OpenMP)"}
 
 
+def bench_surrogate(a):
+    """Surrogate cells per second (features + inference over the 256^3 box),
+    with its accuracy against held-out Monte-Carlo references."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from workloads import surrogate as WS
+    import paper_2312_11448_amd as M
+    from paper_2312_11448_amd import surrogate as SG
+
+    t_start = time.perf_counter()
+    train_specs = WS.training_specs()
+    data = SG.mc_cells(train_specs)
+    with M.Mlp(WS.initial_params(1)) as mlp:
+        losses = SG.train(mlp, data, steps=a.train_steps, log_every=max(1, a.train_steps // 10))
+        lo, hi = SG.envelope(data["features"][data["w"] > 0])
+        mlp.set_envelope(lo, hi)
+        del data
+        eval_specs = WS.evaluation_specs()
+        ref = SG.mc_cells(eval_specs)
+        ref2 = SG.mc_cells(eval_specs, seeds=[s.seed + 1000 for s in eval_specs])
+        acc = SG.evaluate(mlp, ref, ref2)
+        _, _, n_out = mlp.forward(ref["features"], outside=True, count=True)
+        del ref, ref2
+        big = W.make_box("c3")
+        with M.Simulation(big) as sim:
+            t_all, t_inf, n, _ = SG.time_inference(mlp, sim)
+            sim.emit()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.transport()
+            st = sim.tally(want_emitted=False)["stats"][0]
+            torch.cuda.synchronize()
+            t_mc = time.perf_counter() - t0
+            feats = sim.features()
+            sample = feats[:: max(1, n // (1 << 18))][: 1 << 18].cpu().numpy().astype(np.float64)
+        params = np.array(mlp.params(), dtype=np.float64)
+    flops = SG.forward_flops_per_cell() * n
+    achieved = flops / t_inf / 1e12
+    out = {
+        "metric": "surrogate cells/s", "value": n / t_all, "unit": "cells/s", "n_gpus": 1,
+        "steps": 5, "warmup": 2, "ms_per_step": t_all * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "8-64-64-1 ReLU network on the 256^3 k^2 field (features + inference); "
+                               "trained on 24 64^3 boxes (64 packets/cell, z 800-1400, rms 0.2-2), "
+                               "evaluated on 3 held-out 128^3 boxes (256 packets/cell)",
+                   "cells": n, "inference_ms": t_inf * 1e3, "features_ms": (t_all - t_inf) * 1e3,
+                   "mc_transport_s_same_box": t_mc, "mc_crossings": st.crossings,
+                   "speedup_vs_mc": t_mc / t_all, "train_steps": a.train_steps,
+                   "train_loss": losses, "eval_cells_outside_envelope": n_out,
+                   "accuracy_vs_reference_mc": acc, "wall_s": time.perf_counter() - t_start},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None},
+    }
+    if not a.no_cpu_baseline:
+        from oracle import surrogate as OS
+        threads = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        OS.forward(params, sample)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": sample.shape[0] / dt, "unit": "cells/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{sample.shape[0]} cells of the 256^3 box through the FP64 "
+                                         f"numpy network ({dt:.2f} s)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -171,6 +241,8 @@ def main():
     import torch
     import workloads as W
     import paper_2312_11448_amd as M
+    if a.config == "surrogate":
+        return bench_surrogate(a)
 
     specs = W.batch_specs() if a.config == "batch" else [W.make_box(a.config)]
     dev = torch.device("cuda:0")

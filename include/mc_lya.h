@@ -275,8 +275,8 @@ mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uin
  * A per-cell regression of y = ln M_c, the log of the mixing correction that
  * mc_lya_feed returns (M_c = A_c / A_c^fm, Sec. IV.B, Eq. (dotne-mix); M = 1
  * is full mixing), on eight local features, so that the correction can be
- * evaluated without a transport. The network is 8 -> 64 -> 64 -> 1 with SiLU
- * activations (silu(z) = z / (1 + e^-z)); its parameters are one float vector
+ * evaluated without a transport. The network is 8 -> 64 -> 64 -> 1 with ReLU
+ * activations (relu(z) = max(z, 0)); its parameters are one float vector
  * of MC_LYA_MLP_PARAMS numbers: W1 [64][8] at 0, b1 [64] at 512, W2 [64][64]
  * at 576, b2 [64] at 4672, w3 [64] at 4736, b3 at 4800 (row-major
  * [out][in]). */

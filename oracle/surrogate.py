@@ -24,7 +24,8 @@ Features, per cell c of a periodic box (all plain definitions):
   6  z / 1000 - 1.1
   7  0 (padding)
 
-Network: 8 -> 64 -> 64 -> 1 with SiLU activations, silu(z) = z / (1 + e^-z).
+Network: 8 -> 64 -> 64 -> 1 with ReLU activations, relu(z) = max(z, 0) (its
+derivative taken as 0 at z = 0).
 Parameters are one flat vector of 4801 numbers:
   W1 [64][8] at 0, b1 [64] at 512, W2 [64][64] at 576, b2 [64] at 4672,
   w3 [64] at 4736, b3 at 4800;  row-major [out][in].
@@ -98,13 +99,12 @@ def pack(W1, b1, W2, b2, w3, b3):
                            [float(b3)]])
 
 
-def silu(z):
-    return z / (1.0 + np.exp(-z))
+def relu(z):
+    return np.maximum(z, 0.0)
 
 
-def silu_grad(z):
-    s = 1.0 / (1.0 + np.exp(-z))
-    return s * (1.0 + z * (1.0 - s))
+def relu_grad(z):
+    return (z > 0.0).astype(np.float64)
 
 
 def forward(params, X):
@@ -112,9 +112,9 @@ def forward(params, X):
     W1, b1, W2, b2, w3, b3 = unpack(params)
     X = _f64(X)
     z1 = X @ W1.T + b1
-    h1 = silu(z1)
+    h1 = relu(z1)
     z2 = h1 @ W2.T + b2
-    h2 = silu(z2)
+    h2 = relu(z2)
     y = h2 @ w3 + b3
     return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
 
@@ -131,10 +131,10 @@ def loss_and_grad(params, X, t, w):
     gy = 2.0 * w * r / sw                       # dL/dy
     gw3 = c["h2"].T @ gy
     gb3 = gy.sum()
-    gz2 = np.outer(gy, w3) * silu_grad(c["z2"])
+    gz2 = np.outer(gy, w3) * relu_grad(c["z2"])
     gW2 = gz2.T @ c["h1"]
     gb2 = gz2.sum(axis=0)
-    gz1 = (gz2 @ W2) * silu_grad(c["z1"])
+    gz1 = (gz2 @ W2) * relu_grad(c["z1"])
     gW1 = gz1.T @ c["X"]
     gb1 = gz1.sum(axis=0)
     return L, pack(gW1, gb1, gW2, gb2, gw3, gb3)

@@ -1,4 +1,4 @@
-// The mixing-correction surrogate: per-cell features, the 8-64-64-1 SiLU
+// The mixing-correction surrogate: per-cell features, the 8-64-64-1 ReLU
 // network on BF16 matrix cores (inference), and its FP32 training step
 // (weighted-MSE gradient, Adam).
 //
@@ -18,12 +18,10 @@ namespace {
 constexpr int kFeat = 8, kHid = 64;
 constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 4800;
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
-__device__ __forceinline__ float silu_grad(float z)
-{
-    const float s = 1.0f / (1.0f + __expf(-z));
-    return s * (1.0f + z * (1.0f - s));
-}
+// max(z, 0) as one v_med3_f32 (median of z, 0 and the largest float); fmaxf
+// would first canonicalise z with a second instruction
+__device__ __forceinline__ float relu(float z) { return __builtin_amdgcn_fmed3f(z, 0.0f, 3.402823466e38f); }
+__device__ __forceinline__ float relu_grad(float z) { return z > 0.0f ? 1.0f : 0.0f; }
 
 // ---- features ---------------------------------------------------------------
 // Per cell: ln Delta, mean and variance of Delta over the 27 cells around it
@@ -78,23 +76,28 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict
 }
 
 // ---- inference on matrix cores ---------------------------------------------
-// One wave evaluates 32 cells at a time with v_mfma_f32_32x32x8_bf16 and the
-// activations held transposed (hidden units along the matrix rows, cells
-// along the columns). For that instruction lane l holds A[l%32][4(l/32)+e],
-// B[4(l/32)+e][l%32] (e = 0..3) and D[8q + 4(l/32) + t][l%32] in register
-// 4q + t. So the layer-1 output rows a lane holds for its cell are exactly
-// the B-operand rows it must supply to layer 2 (K-step s covers hidden units
-// 8s..8s+7), and no data moves between lanes until the final dot product.
+// One wave evaluates 32 cells at a time with the activations held transposed
+// (hidden units along the matrix rows, cells along the columns), so the
+// layer-1 results a lane holds for its cell are the layer-2 operands it must
+// supply, and no data moves between lanes until the final dot product.
+//   Layer 1: v_mfma_f32_32x32x8_bf16 (K = the 8 features). Lane l holds
+//   A[l%32][4(l/32)+e], B[4(l/32)+e][l%32] (e = 0..3) and
+//   D[8q + 4(l/32) + t][l%32] in register 4q + t.
+//   Layer 2: v_mfma_f32_32x32x16_bf16, K = 16 hidden units per step, lane
+//   half l/32 and element e (0..7) of the A and B operands naming the same
+//   K index. Step s takes its B elements straight from the layer-1 registers,
+//   element e of lane half hb being hidden unit
+//   16 s + 8 (e / 4) + 4 hb + e % 4 (a permutation of 0..63), and the A
+//   operand (W2) is gathered in that same order.
+// Biases enter as the accumulators' initial values.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// binary32 -> bfloat16, round to nearest even (finite inputs)
-__device__ __forceinline__ short to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
+// binary32 -> bfloat16, round to nearest even (one v_cvt_pk_bf16_f32 per pair)
+__device__ __forceinline__ short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
+
+__device__ __forceinline__ int l2_unit(int s, int hb, int e) { return 16 * s + 8 * (e / 4) + 4 * hb + (e % 4); }
 
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restrict__ P, const float *__restrict__ X,
                                                           uint64_t n, float *__restrict__ y,
@@ -106,22 +109,23 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
     __shared__ unsigned long long s_cnt;
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
     if (threadIdx.x == 0) s_cnt = 0;
-    // weights as A operands, biases and w3 in the D-register order
-    bf16x4 a1[2], a2[2][8];
-    float bias1[2][16], bias2[2][16], w3r[2][16];
+    bf16x4 a1[2];
+    bf16x8 a2[2][4];
+    f32x16 c1[2], c2[2];
+    float w3r[2][16];
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) a1[T][e] = to_bf16(P[OFF_W1 + (32 * T + col) * kFeat + 4 * half + e]);
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a2[T][s][e] = to_bf16(P[OFF_W2 + (32 * T + col) * kHid + 8 * s + 4 * half + e]);
+            for (int e = 0; e < 8; ++e) a2[T][s][e] = (__bf16)P[OFF_W2 + (32 * T + col) * kHid + l2_unit(s, half, e)];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int row = 32 * T + 8 * (r / 4) + 4 * half + (r % 4);
-            bias1[T][r] = P[OFF_B1 + row];
-            bias2[T][r] = P[OFF_B2 + row];
+            c1[T][r] = P[OFF_B1 + row];
+            c2[T][r] = P[OFF_B2 + row];
             w3r[T][r] = P[OFF_W3 + row];
         }
     }
@@ -137,13 +141,19 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const uint64_t tiles = (n + 31) / 32;
     uint32_t n_outside = 0;
-    const f32x16 zero = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
-                         0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    // the next tile's features are loaded while this one is computed
+    auto load = [&](uint64_t tile) {
+        const uint64_t cell = tile * 32 + (uint64_t)col;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (cell < n) v = *reinterpret_cast<const float4 *>(X + cell * kFeat + 4 * half);
+        return v;
+    };
+    float4 next = load(wave);
     for (uint64_t tile = wave; tile < tiles; tile += waves) {
         const uint64_t cell = tile * 32 + (uint64_t)col;
         const bool valid = cell < n;
-        float4 xv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (valid) xv = *reinterpret_cast<const float4 *>(X + cell * kFeat + 4 * half);
+        const float4 xv = next;
+        next = load(tile + waves);
         const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
         int out_env = 0;
         bf16x4 bx;
@@ -155,23 +165,22 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
         out_env |= __shfl_xor(out_env, 32, 64);
         f32x16 d1[2];
 #pragma unroll
-        for (int T = 0; T < 2; ++T) d1[T] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[T], bx, zero, 0, 0, 0);
-        bf16x4 b2[8];
+        for (int T = 0; T < 2; ++T) d1[T] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[T], bx, c1[T], 0, 0, 0);
+        bf16x8 b2[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b2[s][e] = (__bf16)relu(d1[s / 2][4 * (2 * (s % 2) + e / 4) + e % 4]);
+        f32x16 d2[2] = {c2[0], c2[1]};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int T = 0; T < 2; ++T) d2[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[T][s], b2[s], d2[T], 0, 0, 0);
+        float part = 0.0f;
 #pragma unroll
         for (int T = 0; T < 2; ++T)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) b2[4 * T + q][t] = to_bf16(silu(d1[T][4 * q + t] + bias1[T][4 * q + t]));
-        float part = 0.0f;
-#pragma unroll
-        for (int T = 0; T < 2; ++T) {
-            f32x16 d2 = zero;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) d2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[T][s], b2[s], d2, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) part += w3r[T][r] * silu(d2[r] + bias2[T][r]);
-        }
+            for (int r = 0; r < 16; ++r) part += w3r[T][r] * relu(d2[T][r]);
         part += __shfl_xor(part, 32, 64);
         if (half == 0 && valid) {
             y[cell] = part + b3;
@@ -226,13 +235,13 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
         float z1 = b1;
 #pragma unroll
         for (int k = 0; k < kFeat; ++k) z1 += w1[k] * x[k];
-        const float h1 = silu(z1);
+        const float h1 = relu(z1);
         s_h1[h] = h1;
         __syncthreads();
         float z2 = b2;
 #pragma unroll
         for (int k = 0; k < kHid; ++k) z2 += w2r[k] * s_h1[k];
-        const float h2 = silu(z2);
+        const float h2 = relu(z2);
         float yv = w3 * h2;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) yv += __shfl_xor(yv, off, 64);
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
         const float gy = 2.0f * wc * r;
         gw3 += gy * h2;
         gb3 += gy;
-        const float gz2 = gy * w3 * silu_grad(z2);
+        const float gz2 = gy * w3 * relu_grad(z2);
         gb2 += gz2;
 #pragma unroll
         for (int k = 0; k < kHid; ++k) gW2[k] += gz2 * s_h1[k];
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
         float gh1 = 0.0f;
 #pragma unroll
         for (int k = 0; k < kHid; ++k) gh1 += w2c[k] * s_gz2[k];
-        const float gz1 = gh1 * silu_grad(z1);
+        const float gz1 = gh1 * relu_grad(z1);
         gb1 += gz1;
 #pragma unroll
         for (int k = 0; k < kFeat; ++k) gW1[k] += gz1 * x[k];

@@ -6,7 +6,7 @@ from . import _abi as A
 
 
 class Mlp:
-    """The 8-64-64-1 SiLU network on one device and stream."""
+    """The 8-64-64-1 ReLU network on one device and stream."""
 
     def __init__(self, params, device="cuda", stream=None):
         self.device = torch.device(device)

@@ -85,24 +85,24 @@ def _random_params(seed, scale=1.0):
 
 
 def test_hand_built_network():
-    """Only W1[0][0] = W2[0][0] = w3[0] = 1: y = silu(silu(x0)) + b3, with
-    silu(z) = z / (1 + e^-z) evaluated from its definition."""
+    """Only W1[0][0] = W2[0][0] = w3[0] = 1: y = max(x0, 0) + b3; a hidden
+    unit fed only by a bias adds relu(relu(b)) through w3; a unit with a
+    negative pre-activation adds nothing."""
     W1 = np.zeros((64, 8)); W1[0, 0] = 1.0
     W2 = np.zeros((64, 64)); W2[0, 0] = 1.0
     w3 = np.zeros(64); w3[0] = 1.0
     p = S.pack(W1, np.zeros(64), W2, np.zeros(64), w3, 0.5)
     X = np.zeros((5, 8)); X[:, 0] = [-3.0, -0.5, 0.0, 0.7, 4.0]
     y, _ = S.forward(p, X)
-    sil = lambda z: z / (1.0 + math.exp(-z))
-    want = [sil(sil(x)) + 0.5 for x in X[:, 0]]
-    assert np.allclose(y, want, rtol=0, atol=1e-15)
-    # a hidden unit whose pre-activation is the same for every input adds a
-    # constant: silu(b) through w3
-    b1 = np.zeros(64); b1[5] = 2.0
-    W2b = W2.copy(); W2b[7, 5] = 1.0
-    w3b = w3.copy(); w3b[7] = -1.0
+    assert np.allclose(y, [0.5, 0.5, 0.5, 1.2, 4.5], rtol=0, atol=1e-15)
+    b1 = np.zeros(64); b1[5] = 2.0; b1[6] = -1.0
+    W2b = W2.copy(); W2b[7, 5] = 1.5; W2b[8, 6] = 1.0
+    w3b = w3.copy(); w3b[7] = -1.0; w3b[8] = 10.0
     y2, _ = S.forward(S.pack(W1, b1, W2b, np.zeros(64), w3b, 0.5), X)
-    assert np.allclose(y2 - y, -sil(sil(2.0)), atol=1e-15)
+    assert np.allclose(y2 - y, -3.0, atol=1e-15)
+    # a sign flip of the first layer: y = max(-x0, 0) + b3
+    y3, _ = S.forward(S.pack(-W1, np.zeros(64), W2, np.zeros(64), w3, 0.5), X)
+    assert np.allclose(y3, [3.5, 1.0, 0.5, 0.5, 0.5], atol=1e-15)
 
 
 def test_gradient_matches_finite_differences():
