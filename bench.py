@@ -204,7 +204,7 @@ def bench_surrogate(a):
         "steps": 5, "warmup": 2, "ms_per_step": t_all * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "8-64-64-1 ReLU network on the 256^3 k^2 field (features + inference); "
-                               "trained on 24 64^3 boxes (64 packets/cell, z 800-1400, rms 0.2-2), "
+                               "trained on 24 64^3 boxes (128 packets/cell, z 800-1400, rms 0.2-2), "
                                "evaluated on 3 held-out 128^3 boxes (256 packets/cell)",
                    "cells": n, "inference_ms": t_inf * 1e3, "features_ms": (t_all - t_inf) * 1e3,
                    "mc_transport_s_same_box": t_mc, "mc_crossings": st.crossings,

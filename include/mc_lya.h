@@ -288,7 +288,9 @@ mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uin
  *   0 ln Delta_c, 1 mean and 2 variance (mean squared deviation) of Delta over
  *   the 3x3x3 cells around c (periodic), 3 div U by central differences in
  *   thermal velocities per cell (0 without a flow), 4 ln(T / 3000 K), 5 x_e,
- *   6 z / 1000 - 1.1, 7 zero.
+ *   6 z / 1000 - 1.1, 7 ln(<Delta^2> / <Delta>^2) over the box (ln(1 + b), b the
+ *   clumping factor of Sec. II.C, Eq. (clumpingfactor); in the no-mixing
+ *   limit M_c = S_c sum(n_1s) / (n_1s,c sum(S)) carries that box-wide ratio).
  *   out  dev [total cells][8] float, box-major, x fastest
  * Asynchronous on the context's stream. Errors: EINVAL, ESTATE, EDEVICE. */
 mc_lya_status mc_lya_features(mc_lya_ctx *ctx, float *out);

@@ -22,7 +22,8 @@ Features, per cell c of a periodic box (all plain definitions):
   4  ln(T / 3000 K)
   5  x_e at c
   6  z / 1000 - 1.1
-  7  0 (padding)
+  7  ln(<Delta^2> / <Delta>^2) over the whole box, ln(1 + b) with b the
+     clumping factor of Sec. II.C, Eq. (clumpingfactor)
 
 Network: 8 -> 64 -> 64 -> 1 with ReLU activations, relu(z) = max(z, 0) (its
 derivative taken as 0 at z = 0).
@@ -79,6 +80,7 @@ def features(overdensity, velocity=None, x_e=0.1, temp_K=3000.0, z=1100.0):
     f[:, 4] = np.log(temp_K / 3000.0)
     f[:, 5] = xe.reshape(-1)
     f[:, 6] = z / 1000.0 - 1.1
+    f[:, 7] = np.log(np.mean(od * od) / np.mean(od) ** 2)
     return f
 
 

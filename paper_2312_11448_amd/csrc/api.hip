@@ -133,6 +133,7 @@ struct mc_lya_ctx {
     std::vector<uint64_t> seg_host;          // packet segments of the persistent part: starts, then ids
     std::vector<FeatBox> featbox;            // surrogate features: per-box inputs
     FeatBox *d_featbox = nullptr;
+    double *d_fmom = nullptr;                // per (box, block): sum Delta, sum Delta^2
     uint64_t *d_seg = nullptr;               // [2 (n_boxes + 1)]
     int tile_share = 100;
     // captured transport (MC_LYA_OPT_GRAPH)
@@ -185,7 +186,7 @@ void free_all(mc_lya_ctx *c)
     c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_fmom, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -995,6 +996,8 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
     const int nb = c->n_boxes;
     if (!c->d_featbox) {
         hipError_t e = hipMalloc(reinterpret_cast<void **>(&c->d_featbox), sizeof(FeatBox) * nb);
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(&c->d_fmom), sizeof(double) * 2 * (size_t)nb * c->max_blk);
         if (e != hipSuccess) return hip_fail(c, e, "feature table allocation");
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
@@ -1018,7 +1021,7 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_featbox, c->featbox.data(), sizeof(FeatBox) * nb, hipMemcpyHostToDevice,
                               c->stream));
-    HIP_TRY(c, launch_features(c->d_featbox, nb, c->max_blk, out, c->stream));
+    HIP_TRY(c, launch_features(c->d_featbox, nb, c->max_blk, c->d_fmom, out, c->stream));
     return MC_LYA_OK;
 }
 

@@ -248,7 +248,7 @@ struct FeatBox {
     float xe_uniform;
     float ln_t;              // ln(T / 3000 K)
     float z_feat;            // z / 1000 - 1.1
-    float pad;
+    float ln_clump;          // ln(<Delta^2> / <Delta>^2), set on the device
 };
 
 constexpr int kMlpParams = 4801;         // 8-64-64-1 network
@@ -260,7 +260,7 @@ struct MlpAdam {
     float bc1, bc2;          // 1 - beta1^t, 1 - beta2^t
 };
 
-hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, float *out, hipStream_t s);
+hipError_t launch_features(FeatBox *fb_dev, int n_boxes, int max_blk, double *part, float *out, hipStream_t s);
 hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, float *y, uint8_t *outside,
                               const float *lo, const float *hi, unsigned long long *n_out, int grid,
                               hipStream_t s);

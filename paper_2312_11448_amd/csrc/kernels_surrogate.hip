@@ -26,12 +26,75 @@ __device__ __forceinline__ float relu_grad(float z) { return z > 0.0f ? 1.0f : 0
 // ---- features ---------------------------------------------------------------
 // Per cell: ln Delta, mean and variance of Delta over the 27 cells around it
 // (periodic), div U by central differences (thermal velocities per cell),
-// ln(T / 3000 K), x_e, z / 1000 - 1.1, 0.
+// ln(T / 3000 K), x_e, z / 1000 - 1.1, and the box's clumping
+// ln(<Delta^2> / <Delta>^2) = ln(1 + b) (Sec. II.C, Eq. (clumpingfactor)): in
+// the no-mixing limit M_c = S_c sum(n_1s) / (n_1s,c sum(S)), which carries
+// that box-wide ratio.
 __device__ __forceinline__ float vel_at(const FeatBox &fb, int comp, uint32_t i)
 {
     const size_t k = (size_t)comp * fb.ncells + i;
     if (fb.vel_dtype == MC_LYA_VEL_F32) return static_cast<const float *>(fb.vel)[k];
     return (float)static_cast<const _Float16 *>(fb.vel)[k];
+}
+
+// Per box: sum of Delta and of Delta^2 (block partials, then one block per
+// box adding them in block order).
+__global__ __launch_bounds__(256) void moments_kernel(const FeatBox *__restrict__ fbs, double *__restrict__ part,
+                                                      int max_blk)
+{
+    __shared__ double s0[4], s1[4];
+    const FeatBox fb = fbs[blockIdx.y];
+    if (blockIdx.x * 256u >= fb.ncells) return;
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < fb.ncells) {
+        a = (double)fb.od[i];
+        b = a * a;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s0[threadIdx.x >> 6] = a;
+        s1[threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* p = part + ((size_t)blockIdx.y * max_blk + blockIdx.x) * 2;
+        p[0] = s0[0] + s0[1] + s0[2] + s0[3];
+        p[1] = s1[0] + s1[1] + s1[2] + s1[3];
+    }
+}
+
+__global__ __launch_bounds__(256) void moments_reduce_kernel(FeatBox *__restrict__ fbs, const double *__restrict__ part,
+                                                             int max_blk)
+{
+    __shared__ double s0[4], s1[4];
+    FeatBox &fb = fbs[blockIdx.x];
+    const uint32_t nblk = (fb.ncells + 255u) / 256u;
+    double a = 0.0, b = 0.0;
+    for (uint32_t k = threadIdx.x; k < nblk; k += 256) {
+        const double *p = part + ((size_t)blockIdx.x * max_blk + k) * 2;
+        a += p[0];
+        b += p[1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s0[threadIdx.x >> 6] = a;
+        s1[threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double n = (double)fb.ncells;
+        const double m1 = (s0[0] + s0[1] + s0[2] + s0[3]) / n, m2 = (s1[0] + s1[1] + s1[2] + s1[3]) / n;
+        fb.ln_clump = m1 > 0.0 ? (float)log(m2 / (m1 * m1)) : 0.0f;
+    }
 }
 
 __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict__ fbs, float *__restrict__ out)
@@ -72,7 +135,7 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict
     const float xe = fb.xe ? fb.xe[i] : fb.xe_uniform;
     float4 *o = reinterpret_cast<float4 *>(out + ((size_t)fb.cell_off + i) * kFeat);
     o[0] = make_float4(logf(v[13]), mean, ss / 27.0f, div);
-    o[1] = make_float4(fb.ln_t, xe, fb.z_feat, 0.0f);
+    o[1] = make_float4(fb.ln_t, xe, fb.z_feat, fb.ln_clump);
 }
 
 // ---- inference on matrix cores ---------------------------------------------
@@ -323,8 +386,11 @@ __global__ __launch_bounds__(256) void mlp_normalise_kernel(float *__restrict__ 
 
 }  // namespace
 
-hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, float *out, hipStream_t s)
+hipError_t launch_features(FeatBox *fb_dev, int n_boxes, int max_blk, double *part, float *out, hipStream_t s)
 {
+    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)max_blk, (unsigned)n_boxes), dim3(256), 0, s, fb_dev, part,
+                       max_blk);
+    hipLaunchKernelGGL(moments_reduce_kernel, dim3((unsigned)n_boxes), dim3(256), 0, s, fb_dev, part, max_blk);
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)max_blk, (unsigned)n_boxes), dim3(256), 0, s, fb_dev, out);
     return hipGetLastError();
 }

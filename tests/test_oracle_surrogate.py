@@ -41,6 +41,20 @@ def test_neighbourhood_mean_and_variance_closed_form(axis):
     assert np.allclose(got_m, mean, rtol=0, atol=1e-13)
     assert np.allclose(got_v, var, rtol=0, atol=1e-13)
     assert np.allclose(np.exp(f[:, 0]), od.reshape(-1), rtol=1e-14)
+    # clumping: <(1 + a sin)^2> = 1 + a^2 / 2 over whole periods, <Delta> = 1
+    assert np.allclose(f[:, 7], math.log(1.0 + a * a / 2.0), rtol=0, atol=1e-13)
+
+
+def test_clumping_of_a_two_phase_box():
+    """Half the cells at 1 + a, half at 1 - a: <Delta^2>/<Delta>^2 = 1 + a^2,
+    whatever the arrangement (Eq. (clumpingfactor), b = a^2)."""
+    rng = np.random.default_rng(9)
+    a = 0.6
+    v = np.where(rng.permutation(512) < 256, 1.0 + a, 1.0 - a).reshape(8, 8, 8)
+    f = S.features(v)
+    assert np.allclose(f[:, 7], math.log(1.0 + a * a), atol=1e-14)
+    f2 = S.features(3.0 * v)           # a uniform rescaling leaves it unchanged
+    assert np.allclose(f2[:, 7], f[:, 7], atol=1e-14)
 
 
 @pytest.mark.parametrize("comp", [0, 1, 2])

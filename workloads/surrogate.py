@@ -31,7 +31,7 @@ def surrogate_box(n, rms, z, field_seed, packets, seed):
                    name=f"{n}^3 rms {rms:.2f} z {z:.0f} field seed {field_seed}")
 
 
-def training_specs(n_boxes=24, n=64, packets_per_cell=64, seed=5000):
+def training_specs(n_boxes=24, n=64, packets_per_cell=128, seed=5000):
     """Training boxes: contrast rms ~ U[0.2, 2], z ~ U[800, 1400]."""
     rng = np.random.Generator(np.random.Philox(seed))
     out = []
