@@ -133,7 +133,6 @@ struct mc_lya_ctx {
     std::vector<uint64_t> seg_host;          // packet segments of the persistent part: starts, then ids
     std::vector<FeatBox> featbox;            // surrogate features: per-box inputs
     FeatBox *d_featbox = nullptr;
-    double *d_fmom = nullptr;                // per (box, block): sum Delta, sum Delta^2
     uint64_t *d_seg = nullptr;               // [2 (n_boxes + 1)]
     int tile_share = 100;
     // captured transport (MC_LYA_OPT_GRAPH)
@@ -186,7 +185,7 @@ void free_all(mc_lya_ctx *c)
     c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_fmom, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -996,8 +995,6 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
     const int nb = c->n_boxes;
     if (!c->d_featbox) {
         hipError_t e = hipMalloc(reinterpret_cast<void **>(&c->d_featbox), sizeof(FeatBox) * nb);
-        if (e == hipSuccess)
-            e = hipMalloc(reinterpret_cast<void **>(&c->d_fmom), sizeof(double) * 2 * (size_t)nb * c->max_blk);
         if (e != hipSuccess) return hip_fail(c, e, "feature table allocation");
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
@@ -1018,10 +1015,13 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
         f.xe_uniform = d.x_e_uniform;
         f.ln_t = (float)std::log(d.temp_K / 3000.0);
         f.z_feat = (float)(d.z / 1000.0 - 1.1);
+        // the box clumping from the pack's FP64 sums (read back by refresh)
+        const double n = (double)f.ncells, m1 = c->red[b].od_sum / n, m2 = c->red[b].od2_sum / n;
+        f.ln_clump = m1 > 0.0 ? (float)std::log(m2 / (m1 * m1)) : 0.0f;
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_featbox, c->featbox.data(), sizeof(FeatBox) * nb, hipMemcpyHostToDevice,
                               c->stream));
-    HIP_TRY(c, launch_features(c->d_featbox, nb, c->max_blk, c->d_fmom, out, c->stream));
+    HIP_TRY(c, launch_features(c->d_featbox, nb, c->max_blk, out, c->stream));
     return MC_LYA_OK;
 }
 

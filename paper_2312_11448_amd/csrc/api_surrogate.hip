@@ -14,7 +14,7 @@ struct mc_lya_mlp {
     hipStream_t stream = nullptr;
     float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr;
     float *d_grad = nullptr;                 // [kMlpParams + 2]: gradient, sum w r^2, sum w
-    float *d_part = nullptr;                 // [kMlpGradBlocks][kMlpPartStride]
+    float *d_part = nullptr;                 // [kMlpGradBlocks + kMlpGradBlocks / 32][kMlpPartStride]
     float *d_env = nullptr;                  // [16]: lower then upper feature bounds
     unsigned long long *d_count = nullptr;
     bool envelope = false;
@@ -94,7 +94,8 @@ mc_lya_status mc_lya_mlp_create(mc_lya_mlp **out, const float *params, void *str
     if ((e = hipMalloc(reinterpret_cast<void **>(&m->d_grad), sizeof(float) * (kMlpParams + 2))) != hipSuccess)
         return bail(e, "allocation");
     if ((e = hipMalloc(reinterpret_cast<void **>(&m->d_part),
-                       sizeof(float) * (size_t)kMlpGradBlocks * kMlpPartStride)) != hipSuccess)
+                       sizeof(float) * (size_t)(kMlpGradBlocks + (kMlpGradBlocks + 31) / 32) * kMlpPartStride)) !=
+        hipSuccess)
         return bail(e, "allocation");
     if ((e = hipMalloc(reinterpret_cast<void **>(&m->d_env), sizeof(float) * 16)) != hipSuccess)
         return bail(e, "allocation");

@@ -44,6 +44,7 @@ struct PackBox {
 struct BoxRed {
     double usum[3];       // sum of the velocity components
     double kappa_sum;     // sum of kappa_c
+    double od_sum, od2_sum;   // sums of Delta and Delta^2
     unsigned long long wmax_bits;   // max emission weight (bit pattern of a double >= 0)
     unsigned long long udev_bits;   // max |U_c - <U>| (bit pattern of a double >= 0)
     uint32_t flags;       // validation failures (bit mask)
@@ -102,9 +103,10 @@ constexpr int kSetupBlock = 256;
 // Per-block partial results of the setup and tally kernels, kPartStride
 // doubles per (box, block): [0..3] sums (pack, then feed), [4] the block's
 // largest emission weight, [5] its largest |U - <U>|, [6] its absorbed-weight
-// sum (uint64 bits). Reduced per box by one-block kernels; no same-address
-// atomics, which serialise at the cache.
-constexpr int kPartStride = 8;
+// sum (uint64 bits), [7] sum of Delta and [8] of Delta^2 (pack). Reduced per
+// box by one-block kernels; no same-address atomics, which serialise at the
+// cache.
+constexpr int kPartStride = 10;
 
 hipError_t launch_pack(const PackBox *pb_dev, int n_boxes, int max_blk, bool vel_rec, void *rec,
                        double *wgt, double *partials, BoxRed *red, hipStream_t s);
@@ -248,7 +250,7 @@ struct FeatBox {
     float xe_uniform;
     float ln_t;              // ln(T / 3000 K)
     float z_feat;            // z / 1000 - 1.1
-    float ln_clump;          // ln(<Delta^2> / <Delta>^2), set on the device
+    float ln_clump;          // ln(<Delta^2> / <Delta>^2) from the pack's box sums
 };
 
 constexpr int kMlpParams = 4801;         // 8-64-64-1 network
@@ -260,10 +262,11 @@ struct MlpAdam {
     float bc1, bc2;          // 1 - beta1^t, 1 - beta2^t
 };
 
-hipError_t launch_features(FeatBox *fb_dev, int n_boxes, int max_blk, double *part, float *out, hipStream_t s);
+hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, float *out, hipStream_t s);
 hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, float *y, uint8_t *outside,
                               const float *lo, const float *hi, unsigned long long *n_out, int grid,
                               hipStream_t s);
+// partial: [blocks + ceil(blocks / 32)][kMlpPartStride] floats of workspace
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
                                float *partial, int blocks, float *grad, hipStream_t s);
 hipError_t launch_mlp_normalise(float *grad, hipStream_t s);

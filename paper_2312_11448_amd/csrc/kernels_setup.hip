@@ -107,7 +107,7 @@ __global__ __launch_bounds__(B) void pack_kernel(const PackBox *__restrict__ pbs
     const PackBox pb = pbs[b];
     if ((int)blockIdx.x >= pb.nblk) return;
     const uint32_t i = blockIdx.x * B + threadIdx.x;
-    double ux = 0.0, uy = 0.0, uz = 0.0, ks = 0.0, w = 0.0;
+    double ux = 0.0, uy = 0.0, uz = 0.0, ks = 0.0, w = 0.0, d1 = 0.0, d2 = 0.0;
     uint32_t flags = 0;
     if (i < pb.ncells) {
         const float od = pb.od[i];
@@ -146,11 +146,15 @@ __global__ __launch_bounds__(B) void pack_kernel(const PackBox *__restrict__ pbs
         uy = vy;
         uz = vz;
         ks = kap;
+        d1 = (double)od;
+        d2 = d1 * d1;
     }
     const double sx = block_sum(ux, lds);
     const double sy = block_sum(uy, lds);
     const double sz = block_sum(uz, lds);
     const double sk = block_sum(ks, lds);
+    const double sd1 = block_sum(d1, lds);
+    const double sd2 = block_sum(d2, lds);
     const double wm = block_max(w, lds);
     // validation failures are rare: an atomic only where one is found
     const uint32_t fl = wave_or(flags);
@@ -162,6 +166,8 @@ __global__ __launch_bounds__(B) void pack_kernel(const PackBox *__restrict__ pbs
         p[2] = sz;
         p[3] = sk;
         p[4] = wm;
+        p[7] = sd1;
+        p[8] = sd2;
     }
 }
 
@@ -173,23 +179,27 @@ __global__ __launch_bounds__(B) void box_reduce_kernel(const PackBox *__restrict
     __shared__ double lds[kWaves];
     const int b = blockIdx.x;
     const int nblk = pbs[b].nblk;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double wm = 0.0;
     for (int k = threadIdx.x; k < nblk; k += B) {
         const double *p = partials + ((size_t)b * max_blk + k) * kPartStride;
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] += p[j];
+        acc[4] += p[7];
+        acc[5] += p[8];
         wm = fmax(wm, p[4]);
     }
-    double tot[4];
+    double tot[6];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) tot[j] = block_sum(acc[j], lds);
+    for (int j = 0; j < 6; ++j) tot[j] = block_sum(acc[j], lds);
     wm = block_max(wm, lds);
     if (threadIdx.x == 0) {
         red[b].usum[0] = tot[0];
         red[b].usum[1] = tot[1];
         red[b].usum[2] = tot[2];
         red[b].kappa_sum = tot[3];
+        red[b].od_sum = tot[4];
+        red[b].od2_sum = tot[5];
         red[b].wmax_bits = (unsigned long long)__double_as_longlong(wm);
     }
 }

@@ -37,66 +37,6 @@ __device__ __forceinline__ float vel_at(const FeatBox &fb, int comp, uint32_t i)
     return (float)static_cast<const _Float16 *>(fb.vel)[k];
 }
 
-// Per box: sum of Delta and of Delta^2 (block partials, then one block per
-// box adding them in block order).
-__global__ __launch_bounds__(256) void moments_kernel(const FeatBox *__restrict__ fbs, double *__restrict__ part,
-                                                      int max_blk)
-{
-    __shared__ double s0[4], s1[4];
-    const FeatBox fb = fbs[blockIdx.y];
-    if (blockIdx.x * 256u >= fb.ncells) return;
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    double a = 0.0, b = 0.0;
-    if (i < fb.ncells) {
-        a = (double)fb.od[i];
-        b = a * a;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_down(a, off, 64);
-        b += __shfl_down(b, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        s0[threadIdx.x >> 6] = a;
-        s1[threadIdx.x >> 6] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double* p = part + ((size_t)blockIdx.y * max_blk + blockIdx.x) * 2;
-        p[0] = s0[0] + s0[1] + s0[2] + s0[3];
-        p[1] = s1[0] + s1[1] + s1[2] + s1[3];
-    }
-}
-
-__global__ __launch_bounds__(256) void moments_reduce_kernel(FeatBox *__restrict__ fbs, const double *__restrict__ part,
-                                                             int max_blk)
-{
-    __shared__ double s0[4], s1[4];
-    FeatBox &fb = fbs[blockIdx.x];
-    const uint32_t nblk = (fb.ncells + 255u) / 256u;
-    double a = 0.0, b = 0.0;
-    for (uint32_t k = threadIdx.x; k < nblk; k += 256) {
-        const double *p = part + ((size_t)blockIdx.x * max_blk + k) * 2;
-        a += p[0];
-        b += p[1];
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_down(a, off, 64);
-        b += __shfl_down(b, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        s0[threadIdx.x >> 6] = a;
-        s1[threadIdx.x >> 6] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double n = (double)fb.ncells;
-        const double m1 = (s0[0] + s0[1] + s0[2] + s0[3]) / n, m2 = (s1[0] + s1[1] + s1[2] + s1[3]) / n;
-        fb.ln_clump = m1 > 0.0 ? (float)log(m2 / (m1 * m1)) : 0.0f;
-    }
-}
-
 __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict__ fbs, float *__restrict__ out)
 {
     const FeatBox fb = fbs[blockIdx.y];
@@ -345,15 +285,29 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
     }
 }
 
-// grad[j] = sum over blocks of partial[b][j] (block order), j < kMlpParams + 2;
-// the last two entries are sum w r^2 and sum w.
-__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *__restrict__ partial, int blocks,
+// grad[j] = sum over blocks of partial[b][j], j < kMlpParams + 2 (the last
+// two entries are sum w r^2 and sum w), in two fixed-order passes: groups of
+// kMlpGroup consecutive blocks into tmp[g][j], then the groups in order.
+constexpr int kMlpGroup = 32;
+
+__global__ __launch_bounds__(256) void mlp_reduce_groups_kernel(const float *__restrict__ partial, int blocks,
+                                                                float *__restrict__ tmp)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
+    if (j >= kMlpParams + 2) return;
+    float s = 0.0f;
+    const int b1 = min(blocks, (g + 1) * kMlpGroup);
+    for (int b = g * kMlpGroup; b < b1; ++b) s += partial[(size_t)b * kMlpPartStride + j];
+    tmp[(size_t)g * kMlpPartStride + j] = s;
+}
+
+__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *__restrict__ tmp, int groups,
                                                          float *__restrict__ grad)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= kMlpParams + 2) return;
     float s = 0.0f;
-    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * kMlpPartStride + j];
+    for (int g = 0; g < groups; ++g) s += tmp[(size_t)g * kMlpPartStride + j];
     grad[j] = s;
 }
 
@@ -386,11 +340,8 @@ __global__ __launch_bounds__(256) void mlp_normalise_kernel(float *__restrict__ 
 
 }  // namespace
 
-hipError_t launch_features(FeatBox *fb_dev, int n_boxes, int max_blk, double *part, float *out, hipStream_t s)
+hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)max_blk, (unsigned)n_boxes), dim3(256), 0, s, fb_dev, part,
-                       max_blk);
-    hipLaunchKernelGGL(moments_reduce_kernel, dim3((unsigned)n_boxes), dim3(256), 0, s, fb_dev, part, max_blk);
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)max_blk, (unsigned)n_boxes), dim3(256), 0, s, fb_dev, out);
     return hipGetLastError();
 }
@@ -407,9 +358,13 @@ hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, f
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
                                float *partial, int blocks, float *grad, hipStream_t s)
 {
+    const int groups = (blocks + kMlpGroup - 1) / kMlpGroup;
+    float *tmp = partial + (size_t)blocks * kMlpPartStride;
     hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)blocks), dim3(64), 0, s, params, X, t, w, n, partial);
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)((kMlpParams + 2 + 255) / 256)), dim3(256), 0, s, partial,
-                       blocks, grad);
+    hipLaunchKernelGGL(mlp_reduce_groups_kernel, dim3((unsigned)((kMlpParams + 2 + 255) / 256), (unsigned)groups),
+                       dim3(256), 0, s, partial, blocks, tmp);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)((kMlpParams + 2 + 255) / 256)), dim3(256), 0, s, tmp,
+                       groups, grad);
     return hipGetLastError();
 }
 
