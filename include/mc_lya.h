@@ -151,9 +151,13 @@ enum {
                                      this percentage of the emission's crossings per compute
                                      unit (default 100); other boxes take the persistent walk.
                                      0 = no box tiled, 1000000 = every box tiled */
-    MC_LYA_OPT_GRAPH_GENS = 11    /* tile generations inside a captured transport graph
+    MC_LYA_OPT_GRAPH_GENS = 11,   /* tile generations inside a captured transport graph
                                      (16..4096, default 64); a replay that needs more
                                      continues eagerly and the next capture takes enough */
+    MC_LYA_OPT_DEFER = 12         /* tiled walk: once a tile's input is used up, a wave with
+                                     at most this many live packets (0..64, default 16) hands
+                                     them to the tile's next generation instead of walking on
+                                     with idle lanes (tiles that took >= 2048 packets) */
 };
 
 /* Creates a context for n_boxes boxes, validates and packs their fields

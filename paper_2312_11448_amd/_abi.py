@@ -21,6 +21,7 @@ MC_LYA_OPT_REFILL, MC_LYA_OPT_MAX_CROSSINGS, MC_LYA_OPT_TIMING, MC_LYA_OPT_GRAPH
 MC_LYA_OPT_QUEUES = 9
 MC_LYA_OPT_TILE_SHARE = 10
 MC_LYA_OPT_GRAPH_GENS = 11
+MC_LYA_OPT_DEFER = 12
 
 
 class mc_lya_box_desc(C.Structure):

@@ -135,6 +135,7 @@ struct mc_lya_ctx {
     FeatBox *d_featbox = nullptr;
     uint64_t *d_seg = nullptr;               // [2 (n_boxes + 1)]
     int tile_share = 100;
+    int defer = 16;                          // MC_LYA_OPT_DEFER
     // captured transport (MC_LYA_OPT_GRAPH)
     bool graph = false;
     hipGraphExec_t graph_exec = nullptr;
@@ -447,6 +448,8 @@ TileParams tile_params(mc_lya_ctx *c, uint64_t first, uint64_t n)
     p.ntiles = (int)c->tiles.size();
     p.chunk = std::min(c->chunk, 1024);
     p.refill = c->refill;
+    p.defer_lanes = c->defer;
+    p.defer_min = 2048;
     p.first = first;
     p.count = n;
     return p;
@@ -651,6 +654,7 @@ std::vector<uint64_t> graph_key(mc_lya_ctx *c, const WalkPlan &w, int budget)
     std::vector<uint64_t> k = {(uint64_t)c->kernel, (uint64_t)c->block, (uint64_t)c->waves_per_cu,
                                (uint64_t)c->chunk, (uint64_t)c->refill, (uint64_t)c->nqueues,
                                (uint64_t)c->max_cross, c->total_packets, c->state_cap, (uint64_t)budget,
+                               (uint64_t)c->defer,
                                (uint64_t)w.tiled, (uint64_t)w.global, (uint64_t)c->tiles.size(),
                                (uint64_t)(uintptr_t)c->d_state[0], (uint64_t)(uintptr_t)c->d_cop,
                                (uint64_t)w.p.n_seg, w.p.count, c->epoch};
@@ -1147,6 +1151,10 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     case MC_LYA_OPT_TILE_SHARE:
         if (v < 0 || v > kAllTiled) return fail(c, MC_LYA_EINVAL, "tile share must be in [0, 1000000]");
         c->tile_share = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_DEFER:
+        if (v < 0 || v > 64) return fail(c, MC_LYA_EINVAL, "defer must be in [0, 64]");
+        c->defer = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_GRAPH_GENS:
         if (v < kGenRound || v > kMaxGenerations)

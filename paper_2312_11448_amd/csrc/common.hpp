@@ -174,11 +174,14 @@ struct alignas(16) PState {
 };
 static_assert(sizeof(PState) == 112, "PState layout");
 
-// Exit lists of one tile in one generation: states in [base, base + off[6]),
+// Exit lists of one tile in one generation: states in [base, base + off[7]),
 // and the states that left through face f are idx[base + off[f] .. base + off[f+1]).
+// Faces 0..5 are -x, +x, -y, +y, -z, +z; list 6 holds packets the tile
+// deferred to its own next generation (kDeferred).
+constexpr int kDeferred = 6;
 struct TileExits {
     uint32_t base;
-    uint32_t off[7];
+    uint32_t off[8];
 };
 
 constexpr int kMaxGenerations = 4096;  // per transport batch (packets cross at most one tile per generation)
@@ -206,6 +209,8 @@ struct TileParams {
     int32_t ntiles;
     int32_t chunk;
     int32_t refill;          // refill a wave once this many lanes are idle
+    int32_t defer_lanes;     // once the tile's input is used up, a wave with at most this many live lanes
+    uint32_t defer_min;      // ... defers them to the next generation, if the tile took >= defer_min packets
 };
 
 hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s);

@@ -12,6 +12,12 @@
 // indexed by face; in the next generation each tile pulls exactly the face
 // lists that point at it and applies the face jump.
 //
+// Once a tile's input is used up, its waves thin out as packets finish; a
+// wave left with only a few live lanes writes them to the tile's own
+// deferred list instead, and the next generation takes them up again with
+// full waves (a packet's walk does not depend on the generation that carries
+// it, so the tallies are the same integers).
+//
 // The per-packet arithmetic is walk_core's, so the integer tallies are the
 // same bits as those of the other drivers.
 #include "walk_core.hpp"
@@ -212,14 +218,15 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         if (tid == 0) {
             uint32_t run = 0;
             const int32_t *src = P.tiles[T].src_tile;
-            for (int k = 0; k < ti.nsrc; ++k) {
-                const int f = (int)((ti.src_faces >> (4 * k)) & 15u);
-                const TileExits &e = P.in_exits[src[k]];
+            for (int k = 0; k <= ti.nsrc; ++k) {
+                // the neighbours' face lists, then this tile's deferred list
+                const int f = k < ti.nsrc ? (int)((ti.src_faces >> (4 * k)) & 15u) : kDeferred;
+                const TileExits &e = P.in_exits[k < ti.nsrc ? src[k] : T];
                 pre[k] = run;
                 lst[k] = e.base + e.off[f];
                 run += e.off[f + 1] - e.off[f];
             }
-            pre[ti.nsrc] = run;
+            pre[ti.nsrc + 1] = run;
             s_total = run;
         }
         __syncthreads();
@@ -229,7 +236,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         if (tid == 0) {
             TileExits e;
             e.base = 0;
-            for (int f = 0; f < 7; ++f) e.off[f] = 0;
+            for (int f = 0; f < 8; ++f) e.off[f] = 0;
             P.out_exits[T] = e;
         }
         return;
@@ -254,6 +261,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     const TileSink<VEL> sink{tally, srec4, sreck, ti.ox, ti.oy, ti.oz, ti.sx, ti.sy, ti.sz};
     Lane L;
     bool alive = false, more = true;
+    bool fresh = false;          // wave-uniform: packets loaded since the wave's last step
     uint32_t cur = 0, end = 0;
     uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0;
     const uint32_t chunk = (uint32_t)P.chunk;
@@ -293,20 +301,35 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
                     init_packet<VEL>(L, B, gp - B.pkt_off, gc, P.rec);
                 } else {
                     int k = 0;
-                    while (k + 1 < ti.nsrc && pre[k + 1] <= j) ++k;
+                    while (k + 1 <= ti.nsrc && pre[k + 1] <= j) ++k;
                     const uint32_t g = P.in_idx[lst[k] + (j - pre[k])];
                     load_state(L, P.in_state[g], B);
-                    finish_entry<VEL>(L, sink.template fetch<VEL>(P.rec, L.c, L.ix, L.iy, L.iz, true));
+                    const Rec r = sink.template fetch<VEL>(P.rec, L.c, L.ix, L.iy, L.iz, true);
+                    if (k < ti.nsrc) finish_entry<VEL>(L, r);   // entering through a face
+                    else L.kap = r.kap;                         // deferred inside its cell
                 }
                 alive = true;
             }
+            fresh = true;
             cur += take;
             idle = __ballot(!alive);
         }
-        if (!__ballot(alive)) {
+        const uint64_t live = __ballot(alive);
+        if (!live) {
             if (!more) break;
             continue;
         }
+        // (only after a step, so every deferred packet has moved in this generation)
+        if (!more && !fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
+            if (alive) {
+                const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
+                save_state(P.out_state[g], L);
+                P.out_face[g] = (uint8_t)kDeferred;
+                atomicAdd(&s_fcnt[kDeferred], 1u);
+            }
+            break;
+        }
+        fresh = false;
         if (alive) {
             uint64_t dep = 0;
             const int fate = walk_step<VEL>(L, P.rec, sink, P.max_cross, dep);
@@ -370,12 +393,12 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         TileExits e;
         e.base = s_base;
         uint32_t run = 0;
-        for (int f = 0; f < 6; ++f) {
+        for (int f = 0; f <= kDeferred; ++f) {
             e.off[f] = run;
             s_fcur[f] = run;
             run += s_fcnt[f];
         }
-        e.off[6] = run;
+        e.off[kDeferred + 1] = run;
         P.out_exits[T] = e;
         if (n_exit) atomicAdd(P.exits, (unsigned long long)n_exit);
     }
