@@ -262,6 +262,24 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     Lane L;
     bool alive = false, more = true;
     bool fresh = false;          // wave-uniform: packets loaded since the wave's last step
+    // A packet that leaves the tile parks in its lane (pending) and is written
+    // out when the wave next refills or stops: one exit-writing pass for many
+    // lanes instead of one per step for a few.
+    bool pending = false;
+    auto flush_exits = [&]() {
+        if (pending) {
+            const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
+            save_state(P.out_state[g], L);
+            // the face it left through: the one coordinate now outside the tile
+            uint32_t f;
+            if ((uint32_t)(L.ix - ti.ox) >= (uint32_t)ti.sx) f = L.kx > 0.0f ? 1u : 0u;
+            else if ((uint32_t)(L.iy - ti.oy) >= (uint32_t)ti.sy) f = L.ky > 0.0f ? 3u : 2u;
+            else f = L.kz > 0.0f ? 5u : 4u;
+            P.out_face[g] = (uint8_t)f;
+            atomicAdd(&s_fcnt[f], 1u);
+            pending = false;
+        }
+    };
     uint32_t cur = 0, end = 0;
     uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0;
     const uint32_t chunk = (uint32_t)P.chunk;
@@ -271,6 +289,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         // refilling stalls the whole wave on the new packets' loads: wait until
         // enough lanes are idle (or all are)
         if ((uint32_t)__popcll(idle) < refill && idle != ~0ull) idle = 0;
+        if (idle && more) flush_exits();
         while (idle && more) {
             if (cur >= end) {
                 uint32_t base = 0;
@@ -316,11 +335,15 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
         const uint64_t live = __ballot(alive);
         if (!live) {
-            if (!more) break;
+            if (!more) {
+                flush_exits();
+                break;
+            }
             continue;
         }
         // (only after a step, so every deferred packet has moved in this generation)
         if (!more && !fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
+            flush_exits();
             if (alive) {
                 const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
                 save_state(P.out_state[g], L);
@@ -334,16 +357,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             uint64_t dep = 0;
             const int fate = walk_step<VEL>(L, P.rec, sink, P.max_cross, dep);
             if (fate == kExit) {
-                const uint32_t slot = atomicAdd(&s_exit, 1u);
-                const uint32_t g = s_base + slot;
-                save_state(P.out_state[g], L);
-                // the face it left through: the one coordinate now outside the tile
-                uint32_t f;
-                if ((uint32_t)(L.ix - ti.ox) >= (uint32_t)ti.sx) f = L.kx > 0.0f ? 1u : 0u;
-                else if ((uint32_t)(L.iy - ti.oy) >= (uint32_t)ti.sy) f = L.ky > 0.0f ? 3u : 2u;
-                else f = L.kz > 0.0f ? 5u : 4u;
-                P.out_face[g] = (uint8_t)f;
-                atomicAdd(&s_fcnt[f], 1u);
+                pending = true;
                 alive = false;
             } else if (fate != kAlive) {
                 a_cross += L.ncross;
