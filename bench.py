@@ -257,6 +257,7 @@ def main():
         r = sim.autotune(1)
         tuned = {"kernel": r.kernel, "tile_share": r.tile_share, "block": r.block,
                  "waves_per_cu": r.waves_per_cu, "chunk": r.chunk, "refill": r.refill,
+                 "tile_chunk": r.tile_chunk, "tile_refill": r.tile_refill,
                  "transport_ms": r.best_ms, "default_ms": r.start_ms}
 
     def step():

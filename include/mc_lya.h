@@ -133,10 +133,10 @@ enum {
                                      tiles once per generation */
     MC_LYA_OPT_BLOCK = 2,         /* threads per workgroup: 64, 128 or 256 */
     MC_LYA_OPT_WAVES_PER_CU = 3,  /* resident waves per compute unit for the persistent grid */
-    MC_LYA_OPT_CHUNK = 4,         /* packets a wave takes from the queue at once (>= 1;
-                                     the tiled walk uses min(chunk, 1024) per workgroup) */
-    MC_LYA_OPT_REFILL = 5,        /* refill a wave once this many lanes are idle (1..64;
-                                     kernels 0 and 2) */
+    MC_LYA_OPT_CHUNK = 4,         /* persistent walk: packets a wave takes from the queue at
+                                     once (>= 1) */
+    MC_LYA_OPT_REFILL = 5,        /* persistent walk: refill a wave once this many lanes are
+                                     idle (1..64) */
     MC_LYA_OPT_MAX_CROSSINGS = 6, /* crossing cap per packet (>= 1, default 1e6) */
     MC_LYA_OPT_TIMING = 7,        /* 1 = time transport kernels with HIP events */
     MC_LYA_OPT_GRAPH = 8,         /* 1 = a whole-emission mc_lya_transport replays a captured
@@ -154,10 +154,14 @@ enum {
     MC_LYA_OPT_GRAPH_GENS = 11,   /* tile generations inside a captured transport graph
                                      (16..4096, default 64); a replay that needs more
                                      continues eagerly and the next capture takes enough */
-    MC_LYA_OPT_DEFER = 12         /* tiled walk: once a tile's input is used up, a wave with
+    MC_LYA_OPT_DEFER = 12,        /* tiled walk: once a tile's input is used up, a wave with
                                      at most this many live packets (0..64, default 16) hands
                                      them to the tile's next generation instead of walking on
                                      with idle lanes (tiles that took >= 2048 packets) */
+    MC_LYA_OPT_TILE_CHUNK = 13,   /* tiled walk: packets a wave takes from its tile's input at
+                                     once (1..1024, default 64) */
+    MC_LYA_OPT_TILE_REFILL = 14   /* tiled walk: refill a wave once this many lanes are idle
+                                     (1..64, default 24) */
 };
 
 /* Creates a context for n_boxes boxes, validates and packs their fields
@@ -244,6 +248,8 @@ typedef struct mc_lya_tune_result {
     int64_t waves_per_cu;         /* MC_LYA_OPT_WAVES_PER_CU */
     int64_t chunk;                /* MC_LYA_OPT_CHUNK */
     int64_t refill;               /* MC_LYA_OPT_REFILL */
+    int64_t tile_chunk;           /* MC_LYA_OPT_TILE_CHUNK */
+    int64_t tile_refill;          /* MC_LYA_OPT_TILE_REFILL */
     double best_ms;               /* fastest transport of the current emission, ms */
     double start_ms;              /* the same with the options set before the call, ms */
     int32_t trials;               /* option sets timed */

@@ -22,6 +22,8 @@ MC_LYA_OPT_QUEUES = 9
 MC_LYA_OPT_TILE_SHARE = 10
 MC_LYA_OPT_GRAPH_GENS = 11
 MC_LYA_OPT_DEFER = 12
+MC_LYA_OPT_TILE_CHUNK = 13
+MC_LYA_OPT_TILE_REFILL = 14
 
 
 class mc_lya_box_desc(C.Structure):
@@ -58,6 +60,7 @@ class mc_lya_packet_trace(C.Structure):
 class mc_lya_tune_result(C.Structure):
     _fields_ = [("kernel", C.c_int64), ("tile_share", C.c_int64), ("block", C.c_int64),
                 ("waves_per_cu", C.c_int64), ("chunk", C.c_int64), ("refill", C.c_int64),
+                ("tile_chunk", C.c_int64), ("tile_refill", C.c_int64),
                 ("best_ms", C.c_double), ("start_ms", C.c_double), ("trials", C.c_int32),
                 ("reserved", C.c_int32)]
 

@@ -16,7 +16,7 @@ using namespace mclya;
 static_assert(sizeof(mc_lya_box_desc) == 152, "mc_lya_box_desc layout");
 static_assert(sizeof(mc_lya_box_stats) == 88, "mc_lya_box_stats layout");
 static_assert(sizeof(mc_lya_packet_trace) == 56, "mc_lya_packet_trace layout");
-static_assert(sizeof(mc_lya_tune_result) == 72, "mc_lya_tune_result layout");
+static_assert(sizeof(mc_lya_tune_result) == 88, "mc_lya_tune_result layout");
 
 namespace {
 
@@ -147,6 +147,7 @@ struct mc_lya_ctx {
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
     int kernel = 2, block = 256, waves_per_cu = 32, chunk = 256, refill = 16, nqueues = 8;
+    int tile_chunk = 64, tile_refill = 24;   // the tiled walk's own chunk and refill
     int64_t max_cross = 1000000;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -446,8 +447,8 @@ TileParams tile_params(mc_lya_ctx *c, uint64_t first, uint64_t n)
     p.tot = c->d_tot;
     p.max_cross = (uint32_t)c->max_cross;
     p.ntiles = (int)c->tiles.size();
-    p.chunk = std::min(c->chunk, 1024);
-    p.refill = c->refill;
+    p.chunk = c->tile_chunk;
+    p.refill = c->tile_refill;
     p.defer_lanes = c->defer;
     p.defer_min = 2048;
     p.first = first;
@@ -653,6 +654,7 @@ std::vector<uint64_t> graph_key(mc_lya_ctx *c, const WalkPlan &w, int budget)
 {
     std::vector<uint64_t> k = {(uint64_t)c->kernel, (uint64_t)c->block, (uint64_t)c->waves_per_cu,
                                (uint64_t)c->chunk, (uint64_t)c->refill, (uint64_t)c->nqueues,
+                               (uint64_t)c->tile_chunk, (uint64_t)c->tile_refill,
                                (uint64_t)c->max_cross, c->total_packets, c->state_cap, (uint64_t)budget,
                                (uint64_t)c->defer,
                                (uint64_t)w.tiled, (uint64_t)w.global, (uint64_t)c->tiles.size(),
@@ -1152,6 +1154,14 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
         if (v < 0 || v > kAllTiled) return fail(c, MC_LYA_EINVAL, "tile share must be in [0, 1000000]");
         c->tile_share = (int)v;
         return MC_LYA_OK;
+    case MC_LYA_OPT_TILE_CHUNK:
+        if (v < 1 || v > 1024) return fail(c, MC_LYA_EINVAL, "tile chunk must be in [1, 1024]");
+        c->tile_chunk = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_TILE_REFILL:
+        if (v < 1 || v > 64) return fail(c, MC_LYA_EINVAL, "tile refill must be in [1, 64]");
+        c->tile_refill = (int)v;
+        return MC_LYA_OK;
     case MC_LYA_OPT_DEFER:
         if (v < 0 || v > 64) return fail(c, MC_LYA_EINVAL, "defer must be in [0, 64]");
         c->defer = (int)v;
@@ -1175,20 +1185,23 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
     if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_autotune before mc_lya_emit");
     if (reps < 1 || reps > 100) return fail(c, MC_LYA_EINVAL, "reps must be in [1, 100]");
     struct Opts {
-        int kernel, share, block, waves, chunk, refill;
+        int kernel, share, block, waves, chunk, refill, tchunk, trefill;
         bool operator==(const Opts &o) const
         {
             return kernel == o.kernel && share == o.share && block == o.block && waves == o.waves &&
-                   chunk == o.chunk && refill == o.refill;
+                   chunk == o.chunk && refill == o.refill && tchunk == o.tchunk && trefill == o.trefill;
         }
     };
-    const Opts start{c->kernel, c->tile_share, c->block, c->waves_per_cu, c->chunk, c->refill};
+    const Opts start{c->kernel, c->tile_share, c->block, c->waves_per_cu, c->chunk, c->refill, c->tile_chunk,
+                     c->tile_refill};
     std::vector<Opts> cand = {start};
+    // tiled walk (with the persistent walk for crowded boxes) at several tile
+    // shares, tile chunks and refill thresholds; the persistent walk alone
     const Opts fixed[] = {
-        {2, 100, 256, 32, 256, 16}, {2, 50, 256, 32, 256, 16}, {2, 25, 256, 32, 256, 16},
-        {2, 100, 256, 32, 256, 8},  {2, 100, 256, 32, 256, 32}, {2, 100, 256, 32, 64, 16},
-        {0, 100, 256, 32, 256, 16}, {0, 100, 256, 16, 256, 16}, {0, 100, 256, 32, 64, 16},
-        {0, 100, 256, 32, 256, 32}, {0, 100, 128, 32, 256, 16},
+        {2, 100, 256, 32, 256, 16, 64, 24}, {2, 50, 256, 32, 256, 16, 64, 24}, {2, 25, 256, 32, 256, 16, 64, 24},
+        {2, 100, 256, 32, 256, 16, 32, 24}, {2, 100, 256, 32, 256, 16, 128, 24}, {2, 100, 256, 32, 256, 16, 64, 16},
+        {0, 100, 256, 32, 256, 16, 64, 24}, {0, 100, 256, 16, 256, 16, 64, 24}, {0, 100, 256, 32, 64, 16, 64, 24},
+        {0, 100, 256, 32, 256, 32, 64, 24}, {0, 100, 128, 32, 256, 16, 64, 24},
     };
     for (const Opts &o : fixed)
         if (std::find(cand.begin(), cand.end(), o) == cand.end()) cand.push_back(o);
@@ -1220,6 +1233,8 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
         c->waves_per_cu = o.waves;
         c->chunk = o.chunk;
         c->refill = o.refill;
+        c->tile_chunk = o.tchunk;
+        c->tile_refill = o.trefill;
         double t_min = 1e300;
         for (int r = 0; r <= reps; ++r) {      // the first run warms up (captures, allocations)
             mc_lya_status st = reset();
@@ -1245,6 +1260,8 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
     c->waves_per_cu = pick.waves;
     c->chunk = pick.chunk;
     c->refill = pick.refill;
+    c->tile_chunk = pick.tchunk;
+    c->tile_refill = pick.trefill;
     mc_lya_status st = reset();
     if (st != MC_LYA_OK) return finish(st);
     if (result) {
@@ -1254,6 +1271,8 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
         result->waves_per_cu = pick.waves;
         result->chunk = pick.chunk;
         result->refill = pick.refill;
+        result->tile_chunk = pick.tchunk;
+        result->tile_refill = pick.trefill;
         result->best_ms = best;
         result->start_ms = first_ms;
         result->trials = (int32_t)cand.size();

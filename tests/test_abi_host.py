@@ -37,7 +37,7 @@ def test_struct_sizes_match_header_layout():
     M = _lib()
     assert C.sizeof(M.mc_lya_packet_trace) == 56
     assert C.sizeof(M.mc_lya_box_stats) == 88
-    assert C.sizeof(M.mc_lya_tune_result) == 72
+    assert C.sizeof(M.mc_lya_tune_result) == 88
     # 4 int32, 11 doubles, w0, 3 pointers, float + int32, 1 pointer
     assert C.sizeof(M.mc_lya_box_desc) == 16 + 88 + 8 + 24 + 8 + 8
 

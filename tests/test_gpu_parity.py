@@ -131,6 +131,8 @@ def test_launch_configuration_and_ranges_bitwise():
         {M.MC_LYA_OPT_KERNEL: 1},
         {M.MC_LYA_OPT_KERNEL: 0},
         {M.MC_LYA_OPT_KERNEL: 2, M.MC_LYA_OPT_TILE_SHARE: ALL_TILED},
+        {M.MC_LYA_OPT_TILE_SHARE: ALL_TILED, M.MC_LYA_OPT_TILE_CHUNK: 7, M.MC_LYA_OPT_TILE_REFILL: 1},
+        {M.MC_LYA_OPT_TILE_SHARE: ALL_TILED, M.MC_LYA_OPT_TILE_CHUNK: 1024, M.MC_LYA_OPT_TILE_REFILL: 64},
         {M.MC_LYA_OPT_KERNEL: 2, M.MC_LYA_OPT_TILE_SHARE: 0},
         {M.MC_LYA_OPT_BLOCK: 64, M.MC_LYA_OPT_WAVES_PER_CU: 8},
         {M.MC_LYA_OPT_CHUNK: 7, M.MC_LYA_OPT_REFILL: 1, M.MC_LYA_OPT_QUEUES: 1},
