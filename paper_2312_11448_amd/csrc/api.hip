@@ -383,14 +383,17 @@ mc_lya_status classify_boxes(mc_lya_ctx *c)
     return MC_LYA_OK;
 }
 
-constexpr uint64_t kTiledBatch = 1ull << 25;   // packets per tiled batch (state buffers of ~3.9 GB)
+// Packets per tiled batch: the whole emission when the packet-state buffers
+// for it (two generations' states, faces and indices) fit in a third of the
+// free device memory, else as many as do, at least 2^25. Fewer batches mean
+// fewer per-generation tile loads and flushes; the 2^28 packets of the 256^3
+// workload (63 GB of state) are one batch on a 288 GB device.
+constexpr uint64_t kMinTiledBatch = 1ull << 25;
 constexpr int kGenRound = 16;                  // generations queued between two checks
+constexpr uint64_t kStateBytes = 2 * (sizeof(PState) + sizeof(uint8_t) + sizeof(uint32_t));
 
-mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
+void free_tile_buffers(mc_lya_ctx *c)
 {
-    const uint64_t cap = std::max<uint64_t>(1, std::min(packets, kTiledBatch));
-    if (cap <= c->state_cap) return MC_LYA_OK;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < 2; ++i) {
         if (c->d_state[i]) (void)hipFree(c->d_state[i]);
         if (c->d_face[i]) (void)hipFree(c->d_face[i]);
@@ -400,18 +403,37 @@ mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
         c->d_idx[i] = nullptr;
     }
     c->state_cap = 0;
-    for (int i = 0; i < 2; ++i) {
-        HIP_TRY(c, dalloc(&c->d_state[i], cap));
-        HIP_TRY(c, dalloc(&c->d_face[i], cap));
-        HIP_TRY(c, dalloc(&c->d_idx[i], cap));
+    ++c->epoch;
+}
+
+mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
+{
+    packets = std::max<uint64_t>(1, packets);
+    if (packets <= c->state_cap) return MC_LYA_OK;             // one batch already
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
+    const uint64_t avail = (uint64_t)free_b + c->state_cap * kStateBytes;   // the current buffers are released
+    uint64_t cap = std::min(packets, std::max(kMinTiledBatch, avail / 3 / kStateBytes));
+    if (cap <= c->state_cap) return MC_LYA_OK;                 // no larger batch possible: keep batching
+    free_tile_buffers(c);
+    for (;;) {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            if ((e = dalloc(&c->d_state[i], cap)) == hipSuccess && (e = dalloc(&c->d_face[i], cap)) == hipSuccess)
+                e = dalloc(&c->d_idx[i], cap);
+        }
+        if (e == hipSuccess) break;
+        free_tile_buffers(c);
+        (void)hipGetLastError();
+        if (e != hipErrorOutOfMemory || cap <= kMinTiledBatch) return hip_fail(c, e, "packet-state buffers");
+        cap = std::max(kMinTiledBatch, cap / 2);               // fragmented memory: smaller batches
     }
     c->state_cap = cap;
     ++c->epoch;
     return MC_LYA_OK;
 }
 
-// Times the work enqueued between timed_begin and timed_end with a pair of
-// HIP events on the context's stream (when MC_LYA_OPT_TIMING is on).
 mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
 {
     *e1 = nullptr;
