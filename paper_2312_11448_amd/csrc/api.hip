@@ -293,18 +293,18 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
     return MC_LYA_OK;
 }
 
-// Tiles of kTileEdge^3 cells per box (the last ones along an axis may be
+// Tiles of kTileX x kTileY x kTileZ cells per box (the last ones along an axis may be
 // thinner). For each tile, the exit lists it pulls: for each of its six faces
 // whose neighbour is another tile, that neighbour's list through the
 // opposite face (a tile that spans an axis wraps onto itself there).
 void build_tiles(mc_lya_ctx *c)
 {
-    const int TE = kTileEdge;
+    const int TE[3] = {kTileX, kTileY, kTileZ};
     c->tiles.clear();
     for (int b = 0; b < c->n_boxes; ++b) {
         if (!c->tiled[b]) continue;
         const mc_lya_box_desc &d = c->desc[b];
-        const int nt[3] = {(d.nx + TE - 1) / TE, (d.ny + TE - 1) / TE, (d.nz + TE - 1) / TE};
+        const int nt[3] = {(d.nx + TE[0] - 1) / TE[0], (d.ny + TE[1] - 1) / TE[1], (d.nz + TE[2] - 1) / TE[2]};
         const int off = (int)c->tiles.size();
         const int n[3] = {d.nx, d.ny, d.nz};
         for (int tz = 0; tz < nt[2]; ++tz)
@@ -316,8 +316,8 @@ void build_tiles(mc_lya_ctx *c)
                     const int tc[3] = {tx, ty, tz};
                     int o[3], e[3];
                     for (int a = 0; a < 3; ++a) {
-                        o[a] = tc[a] * TE;
-                        e[a] = std::min(TE, n[a] - o[a]);
+                        o[a] = tc[a] * TE[a];
+                        e[a] = std::min(TE[a], n[a] - o[a]);
                     }
                     t.ox = o[0];
                     t.oy = o[1];
@@ -344,8 +344,7 @@ void build_tiles(mc_lya_ctx *c)
 
 int tiles_of_box(const mc_lya_box_desc &d)
 {
-    const int TE = kTileEdge;
-    return ((d.nx + TE - 1) / TE) * ((d.ny + TE - 1) / TE) * ((d.nz + TE - 1) / TE);
+    return ((d.nx + kTileX - 1) / kTileX) * ((d.ny + kTileY - 1) / kTileY) * ((d.nz + kTileZ - 1) / kTileZ);
 }
 
 constexpr int kMinTiles = 8;              // fewer tiles than this never pays

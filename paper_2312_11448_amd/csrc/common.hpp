@@ -148,7 +148,17 @@ struct WalkParams {
 constexpr int kMaxQueues = 64;
 
 // ---- tile-decomposed walk -------------------------------------------------
-constexpr int kTileEdge = 16;          // cells per tile edge (tiles of 16^3 cells)
+// Tile extent in cells along x, y, z (the last tiles along an axis may be
+// thinner) and the workgroup that walks one tile.
+#ifndef MCLYA_TILE_Z
+#define MCLYA_TILE_Z 16
+#endif
+#ifndef MCLYA_TILE_BLOCK
+#define MCLYA_TILE_BLOCK 1024
+#endif
+constexpr int kTileX = 16, kTileY = 16, kTileZ = MCLYA_TILE_Z;
+constexpr int kTileCells = kTileX * kTileY * kTileZ;
+constexpr int kTileBlock = MCLYA_TILE_BLOCK;
 
 struct TileInfo {
     int32_t box;

@@ -2,7 +2,7 @@
 //
 // Device-scope 64-bit atomics run at a fixed ~2.4e10 operations/s on this
 // chip whatever the cache residency, while a packet deposits into one cell per
-// crossing. So the grid is cut into tiles of kTileEdge^3 cells and the walk
+// crossing. So the grid is cut into tiles of kTileCells cells and the walk
 // proceeds in generations: in each generation one workgroup owns one tile,
 // walks every packet that is inside it, deposits into a tally in LDS (LDS
 // atomics), and at the end adds that tally to the device tallies with plain
@@ -25,9 +25,9 @@
 namespace mclya {
 namespace {
 
-constexpr int TE = kTileEdge;
-constexpr int TC = TE * TE * TE;
-constexpr int BLK = 1024;          // 16 waves per tile
+constexpr int TC = kTileCells;
+constexpr int BLK = kTileBlock;
+static_assert(TC % BLK == 0, "tile cells must be a multiple of the workgroup size");
 constexpr int kWaves = BLK / 64;
 
 // Deposits and opacity/velocity records of the cells of one tile, both in LDS.
