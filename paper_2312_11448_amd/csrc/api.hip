@@ -83,6 +83,8 @@ hipError_t dalloc(T **p, size_t n)
 
 }  // namespace
 
+constexpr int kEagerGens = 16;
+
 struct mc_lya_ctx {
     hipStream_t stream = nullptr;
     int n_boxes = 0;
@@ -142,6 +144,7 @@ struct mc_lya_ctx {
     hipStream_t cap_stream = nullptr;        // private stream the graph is captured on
     std::vector<uint64_t> graph_key;
     int graph_gens = 64;                     // tile generations inside the graph
+    int eager_gens = kEagerGens;             // tile generations in the first eager round
     uint64_t epoch = 0;                      // bumped whenever a buffer a graph reads is reallocated
 
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
@@ -520,13 +523,16 @@ mc_lya_status exits_after(mc_lya_ctx *c, int gen, unsigned long long *exits)
 
 // Continues a tiled batch from generation gen in rounds of kGenRound, reading
 // the exit count after each round, until no packet is left crossing.
-mc_lya_status drain_generations(mc_lya_ctx *c, TileParams &p, int gen)
+mc_lya_status drain_generations(mc_lya_ctx *c, TileParams &p, int gen, int *end = nullptr)
 {
     for (;;) {
         unsigned long long exits = 0;
         mc_lya_status st = exits_after(c, gen, &exits);
         if (st != MC_LYA_OK) return st;
-        if (exits == 0) return MC_LYA_OK;
+        if (exits == 0) {
+            if (end) *end = gen;
+            return MC_LYA_OK;
+        }
         if (gen >= kMaxGenerations) return fail(c, MC_LYA_EDEVICE, "tiled walk did not drain");
         const int g1 = std::min(gen + kGenRound, kMaxGenerations);
         st = enqueue_generations(c, p, gen, g1, true);
@@ -539,18 +545,33 @@ mc_lya_status drain_generations(mc_lya_ctx *c, TileParams &p, int gen)
 // predecessor moved nothing returns at once. After each round the host reads
 // the last generation's exit count: zero means every packet has finished.
 // Emissions larger than the packet-state buffers walk in batches.
+// The first round takes as many generations as the previous transport of the
+// context needed (plus a few), so a repeated workload usually needs a single
+// host read-back per batch.
 mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
 {
+    int needed = 0;
     for (uint64_t done = 0; done < count;) {
         const uint64_t n = std::min(count - done, c->state_cap);
         TileParams p = tile_params(c, first + done, n);
         HIP_TRY(c, launch_zero_counters(c->d_gen, 2 * kMaxGenerations, c->stream));
-        const int g1 = std::min(kGenRound, kMaxGenerations);
+        const int g1 = std::min(std::max(kGenRound, c->eager_gens), kMaxGenerations);
+        int end = g1;
         mc_lya_status st = enqueue_generations(c, p, 0, g1, true);
-        if (st == MC_LYA_OK) st = drain_generations(c, p, g1);
+        if (st == MC_LYA_OK) st = drain_generations(c, p, g1, &end);
         if (st != MC_LYA_OK) return st;
+        // the last generation that still handed packets on
+        std::vector<unsigned long long> cnt(2 * (size_t)end);
+        HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->d_gen, sizeof(unsigned long long) * cnt.size(),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        int last = 0;
+        for (int g = 0; g < end; ++g)
+            if (cnt[2 * g + 1]) last = g;
+        needed = std::max(needed, last + 2);
         done += n;
     }
+    c->eager_gens = needed + 4;
     return MC_LYA_OK;
 }
 
