@@ -219,7 +219,11 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     const bool bx = L.tmx <= L.tmy && L.tmx <= L.tmz;
     const bool by = !bx && L.tmy <= L.tmz;
     const bool bz = !bx && !by;
-    const double tn = fmin(fmin(L.tmx, L.tmy), L.tmz);   // (a value, not a choice of field)
+    // the chosen face's distance, selected on the bit patterns (fmin would
+    // canonicalise its operands with three extra FP64 instructions)
+    const long long ux = __double_as_longlong(L.tmx), uy = __double_as_longlong(L.tmy),
+                    uz = __double_as_longlong(L.tmz);
+    const double tn = __longlong_as_double(bx ? ux : (by ? uy : uz));
     // only the coordinate on the chosen axis moves, by one cell (periodic);
     // sums of field-or-zero terms: a choice between fields would make the
     // compiler address the lane state in memory
