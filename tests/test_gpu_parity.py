@@ -266,6 +266,21 @@ def test_errors_and_cap():
         with pytest.raises(M.MCLyaError) as e:
             M.mc_lya_transport_range(sim.ctx, 900, 200)
         assert e.value.status == M.MC_LYA_EINVAL
+        # options outside their ranges are refused and leave the context usable
+        for opt, bad in ((M.MC_LYA_OPT_KERNEL, 3), (M.MC_LYA_OPT_BLOCK, 96), (M.MC_LYA_OPT_REFILL, 0),
+                         (M.MC_LYA_OPT_TILE_CHUNK, 2000), (M.MC_LYA_OPT_TILE_REFILL, 65),
+                         (M.MC_LYA_OPT_DEFER, -1), (M.MC_LYA_OPT_TILE_SHARE, -5), (M.MC_LYA_OPT_GRAPH, 2),
+                         (M.MC_LYA_OPT_GRAPH_GENS, 8), (M.MC_LYA_OPT_QUEUES, 0), (99, 1)):
+            with pytest.raises(M.MCLyaError) as e:
+                sim.set_option(opt, bad)
+            assert e.value.status == M.MC_LYA_EINVAL, opt
+        with pytest.raises(M.MCLyaError) as e:
+            M.mc_lya_autotune(sim.ctx, 0)
+        assert e.value.status == M.MC_LYA_EINVAL
+        sim.set_option(M.MC_LYA_OPT_MAX_CROSSINGS, 1_000_000)
+        sim.emit()
+        sim.transport()
+        assert sim.tally()["stats"][0].conserved == 1
 
 
 @pytest.mark.parametrize("shape", [(16, 16, 16), (9, 9, 9), (20, 33, 17), (48, 16, 40), (5, 70, 3)])
