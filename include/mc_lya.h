@@ -160,8 +160,13 @@ enum {
                                      with idle lanes (tiles that took >= 2048 packets) */
     MC_LYA_OPT_TILE_CHUNK = 13,   /* tiled walk: packets a wave takes from its tile's input at
                                      once (1..1024, default 64) */
-    MC_LYA_OPT_TILE_REFILL = 14   /* tiled walk: refill a wave once this many lanes are idle
+    MC_LYA_OPT_TILE_REFILL = 14,  /* tiled walk: refill a wave once this many lanes are idle
                                      (1..64, default 24) */
+    MC_LYA_OPT_TAIL = 15          /* tiled walk: once fewer packets than this many millionths
+                                     of a batch are in flight (0..1000000, default 100000 =
+                                     10 %; 0 = never), one kernel walks them to the end with
+                                     device-wide deposits instead of further, thinning tile
+                                     generations */
 };
 
 /* Creates a context for n_boxes boxes, validates and packs their fields

@@ -24,6 +24,7 @@ MC_LYA_OPT_GRAPH_GENS = 11
 MC_LYA_OPT_DEFER = 12
 MC_LYA_OPT_TILE_CHUNK = 13
 MC_LYA_OPT_TILE_REFILL = 14
+MC_LYA_OPT_TAIL = 15
 
 
 class mc_lya_box_desc(C.Structure):

@@ -145,6 +145,8 @@ struct mc_lya_ctx {
     std::vector<uint64_t> graph_key;
     int graph_gens = 64;                     // tile generations inside the graph
     int eager_gens = kEagerGens;             // tile generations in the first eager round
+    int tail = 100000;                       // MC_LYA_OPT_TAIL (millionths of a batch)
+    uint32_t *d_tail_prefix = nullptr;       // [tiles] first tail packet of each tile
     uint64_t epoch = 0;                      // bumped whenever a buffer a graph reads is reallocated
 
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
@@ -190,7 +192,7 @@ void free_all(mc_lya_ctx *c)
     c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tail_prefix, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -458,6 +460,13 @@ mc_lya_status timed_end(mc_lya_ctx *c, hipEvent_t e1)
     return MC_LYA_OK;
 }
 
+// The tail walk takes over once fewer than this many of a batch's n packets
+// are in flight (MC_LYA_OPT_TAIL, in millionths of the batch).
+uint64_t tail_packets(const mc_lya_ctx *c, uint64_t n)
+{
+    return (uint64_t)((unsigned __int128)n * (uint64_t)c->tail / 1000000u);
+}
+
 TileParams tile_params(mc_lya_ctx *c, uint64_t first, uint64_t n)
 {
     TileParams p;
@@ -475,6 +484,8 @@ TileParams tile_params(mc_lya_ctx *c, uint64_t first, uint64_t n)
     p.refill = c->tile_refill;
     p.defer_lanes = c->defer;
     p.defer_min = 2048;
+    p.tail_min = tail_packets(c, n);
+    p.tail_gen = c->d_gen + kTailGenSlot;
     p.first = first;
     p.count = n;
     return p;
@@ -497,6 +508,7 @@ mc_lya_status enqueue_generations(mc_lya_ctx *c, TileParams &p, int g0, int g1, 
         p.bump = c->d_gen + 2 * gen;
         p.exits = c->d_gen + 2 * gen + 1;
         p.prev_exits = gen > 0 ? c->d_gen + 2 * (gen - 1) + 1 : c->d_gen + 1;
+        p.gen = gen;
         hipEvent_t e1 = nullptr;
         if (timed) {
             mc_lya_status st = timed_begin(c, &e1);
@@ -509,6 +521,38 @@ mc_lya_status enqueue_generations(mc_lya_ctx *c, TileParams &p, int g0, int g1, 
         }
         ++c->generations;
     }
+    return MC_LYA_OK;
+}
+
+// The tail walk of the current batch (a no-op unless a generation stopped).
+mc_lya_status enqueue_tail(mc_lya_ctx *c, uint64_t n, bool timed)
+{
+    const uint64_t capacity = tail_packets(c, n);
+    if (capacity == 0) return MC_LYA_OK;
+    TailParams t;
+    std::memset(&t, 0, sizeof t);
+    t.boxes = c->d_walk;
+    t.tiles = c->d_tiles;
+    t.rec = c->d_rec;
+    t.A = c->d_A;
+    t.tot = c->d_tot;
+    for (int i = 0; i < 2; ++i) {
+        t.state[i] = c->d_state[i];
+        t.face[i] = c->d_face[i];
+        t.idx[i] = c->d_idx[i];
+        t.exits[i] = c->d_texits[i];
+    }
+    t.counters = c->d_gen;
+    t.prefix = c->d_tail_prefix;
+    t.ntiles = (int)c->tiles.size();
+    t.max_cross = (uint32_t)c->max_cross;
+    hipEvent_t e1 = nullptr;
+    if (timed) {
+        mc_lya_status st = timed_begin(c, &e1);
+        if (st != MC_LYA_OK) return st;
+    }
+    HIP_TRY(c, launch_tail_walk(t, capacity, c->vel, c->stream));
+    if (timed) return timed_end(c, e1);
     return MC_LYA_OK;
 }
 
@@ -554,11 +598,12 @@ mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
     for (uint64_t done = 0; done < count;) {
         const uint64_t n = std::min(count - done, c->state_cap);
         TileParams p = tile_params(c, first + done, n);
-        HIP_TRY(c, launch_zero_counters(c->d_gen, 2 * kMaxGenerations, c->stream));
+        HIP_TRY(c, launch_zero_counters(c->d_gen, kGenCounters, c->stream));
         const int g1 = std::min(std::max(kGenRound, c->eager_gens), kMaxGenerations);
         int end = g1;
         mc_lya_status st = enqueue_generations(c, p, 0, g1, true);
         if (st == MC_LYA_OK) st = drain_generations(c, p, g1, &end);
+        if (st == MC_LYA_OK) st = enqueue_tail(c, n, true);
         if (st != MC_LYA_OK) return st;
         // the last generation that still handed packets on
         std::vector<unsigned long long> cnt(2 * (size_t)end);
@@ -698,7 +743,7 @@ std::vector<uint64_t> graph_key(mc_lya_ctx *c, const WalkPlan &w, int budget)
                                (uint64_t)c->chunk, (uint64_t)c->refill, (uint64_t)c->nqueues,
                                (uint64_t)c->tile_chunk, (uint64_t)c->tile_refill,
                                (uint64_t)c->max_cross, c->total_packets, c->state_cap, (uint64_t)budget,
-                               (uint64_t)c->defer,
+                               (uint64_t)c->defer, (uint64_t)c->tail,
                                (uint64_t)w.tiled, (uint64_t)w.global, (uint64_t)c->tiles.size(),
                                (uint64_t)(uintptr_t)c->d_state[0], (uint64_t)(uintptr_t)c->d_cop,
                                (uint64_t)w.p.n_seg, w.p.count, c->epoch};
@@ -730,8 +775,9 @@ mc_lya_status transport_graph(mc_lya_ctx *c, WalkPlan &w)
         }
         const int64_t gens = c->generations;
         if (w.tiled) {
-            e = launch_zero_counters(c->d_gen, 2 * kMaxGenerations, c->stream);
+            e = launch_zero_counters(c->d_gen, kGenCounters, c->stream);
             if (e == hipSuccess && enqueue_generations(c, tp, 0, budget, false) != MC_LYA_OK) e = hipErrorUnknown;
+            if (e == hipSuccess && enqueue_tail(c, c->total_packets, false) != MC_LYA_OK) e = hipErrorUnknown;
         }
         c->generations = gens;
         if (e == hipSuccess && w.global && launch_global_walk(c, w.p, false) != MC_LYA_OK) e = hipErrorUnknown;
@@ -755,7 +801,10 @@ mc_lya_status transport_graph(mc_lya_ctx *c, WalkPlan &w)
     if (st != MC_LYA_OK) return st;
     c->generations = budget;
     if (w.tiled) {
-        st = drain_generations(c, tp, budget);
+        int end = budget;
+        st = drain_generations(c, tp, budget, &end);
+        // generations beyond the budget ran eagerly: their tail walk too
+        if (st == MC_LYA_OK && end > budget) st = enqueue_tail(c, c->total_packets, true);
         if (st != MC_LYA_OK) return st;
         // ran out of captured generations: the next capture takes what this
         // emission needed plus one round of slack (empty generations return
@@ -917,7 +966,8 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
     build_tiles(c);
     const size_t nt = c->tiles.size();
     if ((e = dalloc(&c->d_tiles, nt)) != hipSuccess || (e = dalloc(&c->d_texits[0], nt)) != hipSuccess ||
-        (e = dalloc(&c->d_texits[1], nt)) != hipSuccess || (e = dalloc(&c->d_gen, 2 * kMaxGenerations)) != hipSuccess)
+        (e = dalloc(&c->d_texits[1], nt)) != hipSuccess || (e = dalloc(&c->d_gen, kGenCounters)) != hipSuccess ||
+        (e = dalloc(&c->d_tail_prefix, nt)) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
     if (hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(TileInfo) * nt, hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
@@ -1203,6 +1253,10 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     case MC_LYA_OPT_TILE_REFILL:
         if (v < 1 || v > 64) return fail(c, MC_LYA_EINVAL, "tile refill must be in [1, 64]");
         c->tile_refill = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_TAIL:
+        if (v < 0 || v > 1000000) return fail(c, MC_LYA_EINVAL, "tail must be in [0, 1000000] (ppm)");
+        c->tail = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_DEFER:
         if (v < 0 || v > 64) return fail(c, MC_LYA_EINVAL, "defer must be in [0, 64]");

@@ -195,6 +195,11 @@ struct TileExits {
 };
 
 constexpr int kMaxGenerations = 4096;  // per transport batch (packets cross at most one tile per generation)
+// Counters of a batch: per generation (bump allocator, exits), then the tail
+// hand-off: the generation that found fewer than tail_min packets in flight
+// (0 = none) and the number of packets handed to the tail walk.
+constexpr int kGenCounters = 2 * kMaxGenerations + 2;
+constexpr int kTailGenSlot = 2 * kMaxGenerations, kTailCountSlot = 2 * kMaxGenerations + 1;
 
 struct TileParams {
     const WalkBox *boxes;
@@ -221,9 +226,33 @@ struct TileParams {
     int32_t refill;          // refill a wave once this many lanes are idle
     int32_t defer_lanes;     // once the tile's input is used up, a wave with at most this many live lanes
     uint32_t defer_min;      // ... defers them to the next generation, if the tile took >= defer_min packets
+    int32_t gen;             // index of this generation in the batch
+    uint64_t tail_min;       // fewer packets in flight than this: stop and leave them to the tail walk
+    unsigned long long *tail_gen;   // where the first generation that stops records its index
+};
+
+// The tail walk: the packets the last full generation handed on, walked to
+// the end one per thread with device-scope deposits.
+struct TailParams {
+    const WalkBox *boxes;
+    const TileInfo *tiles;
+    const void *rec;
+    unsigned long long *A;
+    BoxTot *tot;
+    const PState *state[2];
+    const uint8_t *face[2];
+    const uint32_t *idx[2];
+    const TileExits *exits[2];
+    unsigned long long *counters;   // the batch counters (kTailGenSlot, kTailCountSlot)
+    uint32_t *prefix;        // [ntiles] first tail packet of each tile
+    int32_t ntiles;
+    uint32_t max_cross;
 };
 
 hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s);
+// The tail walk of a batch (no-op when no generation stopped); `capacity`
+// bounds the packets it can take (tail_min).
+hipError_t launch_tail_walk(const TailParams &p, uint64_t capacity, bool vel, hipStream_t s);
 hipError_t launch_zero_counters(unsigned long long *c, int n, hipStream_t s);
 
 hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s);

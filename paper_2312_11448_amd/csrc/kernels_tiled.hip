@@ -156,7 +156,16 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
 
     const int T = blockIdx.x;
     const int tid = threadIdx.x;
-    if (!GEN0 && *P.prev_exits == 0) return;       // the walk has drained: nothing moves any more
+    if (!GEN0) {
+        const unsigned long long in_flight = *P.prev_exits;
+        if (in_flight == 0) return;                 // the walk has drained (or went to the tail walk)
+        if (in_flight < P.tail_min) {
+            // few packets left: the tail walk takes them from the previous
+            // generation's lists, and every later generation finds no exits
+            if (blockIdx.x == 0 && threadIdx.x == 0) *P.tail_gen = (unsigned long long)P.gen;
+            return;
+        }
+    }
     const TileInfo ti = P.tiles[T];
     const WalkBox B = P.boxes[ti.box];
     const int ncell = ti.sx * ti.sy * ti.sz;
@@ -424,6 +433,97 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     }
 }
 
+// ---- tail walk -----------------------------------------------------------
+// Exclusive prefix of the tail packets over tiles (one block).
+__global__ __launch_bounds__(1024) void tail_prefix_kernel(TailParams P)
+{
+    __shared__ uint32_t s_wsum[16];
+    __shared__ uint32_t s_carry;
+    const unsigned long long g = P.counters[kTailGenSlot];
+    if (g == 0) {
+        if (threadIdx.x == 0) P.counters[kTailCountSlot] = 0;
+        return;
+    }
+    const TileExits *ex = P.exits[(g - 1) & 1];
+    const uint32_t lane = __lane_id(), wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < P.ntiles; base += 1024) {
+        const int t = base + (int)threadIdx.x;
+        const uint32_t v = t < P.ntiles ? ex[t].off[kDeferred + 1] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if ((int)lane >= off) inc += o;
+        }
+        if (lane == 63) s_wsum[wid] = inc;
+        __syncthreads();
+        uint32_t before = s_carry;
+        for (uint32_t w = 0; w < wid; ++w) before += s_wsum[w];
+        if (t < P.ntiles) P.prefix[t] = before + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t all = 0;
+            for (int w = 0; w < 16; ++w) all += s_wsum[w];
+            s_carry += all;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P.counters[kTailCountSlot] = s_carry;
+}
+
+template <bool VEL>
+__global__ __launch_bounds__(256) void tail_walk_kernel(TailParams P)
+{
+    const unsigned long long g = P.counters[kTailGenSlot];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t esc = 0, cross = 0, capn = 0, capw = 0;
+    int box = -1;
+    if (g != 0 && i < P.counters[kTailCountSlot]) {
+        const int q = (int)((g - 1) & 1);
+        int lo = 0, hi = P.ntiles - 1;             // the tile whose list holds packet i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.prefix[mid] <= (uint32_t)i) lo = mid; else hi = mid - 1;
+        }
+        const TileExits e = P.exits[q][lo];
+        const uint32_t k = P.idx[q][e.base + ((uint32_t)i - P.prefix[lo])];
+        box = P.tiles[lo].box;
+        const WalkBox B = P.boxes[box];
+        Lane L;
+        load_state(L, P.state[q][k], B);
+        const Rec r = load_rec<VEL>(P.rec, L.c);
+        if (P.face[q][k] == kDeferred) L.kap = r.kap;   // deferred inside its cell
+        else finish_entry<VEL>(L, r);                   // entering through a face
+        uint64_t dep = 0;
+        int fate;
+        do {
+            fate = walk_step<VEL>(L, P.rec, GlobalSink{P.A}, P.max_cross, dep);
+        } while (fate == kAlive);
+        cross = L.ncross;
+        esc = fate == kEscaped ? L.w : 0;
+        capn = fate == kCapped ? 1 : 0;
+        capw = fate == kCapped ? L.w : 0;
+    }
+    // per-box totals: one atomic per box present in the wave
+    uint64_t pending = __ballot(box >= 0);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int b = __shfl(box, leader, 64);
+        const bool mine = box == b;
+        const uint64_t se = wave_sum(mine ? esc : 0), sc = wave_sum(mine ? cross : 0),
+                       sn = wave_sum(mine ? capn : 0), sw = wave_sum(mine ? capw : 0);
+        if ((int)__lane_id() == leader) {
+            if (se) atomicAdd(&P.tot[b].escaped, (unsigned long long)se);
+            if (sc) atomicAdd(&P.tot[b].crossings, (unsigned long long)sc);
+            if (sn) atomicAdd(&P.tot[b].capped_packets, (unsigned long long)sn);
+            if (sw) atomicAdd(&P.tot[b].capped_weight, (unsigned long long)sw);
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
 __global__ void zero_counters_kernel(unsigned long long *c, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -442,6 +542,15 @@ hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipS
         if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, false>), grid, block, 0, s, p);
         else hipLaunchKernelGGL((tile_walk_kernel<false, false>), grid, block, 0, s, p);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_walk(const TailParams &p, uint64_t capacity, bool vel, hipStream_t s)
+{
+    hipLaunchKernelGGL(tail_prefix_kernel, dim3(1), dim3(1024), 0, s, p);
+    const dim3 grid((unsigned)std::max<uint64_t>(1, (capacity + 255) / 256));
+    if (vel) hipLaunchKernelGGL(tail_walk_kernel<true>, grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL(tail_walk_kernel<false>, grid, dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

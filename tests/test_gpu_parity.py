@@ -270,7 +270,8 @@ def test_errors_and_cap():
         for opt, bad in ((M.MC_LYA_OPT_KERNEL, 3), (M.MC_LYA_OPT_BLOCK, 96), (M.MC_LYA_OPT_REFILL, 0),
                          (M.MC_LYA_OPT_TILE_CHUNK, 2000), (M.MC_LYA_OPT_TILE_REFILL, 65),
                          (M.MC_LYA_OPT_DEFER, -1), (M.MC_LYA_OPT_TILE_SHARE, -5), (M.MC_LYA_OPT_GRAPH, 2),
-                         (M.MC_LYA_OPT_GRAPH_GENS, 8), (M.MC_LYA_OPT_QUEUES, 0), (99, 1)):
+                         (M.MC_LYA_OPT_GRAPH_GENS, 8), (M.MC_LYA_OPT_QUEUES, 0), (M.MC_LYA_OPT_TAIL, -1),
+                         (99, 1)):
             with pytest.raises(M.MCLyaError) as e:
                 sim.set_option(opt, bad)
             assert e.value.status == M.MC_LYA_EINVAL, opt
@@ -295,12 +296,16 @@ def test_tiled_walk_equals_global_walk(shape):
     spec = W.BoxSpec(n=shape, overdensity=od, velocity=vel, n_packets=60_000, seed=5)
     ref = gpu_run(spec, options={M.MC_LYA_OPT_KERNEL: 0})
     tiled = {M.MC_LYA_OPT_KERNEL: 2, M.MC_LYA_OPT_TILE_SHARE: ALL_TILED}
-    # deferral of thin waves to the next generation: off, default, always
-    for defer in (0, 8, 64):
-        g = gpu_run(spec, options={**tiled, M.MC_LYA_OPT_DEFER: defer})
-        assert np.array_equal(g["A"], ref["A"]), defer
+    # deferral of thin waves (off, default, always) with every generation
+    # walked by tiles (tail 0); the tail walk taking over after generation 0
+    # (tail: the whole batch) or once under a third of it is in flight
+    for defer, tail in ((0, 0), (8, 0), (64, 0), (16, 1_000_000), (16, 333_333)):
+        g = gpu_run(spec, options={**tiled, M.MC_LYA_OPT_DEFER: defer, M.MC_LYA_OPT_TAIL: tail})
+        assert np.array_equal(g["A"], ref["A"]), (defer, tail)
         assert g["escaped"] == ref["escaped"] and g["crossings"] == ref["crossings"]
-    part = gpu_run(spec, options=tiled, ranges=[(0, 17), (17, 31000), (31000, 60000)])
+    part = gpu_run(spec, options={**tiled, M.MC_LYA_OPT_TAIL: 0}, ranges=[(0, 17), (17, 31000), (31000, 60000)])
+    assert np.array_equal(part["A"], ref["A"])
+    part = gpu_run(spec, options={**tiled, M.MC_LYA_OPT_TAIL: 100_000}, ranges=[(0, 17), (17, 31000), (31000, 60000)])
     assert np.array_equal(part["A"], ref["A"])
 
 
@@ -331,10 +336,12 @@ def test_mixed_tiled_and_persistent_batch():
              W.make_box("c2", n=40, n_packets=5_000, field_seed=13, seed=3)]
     ref_A, ref_s, _ = _batch_run(boxes, {M.MC_LYA_OPT_KERNEL: 0})
     assert all(c == 1 for _, _, c in ref_s)
-    tiled_A, tiled_s, n_tiled = _batch_run(boxes, {M.MC_LYA_OPT_TILE_SHARE: ALL_TILED})
-    mixed_A, mixed_s, n_mixed = _batch_run(boxes, {})
+    tiled_A, tiled_s, n_tiled = _batch_run(boxes, {M.MC_LYA_OPT_TILE_SHARE: ALL_TILED, M.MC_LYA_OPT_TAIL: 0})
+    mixed_A, mixed_s, n_mixed = _batch_run(boxes, {M.MC_LYA_OPT_TAIL: 0})
     # all-tiled: whole rounds of 16 generations; mixed: the same plus one persistent launch
     assert n_tiled % 16 == 0 and n_mixed % 16 == 1
+    tail_A, tail_s, n_tail = _batch_run(boxes, {})
+    assert np.array_equal(tail_A, ref_A) and tail_s == ref_s
     assert np.array_equal(tiled_A, ref_A) and tiled_s == ref_s
     assert np.array_equal(mixed_A, ref_A) and mixed_s == ref_s
     split_A, split_s, _ = _batch_run(boxes, {}, ranges=[(0, 15_000), (15_000, 118_000), (118_000, 125_000)])
@@ -370,6 +377,7 @@ def test_graph_replay_equals_eager():
     with M.Simulation(boxes) as sim:
         sim.set_option(M.MC_LYA_OPT_GRAPH, 1)
         sim.set_option(M.MC_LYA_OPT_GRAPH_GENS, 16)
+        sim.set_option(M.MC_LYA_OPT_TAIL, 0)          # every generation by tiles: the budget runs out
         sim.set_option(M.MC_LYA_OPT_TIMING, 1)
         launches = []
         for seeds, (ref_A, ref_s) in zip(seeds_list, eager):
