@@ -30,7 +30,11 @@ HBM_PEAK_GBS = 8000.0
 # only reported while these are unchanged
 WALK_SOURCES = ("paper_2312_11448_amd/csrc/walk_core.hpp", "paper_2312_11448_amd/csrc/kernels_tiled.hip",
                 "paper_2312_11448_amd/csrc/common.hpp")
+# the walk's launches: tile generations and the tail walk (its one-block
+# prefix kernel is timed with it and counted in its bytes, not as a launch)
 WALK_KERNEL = "tile_walk_kernel"
+WALK_LAUNCH_KERNELS = ("tile_walk_kernel", "tail_walk_kernel")
+WALK_BYTE_KERNELS = ("tile_walk_kernel", "tail_walk_kernel", "tail_prefix_kernel")
 
 
 def walk_source_hash():
@@ -91,13 +95,15 @@ def summarize_counters(a):
     per = {}
     launches = {}
     for name, path, counter in (("fetch", f_csv, "FETCH_SIZE"), ("write", w_csv, "WRITE_SIZE")):
-        vals = [float(r["Counter_Value"]) * 1024.0 for r in _counter_rows(path, counter)
-                if WALK_KERNEL in r["Kernel_Name"]]
-        if not vals:
-            raise SystemExit(f"no {WALK_KERNEL} rows in {path}")
-        per[name] = scale[name] * sum(vals) / len(vals)
-        launches[name] = len(vals)
-    out = {"config": a.config, "kernel": WALK_KERNEL, "launches": launches,
+        rows = _counter_rows(path, counter)
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in rows
+                if any(k in r["Kernel_Name"] for k in WALK_BYTE_KERNELS)]
+        n = sum(1 for r in rows if any(k in r["Kernel_Name"] for k in WALK_LAUNCH_KERNELS))
+        if not vals or not n:
+            raise SystemExit(f"no walk rows in {path}")
+        per[name] = scale[name] * sum(vals) / n
+        launches[name] = n
+    out = {"config": a.config, "kernel": " + ".join(WALK_LAUNCH_KERNELS), "launches": launches,
            "fetch_scale": scale["fetch"], "write_scale": scale["write"],
            "fetch_bytes_per_launch": per["fetch"], "write_bytes_per_launch": per["write"],
            "bytes_per_launch": per["fetch"] + per["write"], "source_sha256": walk_source_hash()}

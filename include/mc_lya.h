@@ -200,9 +200,11 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *ctx, const uint64_t *seeds, const uint64_t
 /* Walks every emitted packet (App. A steps 1-4 and the red-wing exit) and
  * accumulates the per-cell absorbed weight and the per-box totals.
  * Asynchronous on the context's stream, except that the tiled walk (kernel 2)
- * reads one device counter back after every 16 generations to learn whether
- * packets are still in flight (a stream synchronisation per 16 launches).
- * Errors: ESTATE, EDEVICE. */
+ * synchronises to learn whether packets are still in flight: after a first
+ * round of as many generations as the previous transport needed, then after
+ * every 16 more. It may allocate its packet-state buffers on first use (the
+ * whole emission's, if they fit a third of the free device memory).
+ * Errors: ESTATE, ENOMEM, EDEVICE. */
 mc_lya_status mc_lya_transport(mc_lya_ctx *ctx);
 
 /* As mc_lya_transport, for global packet ids [first, first + count) only.

@@ -295,11 +295,24 @@ __global__ __launch_bounds__(B) void scan_blocks_kernel(const PackBox *__restric
 
 // Packets p in [0, N) with systematic point floor((2p+1) Qtot / 2N) below Q:
 // the odd integers o with o Qtot < 2 N Q, i.e. floor(ceil(2 N Q / Qtot) / 2).
+// ceil(m / qtot) is below 2n < 2^41 (Q <= qtot): a binary64 quotient is
+// within one of it, and exact 128-bit products settle it (no 128-bit
+// division).
 __device__ __forceinline__ uint64_t count_below(uint64_t Q, uint64_t qtot, uint64_t n)
 {
     const unsigned __int128 m = (unsigned __int128)(2u * n) * Q;
-    const unsigned __int128 c = (m + qtot - 1) / qtot;
-    return (uint64_t)(c >> 1);
+    const double md = (double)(uint64_t)(m >> 64) * 18446744073709551616.0 + (double)(uint64_t)m;
+    uint64_t c = (uint64_t)(md / (double)qtot);
+    unsigned __int128 prod = (unsigned __int128)c * qtot;
+    while (prod < m) {
+        ++c;
+        prod += qtot;
+    }
+    while (c > 0 && prod - qtot >= m) {
+        --c;
+        prod -= qtot;
+    }
+    return c >> 1;
 }
 
 // Allocation: each cell learns its first packet id and its count.
