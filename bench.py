@@ -253,7 +253,9 @@ def main():
     specs = W.batch_specs() if a.config == "batch" else [W.make_box(a.config)]
     dev = torch.device("cuda:0")
     sim = M.Simulation(specs, device=dev)
-    sim.set_option(M.MC_LYA_OPT_TIMING, 1)
+    # one event pair around each transport's walk, its launches counted: the
+    # launches run back to back, as they do untimed
+    sim.set_option(M.MC_LYA_OPT_TIMING, 2)
     graph = a.graph if a.graph is not None else 0
     sim.set_option(M.MC_LYA_OPT_GRAPH, graph)
     seeds, npk = [s.seed for s in specs], [s.n_packets for s in specs]

@@ -138,7 +138,10 @@ enum {
     MC_LYA_OPT_REFILL = 5,        /* persistent walk: refill a wave once this many lanes are
                                      idle (1..64) */
     MC_LYA_OPT_MAX_CROSSINGS = 6, /* crossing cap per packet (>= 1, default 1e6) */
-    MC_LYA_OPT_TIMING = 7,        /* 1 = time transport kernels with HIP events */
+    MC_LYA_OPT_TIMING = 7,        /* 0 = off (default); 1 = a HIP event pair around every walk
+                                     launch; 2 = one pair around each transport's walk, with
+                                     its launches counted (no events between launches, so the
+                                     launches run back to back) */
     MC_LYA_OPT_GRAPH = 8,         /* 1 = a whole-emission mc_lya_transport replays a captured
                                      HIP graph of its kernels (recaptured when options, packet
                                      count or buffers change; tiled emissions larger than the
@@ -276,8 +279,10 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *ctx, int32_t reps, mc_lya_tune_result 
 
 /* Sum of the durations of the transport kernels since the last call (ms),
  * measured with HIP events on the context's stream when MC_LYA_OPT_TIMING is
- * on; also returns the number of launches timed (a graph replay counts as
- * one). Synchronises the stream. */
+ * on; also returns the number of launches timed (timing 1: a graph replay
+ * counts as one; timing 2: the walk launches the transports enqueued or
+ * replayed, with the span of each transport's walk in ms). Synchronises the
+ * stream. Changing MC_LYA_OPT_TIMING drops what was timed so far. */
 mc_lya_status mc_lya_kernel_time(mc_lya_ctx *ctx, double *ms, int64_t *launches);
 
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) on the device: n blocks,

@@ -154,7 +154,9 @@ struct mc_lya_ctx {
     int kernel = 2, block = 256, waves_per_cu = 32, chunk = 256, refill = 16, nqueues = 8;
     int tile_chunk = 64, tile_refill = 24;   // the tiled walk's own chunk and refill
     int64_t max_cross = 1000000;
-    bool timing = false;
+    int timing = 0;                          // 0 off, 1 per launch, 2 per transport
+    int64_t coarse_launches = 0;
+    int64_t graph_launches = 0;              // walk launches in the captured graph
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used = 0;
     std::string err;
@@ -438,10 +440,10 @@ mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
     return MC_LYA_OK;
 }
 
-mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
+// Event pairs: one per walk launch (timing 1), or one per transport with the
+// launches counted (timing 2).
+mc_lya_status event_pair(mc_lya_ctx *c, hipEvent_t *e1)
 {
-    *e1 = nullptr;
-    if (!c->timing) return MC_LYA_OK;
     if (c->events_used == c->events.size()) {
         hipEvent_t a, b;
         HIP_TRY(c, hipEventCreate(&a));
@@ -452,6 +454,14 @@ mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
     *e1 = c->events[c->events_used].second;
     ++c->events_used;
     return MC_LYA_OK;
+}
+
+mc_lya_status timed_begin(mc_lya_ctx *c, hipEvent_t *e1)
+{
+    *e1 = nullptr;
+    if (c->timing == 2) ++c->coarse_launches;
+    if (c->timing != 1) return MC_LYA_OK;
+    return event_pair(c, e1);
 }
 
 mc_lya_status timed_end(mc_lya_ctx *c, hipEvent_t e1)
@@ -601,9 +611,12 @@ mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
         HIP_TRY(c, launch_zero_counters(c->d_gen, kGenCounters, c->stream));
         const int g1 = std::min(std::max(kGenRound, c->eager_gens), kMaxGenerations);
         int end = g1;
+        // the tail walk goes in right after the first round (a no-op unless a
+        // generation stopped in it), so it needs no host round trip
         mc_lya_status st = enqueue_generations(c, p, 0, g1, true);
-        if (st == MC_LYA_OK) st = drain_generations(c, p, g1, &end);
         if (st == MC_LYA_OK) st = enqueue_tail(c, n, true);
+        if (st == MC_LYA_OK) st = drain_generations(c, p, g1, &end);
+        if (st == MC_LYA_OK && end > g1) st = enqueue_tail(c, n, true);
         if (st != MC_LYA_OK) return st;
         // the last generation that still handed packets on
         std::vector<unsigned long long> cnt(2 * (size_t)end);
@@ -792,10 +805,16 @@ mc_lya_status transport_graph(mc_lya_ctx *c, WalkPlan &w)
             return hip_fail(c, e, "capturing the transport graph");
         }
         c->graph_key = key;
+        c->graph_launches = (w.tiled ? budget + (tail_packets(c, c->total_packets) ? 1 : 0) : 0) + (w.global ? 1 : 0);
     }
     hipEvent_t e1 = nullptr;
-    mc_lya_status st = timed_begin(c, &e1);
-    if (st != MC_LYA_OK) return st;
+    mc_lya_status st = MC_LYA_OK;
+    if (c->timing == 2) {
+        c->coarse_launches += c->graph_launches;      // the transport's own event pair times them
+    } else {
+        st = timed_begin(c, &e1);
+        if (st != MC_LYA_OK) return st;
+    }
     HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
     st = timed_end(c, e1);
     if (st != MC_LYA_OK) return st;
@@ -821,6 +840,11 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
     mc_lya_status st = plan_walk(c, first, count, &w);
     if (st != MC_LYA_OK) return st;
     c->generations = 0;
+    hipEvent_t coarse_end = nullptr;
+    if (c->timing == 2) {
+        st = event_pair(c, &coarse_end);
+        if (st != MC_LYA_OK) return st;
+    }
     const bool whole = first == 0 && count == c->total_packets;
     if (c->graph && whole && (!w.tiled || c->total_packets <= c->state_cap)) {
         st = transport_graph(c, w);
@@ -828,6 +852,7 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
         if (w.tiled) st = walk_tiled(c, first, count);
         if (st == MC_LYA_OK && w.global) st = launch_global_walk(c, w.p, true);
     }
+    if (st == MC_LYA_OK && coarse_end) st = timed_end(c, coarse_end);
     if (st != MC_LYA_OK) return st;
     account_walked(c, first, count);
     return MC_LYA_OK;
@@ -1240,7 +1265,13 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
         c->nqueues = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_TIMING:
-        c->timing = v != 0;
+        if (v < 0 || v > 2) return fail(c, MC_LYA_EINVAL, "timing must be 0, 1 or 2");
+        if (v != c->timing) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            c->events_used = 0;        // pairs of the other mode are dropped
+            c->coarse_launches = 0;
+        }
+        c->timing = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_TILE_SHARE:
         if (v < 0 || v > kAllTiled) return fail(c, MC_LYA_EINVAL, "tile share must be in [0, 1000000]");
@@ -1301,8 +1332,8 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
     };
     for (const Opts &o : fixed)
         if (std::find(cand.begin(), cand.end(), o) == cand.end()) cand.push_back(o);
-    const bool timing = c->timing;
-    c->timing = false;
+    const int timing = c->timing;
+    c->timing = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto finish = [&](mc_lya_status st) {
         c->timing = timing;
@@ -1388,8 +1419,9 @@ mc_lya_status mc_lya_kernel_time(mc_lya_ctx *c, double *ms, int64_t *launches)
         tot += t;
     }
     *ms = tot;
-    if (launches) *launches = (int64_t)c->events_used;
+    if (launches) *launches = c->timing == 2 ? c->coarse_launches : (int64_t)c->events_used;
     c->events_used = 0;
+    c->coarse_launches = 0;
     return MC_LYA_OK;
 }
 

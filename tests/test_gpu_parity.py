@@ -393,6 +393,36 @@ def test_graph_replay_equals_eager():
         assert launches[0] > 1 and launches[1] == 1 and launches[2] == 1
 
 
+def test_coarse_timing_counts_the_same_launches():
+    """Timing 2 (one event pair around each transport's walk) counts the walk
+    launches that timing 1 (a pair around every launch) times one by one, on
+    the same emission; on a graph replay it counts the captured generations
+    and the tail walk. The integers do not depend on the timing mode."""
+    box = W.make_box("c2", n=64, n_packets=50_000, field_seed=11, seed=1)
+    with M.Simulation([box]) as sim:
+        sim.set_option(M.MC_LYA_OPT_TILE_SHARE, ALL_TILED)
+        res = {}
+        for mode in (0, 1, 2):
+            sim.set_option(M.MC_LYA_OPT_TIMING, mode)
+            sim.emit()
+            sim.transport()
+            t = sim.tally()
+            res[mode] = (t["absorbed"].cpu().numpy(), sim.kernel_time())
+        assert np.array_equal(res[1][0], res[0][0]) and np.array_equal(res[2][0], res[0][0])
+        (ms1, n1), (ms2, n2) = res[1][1], res[2][1]
+        _say(f"  timing 1: {n1} launches {ms1:.3f} ms; timing 2: {n2} launches {ms2:.3f} ms")
+        assert n1 == n2 and n1 >= 2
+        assert ms1 > 0 and 0.25 * ms1 < ms2 < 4.0 * ms1
+        sim.set_option(M.MC_LYA_OPT_GRAPH, 1)
+        for _ in range(2):
+            sim.emit()
+            sim.transport()
+            t = sim.tally()
+            ms, n = sim.kernel_time()
+            assert np.array_equal(t["absorbed"].cpu().numpy(), res[0][0])
+            assert n == 64 + 1 and ms > 0          # the default budget of 64 generations, and the tail walk
+
+
 def test_autotune_changes_speed_only():
     boxes = [W.make_box("c2", n=48, n_packets=60_000, field_seed=31, seed=4),
              _low_z_box(24, 20_000, 5)]
