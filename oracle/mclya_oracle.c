@@ -25,6 +25,22 @@
  *     (the "lost to redshifting" outcome at the end of App. A).
  * Weights are integers, so sum(absorbed) + escaped == w0 * npackets exactly.
  *
+ * Line profile. Either the thermal (Doppler) profile, or the Voigt profile of
+ * Eq. (MC): the thermal profile convolved with the natural (Lorentz) line of
+ * half width a = A_2p lambda / (4 pi v_th) in Doppler units. Voigt emission
+ * adds a Cauchy deviate a tan(pi (u - 1/2)) to the thermal one. Its
+ * cumulative profile is taken to first order in a,
+ *   Phi_V(x) = erfc(-x)/2 - (2a/pi) F(x),   F = Dawson's integral,
+ * which follows from expanding the Cauchy CDF 1/2 + arctan(s/a)/pi in a; the
+ * neglected terms are O(a^2) (below 2e-7 at a = 8.6e-4). The damping wing
+ * keeps absorbing past -x_eff: an escaping packet leaves behind the expected
+ * share 1 - exp(-kbar Phi_V(x_stop)) of its weight, with kbar the box's mean
+ * kappa (the wing is crossed over hundreds of cells, so it sees the mean) and
+ * x_stop = -x_eff. That share is reported as "wing" (part of the escaped
+ * weight, absorbed far away, i.e. fully mixed). Packets emitted below -x_eff
+ * or above x_blue (blue of every walked frequency) are not walked: they
+ * escape at once with x_stop = x0.
+ *
  * Build: gcc -O2 -fopenmp -shared -fPIC mclya_oracle.c -o libmclya_oracle.so -lm
  * (no fast-math: every floating-point operation is plain IEEE double).
  */
@@ -141,6 +157,9 @@ typedef struct {
     uint64_t w0;         /* weight of one packet */
     uint64_t seed;
     int64_t max_cross;   /* crossing cap per packet */
+    double damping;      /* Voigt a (0: Doppler profile) */
+    double kappa_far;    /* mean kappa of the box, for the far damping wing (0: none) */
+    double x_blue;       /* packets emitted above it are not walked (+inf: all are) */
 } orc_box;
 
 typedef struct {
@@ -153,6 +172,7 @@ typedef struct {
     int64_t absorbed;    /* weight deposited into the grid */
     int32_t fate;        /* 0 absorbed, 1 escaped, 2 capped */
     int32_t pad;
+    int64_t wing;        /* part of the escaped weight absorbed by the far damping wing */
 } orc_packet_rec;
 
 typedef struct {
@@ -162,11 +182,43 @@ typedef struct {
     int64_t cap, n;
 } orc_trace;
 
-/* Cumulative Doppler profile: Phi(x) = int_{-inf}^{x} exp(-y^2)/sqrt(pi) dy. */
-static double orc_Phi(double x)
+/* Dawson's integral F(x) = exp(-x^2) int_0^x exp(t^2) dt, by Rybicki's
+ * sampling-theorem series (G. B. Rybicki, Computers in Physics 3, 85, 1989):
+ * F(x) = lim_{h->0} pi^{-1/2} sum over odd n of exp(-(x - n h)^2) / n. With
+ * h = 0.2 the discretisation error is of order exp(-(pi / 2h)^2) < 1e-26.
+ * The sum is taken about the even multiple x0 = 2 k h nearest to x (nodes
+ * x0 + m h, m odd, weights 1 / (2k + m)), so the offsets x - x0 - m h are
+ * small and exact; nodes with |offset| > 8 (terms below exp(-64)) are left out. */
+static double orc_dawson(double x)
 {
-    return 0.5 * erfc(-x);
+    const double h = 0.2;
+    const double k = nearbyint(x / (2.0 * h));
+    const double xp = x - 2.0 * h * k;
+    double sum = 0.0;
+    for (int m = -41; m <= 41; m += 2) {
+        const double d = xp - (double)m * h;
+        sum += exp(-d * d) / (2.0 * k + (double)m);
+    }
+    return sum / sqrt(M_PI);
 }
+
+/* Cumulative line profile: the Doppler one, erfc(-x)/2 = int_{-inf}^{x}
+ * exp(-y^2)/sqrt(pi) dy, and for a > 0 the Voigt one to first order in a. */
+static double orc_Phi(const orc_box *b, double x)
+{
+    const double phi = 0.5 * erfc(-x);
+    return b->damping > 0.0 ? phi - 2.0 * b->damping / M_PI * orc_dawson(x) : phi;
+}
+
+double orc_profile_cdf(double damping, double x)
+{
+    orc_box b;
+    memset(&b, 0, sizeof b);
+    b.damping = damping;
+    return orc_Phi(&b, x);
+}
+
+double orc_dawson_integral(double x) { return orc_dawson(x); }
 
 static int64_t orc_wrap(int64_t i, int64_t n)
 {
@@ -193,6 +245,9 @@ static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux
     /* frequency: Doppler profile exp(-x^2)/sqrt(pi), a normal law of variance
      * 1/2, by the Box-Muller transform */
     double x = sqrt(-log(u[5])) * cos(2.0 * M_PI * u[6]);
+    /* Voigt: plus the natural line, a Cauchy deviate of half width a */
+    if (b->damping > 0.0) x += b->damping * tan(M_PI * (u[7] - 0.5));
+    double x_stop = 0.0;
 
     int64_t ci[3] = {cell0 % nx, (cell0 / nx) % ny, cell0 / (nx * ny)};
     int64_t n[3] = {nx, ny, nz};
@@ -206,7 +261,7 @@ static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux
     rec->x0 = x;
 
     for (;;) {
-        if (x <= -b->x_eff) { fate = 1; break; }              /* redshifted out */
+        if (x <= -b->x_eff || x > b->x_blue) { fate = 1; x_stop = x; break; }   /* not in the walked window */
         if (ncross >= b->max_cross) { fate = 2; break; }
         int64_t c = ci[0] + nx * (ci[1] + ny * ci[2]);
         ++ncross;
@@ -225,7 +280,7 @@ static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux
 
         double x_out = x - b->delta * s;                     /* Hubble drift */
         int escaping = x_out <= -b->x_eff;
-        double dPhi = escaping ? orc_Phi(x) - orc_Phi(-b->x_eff) : orc_Phi(x) - orc_Phi(x_out);
+        double dPhi = escaping ? orc_Phi(b, x) - orc_Phi(b, -b->x_eff) : orc_Phi(b, x) - orc_Phi(b, x_out);
         /* Phi is non-decreasing: a negative difference of two rounded values
          * (a segment far shorter than a cell) is rounding, not absorption */
         if (dPhi < 0.0) dPhi = 0.0;
@@ -243,7 +298,7 @@ static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux
         } else if (tr) {
             tr->n++;
         }
-        if (escaping) { fate = 1; break; }
+        if (escaping) { fate = 1; x_stop = -b->x_eff; break; }
         if (w == 0) { fate = 0; break; }
 
         /* move to the face, then into the neighbouring cell */
@@ -262,6 +317,14 @@ static void orc_walk_one(const orc_box *b, const double *kappa, const double *ux
             x -= du;                                          /* Eq. (inout), bulk term */
         }
     }
+    /* the far damping wing: expected absorption of the escaping weight */
+    int64_t wing = 0;
+    if (fate == 1 && b->kappa_far > 0.0) {
+        const double pw = -expm1(-b->kappa_far * fmax(orc_Phi(b, x_stop), 0.0));
+        wing = (int64_t)rint((double)w * pw);
+        if (wing > w) wing = w;
+    }
+    rec->wing = wing;
     rec->crossings = ncross;
     rec->escaped = (fate == 0) ? 0 : w;
     rec->absorbed = absorbed;
@@ -279,19 +342,20 @@ static int64_t orc_find_cell(const uint64_t *first, int64_t ncells, uint64_t p)
     return lo;
 }
 
-/* Walk packets [p_begin, p_end). A (ncells) and out[4] = {escaped weight,
- * crossings, capped packets, capped weight} are accumulated into (not reset).
+/* Walk packets [p_begin, p_end). A (ncells) and out[5] = {escaped weight,
+ * crossings, capped packets, capped weight, wing} are accumulated into (not
+ * reset); wing is the part of the escaped weight the far damping wing absorbs.
  * recs, when not NULL, receives one record per packet. Returns 0. */
 int orc_transport(const orc_box *b, const double *kappa, const double *ux, const double *uy,
                   const double *uz, const uint64_t *first, uint64_t p_begin, uint64_t p_end,
-                  int64_t *A, int64_t out[4], orc_packet_rec *recs, int nthreads)
+                  int64_t *A, int64_t out[5], orc_packet_rec *recs, int nthreads)
 {
     const int64_t ncells = (int64_t)b->nx * b->ny * b->nz;
     if (nthreads <= 0) nthreads = omp_get_max_threads();
     int64_t *priv = (int64_t *)calloc((size_t)nthreads * (size_t)ncells, sizeof(int64_t));
     if (!priv) return -1;
-    int64_t esc = 0, cross = 0, capn = 0, capw = 0;
-#pragma omp parallel num_threads(nthreads) reduction(+ : esc, cross, capn, capw)
+    int64_t esc = 0, cross = 0, capn = 0, capw = 0, wing = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : esc, cross, capn, capw, wing)
     {
         int64_t *mine = priv + (size_t)omp_get_thread_num() * (size_t)ncells;
 #pragma omp for schedule(dynamic, 256)
@@ -299,7 +363,7 @@ int orc_transport(const orc_box *b, const double *kappa, const double *ux, const
             orc_packet_rec r;
             orc_walk_one(b, kappa, ux, uy, uz, p, orc_find_cell(first, ncells, p), mine, &r, NULL);
             cross += r.crossings;
-            if (r.fate == 1) esc += r.escaped;
+            if (r.fate == 1) { esc += r.escaped; wing += r.wing; }
             if (r.fate == 2) { capn += 1; capw += r.escaped; }
             if (recs) recs[p - p_begin] = r;
         }
@@ -311,7 +375,7 @@ int orc_transport(const orc_box *b, const double *kappa, const double *ux, const
         A[c] += sum;
     }
     free(priv);
-    out[0] += esc; out[1] += cross; out[2] += capn; out[3] += capw;
+    out[0] += esc; out[1] += cross; out[2] += capn; out[3] += capw; out[4] += wing;
     return 0;
 }
 

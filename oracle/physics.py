@@ -18,7 +18,8 @@ branching (beta_e + Lambda_2g) / (3 A + beta_e + Lambda_2g) of an excited atom.
 """
 import math
 import numpy as np
-from scipy.special import erfc
+from scipy import integrate
+from scipy.special import erfc, dawsn, voigt_profile
 
 # --- constants (CGS) ---------------------------------------------------------
 C_LIGHT = 2.99792458e10          # cm/s
@@ -97,6 +98,12 @@ def thermal_velocity(T):
     return math.sqrt(2.0 * K_B * T / M_H)
 
 
+def damping(T):
+    """Voigt parameter of Eq. (MC): the natural half width Gamma / 2 of the 2p
+    level over the Doppler width omega_alpha v_th, a = A lambda / (4 pi v_th)."""
+    return A_2P1S * LAMBDA_ALPHA / (4.0 * math.pi * thermal_velocity(T))
+
+
 def tau_ab_per_n1s(T, H):
     """Mean optical depth to true absorption per unit n_1s, Eq. (<fnu>):
     3 A p_ab lambda^3 / (8 pi H)."""
@@ -107,6 +114,60 @@ def tau_ab_per_n1s(T, H):
 def Phi(x):
     """Cumulative Doppler profile, int_{-inf}^x exp(-y^2)/sqrt(pi) dy."""
     return 0.5 * erfc(-np.asarray(x, dtype=np.float64))
+
+
+def Phi_voigt(x, a):
+    """Cumulative Voigt profile to first order in a: erfc(-x)/2 - (2a/pi) F(x),
+    F Dawson's integral (the Cauchy CDF 1/2 + arctan(s/a)/pi expanded in a;
+    the principal-value integral of the Gaussian against 1/s is the Dawson
+    function)."""
+    x = np.asarray(x, dtype=np.float64)
+    return 0.5 * erfc(-x) - 2.0 * a / math.pi * dawsn(x)
+
+
+def voigt_cdf_exact(x, a):
+    """Cumulative Voigt profile by quadrature of its definition: the thermal
+    density exp(-y^2)/sqrt(pi) times the Cauchy CDF 1/2 + arctan((x-y)/a)/pi,
+    integrated over y (the quadrature is split where the Cauchy factor turns)."""
+    f = lambda y: math.exp(-y * y) / math.sqrt(math.pi) * (0.5 + math.atan((x - y) / a) / math.pi)
+    lo, hi = min(-12.0, x - 1.0), max(12.0, x + 1.0)
+    cuts = sorted({lo, hi, *[c for c in (x - 50 * a, x - a, x, x + a, x + 50 * a) if lo < c < hi]})
+    return sum(integrate.quad(f, c0, c1, epsabs=1e-16, epsrel=1e-13, limit=400)[0]
+               for c0, c1 in zip(cuts[:-1], cuts[1:]))
+
+
+def voigt_density(x, a):
+    """Normalised Voigt density in Doppler units (Gaussian of variance 1/2
+    convolved with a Cauchy law of half width a)."""
+    return voigt_profile(np.asarray(x, dtype=np.float64), 1.0 / math.sqrt(2.0), a)
+
+
+def wing_homogeneous(tau, X, X_blue, a, kbar=None):
+    """Expected fractions of the emitted weight in a homogeneous, static box
+    with the Voigt profile and escape at -X: (walked absorption, far-wing
+    absorption, true escape). A packet emitted at x0 in (-X, X_blue] keeps
+    exp(-tau (Phi(x0) - Phi(-X))) when it reaches -X, and the wing then takes
+    1 - exp(-kbar Phi(-X)) of it; a packet emitted outside that window is not
+    walked and the wing takes 1 - exp(-kbar Phi(x0)). Integrated over the
+    Voigt emission density by quadrature."""
+    kbar = tau if kbar is None else kbar
+    P = lambda x: float(Phi_voigt(x, a))
+    px = P(-X)
+    def keep(x0):
+        return math.exp(-tau * max(P(x0) - px, 0.0)) if -X < x0 <= X_blue else 1.0
+    def stop(x0):
+        return px if -X < x0 <= X_blue else P(x0)
+    dens = lambda x0: float(voigt_density(x0, a))
+    def integ(fn):
+        pts = [-1e6, -1e3, -50.0, -X, -3.0, 0.0, 3.0, X_blue, 50.0, 1e3, 1e6]
+        return sum(integrate.quad(lambda y: dens(y) * fn(y), p0, p1, limit=400, epsabs=1e-14,
+                                  epsrel=1e-11)[0] for p0, p1 in zip(pts[:-1], pts[1:]))
+    walked = integ(lambda y: 1.0 - keep(y))
+    wing = integ(lambda y: keep(y) * -math.expm1(-kbar * stop(y)))
+    # the mass beyond +-1e6 (Cauchy tails, 2 a / (pi 1e6)) is escaped-and-absorbed
+    # by the wing in full on the blue side and negligible on the red side
+    wing += a / (math.pi * 1e6)
+    return walked, wing, 1.0 - walked - wing
 
 
 def escape_homogeneous(tau, X):
@@ -145,7 +206,12 @@ def box_scalars(spec):
     nH = n_h0(c) * (1.0 + spec.z) ** 3
     return dict(H=H, T=T, v_th=vth, dl_phys=dl, delta=H * dl / vth, n_H=nH,
                 kappa_per_n1s=tau_ab_per_n1s(T, H), alpha=alpha_e(T), beta=beta_e(T),
-                p_ab=p_ab(T))
+                p_ab=p_ab(T), damping=damping(T))
+
+
+def profile_of(spec):
+    """"doppler" (default) or "voigt"."""
+    return getattr(spec, "profile", "doppler")
 
 
 def _f64(a):
@@ -202,27 +268,39 @@ def x_eff(spec):
     return float(spec.x_esc) + 2.0 * float(np.sqrt(((v - mean) ** 2).sum(axis=0)).max())
 
 
+def x_blue(spec):
+    """Voigt only: packets emitted above x_eff + (x_eff - x_esc) are not walked.
+    A walked packet's gas-frame frequency never exceeds its emission frequency
+    plus the velocity margin x_eff - x_esc, so every walked frequency stays
+    below this bound; beyond it the Lorentz tail holds a fraction a / (pi x)
+    of the emission, which meets the line core hundreds of cells away."""
+    xe = x_eff(spec)
+    return 2.0 * xe - float(spec.x_esc)
+
+
 # --- recombination feed (Sec. III.A.1 Eq. rec, Sec. IV.B Eq. dotne-mix) -------
-def feed(spec, A, E, n_packets):
+def feed(spec, A, E, n_packets, wing=0):
     """Per-cell net recombination rate from the absorption tallies.
 
-    A_c is the integer weight absorbed in cell c, E the escaped weight. The
-    absorbed weight is a rate density a_c = A_c * sum(S) / (w0 N); a fraction
-    beta/(beta+Lambda) of it re-ionises. The thermal term uses the Monte-Carlo
-    Peebles factor C_MC = [E + sum(A) Lambda/(beta+Lambda)] / (w0 N). In a
-    homogeneous box this is Eq. (rec); with absorptions distributed like n_1s
-    it is Eq. (dotne-mix).
+    A_c is the integer weight absorbed in cell c, E the escaped weight and
+    wing the part of E that the far damping wing absorbs (Voigt profile; it is
+    spread like n_1s, i.e. fully mixed). The absorbed weight is a rate density
+    a_c = A_c * sum(S) / (w0 N); a fraction beta/(beta+Lambda) of it
+    re-ionises. The thermal term uses the Monte-Carlo Peebles factor
+    C_MC = [E_true + sum(A) Lambda/(beta+Lambda)] / (w0 N), E_true = E - wing.
+    In a homogeneous box this is Eq. (rec); with absorptions distributed like
+    n_1s it is Eq. (dotne-mix).
     """
     sc = box_scalars(spec)
     beta, lam = sc["beta"], LAMBDA_2G
     w = emission_weights(spec)
     S = source_scale(spec) * w
     wtot = float(spec.w0) * float(n_packets)
-    A = np.asarray(A, dtype=np.float64).reshape(-1)
-    a = A * S.sum() / wtot
     n1s = n1s_field(spec)
+    A = np.asarray(A, dtype=np.float64).reshape(-1) + float(wing) * n1s / n1s.sum()
+    a = A * S.sum() / wtot
     boltz = math.exp(-E_ALPHA / (K_B * sc["T"]))
-    c_mc = (float(E) + A.sum() * lam / (beta + lam)) / wtot
+    c_mc = (float(E) - float(wing) + A.sum() * lam / (beta + lam)) / wtot
     ndot = -S + beta / (beta + lam) * a + c_mc * beta * n1s * boltz
     a_fm = A.sum() * n1s / n1s.sum()
     with np.errstate(divide="ignore", invalid="ignore"):

@@ -4,6 +4,7 @@ Everything here is bookkeeping: promote inputs to FP64, call the C functions,
 return numpy arrays. The arithmetic lives in mclya_oracle.c and physics.py.
 """
 import ctypes as C
+import math
 import os
 import numpy as np
 
@@ -16,14 +17,15 @@ _lib = None
 class OrcBox(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("has_vel", C.c_int32),
                 ("delta", C.c_double), ("x_eff", C.c_double), ("w0", C.c_uint64),
-                ("seed", C.c_uint64), ("max_cross", C.c_int64)]
+                ("seed", C.c_uint64), ("max_cross", C.c_int64), ("damping", C.c_double),
+                ("kappa_far", C.c_double), ("x_blue", C.c_double)]
 
 
 REC_DTYPE = np.dtype([("cell0", np.int64), ("fx", np.float64), ("fy", np.float64),
                       ("fz", np.float64), ("kx", np.float64), ("ky", np.float64),
                       ("kz", np.float64), ("x0", np.float64), ("crossings", np.int64),
                       ("escaped", np.int64), ("absorbed", np.int64), ("fate", np.int32),
-                      ("pad", np.int32)])
+                      ("pad", np.int32), ("wing", np.int64)])
 
 
 def lib():
@@ -51,6 +53,10 @@ def lib():
                                        P_(C.c_double), P_(C.c_uint64), P_(C.c_uint64), C.c_int64,
                                        P_(C.c_int64), C.c_void_p]
         L.orc_walk_packets.restype = C.c_int
+        L.orc_profile_cdf.argtypes = [C.c_double, C.c_double]
+        L.orc_profile_cdf.restype = C.c_double
+        L.orc_dawson_integral.argtypes = [C.c_double]
+        L.orc_dawson_integral.restype = C.c_double
         _lib = L
     return _lib
 
@@ -72,6 +78,17 @@ def packet_uniforms(seed, p):
     u = np.zeros(8, dtype=np.float64)
     lib().orc_packet_uniforms(int(seed), int(p), _ptr(u, C.c_double))
     return u
+
+
+def profile_cdf(x, damping=0.0):
+    """The oracle's cumulative line profile at x (Doppler for damping 0, else
+    Voigt to first order in the damping)."""
+    return lib().orc_profile_cdf(float(damping), float(x))
+
+
+def dawson(x):
+    """The oracle's Dawson integral (Rybicki's series)."""
+    return lib().orc_dawson_integral(float(x))
 
 
 def quantize(weights):
@@ -98,7 +115,7 @@ class Prepared:
 
     @classmethod
     def custom(cls, shape, kappa, weights, n_packets, seed, delta, x_eff, vel=None,
-               w0=1 << 32, max_cross=1_000_000):
+               w0=1 << 32, max_cross=1_000_000, damping=0.0, kappa_far=None, x_blue=None):
         """Walk parameters given directly (no physics): for tests of the walk."""
         self = cls.__new__(cls)
         self.spec = None
@@ -112,8 +129,13 @@ class Prepared:
         self.q = quantize(weights)
         self.first = allocate(self.q, self.n_packets)
         nx, ny, nz = (int(t) for t in shape)
+        if kappa_far is None:
+            kappa_far = float(self.kappa.mean()) if damping > 0 else 0.0
+        if x_blue is None:
+            x_blue = 2.0 * self.x_eff - float(x_eff) if damping > 0 else math.inf
         self.box = OrcBox(nx, ny, nz, 0 if self.vel is None else 1, float(delta), self.x_eff,
-                          self.w0, self.seed, int(max_cross))
+                          self.w0, self.seed, int(max_cross), float(damping), float(kappa_far),
+                          float(x_blue))
         return self
 
     def __init__(self, spec, n_packets=None, seed=None, max_cross=1_000_000):
@@ -129,8 +151,12 @@ class Prepared:
         self.q = quantize(P.emission_weights(spec))
         self.first = allocate(self.q, self.n_packets)
         nx, ny, nz = (int(t) for t in spec.n)
+        voigt = P.profile_of(spec) == "voigt"
         self.box = OrcBox(nx, ny, nz, 0 if self.vel is None else 1, self.scal["delta"],
-                          self.x_eff, int(spec.w0), self.seed, int(max_cross))
+                          self.x_eff, int(spec.w0), self.seed, int(max_cross),
+                          self.scal["damping"] if voigt else 0.0,
+                          float(self.kappa.mean()) if voigt else 0.0,
+                          P.x_blue(spec) if voigt else math.inf)
 
     @property
     def emitted_per_cell(self):
@@ -141,11 +167,12 @@ class Prepared:
 
     def transport(self, p_begin=0, p_end=None, records=False, nthreads=None):
         """Walk packets [p_begin, p_end). Returns dict(A, escaped, crossings,
-        capped, capped_weight[, records])."""
+        capped, capped_weight, wing[, records]); wing is the part of the
+        escaped weight that the far damping wing absorbs (Voigt only)."""
         p_end = self.n_packets if p_end is None else int(p_end)
         ncells = self.kappa.size
         A = np.zeros(ncells, dtype=np.int64)
-        out = np.zeros(4, dtype=np.int64)
+        out = np.zeros(5, dtype=np.int64)
         recs = np.zeros(p_end - p_begin, dtype=REC_DTYPE) if records else None
         nt = int(nthreads or os.environ.get("ORACLE_THREADS", 0) or 0)
         lib().orc_transport(C.byref(self.box), _ptr(self.kappa, C.c_double), self._vp(0),
@@ -153,7 +180,7 @@ class Prepared:
                             int(p_end), _ptr(A, C.c_int64), _ptr(out, C.c_int64),
                             None if recs is None else recs.ctypes.data, nt)
         res = dict(A=A, escaped=int(out[0]), crossings=int(out[1]), capped=int(out[2]),
-                   capped_weight=int(out[3]))
+                   capped_weight=int(out[3]), wing=int(out[4]))
         if records:
             res["records"] = recs
         return res

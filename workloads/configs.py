@@ -37,6 +37,7 @@ class BoxSpec:
     x_e_uniform: float = 0.1
     source: Optional[np.ndarray] = None     # float32 [nz, ny, nx] or None
     temp_K: float = 3000.0
+    profile: str = "doppler"               # line profile: "doppler" or "voigt" (damping wing)
     z: float = 1100.0
     zeta: float = 1.0
     x_esc: float = 6.0
