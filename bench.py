@@ -15,6 +15,7 @@ tally update). The CPU baseline is the FP64 oracle on a bounded sample.
 import argparse
 import csv
 import hashlib
+import dataclasses
 import json
 import os
 import sys
@@ -54,6 +55,8 @@ def parse():
                     help="c2: the 128^3 workload (default); batch: 64 uneven boxes in one context; "
                          "surrogate: train the mixing-correction network on Monte-Carlo boxes, evaluate it "
                          "on held-out boxes and time its inference on the 256^3 box")
+    ap.add_argument("--profile", default="doppler", choices=["doppler", "voigt"],
+                    help="line profile of every box (voigt: Eq. (MC) with its damping wing)")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--graph", type=int, choices=[0, 1], default=None,
                     help="replay each transport as a captured HIP graph (default 0)")
@@ -126,11 +129,12 @@ def calibrate_copy(mib):
 
 
 def workload_name(config, specs):
+    voigt = ", Voigt profile" if getattr(specs[0], "profile", "doppler") == "voigt" else ""
     if config == "batch":
         return (f"batch of {len(specs)} boxes, N ~ U{{16..96}}, z ~ U[800, 1400], k^2 GRF rms ~ U[0.2, 2] "
                 f"+ curl-free flow (rms 0.1 v_th), T = T0 (1+z), x_e = 0.1, "
-                f"{specs[0].n_packets:.0e} packets per box")
-    return specs[0].name
+                f"{specs[0].n_packets:.0e} packets per box{voigt}")
+    return specs[0].name + voigt
 
 
 def cpu_baseline(specs, budget_s):
@@ -251,6 +255,8 @@ def main():
         return bench_surrogate(a)
 
     specs = W.batch_specs() if a.config == "batch" else [W.make_box(a.config)]
+    if a.profile != "doppler":
+        specs = [dataclasses.replace(sp, profile=a.profile) for sp in specs]
     dev = torch.device("cuda:0")
     sim = M.Simulation(specs, device=dev)
     # one event pair around each transport's walk, its launches counted: the

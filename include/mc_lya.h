@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MC_LYA_ABI_VERSION 1
+#define MC_LYA_ABI_VERSION 2
 
 typedef struct mc_lya_ctx mc_lya_ctx;
 
@@ -59,6 +59,26 @@ typedef enum mc_lya_status {
 
 /* velocity field element type */
 enum { MC_LYA_VEL_NONE = 0, MC_LYA_VEL_F32 = 1, MC_LYA_VEL_F16 = 2 };
+
+/* Line profile of a box.
+ *   DOPPLER: the thermal profile exp(-x^2)/sqrt(pi).
+ *   VOIGT:   the profile of Eq. (MC), the thermal one convolved with the
+ *            natural (Lorentz) width of the 2p level, half width
+ *            a = A_2p lambda_alpha / (4 pi v_th) in Doppler units (8.6e-4 at
+ *            3000 K). Emission adds a Cauchy deviate of half width a to the
+ *            thermal frequency. The walk uses the cumulative profile to first
+ *            order in a, erfc(-x)/2 - (2a/pi) F(x) with F Dawson's integral
+ *            (error O(a^2)). The damping wing keeps absorbing past -x_eff:
+ *            an escaping packet leaves the expected share
+ *            1 - exp(-<kappa> Phi(x_stop)) of its weight to it (<kappa> the
+ *            box's mean kappa; x_stop = -x_eff, or the emission frequency of
+ *            a packet emitted outside the walked window). That share is
+ *            counted in `escaped` and reported as `wing`; the feed treats it
+ *            as absorbed and spread like n_1s (fully mixed). Packets emitted
+ *            above x_blue = x_eff + (x_eff - x_esc), blue of every frequency
+ *            a walked packet can reach, are not walked (App. A's photons far
+ *            in the blue wing meet the line hundreds of cells away). */
+enum { MC_LYA_PROFILE_DOPPLER = 0, MC_LYA_PROFILE_VOIGT = 1 };
 
 /* One periodic box: its grid, its physics and its (caller-owned) fields.
  * Physics parameters are those of the paper's runs (Sec. II.C): cosmology
@@ -80,7 +100,7 @@ typedef struct mc_lya_box_desc {
                                      thermal velocity sqrt(2kT/m_H), or NULL */
     const float *x_e;             /* dev [ncells] free-electron fraction in [0, 1.2], or NULL */
     float x_e_uniform;            /* used when x_e == NULL */
-    int32_t reserved;             /* must be 0 */
+    int32_t profile;              /* MC_LYA_PROFILE_DOPPLER (0) or MC_LYA_PROFILE_VOIGT */
     const float *source;          /* dev [ncells] emission rate density (cm^-3 s^-1, finite,
                                      >= 0), or NULL for alpha_e(T) n_e^2 */
 } mc_lya_box_desc;
@@ -99,19 +119,24 @@ typedef struct mc_lya_box_stats {
     double delta;                 /* red drift per cell width, Doppler units (App. A step 4) */
     double x_eff;                 /* escape threshold used (x_esc + velocity margin) */
     double tau_ab_mean;           /* <kappa_c>: mean optical depth to true absorption */
+    double damping;               /* Voigt a (0 for the Doppler profile) */
+    int64_t wing;                 /* part of `escaped` that the far damping wing absorbs
+                                     (Voigt; 0 for the Doppler profile) */
 } mc_lya_box_stats;
 
 /* Per-box scalars from mc_lya_feed. */
 typedef struct mc_lya_feed_stats {
-    double c_mc;                  /* Monte-Carlo Peebles factor [E + sum(A) L/(b+L)] / (w0 N) */
+    double c_mc;                  /* Monte-Carlo Peebles factor [E + sum(A) L/(b+L)] / (w0 N),
+                                     E = escaped - wing and sum(A) including wing */
     double c_mix;                 /* Eq. (Cfactor) with R_alpha -> R_alpha^mix (Sec. IV.A.2) */
-    double f_escape;              /* escaped / emitted */
+    double f_escape;              /* (escaped - wing) / emitted: the weight that truly escapes */
     double f_absorbed;            /* absorbed / emitted */
     double x_e_global;            /* X_e = <n_e> / <n_H> (Sec. II.A) */
     double ndot_e_mean;           /* volume mean of the per-cell rate, cm^-3 s^-1 */
+    double f_wing;                /* wing / emitted (Voigt: absorbed by the far damping wing) */
 } mc_lya_feed_stats;
 
-/* One packet's history from mc_lya_trace (56 bytes). */
+/* One packet's history from mc_lya_trace (64 bytes). */
 typedef struct mc_lya_packet_trace {
     uint32_t cell0;               /* global emission cell */
     float fx, fy, fz;             /* emission position inside the cell, [0,1) */
@@ -121,6 +146,7 @@ typedef struct mc_lya_packet_trace {
     int64_t absorbed;             /* weight deposited into the grid */
     uint32_t crossings;
     int32_t fate;                 /* 0 absorbed, 1 escaped, 2 capped */
+    int64_t wing;                 /* part of `escaped` the far damping wing absorbs (Voigt) */
 } mc_lya_packet_trace;
 
 /* Tunables for mc_lya_set_option (all results are independent of them, bit

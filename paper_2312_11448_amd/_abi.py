@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libmclya.so")
 MC_LYA_OK, MC_LYA_EINVAL, MC_LYA_ENOMEM, MC_LYA_EDEVICE = 0, 1, 2, 3
 MC_LYA_EOVERFLOW, MC_LYA_ESTATE, MC_LYA_ECAP, MC_LYA_ECONSERVE = 4, 5, 6, 7
 MC_LYA_VEL_NONE, MC_LYA_VEL_F32, MC_LYA_VEL_F16 = 0, 1, 2
+MC_LYA_PROFILE_DOPPLER, MC_LYA_PROFILE_VOIGT = 0, 1
 MC_LYA_OPT_KERNEL, MC_LYA_OPT_BLOCK, MC_LYA_OPT_WAVES_PER_CU, MC_LYA_OPT_CHUNK = 1, 2, 3, 4
 MC_LYA_OPT_REFILL, MC_LYA_OPT_MAX_CROSSINGS, MC_LYA_OPT_TIMING, MC_LYA_OPT_GRAPH = 5, 6, 7, 8
 MC_LYA_OPT_QUEUES = 9
@@ -34,7 +35,7 @@ class mc_lya_box_desc(C.Structure):
                 ("omega_b_h2", C.c_double), ("omega_c_h2", C.c_double), ("y_p", C.c_double),
                 ("t_cmb0", C.c_double), ("n_eff", C.c_double), ("w0", C.c_uint64),
                 ("overdensity", C.c_void_p), ("velocity", C.c_void_p), ("x_e", C.c_void_p),
-                ("x_e_uniform", C.c_float), ("reserved", C.c_int32), ("source", C.c_void_p)]
+                ("x_e_uniform", C.c_float), ("profile", C.c_int32), ("source", C.c_void_p)]
 
 
 class mc_lya_box_stats(C.Structure):
@@ -42,20 +43,20 @@ class mc_lya_box_stats(C.Structure):
                 ("capped_weight", C.c_int64), ("capped_packets", C.c_int64),
                 ("crossings", C.c_int64), ("packets", C.c_int64), ("conserved", C.c_int32),
                 ("reserved", C.c_int32), ("delta", C.c_double), ("x_eff", C.c_double),
-                ("tau_ab_mean", C.c_double)]
+                ("tau_ab_mean", C.c_double), ("damping", C.c_double), ("wing", C.c_int64)]
 
 
 class mc_lya_feed_stats(C.Structure):
     _fields_ = [("c_mc", C.c_double), ("c_mix", C.c_double), ("f_escape", C.c_double),
                 ("f_absorbed", C.c_double), ("x_e_global", C.c_double),
-                ("ndot_e_mean", C.c_double)]
+                ("ndot_e_mean", C.c_double), ("f_wing", C.c_double)]
 
 
 class mc_lya_packet_trace(C.Structure):
     _fields_ = [("cell0", C.c_uint32), ("fx", C.c_float), ("fy", C.c_float), ("fz", C.c_float),
                 ("kx", C.c_float), ("ky", C.c_float), ("kz", C.c_float), ("x0", C.c_float),
                 ("escaped", C.c_int64), ("absorbed", C.c_int64), ("crossings", C.c_uint32),
-                ("fate", C.c_int32)]
+                ("fate", C.c_int32), ("wing", C.c_int64)]
 
 
 class mc_lya_tune_result(C.Structure):

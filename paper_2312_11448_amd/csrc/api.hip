@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -14,8 +15,9 @@
 using namespace mclya;
 
 static_assert(sizeof(mc_lya_box_desc) == 152, "mc_lya_box_desc layout");
-static_assert(sizeof(mc_lya_box_stats) == 88, "mc_lya_box_stats layout");
-static_assert(sizeof(mc_lya_packet_trace) == 56, "mc_lya_packet_trace layout");
+static_assert(sizeof(mc_lya_box_stats) == 104, "mc_lya_box_stats layout");
+static_assert(sizeof(mc_lya_feed_stats) == 56, "mc_lya_feed_stats layout");
+static_assert(sizeof(mc_lya_packet_trace) == 64, "mc_lya_packet_trace layout");
 static_assert(sizeof(mc_lya_tune_result) == 88, "mc_lya_tune_result layout");
 
 namespace {
@@ -42,7 +44,7 @@ constexpr double kL2g = 8.22458;              // s^-1
 constexpr double kPi = 3.14159265358979323846;
 
 struct Box {
-    double H, vth, delta, nH, kappa_unit, alpha, beta, pab, boltz;
+    double H, vth, delta, nH, kappa_unit, alpha, beta, pab, boltz, damping;
 };
 
 inline Box scalars(const mc_lya_box_desc &d)
@@ -69,6 +71,9 @@ inline Box scalars(const mc_lya_box_desc &d)
     // kappa_c = p_ab 3 lambda^3 A n_1s / (8 pi zeta H), n_1s = nH (1 - x_e) Delta
     o.kappa_unit = o.pab * 3.0 * kLya * kLya * kLya * kA2p / (8.0 * kPi * o.H) * o.nH;
     o.boltz = std::exp(-0.75 * kEion / (kBoltz * T));
+    // Voigt parameter of Eq. (MC): half the natural width A over the Doppler
+    // width nu_alpha v_th / c, in angular units, a = A lambda / (4 pi v_th)
+    o.damping = kA2p * kLya / (4.0 * kPi * o.vth);
     return o;
 }
 }  // namespace phys
@@ -98,6 +103,7 @@ struct mc_lya_ctx {
     uint64_t total_packets = 0;
     int max_blk = 1;
     bool vel = false;
+    bool voigt = false;                      // some box has the Voigt profile
     int num_cu = 256;
 
     PackBox *d_pack = nullptr;
@@ -228,7 +234,8 @@ std::string check_desc(const mc_lya_box_desc &d, int b)
     if ((d.vel_dtype == MC_LYA_VEL_NONE) != (d.velocity == nullptr))
         return bad("velocity must be given exactly when vel_dtype is not NONE");
     if (!d.x_e && !(d.x_e_uniform >= 0.0f && d.x_e_uniform <= 1.2f)) return bad("x_e_uniform outside [0, 1.2]");
-    if (d.reserved != 0) return bad("reserved must be 0");
+    if (d.profile != MC_LYA_PROFILE_DOPPLER && d.profile != MC_LYA_PROFILE_VOIGT)
+        return bad("profile must be MC_LYA_PROFILE_DOPPLER or MC_LYA_PROFILE_VOIGT");
     return std::string();
 }
 
@@ -293,8 +300,20 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
         WalkBox &w = c->walk[b];
         w.x_eff = (float)(c->desc[b].x_esc + 2.0 * udev);
         w.delta = (float)c->ph[b].delta;
-        w.valid = 1;
-        c->cpp[b] = crossings_per_packet(c->red[b].kappa_sum / (double)w.ncells, w.delta, w.x_eff, (double)w.w0);
+        if (c->desc[b].profile == MC_LYA_PROFILE_VOIGT) {
+            // Voigt: the weight 2a/pi of Dawson's integral, the mean kappa seen
+            // by the far damping wing, and the top of the walked window (a
+            // walked packet never rises more than the velocity margin above
+            // its emission frequency)
+            w.damp = (float)(2.0 * c->ph[b].damping / phys::kPi);
+            w.kfar = (float)(c->red[b].kappa_sum / (double)w.cells());
+            w.xblue = (float)(c->desc[b].x_esc + 4.0 * udev);
+        } else {
+            w.damp = 0.0f;
+            w.kfar = 0.0f;
+            w.xblue = std::numeric_limits<float>::infinity();
+        }
+        c->cpp[b] = crossings_per_packet(c->red[b].kappa_sum / (double)w.cells(), w.delta, w.x_eff, (double)w.w0);
     }
     c->state = 0;
     return MC_LYA_OK;
@@ -524,7 +543,7 @@ mc_lya_status enqueue_generations(mc_lya_ctx *c, TileParams &p, int g0, int g1, 
             mc_lya_status st = timed_begin(c, &e1);
             if (st != MC_LYA_OK) return st;
         }
-        HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->stream));
+        HIP_TRY(c, launch_tile_generation(p, gen == 0, c->vel, c->voigt, c->stream));
         if (timed) {
             mc_lya_status st = timed_end(c, e1);
             if (st != MC_LYA_OK) return st;
@@ -561,7 +580,7 @@ mc_lya_status enqueue_tail(mc_lya_ctx *c, uint64_t n, bool timed)
         mc_lya_status st = timed_begin(c, &e1);
         if (st != MC_LYA_OK) return st;
     }
-    HIP_TRY(c, launch_tail_walk(t, capacity, c->vel, c->stream));
+    HIP_TRY(c, launch_tail_walk(t, capacity, c->vel, c->voigt, c->stream));
     if (timed) return timed_end(c, e1);
     return MC_LYA_OK;
 }
@@ -674,6 +693,7 @@ mc_lya_status plan_walk(mc_lya_ctx *c, uint64_t first, uint64_t count, WalkPlan 
     p.boxes = c->d_walk;
     p.n_boxes = c->n_boxes;
     p.vel = c->vel ? 1 : 0;
+    p.voigt = c->voigt ? 1 : 0;
     p.rec = c->d_rec;
     p.A = c->d_A;
     p.tot = c->d_tot;
@@ -873,7 +893,7 @@ mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed)
     } else {
         const int waves_per_block = c->block / 64;
         // never more workgroups than can be resident at once
-        const int resident = persistent_blocks_per_cu(c->vel, c->block);
+        const int resident = persistent_blocks_per_cu(c->vel, c->voigt, c->block);
         const int per_cu = std::max(1, std::min(c->waves_per_cu / waves_per_block, resident));
         int grid = c->num_cu * per_cu;
         const uint64_t need = (count + 63) / 64;     // no more waves than packets
@@ -955,9 +975,9 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         w.ny = d.ny;
         w.nz = d.nz;
         w.cell_off = (uint32_t)off;
-        w.ncells = (uint32_t)n;
-        w.w0 = d.w0;
+        w.w0 = (uint32_t)d.w0;
         if (d.vel_dtype != MC_LYA_VEL_NONE) c->vel = true;
+        if (d.profile == MC_LYA_PROFILE_VOIGT) c->voigt = true;
         off += n;
     }
     c->max_blk = max_blk;
@@ -1102,7 +1122,9 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, m
             s.conserved = ok ? 1 : 0;
             s.delta = c->walk[b].delta;
             s.x_eff = c->walk[b].x_eff;
-            s.tau_ab_mean = c->red[b].kappa_sum / (double)c->walk[b].ncells;
+            s.tau_ab_mean = c->red[b].kappa_sum / (double)c->walk[b].cells();
+            s.damping = c->desc[b].profile == MC_LYA_PROFILE_VOIGT ? c->ph[b].damping : 0.0;
+            s.wing = (int64_t)tot[b].wing;
         }
     }
     if (broken) return fail(c, MC_LYA_ECONSERVE, "sum(absorbed) + escaped + capped != w0 * packets");
@@ -1169,21 +1191,25 @@ mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya
     for (int b = 0; b < nb; ++b) {
         const phys::Box &ph = c->ph[b];
         const mc_lya_box_desc &d = c->desc[b];
-        const double ncell = (double)c->walk[b].ncells;
+        const double ncell = (double)c->walk[b].cells();
         const double wtot = (double)c->walked[b] * (double)d.w0;
         const double s_scale = d.source ? 1.0 : ph.alpha * ph.nH * ph.nH;
         const double sum_s = s_scale * sums[4 * b + 0];
         const double sum_n1s = ph.nH * sums[4 * b + 1];
-        const double sum_A = (double)abs[b];
+        // the far damping wing's share of the escaped weight (Voigt profile)
+        // is absorbed far away: it joins the absorption, spread like n_1s
+        const double wing = (double)tot[b].wing;
+        const double sum_A = (double)abs[b] + wing;
         const double reion = ph.beta / (ph.beta + phys::kL2g);
-        const double c_mc = wtot > 0.0 ? ((double)tot[b].escaped + sum_A * phys::kL2g / (ph.beta + phys::kL2g)) / wtot
-                                       : 0.0;
+        const double e_true = (double)tot[b].escaped - wing;
+        const double c_mc = wtot > 0.0 ? (e_true + sum_A * phys::kL2g / (ph.beta + phys::kL2g)) / wtot : 0.0;
         fb[b].S_scale = s_scale;
         fb[b].n_h = ph.nH;
         fb[b].a_norm = wtot > 0.0 ? sum_s / wtot : 0.0;
         fb[b].reion = reion;
         fb[b].thermal = c_mc * ph.beta * ph.boltz;
         fb[b].fm_norm = sum_n1s > 0.0 ? sum_A / sum_n1s : 0.0;
+        fb[b].wing_n1s = sum_n1s > 0.0 ? wing / sum_n1s : 0.0;
         if (stats) {
             mc_lya_feed_stats &s = stats[b];
             const double n1s_mean = sum_n1s / ncell;
@@ -1191,7 +1217,8 @@ mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya
                                  (phys::kLya * phys::kLya * phys::kLya * n1s_mean);
             s.c_mc = c_mc;
             s.c_mix = (phys::kL2g + r_mix) / (ph.beta + phys::kL2g + r_mix);
-            s.f_escape = wtot > 0.0 ? (double)tot[b].escaped / wtot : 0.0;
+            s.f_escape = wtot > 0.0 ? e_true / wtot : 0.0;
+            s.f_wing = wtot > 0.0 ? wing / wtot : 0.0;
             s.f_absorbed = wtot > 0.0 ? sum_A / wtot : 0.0;
             s.x_e_global = sums[4 * b + 3] > 0.0 ? sums[4 * b + 2] / sums[4 * b + 3] : 0.0;
             // volume mean of the rate: -<S> + reion <a> + thermal <n1s>
@@ -1223,6 +1250,7 @@ mc_lya_status mc_lya_trace(mc_lya_ctx *c, uint64_t first, uint64_t count, mc_lya
     p.boxes = c->d_walk;
     p.n_boxes = c->n_boxes;
     p.vel = c->vel ? 1 : 0;
+    p.voigt = c->voigt ? 1 : 0;
     p.rec = c->d_rec;
     p.cell_of_packet = c->d_cop;
     p.first = first;

@@ -14,15 +14,18 @@ namespace mclya {
 // ---------------------------------------------------------------------------
 struct alignas(64) WalkBox {
     int32_t nx, ny, nz;
-    int32_t valid;        // 0 when the box's fields failed validation
+    float damp;           // Voigt profile: 2a/pi, the weight of Dawson's integral in the
+                          // cumulative profile (0: Doppler profile)
     uint32_t cell_off;    // first global cell of the box
-    uint32_t ncells;
+    float xblue;          // packets emitted above it are not walked (+inf: all are)
     uint64_t pkt_off;     // first global packet id of the box
     uint64_t npkt;        // packets emitted in the box
     uint64_t seed;        // Philox key
-    uint64_t w0;          // weight of one packet
+    uint32_t w0;          // weight of one packet
+    float kfar;           // Voigt profile: mean kappa, for the far damping wing (0: none)
     float delta;          // red drift per cell width (Doppler units)
     float x_eff;          // escape once x <= -x_eff
+    __host__ __device__ uint32_t cells() const { return (uint32_t)nx * (uint32_t)ny * (uint32_t)nz; }
 };
 static_assert(sizeof(WalkBox) == 64, "WalkBox layout");
 
@@ -58,6 +61,8 @@ struct BoxTot {
     unsigned long long crossings;
     unsigned long long capped_packets;
     unsigned long long capped_weight;
+    unsigned long long wing;          // part of the escaped weight the far damping wing absorbs
+    unsigned long long pad[3];
 };
 
 enum : uint32_t {
@@ -130,6 +135,8 @@ struct WalkParams {
     int32_t n_boxes;
     int32_t vel;             // record layout: 0 = kappa only, 1 = float4 (kappa, U)
     const void *rec;
+    int32_t voigt;           // some box has the Voigt profile (its own constants are in the box)
+    int32_t pad0;
     const uint32_t *cell_of_packet;
     unsigned long long *A;   // per-cell absorbed weight
     BoxTot *tot;
@@ -249,15 +256,15 @@ struct TailParams {
     uint32_t max_cross;
 };
 
-hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s);
+hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, bool voigt, hipStream_t s);
 // The tail walk of a batch (no-op when no generation stopped); `capacity`
 // bounds the packets it can take (tail_min).
-hipError_t launch_tail_walk(const TailParams &p, uint64_t capacity, bool vel, hipStream_t s);
+hipError_t launch_tail_walk(const TailParams &p, uint64_t capacity, bool vel, bool voigt, hipStream_t s);
 hipError_t launch_zero_counters(unsigned long long *c, int n, hipStream_t s);
 
 hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s);
 hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipStream_t s);
-int persistent_blocks_per_cu(bool vel, int block);   // resident workgroups per CU
+int persistent_blocks_per_cu(bool vel, bool voigt, int block);   // resident workgroups per CU
 hipError_t launch_trace(const WalkParams &p, mc_lya_packet_trace *out, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, uint64_t n,
                          hipStream_t s);
@@ -272,7 +279,8 @@ struct FeedBox {
     double a_norm;           // sum(S) / (w0 N)
     double reion;            // beta / (beta + Lambda)
     double thermal;          // C_MC beta exp(-E_alpha/kT)
-    double fm_norm;          // sum(A) / sum(n_1s)
+    double fm_norm;          // (sum(A) + wing) / sum(n_1s)
+    double wing_n1s;         // wing / sum(n_1s): the far damping wing's absorption per unit n_1s
 };
 hipError_t launch_feed_sums(const PackBox *pb_dev, int n_boxes, int max_blk, const double *wgt,
                             double *partials, hipStream_t s);

@@ -45,10 +45,10 @@ __global__ __launch_bounds__(B) void tally_kernel(const WalkBox *__restrict__ wb
     __shared__ unsigned long long lds[kWaves];
     const int b = blockIdx.y;
     const WalkBox wb = wbs[b];
-    if (blockIdx.x * (uint32_t)B >= wb.ncells) return;
+    if (blockIdx.x * (uint32_t)B >= wb.cells()) return;
     const uint32_t i = blockIdx.x * B + threadIdx.x;
     unsigned long long a = 0;
-    if (i < wb.ncells) {
+    if (i < wb.cells()) {
         const size_t g = (size_t)wb.cell_off + i;
         a = A[g];
         if (absorbed_out) absorbed_out[g] = (int64_t)a;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(B) void tally_reduce_kernel(const WalkBox *__restri
 {
     __shared__ unsigned long long lds[kWaves];
     const int b = blockIdx.x;
-    const uint32_t nblk = (wbs[b].ncells + B - 1) / B;
+    const uint32_t nblk = (wbs[b].cells() + B - 1) / B;
     const unsigned long long *p = reinterpret_cast<const unsigned long long *>(partials);
     unsigned long long a = 0;
     for (uint32_t k = threadIdx.x; k < nblk; k += B) a += p[((size_t)b * max_blk + k) * kPartStride + 6];
@@ -145,7 +145,8 @@ __global__ __launch_bounds__(B) void feed_kernel(const PackBox *__restrict__ pbs
     const double od = (double)pb.od[i];
     const double xe = (double)(pb.xe ? pb.xe[i] : pb.xe_uniform);
     const double n1s = fb.n_h * (1.0 - xe) * od;
-    const double a = (double)A[g];
+    // the far damping wing's share is spread like n_1s (fully mixed)
+    const double a = (double)A[g] + fb.wing_n1s * n1s;
     if (ndot) ndot[g] = -fb.S_scale * wgt[g] + fb.reion * (a * fb.a_norm) + fb.thermal * n1s;
     if (mix) {
         const double fm = fb.fm_norm * n1s;

@@ -141,7 +141,7 @@ __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkB
 // One generation. GEN0: the tile's input is the packets emitted in its cells
 // (within the requested packet range); otherwise it is the face lists of the
 // previous generation that point at this tile.
-template <bool VEL, bool GEN0>
+template <bool VEL, bool GEN0, bool VOIGT>
 __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
 {
     __shared__ unsigned long long tally[TC];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     __shared__ uint32_t s_tsum[kWaves];
     __shared__ uint32_t s_next, s_exit, s_total, s_base;
     __shared__ uint32_t s_fcnt[8], s_fcur[8];
-    __shared__ unsigned long long s_red[kWaves][4];
+    __shared__ unsigned long long s_red[kWaves][5];
 
     const int T = blockIdx.x;
     const int tid = threadIdx.x;
@@ -168,6 +168,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     }
     const TileInfo ti = P.tiles[T];
     const WalkBox B = P.boxes[ti.box];
+    const Line ln = line_of(B);       // tile-uniform
     const int ncell = ti.sx * ti.sy * ti.sz;
     const uint32_t lane = __lane_id();
     const uint64_t r_lo = P.first, r_hi = P.first + P.count;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
     };
     uint32_t cur = 0, end = 0;
-    uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0;
+    uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0, a_wing = 0;
     const uint32_t chunk = (uint32_t)P.chunk;
     const uint32_t refill = (uint32_t)P.refill;
     for (;;) {
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
                                         (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
                     const uint64_t pf = P.pfirst[gc];
                     const uint64_t gp = (pf > r_lo ? pf : r_lo) + (j - pre[lo]);
-                    init_packet<VEL>(L, B, gp - B.pkt_off, gc, P.rec);
+                    init_packet<VEL, VOIGT>(L, B, gp - B.pkt_off, gc, P.rec);
                 } else {
                     int k = 0;
                     while (k + 1 <= ti.nsrc && pre[k + 1] <= j) ++k;
@@ -364,7 +365,8 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         fresh = false;
         if (alive) {
             uint64_t dep = 0;
-            const int fate = walk_step<VEL>(L, P.rec, sink, P.max_cross, dep);
+            uint32_t wing = 0;
+            const int fate = walk_step<VEL, VOIGT>(L, P.rec, sink, P.max_cross, dep, ln, wing);
             if (fate == kExit) {
                 pending = true;
                 alive = false;
@@ -373,6 +375,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
                 a_esc += fate == kEscaped ? L.w : 0;
                 a_capn += fate == kCapped ? 1 : 0;
                 a_capw += fate == kCapped ? L.w : 0;
+                if (VOIGT) a_wing += wing;
                 alive = false;
             }
         }
@@ -383,11 +386,13 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     a_cross = wave_sum(a_cross);
     a_capn = wave_sum(a_capn);
     a_capw = wave_sum(a_capw);
+    if (VOIGT) a_wing = wave_sum(a_wing);
     if (lane == 0) {
         s_red[tid >> 6][0] = a_esc;
         s_red[tid >> 6][1] = a_cross;
         s_red[tid >> 6][2] = a_capn;
         s_red[tid >> 6][3] = a_capw;
+        s_red[tid >> 6][4] = a_wing;
     }
     __threadfence_block();
     __syncthreads();
@@ -400,14 +405,15 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             P.A[gc] += v;    // this workgroup alone owns these cells in this generation
         }
     }
-    if (tid < 4) {
+    if (tid < (VOIGT ? 5 : 4)) {
         unsigned long long t = 0;
         for (int w = 0; w < kWaves; ++w) t += s_red[w][tid];
         if (t) {
             unsigned long long *dst = tid == 0 ? &P.tot[ti.box].escaped
                                    : tid == 1 ? &P.tot[ti.box].crossings
                                    : tid == 2 ? &P.tot[ti.box].capped_packets
-                                              : &P.tot[ti.box].capped_weight;
+                                   : tid == 3 ? &P.tot[ti.box].capped_weight
+                                              : &P.tot[ti.box].wing;
             atomicAdd(dst, t);
         }
     }
@@ -473,12 +479,12 @@ __global__ __launch_bounds__(1024) void tail_prefix_kernel(TailParams P)
     if (threadIdx.x == 0) P.counters[kTailCountSlot] = s_carry;
 }
 
-template <bool VEL>
+template <bool VEL, bool VOIGT>
 __global__ __launch_bounds__(256) void tail_walk_kernel(TailParams P)
 {
     const unsigned long long g = P.counters[kTailGenSlot];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t esc = 0, cross = 0, capn = 0, capw = 0;
+    uint64_t esc = 0, cross = 0, capn = 0, capw = 0, gw = 0;
     int box = -1;
     if (g != 0 && i < P.counters[kTailCountSlot]) {
         const int q = (int)((g - 1) & 1);
@@ -496,15 +502,18 @@ __global__ __launch_bounds__(256) void tail_walk_kernel(TailParams P)
         const Rec r = load_rec<VEL>(P.rec, L.c);
         if (P.face[q][k] == kDeferred) L.kap = r.kap;   // deferred inside its cell
         else finish_entry<VEL>(L, r);                   // entering through a face
+        const Line ln = line_of(B);
         uint64_t dep = 0;
+        uint32_t wing = 0;
         int fate;
         do {
-            fate = walk_step<VEL>(L, P.rec, GlobalSink{P.A}, P.max_cross, dep);
+            fate = walk_step<VEL, VOIGT>(L, P.rec, GlobalSink{P.A}, P.max_cross, dep, ln, wing);
         } while (fate == kAlive);
         cross = L.ncross;
         esc = fate == kEscaped ? L.w : 0;
         capn = fate == kCapped ? 1 : 0;
         capw = fate == kCapped ? L.w : 0;
+        gw = wing;
     }
     // per-box totals: one atomic per box present in the wave
     uint64_t pending = __ballot(box >= 0);
@@ -514,7 +523,9 @@ __global__ __launch_bounds__(256) void tail_walk_kernel(TailParams P)
         const bool mine = box == b;
         const uint64_t se = wave_sum(mine ? esc : 0), sc = wave_sum(mine ? cross : 0),
                        sn = wave_sum(mine ? capn : 0), sw = wave_sum(mine ? capw : 0);
+        const uint64_t sg = VOIGT ? wave_sum(mine ? gw : 0) : 0;
         if ((int)__lane_id() == leader) {
+            if (sg) atomicAdd(&P.tot[b].wing, (unsigned long long)sg);
             if (se) atomicAdd(&P.tot[b].escaped, (unsigned long long)se);
             if (sc) atomicAdd(&P.tot[b].crossings, (unsigned long long)sc);
             if (sn) atomicAdd(&P.tot[b].capped_packets, (unsigned long long)sn);
@@ -532,25 +543,40 @@ __global__ void zero_counters_kernel(unsigned long long *c, int n)
 
 }  // namespace
 
-hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, hipStream_t s)
+hipError_t launch_tile_generation(const TileParams &p, bool gen0, bool vel, bool voigt, hipStream_t s)
 {
     const dim3 grid((unsigned)p.ntiles), block(BLK);
-    if (gen0) {
-        if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, true>), grid, block, 0, s, p);
-        else hipLaunchKernelGGL((tile_walk_kernel<false, true>), grid, block, 0, s, p);
+    if (voigt) {
+        if (gen0) {
+            if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, true, true>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((tile_walk_kernel<false, true, true>), grid, block, 0, s, p);
+        } else {
+            if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, false, true>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((tile_walk_kernel<false, false, true>), grid, block, 0, s, p);
+        }
     } else {
-        if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, false>), grid, block, 0, s, p);
-        else hipLaunchKernelGGL((tile_walk_kernel<false, false>), grid, block, 0, s, p);
+        if (gen0) {
+            if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, true, false>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((tile_walk_kernel<false, true, false>), grid, block, 0, s, p);
+        } else {
+            if (vel) hipLaunchKernelGGL((tile_walk_kernel<true, false, false>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((tile_walk_kernel<false, false, false>), grid, block, 0, s, p);
+        }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_tail_walk(const TailParams &p, uint64_t capacity, bool vel, hipStream_t s)
+hipError_t launch_tail_walk(const TailParams &p, uint64_t capacity, bool vel, bool voigt, hipStream_t s)
 {
     hipLaunchKernelGGL(tail_prefix_kernel, dim3(1), dim3(1024), 0, s, p);
     const dim3 grid((unsigned)std::max<uint64_t>(1, (capacity + 255) / 256));
-    if (vel) hipLaunchKernelGGL(tail_walk_kernel<true>, grid, dim3(256), 0, s, p);
-    else hipLaunchKernelGGL(tail_walk_kernel<false>, grid, dim3(256), 0, s, p);
+    if (voigt) {
+        if (vel) hipLaunchKernelGGL((tail_walk_kernel<true, true>), grid, dim3(256), 0, s, p);
+        else hipLaunchKernelGGL((tail_walk_kernel<false, true>), grid, dim3(256), 0, s, p);
+    } else {
+        if (vel) hipLaunchKernelGGL((tail_walk_kernel<true, false>), grid, dim3(256), 0, s, p);
+        else hipLaunchKernelGGL((tail_walk_kernel<false, false>), grid, dim3(256), 0, s, p);
+    }
     return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 // Per-lane per-box totals, flushed with one atomic per box per wave.
 struct Acc {
     int32_t box;
-    uint64_t esc, cross, capn, capw;
+    uint64_t esc, cross, capn, capw, wing;
 };
 
 // Convergent: every lane of the wave must call it. Lanes with `give` add
@@ -66,23 +66,26 @@ __device__ __forceinline__ void flush(Acc &a, bool give, BoxTot *__restrict__ to
         const uint64_t c = wave_sum_u64(mine ? a.cross : 0);
         const uint64_t n = wave_sum_u64(mine ? a.capn : 0);
         const uint64_t w = wave_sum_u64(mine ? a.capw : 0);
+        const uint64_t g = wave_sum_u64(mine ? a.wing : 0);
         if ((int)lane_id() == leader) {
             if (e) atomicAdd(&tot[b].escaped, (unsigned long long)e);
             if (c) atomicAdd(&tot[b].crossings, (unsigned long long)c);
             if (n) atomicAdd(&tot[b].capped_packets, (unsigned long long)n);
             if (w) atomicAdd(&tot[b].capped_weight, (unsigned long long)w);
+            if (g) atomicAdd(&tot[b].wing, (unsigned long long)g);
         }
         pending &= ~__ballot(mine);
     }
-    if (give) a.esc = a.cross = a.capn = a.capw = 0;
+    if (give) a.esc = a.cross = a.capn = a.capw = a.wing = 0;
 }
 
-__device__ __forceinline__ void account(Acc &a, const Lane &L, int fate)
+__device__ __forceinline__ void account(Acc &a, const Lane &L, int fate, uint32_t wing)
 {
     a.cross += L.ncross;
     a.esc += fate == kEscaped ? L.w : 0;
     a.capn += fate == kCapped ? 1 : 0;
     a.capw += fate == kCapped ? L.w : 0;
+    a.wing += wing;
 }
 
 // Box of a global packet id (boxes sorted by packet offset).
@@ -109,7 +112,7 @@ __device__ __forceinline__ uint64_t packet_id(const WalkParams &P, uint64_t i)
 }
 
 // ---- persistent driver ---------------------------------------------------
-template <bool VEL>
+template <bool VEL, bool VOIGT>
 __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
 {
     extern __shared__ WalkBox sbox[];
@@ -119,7 +122,8 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
     const uint32_t lane = lane_id();
     const uint32_t max_cross = (uint32_t)P.max_cross;
     Lane L;
-    Acc acc{-1, 0, 0, 0, 0};
+    Line ln{0.0f, 0.0f, 0.0f};
+    Acc acc{-1, 0, 0, 0, 0, 0};
     bool alive = false;
     bool more = true;                 // wave-uniform: queue not drained
     uint64_t cur = 0, end = 0;        // wave-uniform: current block of packet ids
@@ -166,7 +170,8 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
                 if (fresh) {
                     acc.box = nb;
                     const WalkBox &B = sbox[nb];
-                    init_packet<VEL>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec);
+                    init_packet<VEL, VOIGT>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec);
+                    if (VOIGT) ln = line_of(B);
                     alive = true;
                 }
                 cur += take;
@@ -179,9 +184,10 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
         }
         if (alive) {
             uint64_t dep = 0;
-            const int fate = walk_step<VEL>(L, P.rec, GlobalSink{P.A}, max_cross, dep);
+            uint32_t wing = 0;
+            const int fate = walk_step<VEL, VOIGT>(L, P.rec, GlobalSink{P.A}, max_cross, dep, ln, wing);
             if (fate != kAlive) {
-                account(acc, L, fate);
+                account(acc, L, fate, wing);
                 alive = false;
             }
         }
@@ -190,33 +196,35 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
 }
 
 // ---- one thread per packet -------------------------------------------------
-template <bool VEL>
+template <bool VEL, bool VOIGT>
 __global__ __launch_bounds__(256) void walk_simple_kernel(WalkParams P)
 {
     extern __shared__ WalkBox sbox[];
     for (int i = threadIdx.x; i < P.n_boxes; i += blockDim.x) sbox[i] = P.boxes[i];
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    Acc acc{-1, 0, 0, 0, 0};
+    Acc acc{-1, 0, 0, 0, 0, 0};
     if (i < P.count) {
         const uint64_t gp = packet_id(P, i);
         const int nb = P.n_boxes == 1 ? 0 : box_of(sbox, P.n_boxes, gp);
         const WalkBox &B = sbox[nb];
         Lane L;
-        init_packet<VEL>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec);
+        init_packet<VEL, VOIGT>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec);
+        const Line ln = line_of(B);
         acc.box = nb;
         uint64_t dep = 0;
+        uint32_t wing = 0;
         int fate;
         do {
-            fate = walk_step<VEL>(L, P.rec, GlobalSink{P.A}, (uint32_t)P.max_cross, dep);
+            fate = walk_step<VEL, VOIGT>(L, P.rec, GlobalSink{P.A}, (uint32_t)P.max_cross, dep, ln, wing);
         } while (fate == kAlive);
-        account(acc, L, fate);
+        account(acc, L, fate, wing);
     }
     flush(acc, true, P.tot);
 }
 
 // ---- packet histories (no tallies) -------------------------------------------
-template <bool VEL>
+template <bool VEL, bool VOIGT>
 __global__ __launch_bounds__(256) void trace_kernel(WalkParams P, mc_lya_packet_trace *out)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -226,7 +234,8 @@ __global__ __launch_bounds__(256) void trace_kernel(WalkParams P, mc_lya_packet_
     const WalkBox B = P.boxes[nb];
     Lane L;
     float f0[3];
-    init_packet<VEL>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec, f0);
+    init_packet<VEL, VOIGT>(L, B, gp - B.pkt_off, P.cell_of_packet[gp], P.rec, f0);
+    const Line ln = line_of(B);
     mc_lya_packet_trace t;
     t.cell0 = L.c;
     t.fx = f0[0];
@@ -237,11 +246,13 @@ __global__ __launch_bounds__(256) void trace_kernel(WalkParams P, mc_lya_packet_
     t.kz = L.kz;
     t.x0 = L.x;
     uint64_t dep = 0;
+    uint32_t wing = 0;
     int fate;
     do {
-        fate = walk_step<VEL>(L, P.rec, NullSink{}, (uint32_t)P.max_cross, dep);
+        fate = walk_step<VEL, VOIGT>(L, P.rec, NullSink{}, (uint32_t)P.max_cross, dep, ln, wing);
     } while (fate == kAlive);
     t.escaped = fate == kAbsorbed ? 0 : (int64_t)L.w;
+    t.wing = (int64_t)wing;
     t.absorbed = (int64_t)dep;
     t.crossings = L.ncross;
     t.fate = fate == kEscaped ? 1 : (fate == kCapped ? 2 : 0);
@@ -265,12 +276,17 @@ __global__ void reset_queue_kernel(unsigned long long *q, int n)
 
 }  // namespace
 
-int persistent_blocks_per_cu(bool vel, int block)
+int persistent_blocks_per_cu(bool vel, bool voigt, int block)
 {
     int n = 0;
     const size_t lds = sizeof(WalkBox);
-    hipError_t e = vel ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<true>, block, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<false>, block, lds);
+    hipError_t e;
+    if (voigt)
+        e = vel ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<true, true>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<false, true>, block, lds);
+    else
+        e = vel ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<true, false>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_persistent_kernel<false, false>, block, lds);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
@@ -278,10 +294,14 @@ hipError_t launch_walk_persistent(const WalkParams &p, int block, int grid, hipS
 {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, p.queue, (int)p.nqueues);
     const size_t lds = sizeof(WalkBox) * (size_t)p.n_boxes;
-    if (p.vel)
-        hipLaunchKernelGGL(walk_persistent_kernel<true>, dim3((unsigned)grid), dim3((unsigned)block), lds, s, p);
-    else
-        hipLaunchKernelGGL(walk_persistent_kernel<false>, dim3((unsigned)grid), dim3((unsigned)block), lds, s, p);
+    const dim3 g((unsigned)grid), b((unsigned)block);
+    if (p.voigt) {
+        if (p.vel) hipLaunchKernelGGL((walk_persistent_kernel<true, true>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((walk_persistent_kernel<false, true>), g, b, lds, s, p);
+    } else {
+        if (p.vel) hipLaunchKernelGGL((walk_persistent_kernel<true, false>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((walk_persistent_kernel<false, false>), g, b, lds, s, p);
+    }
     return hipGetLastError();
 }
 
@@ -289,20 +309,27 @@ hipError_t launch_walk_simple(const WalkParams &p, int block, hipStream_t s)
 {
     const uint64_t grid = (p.count + (uint64_t)block - 1) / (uint64_t)block;
     const size_t lds = sizeof(WalkBox) * (size_t)p.n_boxes;
-    if (p.vel)
-        hipLaunchKernelGGL(walk_simple_kernel<true>, dim3((unsigned)grid), dim3((unsigned)block), lds, s, p);
-    else
-        hipLaunchKernelGGL(walk_simple_kernel<false>, dim3((unsigned)grid), dim3((unsigned)block), lds, s, p);
+    const dim3 g((unsigned)grid), b((unsigned)block);
+    if (p.voigt) {
+        if (p.vel) hipLaunchKernelGGL((walk_simple_kernel<true, true>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((walk_simple_kernel<false, true>), g, b, lds, s, p);
+    } else {
+        if (p.vel) hipLaunchKernelGGL((walk_simple_kernel<true, false>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((walk_simple_kernel<false, false>), g, b, lds, s, p);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_trace(const WalkParams &p, mc_lya_packet_trace *out, hipStream_t s)
 {
-    const uint64_t grid = (p.count + 255) / 256;
-    if (p.vel)
-        hipLaunchKernelGGL(trace_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, p, out);
-    else
-        hipLaunchKernelGGL(trace_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, p, out);
+    const dim3 g((unsigned)((p.count + 255) / 256)), b(256);
+    if (p.voigt) {
+        if (p.vel) hipLaunchKernelGGL((trace_kernel<true, true>), g, b, 0, s, p, out);
+        else hipLaunchKernelGGL((trace_kernel<false, true>), g, b, 0, s, p, out);
+    } else {
+        if (p.vel) hipLaunchKernelGGL((trace_kernel<true, false>), g, b, 0, s, p, out);
+        else hipLaunchKernelGGL((trace_kernel<false, false>), g, b, 0, s, p, out);
+    }
     return hipGetLastError();
 }
 

@@ -5,9 +5,22 @@
 // of the profile, the depth of Eq. (<fnu>)) and escape by redshifting (end of
 // App. A). Drivers differ only in where deposits go and which cells they own,
 // so every driver produces the same integers.
+//
+// Two line profiles: the thermal (Doppler) one, and the Voigt profile of
+// Eq. (MC) (the thermal profile convolved with the natural width of the 2p
+// level, half width a in Doppler units). For the Voigt profile the emission
+// adds a Cauchy deviate a tan(pi (u - 1/2)) to the thermal one, the cumulative
+// profile is taken to first order in a, Phi_V = erfc(-x)/2 - (2a/pi) F(x)
+// with F Dawson's integral (the neglected terms are O(a^2), below 2e-7 at
+// a = 8.6e-4), and an escaping packet leaves the expected share
+// 1 - exp(-kbar Phi_V(x_stop)) of its weight to the far damping wing (kbar the
+// box's mean kappa: beyond -x_eff the wing is crossed over hundreds of cells).
+// Packets emitted above x_blue, blue of every walked frequency, are not
+// walked: they escape at once and the wing takes its share at x0.
 #pragma once
 
 #include "common.hpp"
+#include "dawson.hpp"
 
 namespace mclya {
 
@@ -57,11 +70,25 @@ __device__ __forceinline__ Rec load_rec(const void *__restrict__ rec, uint32_t c
     return r;
 }
 
+// Profile constants of a box for the Voigt walk (uniform over a tile).
+struct Line {
+    float damp;     // 2a/pi
+    float kfar;     // mean kappa of the box
+    float xblue;    // packets above it are not walked
+};
+
+__device__ __forceinline__ Line line_of(const WalkBox &B)
+{
+    return Line{B.damp, B.kfar, B.xblue};
+}
+
 // Emission of packet p (box-local id) in global cell gcell: position uniform
 // in the cell, isotropic direction, frequency from the Doppler profile
-// exp(-x^2)/sqrt(pi) by the Box-Muller transform. Optionally returns the
-// initial state (position inside the cell and direction) for traces.
-template <bool VEL>
+// exp(-x^2)/sqrt(pi) by the Box-Muller transform, plus for the Voigt profile
+// the Cauchy deviate of the natural line from the eighth uniform. Optionally
+// returns the initial state (position inside the cell and direction) for
+// traces.
+template <bool VEL, bool VOIGT = false>
 __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t p, uint32_t gcell,
                                             const void *__restrict__ rec, float *state = nullptr)
 {
@@ -99,6 +126,11 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
     L.ky = (float)ky;
     L.kz = (float)kz;
     L.x = sqrtf(-logf(u01(b[1]))) * cospif(2.0f * u01(b[2]));
+    if (VOIGT) {
+        // a tan(pi v), v = u - 1/2 in (-1/2, 1/2), a = (pi/2) (2a/pi)
+        const float v = u01(b[3]) - 0.5f;
+        L.x += 1.5707963267948966f * B.damp * (sinpif(v) / cospif(v));
+    }
     L.w = (uint32_t)B.w0;
     L.ncross = 0;
     const Rec r = load_rec<VEL>(rec, gcell);
@@ -134,6 +166,27 @@ __device__ __forceinline__ float swept_profile(float x, float dx)
     const float lo = x - dx;
     const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(x)) : 0.5f * (erfcf(-x) - erfcf(-lo));
     return fmaxf(d, 0.0f);
+}
+
+// The same swept mass for the Voigt profile to first order in a:
+// Phi_V(x) - Phi_V(x - dx) = (thermal part) - (2a/pi) int_{x-dx}^{x} F'(y) dy,
+// F' = 1 - 2yF. Short segments take the integral by the midpoint rule (one
+// Dawson evaluation). Its relative error is dx^2 / 24 times the ratio of the
+// third derivative of F to F', about 6 / y^2 in the wing: below 3e-4 for
+// dx <= 0.1 at |y| >= 3 and 3e-5 for the paper's cells (dx <= 0.033); in the
+// core the thermal part dominates. Longer segments use the difference
+// F(x - dx) - F(x). Never negative.
+__device__ __forceinline__ float swept_profile_voigt(float x, float dx, float damp)
+{
+    const float corr = dx <= 0.1f ? -dx * dawson_deriv_f32(x - 0.5f * dx)
+                                  : dawson_f32(x - dx) - dawson_f32(x);
+    return fmaxf(fmaf(damp, corr, swept_profile(x, dx)), 0.0f);
+}
+
+// Cumulative Voigt profile to first order in a (the far-wing share).
+__device__ __forceinline__ float cumulative_voigt(float x, float damp)
+{
+    return fmaxf(0.5f * erfcf(-x) - damp * dawson_f32(x), 0.0f);
 }
 
 // 1 - exp(-tau) for tau >= 0 without cancellation (series below 0.1).
@@ -207,11 +260,17 @@ enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
 // (harmless for a packet that has finished, whose weight and crossing count
 // are left as they were). Early returns would make the compiler copy the
 // whole lane state on every path.
-template <bool VEL, class Sink>
+//
+// VOIGT: the Voigt profile of the box's Line; `wing` receives the far-wing
+// share of an escaping packet's weight (0 otherwise). The packet's own weight
+// L.w is left whole: the share is part of the escaped weight.
+template <bool VEL, bool VOIGT, class Sink>
 __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, const Sink &sink,
-                                         uint32_t max_cross, uint64_t &deposited)
+                                         uint32_t max_cross, uint64_t &deposited, const Line &ln,
+                                         uint32_t &wing)
 {
-    const bool gone = L.x <= -L.xeff;                     // redshifted out of the line
+    // redshifted out of the line (or, Voigt, emitted blue of the walked window)
+    const bool gone = VOIGT ? (L.x <= -L.xeff) | (L.x > ln.xblue) : L.x <= -L.xeff;
     const bool capped = !gone && L.ncross >= max_cross;
     const bool walk = !gone && !capped;
 
@@ -242,7 +301,8 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     const float s = (float)(tn - L.t);
     const float xo = fmaf(-L.delta, s, L.x);
     const bool esc = xo <= -L.xeff;
-    const float dphi = swept_profile(L.x, esc ? L.x + L.xeff : L.delta * s);
+    const float dx = esc ? L.x + L.xeff : L.delta * s;
+    const float dphi = VOIGT ? swept_profile_voigt(L.x, dx, ln.damp) : swept_profile(L.x, dx);
     const float pabs = one_minus_exp(L.kap * dphi);
     const uint32_t d = walk ? min((uint32_t)rintf((float)L.w * pabs), L.w) : 0u;
     if (d) sink.deposit(L, d);
@@ -254,6 +314,13 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
                    : esc ? kEscaped
                    : L.w == 0 ? kAbsorbed
                    : stay ? kAlive : kExit;
+    wing = 0u;
+    if (VOIGT && fate == kEscaped) {
+        // the far damping wing beyond the stopping frequency
+        const float xs = gone ? L.x : -L.xeff;
+        const float pw = one_minus_exp(ln.kfar * cumulative_voigt(xs, ln.damp));
+        wing = min((uint32_t)rintf((float)L.w * pw), L.w);
+    }
 
     // cross the face
     L.t = tn;

@@ -14,7 +14,8 @@ from . import _abi as A
 TRACE_DTYPE = np.dtype([("cell0", np.uint32), ("fx", np.float32), ("fy", np.float32),
                         ("fz", np.float32), ("kx", np.float32), ("ky", np.float32),
                         ("kz", np.float32), ("x0", np.float32), ("escaped", np.int64),
-                        ("absorbed", np.int64), ("crossings", np.uint32), ("fate", np.int32)])
+                        ("absorbed", np.int64), ("crossings", np.uint32), ("fate", np.int32),
+                        ("wing", np.int64)])
 assert TRACE_DTYPE.itemsize == C.sizeof(A.mc_lya_packet_trace)
 
 
@@ -48,7 +49,11 @@ def desc_from_spec(spec, tensors, device="cuda"):
         n_eff=c.n_eff, w0=int(spec.w0), overdensity=od.data_ptr(),
         velocity=None if vel is None else vel.data_ptr(),
         x_e=None if xe is None else xe.data_ptr(), x_e_uniform=float(spec.x_e_uniform),
-        reserved=0, source=None if src is None else src.data_ptr())
+        profile=_PROFILES[getattr(spec, "profile", "doppler")],
+        source=None if src is None else src.data_ptr())
+
+
+_PROFILES = {"doppler": A.MC_LYA_PROFILE_DOPPLER, "voigt": A.MC_LYA_PROFILE_VOIGT}
 
 
 class Simulation:

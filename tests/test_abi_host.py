@@ -35,8 +35,9 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_sizes_match_header_layout():
     M = _lib()
-    assert C.sizeof(M.mc_lya_packet_trace) == 56
-    assert C.sizeof(M.mc_lya_box_stats) == 88
+    assert C.sizeof(M.mc_lya_packet_trace) == 64
+    assert C.sizeof(M.mc_lya_box_stats) == 104
+    assert C.sizeof(M.mc_lya_feed_stats) == 56
     assert C.sizeof(M.mc_lya_tune_result) == 88
     # 4 int32, 11 doubles, w0, 3 pointers, float + int32, 1 pointer
     assert C.sizeof(M.mc_lya_box_desc) == 16 + 88 + 8 + 24 + 8 + 8
@@ -53,7 +54,7 @@ def _desc(M, **kw):
     d = dict(nx=4, ny=4, nz=4, vel_dtype=0, cell_comoving_cm=2.9e20, z=1100.0, zeta=1.0,
              x_esc=6.0, temp_K=3000.0, h=0.67, omega_b_h2=0.0224, omega_c_h2=0.12, y_p=0.24,
              t_cmb0=2.7255, n_eff=3.046, w0=1 << 31, overdensity=0x1000, velocity=None,
-             x_e=None, x_e_uniform=0.1, reserved=0, source=None)
+             x_e=None, x_e_uniform=0.1, profile=0, source=None)
     d.update(kw)
     return M.mc_lya_box_desc(**d)
 
@@ -64,7 +65,7 @@ def _desc(M, **kw):
                                      (dict(vel_dtype=1), "velocity"),
                                      (dict(x_e_uniform=1.5), "x_e_uniform"),
                                      (dict(temp_K=float("nan")), "temp_K"),
-                                     (dict(reserved=3), "reserved")])
+                                     (dict(profile=3), "profile")])
 def test_init_rejects_bad_descriptors_before_any_device_call(bad, msg):
     M = _lib()
     with pytest.raises(M.MCLyaError) as e:
