@@ -187,19 +187,31 @@ typedef struct {
  * F(x) = lim_{h->0} pi^{-1/2} sum over odd n of exp(-(x - n h)^2) / n. With
  * h = 0.2 the discretisation error is of order exp(-(pi / 2h)^2) < 1e-26.
  * The sum is taken about the even multiple x0 = 2 k h nearest to x (nodes
- * x0 + m h, m odd, weights 1 / (2k + m)), so the offsets x - x0 - m h are
- * small and exact; nodes with |offset| > 8 (terms below exp(-64)) are left out. */
+ * x0 + m h, m odd, weights 1 / (2k + m)), so the offsets xp - m h, xp = x - x0,
+ * are small and exact; nodes with |offset| > 8 (terms below exp(-64)) are left
+ * out. Each term exp(-(xp - m h)^2) = exp(-xp^2) exp(-(m h)^2) E^m with
+ * E = exp(2 xp h), so one evaluation takes two exponentials. */
+#define ORC_RYB_M 41
+static double orc_ryb_c[ORC_RYB_M + 1];     /* exp(-(m h)^2), odd m */
+
+__attribute__((constructor)) static void orc_ryb_init(void)
+{
+    for (int m = 1; m <= ORC_RYB_M; m += 2) orc_ryb_c[m] = exp(-(0.2 * m) * (0.2 * m));
+}
+
 static double orc_dawson(double x)
 {
     const double h = 0.2;
     const double k = nearbyint(x / (2.0 * h));
     const double xp = x - 2.0 * h * k;
-    double sum = 0.0;
-    for (int m = -41; m <= 41; m += 2) {
-        const double d = xp - (double)m * h;
-        sum += exp(-d * d) / (2.0 * k + (double)m);
+    const double E = exp(2.0 * xp * h), Ei = 1.0 / E, E2 = E * E, Ei2 = Ei * Ei;
+    double up = E, dn = Ei, sum = 0.0;
+    for (int m = 1; m <= ORC_RYB_M; m += 2) {
+        sum += orc_ryb_c[m] * (up / (2.0 * k + (double)m) + dn / (2.0 * k - (double)m));
+        up *= E2;
+        dn *= Ei2;
     }
-    return sum / sqrt(M_PI);
+    return exp(-xp * xp) * sum / sqrt(M_PI);
 }
 
 /* Cumulative line profile: the Doppler one, erfc(-x)/2 = int_{-inf}^{x}
@@ -403,4 +415,317 @@ int64_t orc_trace_packet(const orc_box *b, const double *kappa, const double *ux
     orc_trace tr = {cells, deposits, x_in, x_out, length, cap, 0};
     orc_walk_one(b, kappa, ux, uy, uz, p, orc_find_cell(first, ncells, p), A, rec, &tr);
     return tr.n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Resonant scattering (App. A, steps 1-8)                                    */
+/*                                                                           */
+/* A photon is followed scattering by scattering. Its free path is drawn as   */
+/* an optical depth -ln(u) (App. A steps 2-6 with the step length taken to    */
+/* zero: the depth along a path is kappa_sc [Phi(x_in) - Phi(x_out)], with    */
+/* kappa_sc = kappa / p_ab the full line opacity per unit of swept profile).  */
+/* At a scattering it is destroyed with probability p_ab (step 7); else the   */
+/* scattering atom's velocity is drawn from Eq. (MC) (step 8): the parallel   */
+/* component from exp(-u^2) / ((x - u)^2 + a^2) and the perpendicular one     */
+/* projected on the scattering plane from exp(-u^2) (variance 1/2); the new   */
+/* direction is isotropic, mu = k_in . k_out, and the new gas-frame frequency */
+/* is Eq. (inout) without its bulk term, x - u_par (1 - mu) + u_perp sqrt(1 - */
+/* mu^2). Bulk-velocity terms of Eq. (inout) apply at cell faces, as in the   */
+/* streaming walk. A photon redshifted below -x_inert is lost to the line     */
+/* (end of App. A); the expected share of it that the far damping wing still  */
+/* destroys, 1 - exp(-kbar Phi(-x_inert)), is reported as "wing". A photon    */
+/* bluer than +x_inert is treated the same way at its own frequency.          */
+/*                                                                           */
+/* Random numbers: event k of photon p uses the Philox block with counter     */
+/* (p_lo, p_hi, k, 1): u0 the free path, u1 the destruction test, u2 and u3   */
+/* the new direction (cos theta = 2 u2 - 1, azimuth 2 pi u3). Block           */
+/* (p_lo, p_hi, k, 2): u0, u1 the perpendicular velocity (Box-Muller).        */
+/* Trial j of the parallel-velocity draw uses block (p_lo, p_hi, k, 3 + j):   */
+/* u0 the envelope part, u1 (and u2) the proposal, u3 the acceptance.         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double p_ab;          /* the box's p_ab: kappa / p_ab is the scattering depth per unit Phi */
+    double p_destroy;     /* destruction probability per scattering (p_ab; other values for tests) */
+    double x_inert;       /* lost to the line below -x_inert (and far above +x_inert) */
+    int64_t max_events;   /* scatterings before a photon is stopped (capped) */
+    int32_t fixed_x0;     /* 1: every photon is injected at x0 */
+    int32_t pad;
+    double x0;
+    double x_return;      /* > 0: a photon scattered back inside |x| < x_return stops (fate 3) */
+} orc_scatter_params;
+
+typedef struct {
+    int64_t cell0, cell_end;
+    double x0, x_end;
+    int64_t scatterings, crossings;
+    int64_t escaped, absorbed, wing;
+    int32_t fate;        /* 0 destroyed, 1 lost to the line, 2 capped, 3 returned (test hook) */
+    int32_t pad;
+} orc_scatter_rec;
+
+static void orc_block(uint64_t seed, uint64_t p, uint32_t k, uint32_t stream, double u[4])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)p, (uint32_t)(p >> 32), k, stream};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    for (int i = 0; i < 4; ++i) u[i] = orc_uniform(r[i]);
+}
+
+/* First-order Voigt (or Doppler) line density, the derivative of orc_Phi. */
+static double orc_density(const orc_box *b, double y)
+{
+    const double g = exp(-y * y) / sqrt(M_PI);
+    return b->damping > 0.0 ? g - 2.0 * b->damping / M_PI * (1.0 - 2.0 * y * orc_dawson(y)) : g;
+}
+
+/* Swept profile Phi(x) - Phi(x - dx), dx >= 0: the midpoint rule below
+ * dx = 1e-4 (relative error under 1e-9; the difference of two rounded
+ * values would keep only a few digits there), the difference above. */
+static double orc_swept(const orc_box *b, double x, double dx)
+{
+    if (dx < 1e-4) return dx * orc_density(b, x - 0.5 * dx);
+    const double d = orc_Phi(b, x) - orc_Phi(b, x - dx);
+    return d > 0.0 ? d : 0.0;
+}
+
+/* Length s in (0, s_max] with kap * swept(x, delta s) = tau, by Newton's
+ * method kept inside a shrinking bracket (the swept mass grows with s). */
+static double orc_flight_length(const orc_box *b, double kap, double x, double tau, double s_max)
+{
+    const double d = b->delta;
+    double lo = 0.0, hi = s_max;
+    double s = tau / (kap * d * orc_density(b, x));
+    if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        const double g = kap * orc_swept(b, x, d * s) - tau;
+        if (g > 0.0) hi = s; else lo = s;
+        double sn = s - g / (kap * d * orc_density(b, x - d * s));
+        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+        if (fabs(sn - s) <= 1e-12 * s || hi - lo <= 1e-14 * hi) return sn;
+        s = sn;
+    }
+    return s;
+}
+
+/* Parallel velocity of the scattering atom for a photon at x >= 0: a draw
+ * from exp(-u^2) / ((x - u)^2 + a^2) by rejection from a two-part envelope
+ * split at u0 (after Zheng & Miralda-Escude 2002). Below u0 the envelope is
+ * the Cauchy factor alone (|x| < 5) or the Gaussian over (x - u0)^2
+ * (|x| >= 5, where the draw is mostly thermal); above u0 it is the Cauchy
+ * factor times exp(-u0^2). The split point only changes the number of
+ * trials: u0 = x - 0.02 - 0.1 max(0, x - 1)^2 (at least 0) for x < 5,
+ * sqrt(6.3 + 3.2 ln x) beyond. For a = 0 the atom is resonant, u = x. */
+static double orc_atom_upar(double x, double a, uint64_t seed, uint64_t p, uint32_t k)
+{
+    if (a == 0.0) return x;
+    const int neg = x < 0.0;
+    const double xa = neg ? -x : x;
+    const int wing = xa >= 5.0;
+    double u0;
+    if (wing) {
+        u0 = sqrt(6.3 + 3.2 * log(xa));
+    } else {
+        const double q = xa > 1.0 ? xa - 1.0 : 0.0;
+        u0 = xa - 0.02 - 0.1 * q * q;
+        if (u0 < 0.0) u0 = 0.0;
+    }
+    const double th0 = atan((u0 - xa) / a);
+    const double m2 = exp(-u0 * u0) * (0.5 * M_PI - th0);             /* in units of 1/a */
+    const double m1 = wing ? 0.5 * sqrt(M_PI) * erfc(-u0) * a / ((xa - u0) * (xa - u0)) : th0 + 0.5 * M_PI;
+    const double p1 = m1 / (m1 + m2);
+    for (uint32_t j = 0;; ++j) {
+        double r[4];
+        orc_block(seed, p, k, 3u + j, r);
+        double u, acc;
+        if (r[0] < p1) {
+            if (wing) {
+                u = sqrt(-log(r[1])) * cos(2.0 * M_PI * r[2]);
+                if (u > u0) continue;
+                acc = (xa - u0) * (xa - u0) / ((xa - u) * (xa - u) + a * a);
+            } else {
+                const double th = -0.5 * M_PI + (th0 + 0.5 * M_PI) * r[1];
+                u = xa + a * tan(th);
+                acc = exp(-u * u);
+            }
+        } else {
+            const double th = th0 + (0.5 * M_PI - th0) * r[1];
+            u = xa + a * tan(th);
+            acc = exp(u0 * u0 - u * u);
+        }
+        if (r[3] <= acc) return neg ? -u : u;
+    }
+}
+
+/* One re-emission: atom velocity, isotropic new direction, new frequency. */
+static void orc_redistribute(double a, uint64_t seed, uint64_t p, uint32_t k, const double e[4], double kdir[3],
+                             double *x)
+{
+    double t[4];
+    orc_block(seed, p, k, 2u, t);
+    const double uperp = sqrt(-log(t[0])) * cos(2.0 * M_PI * t[1]);
+    const double upar = orc_atom_upar(*x, a, seed, p, k);
+    const double ct = 2.0 * e[2] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    const double ph = 2.0 * M_PI * e[3];
+    const double kn[3] = {st * cos(ph), st * sin(ph), ct};
+    double mu = kdir[0] * kn[0] + kdir[1] * kn[1] + kdir[2] * kn[2];
+    if (mu > 1.0) mu = 1.0;
+    if (mu < -1.0) mu = -1.0;
+    *x = *x - upar * (1.0 - mu) + uperp * sqrt(1.0 - mu * mu);
+    for (int i = 0; i < 3; ++i) kdir[i] = kn[i];
+}
+
+static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, const double *kappa, const double *ux,
+                            const double *uy, const double *uz, uint64_t p, int64_t cell0, int64_t *A,
+                            orc_scatter_rec *rec)
+{
+    const int64_t nx = b->nx, ny = b->ny, nz = b->nz;
+    double u[8];
+    orc_packet_uniforms(b->seed, p, u);
+    double f[3] = {u[0], u[1], u[2]};
+    double mu0 = 2.0 * u[3] - 1.0, ph0 = 2.0 * M_PI * u[4];
+    double st0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
+    double k[3] = {st0 * cos(ph0), st0 * sin(ph0), mu0};
+    double x = sqrt(-log(u[5])) * cos(2.0 * M_PI * u[6]);
+    if (b->damping > 0.0) x += b->damping * tan(M_PI * (u[7] - 0.5));
+    if (sp->fixed_x0) x = sp->x0;
+    int64_t ci[3] = {cell0 % nx, (cell0 / nx) % ny, cell0 / (nx * ny)};
+    const int64_t n[3] = {nx, ny, nz};
+    const int64_t w = (int64_t)b->w0;
+    int64_t nscat = 0, ncross = 0;
+    int fate = 2;
+    double x_stop = 0.0;
+    int64_t c = cell0;
+    rec->cell0 = cell0;
+    rec->x0 = x;
+    for (;;) {
+        if (x <= -sp->x_inert || x > sp->x_inert) { fate = 1; x_stop = x; break; }
+        if (nscat >= sp->max_events) { fate = 2; break; }
+        double e[4];
+        orc_block(b->seed, p, (uint32_t)nscat, 1u, e);
+        double tau = -log(e[0]);
+        int lost = 0;
+        for (;;) {                                            /* free flight */
+            c = ci[0] + nx * (ci[1] + ny * ci[2]);
+            const double kap = kappa[c] / sp->p_ab;
+            double t[3];
+            for (int a = 0; a < 3; ++a) {
+                if (k[a] > 0.0) t[a] = (1.0 - f[a]) / k[a];
+                else if (k[a] < 0.0) t[a] = f[a] / (-k[a]);
+                else t[a] = INFINITY;
+            }
+            int axis = 0;
+            if (t[1] < t[axis]) axis = 1;
+            if (t[2] < t[axis]) axis = 2;
+            const double sf = t[axis];
+            const double xf = x - b->delta * sf;
+            const int inert = xf <= -sp->x_inert;
+            const double slim = inert ? (x + sp->x_inert) / b->delta : sf;
+            const double dtau = kap * orc_swept(b, x, inert ? x + sp->x_inert : b->delta * sf);
+            if (dtau < tau) {
+                if (inert) { lost = 1; break; }
+                tau -= dtau;
+                for (int a = 0; a < 3; ++a) {
+                    if (a == axis) continue;
+                    const double g = f[a] + k[a] * sf;
+                    f[a] = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+                }
+                const int64_t old = c;
+                if (k[axis] > 0.0) { f[axis] = 0.0; ci[axis] = orc_wrap(ci[axis] + 1, n[axis]); }
+                else { f[axis] = 1.0; ci[axis] = orc_wrap(ci[axis] - 1, n[axis]); }
+                x = xf;
+                ++ncross;
+                if (b->has_vel) {
+                    const int64_t cn = ci[0] + nx * (ci[1] + ny * ci[2]);
+                    x -= k[0] * (ux[cn] - ux[old]) + k[1] * (uy[cn] - uy[old]) + k[2] * (uz[cn] - uz[old]);
+                }
+                continue;
+            }
+            const double s = orc_flight_length(b, kap, x, tau, slim);
+            for (int a = 0; a < 3; ++a) {
+                const double g = f[a] + k[a] * s;
+                f[a] = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+            }
+            x -= b->delta * s;
+            break;
+        }
+        if (lost) { fate = 1; x_stop = -sp->x_inert; break; }
+        ++nscat;                                              /* a scattering in cell c */
+        if (e[1] < sp->p_destroy) { fate = 0; break; }
+        orc_redistribute(b->damping, b->seed, p, (uint32_t)(nscat - 1), e, k, &x);
+        if (sp->x_return > 0.0 && fabs(x) < sp->x_return) { fate = 3; break; }
+    }
+    int64_t wing = 0;
+    if (fate == 1 && b->kappa_far > 0.0) {
+        const double pw = -expm1(-b->kappa_far * fmax(orc_Phi(b, x_stop), 0.0));
+        wing = (int64_t)rint((double)w * pw);
+        if (wing > w) wing = w;
+    }
+    if (fate == 0) A[c] += w;
+    rec->cell_end = c;
+    rec->x_end = fate == 1 ? x_stop : x;
+    rec->scatterings = nscat;
+    rec->crossings = ncross;
+    rec->escaped = (fate == 1 || fate == 2) ? w : 0;
+    rec->absorbed = fate == 0 ? w : 0;
+    rec->wing = wing;
+    rec->fate = fate;
+    rec->pad = 0;
+}
+
+/* Photons [p_begin, p_end) with resonant scattering. A (ncells) and out[6] =
+ * {escaped weight, crossings, capped photons, capped weight, wing,
+ * scatterings} are accumulated into. recs, when not NULL, gets one record per
+ * photon. */
+int orc_scatter(const orc_box *b, const orc_scatter_params *sp, const double *kappa, const double *ux,
+                const double *uy, const double *uz, const uint64_t *first, uint64_t p_begin, uint64_t p_end,
+                int64_t *A, int64_t out[6], orc_scatter_rec *recs, int nthreads)
+{
+    const int64_t ncells = (int64_t)b->nx * b->ny * b->nz;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+    int64_t *priv = (int64_t *)calloc((size_t)nthreads * (size_t)ncells, sizeof(int64_t));
+    if (!priv) return -1;
+    int64_t esc = 0, cross = 0, capn = 0, capw = 0, wing = 0, nscat = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : esc, cross, capn, capw, wing, nscat)
+    {
+        int64_t *mine = priv + (size_t)omp_get_thread_num() * (size_t)ncells;
+#pragma omp for schedule(dynamic, 16)
+        for (uint64_t p = p_begin; p < p_end; ++p) {
+            orc_scatter_rec r;
+            orc_scatter_one(b, sp, kappa, ux, uy, uz, p, orc_find_cell(first, ncells, p), mine, &r);
+            cross += r.crossings;
+            nscat += r.scatterings;
+            if (r.fate == 1) { esc += r.escaped; wing += r.wing; }
+            if (r.fate == 2) { capn += 1; capw += r.escaped; }
+            if (recs) recs[p - p_begin] = r;
+        }
+    }
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t c = 0; c < ncells; ++c) {
+        int64_t sum = 0;
+        for (int t = 0; t < nthreads; ++t) sum += priv[(size_t)t * (size_t)ncells + c];
+        A[c] += sum;
+    }
+    free(priv);
+    out[0] += esc; out[1] += cross; out[2] += capn; out[3] += capw; out[4] += wing; out[5] += nscat;
+    return 0;
+}
+
+/* Test hooks: n draws of the atom's parallel velocity at frequency x (photon
+ * ids 0..n-1, event 0), and n successive re-emissions of one photon starting
+ * at x0 with direction (0, 0, 1), with no flight between them. */
+void orc_atom_upar_draws(double x, double a, uint64_t seed, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_atom_upar(x, a, seed, (uint64_t)i, 0u);
+}
+
+void orc_redistribution_chain(double x0, double a, uint64_t seed, uint64_t p, int64_t n, double *xs)
+{
+    double k[3] = {0.0, 0.0, 1.0}, x = x0;
+    for (int64_t i = 0; i < n; ++i) {
+        double e[4];
+        orc_block(seed, p, (uint32_t)i, 1u, e);
+        orc_redistribute(a, seed, p, (uint32_t)i, e, k, &x);
+        xs[i] = x;
+    }
 }

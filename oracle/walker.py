@@ -21,6 +21,19 @@ class OrcBox(C.Structure):
                 ("kappa_far", C.c_double), ("x_blue", C.c_double)]
 
 
+class OrcScatterParams(C.Structure):
+    _fields_ = [("p_ab", C.c_double), ("p_destroy", C.c_double), ("x_inert", C.c_double),
+                ("max_events", C.c_int64),
+                ("fixed_x0", C.c_int32), ("pad", C.c_int32), ("x0", C.c_double),
+                ("x_return", C.c_double)]
+
+
+SCATTER_REC_DTYPE = np.dtype([("cell0", np.int64), ("cell_end", np.int64), ("x0", np.float64),
+                              ("x_end", np.float64), ("scatterings", np.int64),
+                              ("crossings", np.int64), ("escaped", np.int64), ("absorbed", np.int64),
+                              ("wing", np.int64), ("fate", np.int32), ("pad", np.int32)])
+
+
 REC_DTYPE = np.dtype([("cell0", np.int64), ("fx", np.float64), ("fy", np.float64),
                       ("fz", np.float64), ("kx", np.float64), ("ky", np.float64),
                       ("kz", np.float64), ("x0", np.float64), ("crossings", np.int64),
@@ -53,6 +66,13 @@ def lib():
                                        P_(C.c_double), P_(C.c_uint64), P_(C.c_uint64), C.c_int64,
                                        P_(C.c_int64), C.c_void_p]
         L.orc_walk_packets.restype = C.c_int
+        L.orc_scatter.argtypes = [P_(OrcBox), P_(OrcScatterParams), P_(C.c_double), P_(C.c_double),
+                                  P_(C.c_double), P_(C.c_double), P_(C.c_uint64), C.c_uint64,
+                                  C.c_uint64, P_(C.c_int64), P_(C.c_int64), C.c_void_p, C.c_int]
+        L.orc_scatter.restype = C.c_int
+        L.orc_atom_upar_draws.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int64, P_(C.c_double)]
+        L.orc_redistribution_chain.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_uint64, C.c_int64,
+                                               P_(C.c_double)]
         L.orc_profile_cdf.argtypes = [C.c_double, C.c_double]
         L.orc_profile_cdf.restype = C.c_double
         L.orc_dawson_integral.argtypes = [C.c_double]
@@ -89,6 +109,20 @@ def profile_cdf(x, damping=0.0):
 def dawson(x):
     """The oracle's Dawson integral (Rybicki's series)."""
     return lib().orc_dawson_integral(float(x))
+
+
+def atom_upar_draws(x, a, n, seed=1):
+    """n draws of the scattering atom's parallel velocity for a photon at x."""
+    out = np.zeros(int(n))
+    lib().orc_atom_upar_draws(float(x), float(a), int(seed), int(n), _ptr(out, C.c_double))
+    return out
+
+
+def redistribution_chain(x0, a, n, seed=1, p=0):
+    """Frequencies after each of n successive re-emissions of one photon."""
+    out = np.zeros(int(n))
+    lib().orc_redistribution_chain(float(x0), float(a), int(seed), int(p), int(n), _ptr(out, C.c_double))
+    return out
 
 
 def quantize(weights):
@@ -181,6 +215,34 @@ class Prepared:
                             None if recs is None else recs.ctypes.data, nt)
         res = dict(A=A, escaped=int(out[0]), crossings=int(out[1]), capped=int(out[2]),
                    capped_weight=int(out[3]), wing=int(out[4]))
+        if records:
+            res["records"] = recs
+        return res
+
+    def scatter(self, p_ab, x_inert=300.0, max_events=1 << 31, x0=None, p_begin=0, p_end=None,
+                records=False, nthreads=None, x_return=0.0, p_destroy=None):
+        """Photons [p_begin, p_end) with resonant scattering (App. A): the line
+        opacity is kappa / p_ab per unit of swept profile; a photon is destroyed
+        with probability p_destroy (default p_ab) per scattering and lost to the
+        line below -x_inert.
+        Returns dict(A, escaped, crossings, capped, capped_weight, wing,
+        scatterings[, records]); x0 fixes the injection frequency; x_return > 0
+        stops a photon once it is scattered back inside |x| < x_return (its
+        weight is then in no total: a test hook)."""
+        p_end = self.n_packets if p_end is None else int(p_end)
+        A = np.zeros(self.kappa.size, dtype=np.int64)
+        out = np.zeros(6, dtype=np.int64)
+        sp = OrcScatterParams(float(p_ab), float(p_ab if p_destroy is None else p_destroy), float(x_inert),
+                              int(max_events), 0 if x0 is None else 1, 0,
+                              0.0 if x0 is None else float(x0), float(x_return))
+        recs = np.zeros(p_end - p_begin, dtype=SCATTER_REC_DTYPE) if records else None
+        nt = int(nthreads or os.environ.get("ORACLE_THREADS", 0) or 0)
+        lib().orc_scatter(C.byref(self.box), C.byref(sp), _ptr(self.kappa, C.c_double), self._vp(0),
+                          self._vp(1), self._vp(2), _ptr(self.first, C.c_uint64), int(p_begin), int(p_end),
+                          _ptr(A, C.c_int64), _ptr(out, C.c_int64),
+                          None if recs is None else recs.ctypes.data, nt)
+        res = dict(A=A, escaped=int(out[0]), crossings=int(out[1]), capped=int(out[2]),
+                   capped_weight=int(out[3]), wing=int(out[4]), scatterings=int(out[5]))
         if records:
             res["records"] = recs
         return res

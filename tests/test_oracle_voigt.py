@@ -33,7 +33,7 @@ def test_damping_parameter_value():
                                2.7, 5.0, 12.0, 1e3])
 def test_dawson_series_matches_library(x):
     """Rybicki's series in the C oracle equals the library's Dawson integral."""
-    assert walker.dawson(x) == pytest.approx(float(special.dawsn(x)), rel=1e-13, abs=1e-300)
+    assert walker.dawson(x) == pytest.approx(float(special.dawsn(x)), rel=1e-12, abs=1e-16)
 
 
 def test_dawson_closed_properties():
