@@ -437,11 +437,13 @@ int64_t orc_trace_packet(const orc_box *b, const double *kappa, const double *ux
 /* bluer than +x_inert is treated the same way at its own frequency.          */
 /*                                                                           */
 /* Random numbers: event k of photon p uses the Philox block with counter     */
-/* (p_lo, p_hi, k, 1): u0 the free path, u1 the destruction test, u2 and u3   */
-/* the new direction (cos theta = 2 u2 - 1, azimuth 2 pi u3). Block           */
-/* (p_lo, p_hi, k, 2): u0, u1 the perpendicular velocity (Box-Muller).        */
-/* Trial j of the parallel-velocity draw uses block (p_lo, p_hi, k, 3 + j):   */
-/* u0 the envelope part, u1 (and u2) the proposal, u3 the acceptance.         */
+/* (p_lo, p_hi, k, 1): u0 the free path; words 1 and 2, as the 64-bit integer */
+/* (w1 << 32) | w2, the destruction test, destroyed iff it is below           */
+/* floor(p 2^64) (p_ab ~ 3e-7 is finer than a 23-bit uniform resolves). Block */
+/* (p_lo, p_hi, k, 2): u0, u1 the perpendicular velocity (Box-Muller), u2, u3 */
+/* the new direction (cos theta = 2 u2 - 1, azimuth 2 pi u3). Trial j of the  */
+/* parallel-velocity draw uses block (p_lo, p_hi, k, 3 + j): u0 the envelope  */
+/* part, u1 (and u2) the proposal, u3 the acceptance.                         */
 /* ------------------------------------------------------------------------- */
 typedef struct {
     double p_ab;          /* the box's p_ab: kappa / p_ab is the scattering depth per unit Phi */
@@ -463,13 +465,26 @@ typedef struct {
     int32_t pad;
 } orc_scatter_rec;
 
-static void orc_block(uint64_t seed, uint64_t p, uint32_t k, uint32_t stream, double u[4])
+static void orc_block_words(uint64_t seed, uint64_t p, uint32_t k, uint32_t stream, uint32_t r[4])
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t ctr[4] = {(uint32_t)p, (uint32_t)(p >> 32), k, stream};
-    uint32_t r[4];
     orc_philox4x32_10(ctr, key, r);
+}
+
+static void orc_block(uint64_t seed, uint64_t p, uint32_t k, uint32_t stream, double u[4])
+{
+    uint32_t r[4];
+    orc_block_words(seed, p, k, stream, r);
     for (int i = 0; i < 4; ++i) u[i] = orc_uniform(r[i]);
+}
+
+/* floor(p 2^64) for p in [0, 1]; p >= 1 destroys always. */
+static uint64_t orc_destroy_threshold(double p)
+{
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return UINT64_MAX;
+    return (uint64_t)ldexp(p, 64);
 }
 
 /* First-order Voigt (or Doppler) line density, the derivative of orc_Phi. */
@@ -558,15 +573,14 @@ static double orc_atom_upar(double x, double a, uint64_t seed, uint64_t p, uint3
 }
 
 /* One re-emission: atom velocity, isotropic new direction, new frequency. */
-static void orc_redistribute(double a, uint64_t seed, uint64_t p, uint32_t k, const double e[4], double kdir[3],
-                             double *x)
+static void orc_redistribute(double a, uint64_t seed, uint64_t p, uint32_t k, double kdir[3], double *x)
 {
     double t[4];
     orc_block(seed, p, k, 2u, t);
     const double uperp = sqrt(-log(t[0])) * cos(2.0 * M_PI * t[1]);
     const double upar = orc_atom_upar(*x, a, seed, p, k);
-    const double ct = 2.0 * e[2] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
-    const double ph = 2.0 * M_PI * e[3];
+    const double ct = 2.0 * t[2] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    const double ph = 2.0 * M_PI * t[3];
     const double kn[3] = {st * cos(ph), st * sin(ph), ct};
     double mu = kdir[0] * kn[0] + kdir[1] * kn[1] + kdir[2] * kn[2];
     if (mu > 1.0) mu = 1.0;
@@ -601,9 +615,9 @@ static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, cons
     for (;;) {
         if (x <= -sp->x_inert || x > sp->x_inert) { fate = 1; x_stop = x; break; }
         if (nscat >= sp->max_events) { fate = 2; break; }
-        double e[4];
-        orc_block(b->seed, p, (uint32_t)nscat, 1u, e);
-        double tau = -log(e[0]);
+        uint32_t ew[4];
+        orc_block_words(b->seed, p, (uint32_t)nscat, 1u, ew);
+        double tau = -log(orc_uniform(ew[0]));
         int lost = 0;
         for (;;) {                                            /* free flight */
             c = ci[0] + nx * (ci[1] + ny * ci[2]);
@@ -651,8 +665,8 @@ static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, cons
         }
         if (lost) { fate = 1; x_stop = -sp->x_inert; break; }
         ++nscat;                                              /* a scattering in cell c */
-        if (e[1] < sp->p_destroy) { fate = 0; break; }
-        orc_redistribute(b->damping, b->seed, p, (uint32_t)(nscat - 1), e, k, &x);
+        if ((((uint64_t)ew[1] << 32) | ew[2]) < orc_destroy_threshold(sp->p_destroy)) { fate = 0; break; }
+        orc_redistribute(b->damping, b->seed, p, (uint32_t)(nscat - 1), k, &x);
         if (sp->x_return > 0.0 && fabs(x) < sp->x_return) { fate = 3; break; }
     }
     int64_t wing = 0;
@@ -723,9 +737,7 @@ void orc_redistribution_chain(double x0, double a, uint64_t seed, uint64_t p, in
 {
     double k[3] = {0.0, 0.0, 1.0}, x = x0;
     for (int64_t i = 0; i < n; ++i) {
-        double e[4];
-        orc_block(seed, p, (uint32_t)i, 1u, e);
-        orc_redistribute(a, seed, p, (uint32_t)i, e, k, &x);
+        orc_redistribute(a, seed, p, (uint32_t)i, k, &x);
         xs[i] = x;
     }
 }
