@@ -122,6 +122,7 @@ typedef struct mc_lya_box_stats {
     double damping;               /* Voigt a (0 for the Doppler profile) */
     int64_t wing;                 /* part of `escaped` that the far damping wing absorbs
                                      (Voigt; 0 for the Doppler profile) */
+    int64_t scatterings;          /* resonant scatterings (mc_lya_scatter; 0 for the walk) */
 } mc_lya_box_stats;
 
 /* Per-box scalars from mc_lya_feed. */
@@ -265,6 +266,63 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *ctx, int64_t *absorbed, int64_t *emitted,
  * Synchronises the stream. Errors: ESTATE, EDEVICE. */
 mc_lya_status mc_lya_feed(mc_lya_ctx *ctx, double *ndot_e, float *mix_corr,
                           mc_lya_feed_stats *stats);
+
+/* ---- resonant scattering (App. A, steps 1-8) ------------------------------
+ * The paper's own Monte Carlo: each photon is followed scattering by
+ * scattering instead of streaming with a continuous absorption depth.
+ *   - Free paths: an optical depth -ln(u), accumulated along straight
+ *     segments as (kappa_c / p_ab) times the swept line profile, with the
+ *     Hubble drift and the face jumps of the walk (App. A steps 2-6 with the
+ *     step length taken to zero).
+ *   - At a scattering the photon is destroyed with probability p_destroy
+ *     (the box's p_ab unless overridden), deposited whole (w0) into the cell
+ *     (step 7; the feed splits ionisation from two-photon decay as for the
+ *     walk).
+ *   - Otherwise it is re-emitted (step 8): the scattering atom's parallel
+ *     velocity drawn from exp(-u^2)/((x-u)^2 + a^2) of Eq. (MC) (resonant,
+ *     u = x, for the Doppler profile), its perpendicular velocity projected on
+ *     the scattering plane drawn from exp(-u^2), an isotropic new direction,
+ *     and x -> x - u_par (1 - mu) + u_perp sqrt(1 - mu^2) (Eq. (inout)).
+ *   - A photon redshifted below -x_inert is lost to the line (counted in
+ *     `escaped`); for the Voigt profile the far damping wing takes the
+ *     expected share 1 - exp(-<kappa> Phi(-x_inert)) of it (`wing`).
+ * The photons are those of the last mc_lya_emit (same cells, positions,
+ * directions and frequencies as the walk's packets); tallies, totals and
+ * mc_lya_tally / mc_lya_feed work as after mc_lya_transport, with
+ * `scatterings` counted per box. */
+typedef struct mc_lya_scatter_opts {
+    double x_inert;               /* > 0; 0 selects 300 (well past x_50 ~ 60 of App. A) */
+    double p_destroy;             /* destruction probability per scattering; < 0 selects each
+                                     box's p_ab (test problems raise it to shorten histories) */
+    uint64_t max_events;          /* scatterings before a photon is stopped as capped;
+                                     0 selects 2^32 - 1 */
+    int32_t fixed_x0;             /* 1: every photon is injected at x0 (App. A step 1 injects at
+                                     line centre); 0: the emission's profile-drawn frequency */
+    float x0;
+    double x_return;              /* > 0: a photon re-emitted inside |x| < x_return stops and is
+                                     counted nowhere (fate 3 in the records; a test of x_50);
+                                     tallies are then not conserved. 0: off */
+} mc_lya_scatter_opts;
+
+/* One photon's history from mc_lya_scatter (56 bytes). */
+typedef struct mc_lya_scatter_record {
+    uint32_t cell0, cell_end;     /* global emission cell; cell of the last event */
+    float x0, x_end;              /* injection frequency; frequency at the end (-x_inert if lost) */
+    uint64_t scatterings;
+    uint32_t crossings;
+    int32_t fate;                 /* 0 destroyed, 1 lost to the line, 2 capped, 3 returned */
+    int64_t escaped, absorbed, wing;
+} mc_lya_scatter_record;
+
+/* Scatters photons [first, first + count) of the current emission into the
+ * tallies (as mc_lya_transport_range does for the walk; disjoint ranges add
+ * up to the whole).
+ *   opts     host, or NULL for the defaults
+ *   records  dev [count], or NULL
+ * Asynchronous on the context's stream. Errors: EINVAL (range, options),
+ * ESTATE, ENOMEM, EDEVICE. */
+mc_lya_status mc_lya_scatter(mc_lya_ctx *ctx, uint64_t first, uint64_t count,
+                             const mc_lya_scatter_opts *opts, mc_lya_scatter_record *records);
 
 /* Replays packets [first, first + count) of the current emission and writes
  * their histories without touching the tallies.

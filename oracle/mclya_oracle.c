@@ -530,7 +530,9 @@ static double orc_flight_length(const orc_box *b, double kap, double x, double t
  * (|x| >= 5, where the draw is mostly thermal); above u0 it is the Cauchy
  * factor times exp(-u0^2). The split point only changes the number of
  * trials: u0 = x - 0.02 - 0.1 max(0, x - 1)^2 (at least 0) for x < 5,
- * sqrt(6.3 + 3.2 ln x) beyond. For a = 0 the atom is resonant, u = x. */
+ * sqrt(6.3 + 3.2 ln x) beyond. For a = 0 the atom is resonant, u = x.
+ * The trials stop after 4096 (the resonant u = x is then returned), so that
+ * every draw ends. */
 static double orc_atom_upar(double x, double a, uint64_t seed, uint64_t p, uint32_t k)
 {
     if (a == 0.0) return x;
@@ -549,7 +551,7 @@ static double orc_atom_upar(double x, double a, uint64_t seed, uint64_t p, uint3
     const double m2 = exp(-u0 * u0) * (0.5 * M_PI - th0);             /* in units of 1/a */
     const double m1 = wing ? 0.5 * sqrt(M_PI) * erfc(-u0) * a / ((xa - u0) * (xa - u0)) : th0 + 0.5 * M_PI;
     const double p1 = m1 / (m1 + m2);
-    for (uint32_t j = 0;; ++j) {
+    for (uint32_t j = 0; j < 4096u; ++j) {       /* at worst ~14 trials are expected */
         double r[4];
         orc_block(seed, p, k, 3u + j, r);
         double u, acc;
@@ -570,6 +572,7 @@ static double orc_atom_upar(double x, double a, uint64_t seed, uint64_t p, uint3
         }
         if (r[3] <= acc) return neg ? -u : u;
     }
+    return x;                                       /* unreachable in practice (probability < 1e-100) */
 }
 
 /* One re-emission: atom velocity, isotropic new direction, new frequency. */

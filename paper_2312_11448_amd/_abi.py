@@ -43,7 +43,19 @@ class mc_lya_box_stats(C.Structure):
                 ("capped_weight", C.c_int64), ("capped_packets", C.c_int64),
                 ("crossings", C.c_int64), ("packets", C.c_int64), ("conserved", C.c_int32),
                 ("reserved", C.c_int32), ("delta", C.c_double), ("x_eff", C.c_double),
-                ("tau_ab_mean", C.c_double), ("damping", C.c_double), ("wing", C.c_int64)]
+                ("tau_ab_mean", C.c_double), ("damping", C.c_double), ("wing", C.c_int64),
+                ("scatterings", C.c_int64)]
+
+
+class mc_lya_scatter_opts(C.Structure):
+    _fields_ = [("x_inert", C.c_double), ("p_destroy", C.c_double), ("max_events", C.c_uint64),
+                ("fixed_x0", C.c_int32), ("x0", C.c_float), ("x_return", C.c_double)]
+
+
+class mc_lya_scatter_record(C.Structure):
+    _fields_ = [("cell0", C.c_uint32), ("cell_end", C.c_uint32), ("x0", C.c_float), ("x_end", C.c_float),
+                ("scatterings", C.c_uint64), ("crossings", C.c_uint32), ("fate", C.c_int32),
+                ("escaped", C.c_int64), ("absorbed", C.c_int64), ("wing", C.c_int64)]
 
 
 class mc_lya_feed_stats(C.Structure):
@@ -68,7 +80,7 @@ class mc_lya_tune_result(C.Structure):
 
 
 EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
-           "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace",
+           "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace", "mc_lya_scatter",
            "mc_lya_set_option", "mc_lya_autotune", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
            "mc_lya_features", "mc_lya_mlp_create", "mc_lya_mlp_get_params", "mc_lya_mlp_set_envelope",
@@ -110,6 +122,7 @@ def load():
     L.mc_lya_tally.argtypes = [vp, vp, vp, P(mc_lya_box_stats)]
     L.mc_lya_feed.argtypes = [vp, vp, vp, P(mc_lya_feed_stats)]
     L.mc_lya_trace.argtypes = [vp, u64, u64, vp]
+    L.mc_lya_scatter.argtypes = [vp, u64, u64, P(mc_lya_scatter_opts), vp]
     L.mc_lya_set_option.argtypes = [vp, i32, i64]
     L.mc_lya_autotune.argtypes = [vp, i32, P(mc_lya_tune_result)]
     L.mc_lya_kernel_time.argtypes = [vp, P(C.c_double), P(i64)]
@@ -199,6 +212,11 @@ def mc_lya_feed(ctx, ndot_ptr, mix_ptr, n_boxes):
 
 def mc_lya_trace(ctx, first, count, out_ptr):
     return _check(load().mc_lya_trace(ctx, int(first), int(count), out_ptr), ctx)
+
+
+def mc_lya_scatter(ctx, first, count, opts=None, records_ptr=None):
+    return _check(load().mc_lya_scatter(ctx, int(first), int(count),
+                                        None if opts is None else C.byref(opts), records_ptr), ctx)
 
 
 def mc_lya_set_option(ctx, option, value):

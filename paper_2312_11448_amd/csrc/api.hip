@@ -15,7 +15,9 @@
 using namespace mclya;
 
 static_assert(sizeof(mc_lya_box_desc) == 152, "mc_lya_box_desc layout");
-static_assert(sizeof(mc_lya_box_stats) == 104, "mc_lya_box_stats layout");
+static_assert(sizeof(mc_lya_box_stats) == 112, "mc_lya_box_stats layout");
+static_assert(sizeof(mc_lya_scatter_record) == 56, "mc_lya_scatter_record layout");
+static_assert(sizeof(mc_lya_scatter_opts) == 40, "mc_lya_scatter_opts layout");
 static_assert(sizeof(mc_lya_feed_stats) == 56, "mc_lya_feed_stats layout");
 static_assert(sizeof(mc_lya_packet_trace) == 64, "mc_lya_packet_trace layout");
 static_assert(sizeof(mc_lya_tune_result) == 88, "mc_lya_tune_result layout");
@@ -118,6 +120,7 @@ struct mc_lya_ctx {
     uint32_t *d_npk = nullptr;
     unsigned long long *d_A = nullptr;
     unsigned long long *d_queue = nullptr;
+    ScatBox *d_sbox = nullptr;               // scattering constants per box (allocated on first use)
     unsigned long long *d_boxabs = nullptr;
     double *d_fsum = nullptr;
     FeedBox *d_feed = nullptr;
@@ -200,7 +203,7 @@ void free_all(mc_lya_ctx *c)
     c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tail_prefix, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0],
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tail_prefix, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0], c->d_sbox,
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1125,6 +1128,7 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, m
             s.tau_ab_mean = c->red[b].kappa_sum / (double)c->walk[b].cells();
             s.damping = c->desc[b].profile == MC_LYA_PROFILE_VOIGT ? c->ph[b].damping : 0.0;
             s.wing = (int64_t)tot[b].wing;
+            s.scatterings = (int64_t)tot[b].pad[0];
         }
     }
     if (broken) return fail(c, MC_LYA_ECONSERVE, "sum(absorbed) + escaped + capped != w0 * packets");
@@ -1257,6 +1261,79 @@ mc_lya_status mc_lya_trace(mc_lya_ctx *c, uint64_t first, uint64_t count, mc_lya
     p.count = count;
     p.max_cross = c->max_cross;
     HIP_TRY(c, launch_trace(p, out, c->stream));
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_scatter(mc_lya_ctx *c, uint64_t first, uint64_t count, const mc_lya_scatter_opts *opts,
+                             mc_lya_scatter_record *records)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 1) return fail(c, MC_LYA_ESTATE, "mc_lya_scatter before mc_lya_emit");
+    if (first > c->total_packets || count > c->total_packets - first)
+        return fail(c, MC_LYA_EINVAL, "packet range outside the emitted packets");
+    mc_lya_scatter_opts o{};
+    if (opts) o = *opts;
+    if (o.x_inert == 0.0) o.x_inert = 300.0;
+    if (!(o.x_inert > 0.0) || !std::isfinite(o.x_inert)) return fail(c, MC_LYA_EINVAL, "x_inert must be > 0");
+    if (!(o.p_destroy <= 1.0) || std::isnan(o.p_destroy)) return fail(c, MC_LYA_EINVAL, "p_destroy must be <= 1");
+    if (o.max_events == 0) o.max_events = 0xffffffffull;
+    if (o.max_events > 0xffffffffull) return fail(c, MC_LYA_EINVAL, "max_events must be < 2^32");
+    if (!(o.x_return >= 0.0)) return fail(c, MC_LYA_EINVAL, "x_return must be >= 0");
+    if (o.fixed_x0 != 0 && o.fixed_x0 != 1) return fail(c, MC_LYA_EINVAL, "fixed_x0 must be 0 or 1");
+    if (o.fixed_x0 && !std::isfinite(o.x0)) return fail(c, MC_LYA_EINVAL, "x0 must be finite");
+    if (count == 0) return MC_LYA_OK;
+    mc_lya_status st = ensure_cell_of_packet(c);
+    if (st != MC_LYA_OK) return st;
+    const int nb = c->n_boxes;
+    if (!c->d_sbox) {
+        hipError_t e = dalloc(&c->d_sbox, (size_t)nb);
+        if (e != hipSuccess) return hip_fail(c, e, "scattering table allocation");
+    }
+    std::vector<ScatBox> sb(nb);
+    for (int b = 0; b < nb; ++b) {
+        const phys::Box &ph = c->ph[b];
+        const bool voigt = c->desc[b].profile == MC_LYA_PROFILE_VOIGT;
+        const double p = o.p_destroy < 0.0 ? ph.pab : o.p_destroy;
+        sb[b].inv_pab = (float)(1.0 / ph.pab);
+        sb[b].x_inert = (float)o.x_inert;
+        sb[b].a = voigt ? (float)ph.damping : 0.0f;
+        sb[b].damp = voigt ? (float)(2.0 * ph.damping / phys::kPi) : 0.0f;
+        // destroyed iff the event's 64-bit word is below floor(p 2^64)
+        sb[b].destroy = p <= 0.0 ? 0ull : (p >= 1.0 ? ~0ull : (uint64_t)std::ldexp(p, 64));
+        sb[b].pad = 0;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));          // the previous table may still be in use
+    HIP_TRY(c, hipMemcpyAsync(c->d_sbox, sb.data(), sizeof(ScatBox) * nb, hipMemcpyHostToDevice, c->stream));
+    ScatterParams p{};
+    p.boxes = c->d_walk;
+    p.sbox = c->d_sbox;
+    p.n_boxes = nb;
+    p.vel = c->vel ? 1 : 0;
+    p.rec = c->d_rec;
+    p.cell_of_packet = c->d_cop;
+    p.A = c->d_A;
+    p.tot = c->d_tot;
+    p.queue = c->d_queue;
+    p.first = first;
+    p.count = count;
+    p.max_events = o.max_events;
+    p.chunk = 64;
+    p.refill = 16;
+    p.nqueues = (int32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, count / 64));
+    p.fixed_x0 = o.fixed_x0;
+    p.x0 = o.x0;
+    p.x_return = (float)o.x_return;
+    p.records = records;
+    // resident waves: 8 workgroups of 256 per compute unit, capped by the work
+    const uint64_t want = (count + 255) / 256;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)c->num_cu * 8, want));
+    hipEvent_t e1 = nullptr;
+    st = timed_begin(c, &e1);
+    if (st != MC_LYA_OK) return st;
+    HIP_TRY(c, launch_scatter(p, 256, grid, c->stream));
+    st = timed_end(c, e1);
+    if (st != MC_LYA_OK) return st;
+    account_walked(c, first, count);
     return MC_LYA_OK;
 }
 

@@ -154,6 +154,37 @@ struct WalkParams {
 };
 constexpr int kMaxQueues = 64;
 
+// ---- resonant scattering ----------------------------------------------------
+// Per-box constants of the scattering Monte Carlo.
+struct ScatBox {
+    float inv_pab;           // 1/p_ab: the line opacity is kappa / p_ab per unit of swept profile
+    float x_inert;           // lost to the line below -x_inert (and far above +x_inert)
+    float a;                 // Voigt a (0: Doppler profile, resonant atoms)
+    float damp;              // 2a/pi
+    uint64_t destroy;        // destroyed iff a 64-bit event word is below this (floor(p 2^64))
+    uint64_t pad;
+};
+
+struct ScatterParams {
+    const WalkBox *boxes;
+    const ScatBox *sbox;
+    int32_t n_boxes;
+    int32_t vel;
+    const void *rec;
+    const uint32_t *cell_of_packet;
+    unsigned long long *A;
+    BoxTot *tot;             // pad[0]: scatterings
+    unsigned long long *queue;
+    uint64_t first, count;
+    uint64_t max_events;
+    int32_t chunk, refill, nqueues;
+    int32_t fixed_x0;        // test hook: inject every photon at x0
+    float x0;
+    float x_return;          // test hook: > 0 stops a photon scattered back inside |x| < x_return
+    mc_lya_scatter_record *records;   // optional, one per photon of [first, first + count)
+};
+hipError_t launch_scatter(const ScatterParams &p, int block, int grid, hipStream_t s);
+
 // ---- tile-decomposed walk -------------------------------------------------
 // Tile extent in cells along x, y, z (the last tiles along an axis may be
 // thinner) and the workgroup that walks one tile.

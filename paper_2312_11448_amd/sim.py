@@ -18,6 +18,12 @@ TRACE_DTYPE = np.dtype([("cell0", np.uint32), ("fx", np.float32), ("fy", np.floa
                         ("wing", np.int64)])
 assert TRACE_DTYPE.itemsize == C.sizeof(A.mc_lya_packet_trace)
 
+SCATTER_DTYPE = np.dtype([("cell0", np.uint32), ("cell_end", np.uint32), ("x0", np.float32),
+                          ("x_end", np.float32), ("scatterings", np.uint64), ("crossings", np.uint32),
+                          ("fate", np.int32), ("escaped", np.int64), ("absorbed", np.int64),
+                          ("wing", np.int64)])
+assert SCATTER_DTYPE.itemsize == C.sizeof(A.mc_lya_scatter_record)
+
 
 def _dev(a, dtype, device):
     if a is None:
@@ -115,6 +121,24 @@ class Simulation:
         A.mc_lya_trace(self.ctx, first, count, buf.data_ptr())
         torch.cuda.synchronize(self.device)
         return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=TRACE_DTYPE)
+
+    def scatter(self, first=0, count=None, x_inert=0.0, p_destroy=-1.0, max_events=0, x0=None,
+                x_return=0.0, records=False):
+        """Resonant-scattering Monte Carlo (App. A) of photons [first,
+        first + count) into the tallies; with records=True also returns one
+        history per photon (numpy structured array)."""
+        count = sum(self.n_packets) - first if count is None else int(count)
+        o = A.mc_lya_scatter_opts(x_inert=float(x_inert), p_destroy=float(p_destroy),
+                                  max_events=int(max_events), fixed_x0=0 if x0 is None else 1,
+                                  x0=0.0 if x0 is None else float(x0), x_return=float(x_return))
+        buf = None
+        if records:
+            buf = torch.empty(max(1, count) * SCATTER_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        A.mc_lya_scatter(self.ctx, first, count, o, None if buf is None else buf.data_ptr())
+        if records:
+            torch.cuda.synchronize(self.device)
+            return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=SCATTER_DTYPE)[:count]
+        return None
 
     def set_option(self, option, value):
         A.mc_lya_set_option(self.ctx, option, value)

@@ -36,7 +36,9 @@ def test_every_declared_symbol_is_exported():
 def test_struct_sizes_match_header_layout():
     M = _lib()
     assert C.sizeof(M.mc_lya_packet_trace) == 64
-    assert C.sizeof(M.mc_lya_box_stats) == 104
+    assert C.sizeof(M.mc_lya_box_stats) == 112
+    assert C.sizeof(M.mc_lya_scatter_record) == 56
+    assert C.sizeof(M.mc_lya_scatter_opts) == 40
     assert C.sizeof(M.mc_lya_feed_stats) == 56
     assert C.sizeof(M.mc_lya_tune_result) == 88
     # 4 int32, 11 doubles, w0, 3 pointers, float + int32, 1 pointer
