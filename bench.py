@@ -51,13 +51,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "batch", "surrogate"],
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "batch", "surrogate", "scatter"],
                     help="c2: the 128^3 workload (default); batch: 64 uneven boxes in one context; "
                          "surrogate: train the mixing-correction network on Monte-Carlo boxes, evaluate it "
                          "on held-out boxes and time its inference on the 256^3 box")
     ap.add_argument("--profile", default="doppler", choices=["doppler", "voigt"],
                     help="line profile of every box (voigt: Eq. (MC) with its damping wing)")
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--photons", type=int, default=1 << 20, help="scatter: photons per step")
+    ap.add_argument("--zeta", type=float, default=1e4,
+                    help="scatter: expansion-rate factor of the App. A test problem (1e4: tau_S = 6e4, "
+                         "about 7e4 scatterings per photon)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=None,
                     help="replay each transport as a captured HIP graph (default 0)")
     ap.add_argument("--autotune", action="store_true",
@@ -170,6 +174,89 @@ def cpu_baseline(specs, budget_s):
                       f"transport, FP64 C + OpenMP)"}
 
 
+# VALU issue peak of the chip in wave instructions: 256 compute units x 4
+# SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz.
+VALU_PEAK_GINSTR = 256 * 4 * 2.4e9 / 4 / 1e9
+SCATTER_SOURCES = ("paper_2312_11448_amd/csrc/kernels_scatter.hip", "paper_2312_11448_amd/csrc/walk_core.hpp",
+                   "paper_2312_11448_amd/csrc/dawson.hpp", "paper_2312_11448_amd/csrc/common.hpp")
+
+
+def scatter_source_hash():
+    h = hashlib.sha256()
+    for rel in SCATTER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def bench_scatter(a):
+    """Resonant-scattering Monte Carlo (App. A): scatterings per second of
+    whole steps (emit, scatter, tally, feed) over a photon batch of the 32^3
+    lognormal box at z = 1100 with the Voigt profile and the physical p_ab,
+    with the expansion rate scaled by zeta as in the App. A test problem (at
+    zeta = 1 a photon scatters ~3e6 times and the slowest of a batch sets the
+    step time)."""
+    import torch
+    import workloads as W
+    import paper_2312_11448_amd as M
+    spec = W.make_box("c1", n_packets=a.photons, profile="voigt", zeta=a.zeta)
+    dev = torch.device("cuda:0")
+    sim = M.Simulation([spec], device=dev)
+    sim.set_option(M.MC_LYA_OPT_TIMING, 1)
+
+    def step():
+        sim.emit()
+        sim.scatter()
+        t = sim.tally(want_emitted=False)
+        f = sim.feed()
+        return t, f
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    sim.kernel_time()
+    t0 = time.perf_counter()
+    nscat = cross = 0
+    for _ in range(a.steps):
+        t, f = step()
+        st = t["stats"][0]
+        if st.conserved != 1 or st.capped_packets:
+            raise SystemExit("conservation identity failed")
+        nscat += st.scatterings
+        cross += st.crossings
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    kms, launches = sim.kernel_time()
+    sim.close()
+    rate = nscat / dt
+    valu = None
+    path = os.path.join(ROOT, "profiles", "scatter_valu.json")
+    if os.path.exists(path):
+        with open(path) as fh:
+            pr = json.load(fh)
+        if (pr.get("source_sha256") == scatter_source_hash() and pr.get("photons") == a.photons
+                and pr.get("zeta") == a.zeta):
+            valu = pr["valu_wave_instr_per_scattering"]
+    achieved = None if valu is None else valu * (nscat / (kms / 1e3)) / 1e9
+    fs = f["stats"][0]
+    out = {
+        "metric": "resonant scatterings/s", "value": rate, "unit": "scatterings/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"App. A scattering Monte Carlo: {a.photons} photons of the 32^3 lognormal "
+                               f"(ln-sigma 0.3) box, z=1100, T=3000K, x_e=0.1, zeta={a.zeta:g}, Voigt profile, "
+                               f"physical p_ab, lost below x=-300",
+                   "photons": a.photons, "scatterings_per_step": nscat / a.steps,
+                   "scatterings_per_photon": nscat / a.steps / a.photons,
+                   "crossings_per_step": cross / a.steps, "kernel_ms_per_step": kms / a.steps,
+                   "c_mc": fs.c_mc, "f_escape": fs.f_escape, "f_absorbed": fs.f_absorbed, "f_wing": fs.f_wing},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GINSTR,
+                     "unit": "G wave-instr/s (VALU issue)",
+                     "frac": None if achieved is None else achieved / VALU_PEAK_GINSTR, "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_surrogate(a):
     """Surrogate cells per second (features + inference over the 256^3 box),
     with its accuracy against held-out Monte-Carlo references."""
@@ -253,6 +340,8 @@ def main():
     import paper_2312_11448_amd as M
     if a.config == "surrogate":
         return bench_surrogate(a)
+    if a.config == "scatter":
+        return bench_scatter(a)
 
     specs = W.batch_specs() if a.config == "batch" else [W.make_box(a.config)]
     if a.profile != "doppler":

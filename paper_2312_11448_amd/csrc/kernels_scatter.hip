@@ -55,21 +55,25 @@ __device__ __forceinline__ float swept(float x, float dx, float damp)
 
 // Length s in (0, s_max] with kap * swept(x, delta s) = tau: Newton's method
 // inside a shrinking bracket (the swept mass grows with s), from the linear
-// estimate tau / (kap delta phi(x)).
-__device__ __forceinline__ float flight_length(float kap, float delta, float damp, float x, float tau, float s_max)
+// estimate tau / (kap delta phi(x)). `found` is false when the depth over
+// the whole of (0, s_max] stays below tau (no root was bracketed).
+__device__ __forceinline__ float flight_length(float kap, float delta, float damp, float x, float tau, float s_max,
+                                               bool &found)
 {
     float lo = 0.0f, hi = s_max;
-    float s = tau / (kap * delta * line_density(x, damp));
+    float s = tau * __builtin_amdgcn_rcpf(kap * delta * line_density(x, damp));
     if (!(s > lo && s < hi)) s = 0.5f * (lo + hi);
+#pragma unroll 1
     for (int it = 0; it < 12; ++it) {
         const float g = kap * swept(x, delta * s, damp) - tau;
         if (g > 0.0f) hi = s; else lo = s;
-        float sn = s - g / (kap * delta * line_density(x - delta * s, damp));
+        float sn = s - g * __builtin_amdgcn_rcpf(kap * delta * line_density(x - delta * s, damp));
         if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
         const bool done = fabsf(sn - s) <= 1e-6f * s;
         s = sn;
         if (done) break;
     }
+    found = hi < s_max;
     return s;
 }
 
@@ -100,6 +104,7 @@ __device__ __forceinline__ float atom_upar(float x, float a, uint64_t seed, uint
     const float m2 = expf(-u0 * u0) * (kHalfPi - th0);
     const float m1 = wing ? 0.886226925452758f * erfcf(-u0) * a / ((xa - u0) * (xa - u0)) : th0 + kHalfPi;
     const float p1 = m1 / (m1 + m2);
+#pragma unroll 1
     for (uint32_t j = 0; j < 4096u; ++j) {       // at worst ~14 trials are expected
         uint32_t w[4];
         event_block(seed, p, k, 3u + j, w);
@@ -184,43 +189,6 @@ __device__ __forceinline__ void init_photon(Photon &P, const WalkBox &B, float a
     P.need_event = true;
 }
 
-// Per-lane per-box totals, flushed with one atomic per box per wave.
-struct SAcc {
-    int32_t box;
-    uint64_t esc, cross, capn, capw, wing, nscat;
-};
-
-__device__ __forceinline__ uint64_t wsum(uint64_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Convergent: every lane of the wave calls it.
-__device__ __forceinline__ void sflush(SAcc &a, bool give, BoxTot *__restrict__ tot)
-{
-    uint64_t pending = __ballot(give && a.box >= 0);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int b = __shfl(a.box, leader, 64);
-        const bool mine = give && a.box == b;
-        const uint64_t e = wsum(mine ? a.esc : 0), c = wsum(mine ? a.cross : 0);
-        const uint64_t n = wsum(mine ? a.capn : 0), w = wsum(mine ? a.capw : 0);
-        const uint64_t g = wsum(mine ? a.wing : 0), s = wsum(mine ? a.nscat : 0);
-        if ((int)__lane_id() == leader) {
-            if (e) atomicAdd(&tot[b].escaped, (unsigned long long)e);
-            if (c) atomicAdd(&tot[b].crossings, (unsigned long long)c);
-            if (n) atomicAdd(&tot[b].capped_packets, (unsigned long long)n);
-            if (w) atomicAdd(&tot[b].capped_weight, (unsigned long long)w);
-            if (g) atomicAdd(&tot[b].wing, (unsigned long long)g);
-            if (s) atomicAdd(&tot[b].pad[0], (unsigned long long)s);
-        }
-        pending &= ~__ballot(mine);
-    }
-    if (give) a.esc = a.cross = a.capn = a.capw = a.wing = a.nscat = 0;
-}
-
 __device__ __forceinline__ int box_index(const WalkBox *boxes, int n_boxes, uint64_t gp)
 {
     int lo = 0, hi = n_boxes - 1;
@@ -232,6 +200,11 @@ __device__ __forceinline__ int box_index(const WalkBox *boxes, int n_boxes, uint
 }
 
 enum : int { kSAlive = 0, kSDestroyed = 1, kSLost = 2, kSCapped = 3, kSReturned = 4 };
+constexpr int kBurst = 64;
+
+template <bool VEL>
+__device__ __forceinline__ int scatter_at(Photon &P, const WalkBox &B, const ScatBox &S, unsigned long long *A,
+                                          const ScatterParams &SP, float s);
 
 // One event of a photon: a face crossing, or a scattering (free-path end,
 // destruction test, re-emission). Returns the photon's state afterwards.
@@ -254,6 +227,24 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
         P.need_event = false;
     }
     const float kap = P.r.kap * S.inv_pab;
+    // Most flights (in the line core) are far shorter than the distance to
+    // the nearest face in any direction, r_safe: the linear estimate of the
+    // flight and the cell-independent bound on how much it can grow over
+    // delta s <= 1e-3 (phi changes by under 1 %) decide it without the face
+    // search, and the root is then sought in (0, r_safe].
+    {
+        const double rsafe = fmin(fmin(fmin(P.fx, 1.0 - P.fx), fmin(P.fy, 1.0 - P.fy)), fmin(P.fz, 1.0 - P.fz));
+        const float s_lin = P.tau * __builtin_amdgcn_rcpf(kap * B.delta * line_density(P.x, S.damp));
+        if (B.delta * s_lin <= 1e-3f && 1.02f * s_lin < (float)rsafe && P.x - 2e-3f > -S.x_inert) {
+            // over delta s < 1e-6 the density changes by about 1e-5 of itself
+            // at most (|phi'/phi| = 2|x| in the thermal core, 2/|x| in the
+            // damping wing): the linear estimate is the flight
+            if (B.delta * s_lin < 1e-6f) return scatter_at<VEL>(P, B, S, A, SP, s_lin);
+            bool found = false;
+            const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, (float)rsafe, found);
+            if (found) return scatter_at<VEL>(P, B, S, A, SP, s);
+        }
+    }
     // next face (ties: x, then y, then z)
     const double tx = P.kx > 0.0 ? (1.0 - P.fx) / P.kx : (P.kx < 0.0 ? P.fx / -P.kx : 1.0e300);
     const double ty = P.ky > 0.0 ? (1.0 - P.fy) / P.ky : (P.ky < 0.0 ? P.fy / -P.ky : 1.0e300);
@@ -301,7 +292,16 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
     }
     // the scattering point inside this cell
     const float slim = inert ? (P.x + S.x_inert) / B.delta : (float)sf;
-    const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, slim);
+    bool found = false;
+    const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, slim, found);
+    return scatter_at<VEL>(P, B, S, A, SP, s);
+}
+
+// Moves the photon s along its path and scatters it there (steps 7-8).
+template <bool VEL>
+__device__ __forceinline__ int scatter_at(Photon &P, const WalkBox &B, const ScatBox &S, unsigned long long *A,
+                                          const ScatterParams &SP, float s)
+{
     const double sd = (double)s;
     P.fx = fmin(fmax(P.fx + P.kx * sd, 0.0), 1.0);
     P.fy = fmin(fmax(P.fy + P.ky * sd, 0.0), 1.0);
@@ -319,11 +319,12 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
     event_block(B.seed, P.p, k, 2u, t);
     const float uperp = sqrtf(-logf(u01(t[0]))) * cospif(2.0f * u01(t[1]));
     const float upar = atom_upar(P.x, S.a, B.seed, P.p, k);
+    // new direction: cos theta exact, the azimuth in binary32
     const double ct = 2.0 * (double)u01(t[2]) - 1.0;
     const double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
-    double sp, cp;
-    sincospi(2.0 * (double)u01(t[3]), &sp, &cp);
-    const double nkx = st * cp, nky = st * sp, nkz = ct;
+    float spf, cpf;
+    sincospif(2.0f * u01(t[3]), &spf, &cpf);
+    const double nkx = st * (double)cpf, nky = st * (double)spf, nkz = ct;
     const float mu = fminf(fmaxf((float)(P.kx * nkx + P.ky * nky + P.kz * nkz), -1.0f), 1.0f);
     P.x = P.x - upar * (1.0f - mu) + uperp * sqrtf((1.0f - mu) * (1.0f + mu));
     P.kx = nkx;
@@ -333,19 +334,70 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
     return kSAlive;
 }
 
-template <bool VEL>
-__global__ __launch_bounds__(256) void scatter_kernel(ScatterParams SP)
+// The end of a photon: its totals (one set of atomics per photon: a photon
+// lives for thousands to millions of events) and its record.
+__device__ __forceinline__ void finish_photon(const Photon &P, const WalkBox &B, int box, int st, float x_stop,
+                                              const ScatterParams &SP)
+{
+    uint32_t wing = 0;
+    if (st == kSLost && B.kfar > 0.0f) {
+        const float pw = one_minus_exp(B.kfar * cumulative_voigt(x_stop, B.damp));
+        wing = min((uint32_t)rintf((float)B.w0 * pw), B.w0);
+    }
+    BoxTot &t = SP.tot[box];
+    const bool out = st == kSLost || st == kSCapped;
+    if (out) atomicAdd(&t.escaped, (unsigned long long)B.w0);
+    if (P.ncross) atomicAdd(&t.crossings, (unsigned long long)P.ncross);
+    if (st == kSCapped) {
+        atomicAdd(&t.capped_packets, 1ull);
+        atomicAdd(&t.capped_weight, (unsigned long long)B.w0);
+    }
+    if (wing) atomicAdd(&t.wing, (unsigned long long)wing);
+    if (P.nscat) atomicAdd(&t.pad[0], (unsigned long long)P.nscat);
+    if (SP.records) {
+        mc_lya_scatter_record &o = SP.records[P.p + B.pkt_off - SP.first];
+        o.cell0 = P.cell0;
+        o.cell_end = P.c;
+        o.x0 = P.x0;
+        o.x_end = st == kSLost ? x_stop : P.x;
+        o.scatterings = P.nscat;
+        o.crossings = P.ncross;
+        o.fate = st == kSDestroyed ? 0 : st == kSLost ? 1 : st == kSCapped ? 2 : 3;
+        o.escaped = out ? (int64_t)B.w0 : 0;
+        o.absorbed = st == kSDestroyed ? (int64_t)B.w0 : 0;
+        o.wing = (int64_t)wing;
+    }
+}
+
+// Waves per SIMD the register allocation aims at (0: the compiler's choice).
+#ifndef MCLYA_SCATTER_WAVES
+#define MCLYA_SCATTER_WAVES 0
+#endif
+#if MCLYA_SCATTER_WAVES > 0
+#define MCLYA_SCATTER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MCLYA_SCATTER_WAVES)))
+#else
+#define MCLYA_SCATTER_OCCUPANCY
+#endif
+
+// SINGLE: one box, whose constants are wave-uniform (scalar registers).
+template <bool VEL, bool SINGLE>
+__global__ __launch_bounds__(256) MCLYA_SCATTER_OCCUPANCY void scatter_kernel(ScatterParams SP)
 {
     const uint32_t lane = __lane_id();
     Photon P;
-    int box = -1;
-    SAcc acc{-1, 0, 0, 0, 0, 0, 0};
+    int box = 0;
     bool alive = false;
     bool more = true;
     uint64_t cur = 0, end = 0;
     const uint32_t nq = (uint32_t)SP.nqueues;
     uint32_t part = blockIdx.x % nq, tried = 0;
     const uint64_t chunk = (uint64_t)SP.chunk;
+    WalkBox B1;
+    ScatBox S1;
+    if (SINGLE) {
+        B1 = SP.boxes[0];
+        S1 = SP.sbox[0];
+    }
     for (;;) {
         uint64_t idle = __ballot(!alive);
         if (more && (uint32_t)__popcll(idle) >= (uint32_t)SP.refill) {
@@ -367,21 +419,17 @@ __global__ __launch_bounds__(256) void scatter_kernel(ScatterParams SP)
                 const uint64_t take = n_idle < end - cur ? n_idle : end - cur;
                 const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-                const bool fresh = !alive && (uint64_t)r < take;
-                int nb = box;
-                uint64_t gp = 0;
-                if (fresh) {
-                    gp = SP.first + cur + r;
-                    nb = SP.n_boxes == 1 ? 0 : box_index(SP.boxes, SP.n_boxes, gp);
-                }
-                const bool change = fresh && nb != acc.box;
-                if (__ballot(change && acc.box >= 0)) sflush(acc, change, SP.tot);
-                if (fresh) {
-                    box = nb;
-                    acc.box = nb;
-                    const WalkBox B = SP.boxes[nb];
-                    init_photon<VEL>(P, B, SP.sbox[nb].a, gp - B.pkt_off, SP.cell_of_packet[gp], SP.rec,
-                                     SP.fixed_x0 != 0, SP.x0);
+                if (!alive && (uint64_t)r < take) {
+                    const uint64_t gp = SP.first + cur + r;
+                    if (SINGLE) {
+                        init_photon<VEL>(P, B1, S1.a, gp - B1.pkt_off, SP.cell_of_packet[gp], SP.rec,
+                                         SP.fixed_x0 != 0, SP.x0);
+                    } else {
+                        box = box_index(SP.boxes, SP.n_boxes, gp);
+                        const WalkBox B = SP.boxes[box];
+                        init_photon<VEL>(P, B, SP.sbox[box].a, gp - B.pkt_off, SP.cell_of_packet[gp], SP.rec,
+                                         SP.fixed_x0 != 0, SP.x0);
+                    }
                     alive = true;
                 }
                 cur += take;
@@ -393,40 +441,22 @@ __global__ __launch_bounds__(256) void scatter_kernel(ScatterParams SP)
             continue;
         }
         if (alive) {
-            const WalkBox B = SP.boxes[box];
-            const ScatBox S = SP.sbox[box];
-            float x_stop = 0.0f;
-            const int st = scatter_event<VEL>(P, B, S, SP.rec, SP.A, SP, x_stop);
-            if (st != kSAlive) {
-                uint32_t wing = 0;
-                if (st == kSLost && B.kfar > 0.0f) {
-                    const float pw = one_minus_exp(B.kfar * cumulative_voigt(x_stop, B.damp));
-                    wing = min((uint32_t)rintf((float)B.w0 * pw), B.w0);
+            // up to kBurst events per lane before the wave looks at refills
+            // again (photons live for up to millions of events)
+            const WalkBox B = SINGLE ? B1 : SP.boxes[box];
+            const ScatBox S = SINGLE ? S1 : SP.sbox[box];
+#pragma unroll 1
+            for (int ev = 0; ev < kBurst; ++ev) {
+                float x_stop = 0.0f;
+                const int st = scatter_event<VEL>(P, B, S, SP.rec, SP.A, SP, x_stop);
+                if (st != kSAlive) {
+                    finish_photon(P, B, box, st, x_stop, SP);
+                    alive = false;
+                    break;
                 }
-                acc.cross += P.ncross;
-                acc.nscat += P.nscat;
-                acc.esc += (st == kSLost || st == kSCapped) ? B.w0 : 0;
-                acc.capn += st == kSCapped ? 1 : 0;
-                acc.capw += st == kSCapped ? B.w0 : 0;
-                acc.wing += wing;
-                if (SP.records) {
-                    mc_lya_scatter_record &o = SP.records[P.p + B.pkt_off - SP.first];
-                    o.cell0 = P.cell0;
-                    o.cell_end = P.c;
-                    o.x0 = P.x0;
-                    o.x_end = st == kSLost ? x_stop : P.x;
-                    o.scatterings = P.nscat;
-                    o.crossings = P.ncross;
-                    o.fate = st == kSDestroyed ? 0 : st == kSLost ? 1 : st == kSCapped ? 2 : 3;
-                    o.escaped = (st == kSLost || st == kSCapped) ? (int64_t)B.w0 : 0;
-                    o.absorbed = st == kSDestroyed ? (int64_t)B.w0 : 0;
-                    o.wing = (int64_t)wing;
-                }
-                alive = false;
             }
         }
     }
-    sflush(acc, true, SP.tot);
 }
 
 __global__ void reset_scatter_queue_kernel(unsigned long long *q, int n)
@@ -439,10 +469,14 @@ __global__ void reset_scatter_queue_kernel(unsigned long long *q, int n)
 hipError_t launch_scatter(const ScatterParams &p, int block, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_scatter_queue_kernel, dim3(1), dim3(64), 0, s, p.queue, (int)p.nqueues);
-    if (p.vel)
-        hipLaunchKernelGGL(scatter_kernel<true>, dim3((unsigned)grid), dim3((unsigned)block), 0, s, p);
-    else
-        hipLaunchKernelGGL(scatter_kernel<false>, dim3((unsigned)grid), dim3((unsigned)block), 0, s, p);
+    const dim3 g((unsigned)grid), b((unsigned)block);
+    if (p.n_boxes == 1) {
+        if (p.vel) hipLaunchKernelGGL((scatter_kernel<true, true>), g, b, 0, s, p);
+        else hipLaunchKernelGGL((scatter_kernel<false, true>), g, b, 0, s, p);
+    } else {
+        if (p.vel) hipLaunchKernelGGL((scatter_kernel<true, false>), g, b, 0, s, p);
+        else hipLaunchKernelGGL((scatter_kernel<false, false>), g, b, 0, s, p);
+    }
     return hipGetLastError();
 }
 
