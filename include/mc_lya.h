@@ -324,6 +324,28 @@ typedef struct mc_lya_scatter_record {
 mc_lya_status mc_lya_scatter(mc_lya_ctx *ctx, uint64_t first, uint64_t count,
                              const mc_lya_scatter_opts *opts, mc_lya_scatter_record *records);
 
+/* ---- recombination history (Sec. III.A.1, Sec. IV.B) -------------------------
+ * Advances the free-electron fraction of every cell from z0 to z1 (z0 > z1 >
+ * 0, forward in time) with the net rate the Monte Carlo feeds: dx_e/dz =
+ * -ndot_e / (n_H,c (1 + z) H), ndot_e from mc_lya_feed. The classic
+ * fourth-order Runge-Kutta method in z takes n_steps equal steps; each of its
+ * four stages moves every box to the stage's redshift with T = T_cmb0 (1+z)
+ * (one temperature for matter and radiation), re-packs the fields (the x_e
+ * of the stage), emits n_packets[b] packets per box, transports them and
+ * runs the feed. Stage s of step i emits with seeds seed + ((4 i + s) << 20)
+ * + b. Helium is not followed.
+ *   x_e    host [n_boxes] of dev pointers: each box's own x_e field (the
+ *          array its descriptor's x_e points to, which must not be NULL),
+ *          overwritten with x_e(z1) (binary32, kept inside [0, 1]);
+ *   X_out  host [n_steps + 1][n_boxes], or NULL: the global X_e = <n_e>/<n_H>
+ *          of each box at z0 and after every step.
+ * The context is left at z1 and re-packed (emit before transporting again).
+ * The call allocates 6 doubles per cell on first use and synchronises the
+ * stream at every stage. Errors: EINVAL, ESTATE, ENOMEM, EDEVICE, and those of
+ * the emission and transport. */
+mc_lya_status mc_lya_evolve(mc_lya_ctx *ctx, double z0, double z1, int32_t n_steps, const uint64_t *n_packets,
+                            uint64_t seed, float *const *x_e, double *X_out);
+
 /* Replays packets [first, first + count) of the current emission and writes
  * their histories without touching the tallies.
  *   out  dev [count]

@@ -81,6 +81,7 @@ class mc_lya_tune_result(C.Structure):
 
 EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace", "mc_lya_scatter",
+           "mc_lya_evolve",
            "mc_lya_set_option", "mc_lya_autotune", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
            "mc_lya_features", "mc_lya_mlp_create", "mc_lya_mlp_get_params", "mc_lya_mlp_set_envelope",
@@ -123,6 +124,7 @@ def load():
     L.mc_lya_feed.argtypes = [vp, vp, vp, P(mc_lya_feed_stats)]
     L.mc_lya_trace.argtypes = [vp, u64, u64, vp]
     L.mc_lya_scatter.argtypes = [vp, u64, u64, P(mc_lya_scatter_opts), vp]
+    L.mc_lya_evolve.argtypes = [vp, C.c_double, C.c_double, i32, P(u64), u64, P(vp), P(C.c_double)]
     L.mc_lya_set_option.argtypes = [vp, i32, i64]
     L.mc_lya_autotune.argtypes = [vp, i32, P(mc_lya_tune_result)]
     L.mc_lya_kernel_time.argtypes = [vp, P(C.c_double), P(i64)]
@@ -217,6 +219,16 @@ def mc_lya_trace(ctx, first, count, out_ptr):
 def mc_lya_scatter(ctx, first, count, opts=None, records_ptr=None):
     return _check(load().mc_lya_scatter(ctx, int(first), int(count),
                                         None if opts is None else C.byref(opts), records_ptr), ctx)
+
+
+def mc_lya_evolve(ctx, z0, z1, n_steps, n_packets, seed, xe_ptrs, X_out=None):
+    nb = len(n_packets)
+    npk = _arr(C.c_uint64, n_packets)
+    ptrs = (C.c_void_p * nb)(*[int(v) for v in xe_ptrs])
+    out = None
+    if X_out is not None:
+        out = X_out.ctypes.data_as(C.POINTER(C.c_double))
+    return _check(load().mc_lya_evolve(ctx, float(z0), float(z1), int(n_steps), npk, int(seed), ptrs, out), ctx)
 
 
 def mc_lya_set_option(ctx, option, value):

@@ -121,6 +121,8 @@ struct mc_lya_ctx {
     unsigned long long *d_A = nullptr;
     unsigned long long *d_queue = nullptr;
     ScatBox *d_sbox = nullptr;               // scattering constants per box (allocated on first use)
+    double *d_ev = nullptr;                  // evolution: y0, k0..k3, ndot [6][total cells] (first use)
+    double *d_ev_coef = nullptr;             // evolution: -1 / (n_H (1+z) H) per box
     unsigned long long *d_boxabs = nullptr;
     double *d_fsum = nullptr;
     FeedBox *d_feed = nullptr;
@@ -203,7 +205,7 @@ void free_all(mc_lya_ctx *c)
     c->cap_stream = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
-                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tail_prefix, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0], c->d_sbox,
+                    c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tail_prefix, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0], c->d_sbox, c->d_ev, c->d_ev_coef,
                     c->d_state[1], c->d_face[0], c->d_face[1], c->d_idx[0], c->d_idx[1], c->d_gen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1335,6 +1337,104 @@ mc_lya_status mc_lya_scatter(mc_lya_ctx *c, uint64_t first, uint64_t count, cons
     if (st != MC_LYA_OK) return st;
     account_walked(c, first, count);
     return MC_LYA_OK;
+}
+
+// Moves every box to redshift z with T = T_cmb0 (1 + z): the physical
+// scalars, the packed opacity unit and the descriptors (the next refresh
+// re-packs the fields with them).
+mc_lya_status set_epoch(mc_lya_ctx *c, double z)
+{
+    for (int b = 0; b < c->n_boxes; ++b) {
+        mc_lya_box_desc &d = c->desc[b];
+        d.z = z;
+        d.temp_K = d.t_cmb0 * (1.0 + z);
+        c->ph[b] = phys::scalars(d);
+        c->pack[b].kappa_unit = c->ph[b].kappa_unit;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_pack, c->pack.data(), sizeof(PackBox) * c->n_boxes, hipMemcpyHostToDevice,
+                              c->stream));
+    drop_graph(c);
+    ++c->epoch;
+    return MC_LYA_OK;
+}
+
+// Global X_e = sum(x_e Delta) / sum(Delta) of every box from the fields.
+mc_lya_status global_xe(mc_lya_ctx *c, double *X)
+{
+    const int nb = c->n_boxes;
+    HIP_TRY(c, launch_feed_sums(c->d_pack, nb, c->max_blk, c->d_wgt, c->d_part, c->stream));
+    HIP_TRY(c, launch_feed_reduce(nb, c->max_blk, c->d_pack, c->d_part, c->d_fsum, c->stream));
+    std::vector<double> sums((size_t)4 * nb);
+    HIP_TRY(c, hipMemcpyAsync(sums.data(), c->d_fsum, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nb; ++b) X[b] = sums[4 * b + 3] > 0.0 ? sums[4 * b + 2] / sums[4 * b + 3] : 0.0;
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_evolve(mc_lya_ctx *c, double z0, double z1, int32_t n_steps, const uint64_t *n_packets,
+                            uint64_t seed, float *const *x_e, double *X_out)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 0) return fail(c, MC_LYA_ESTATE, "fields failed validation; call mc_lya_refresh");
+    if (!(n_steps > 0)) return fail(c, MC_LYA_EINVAL, "n_steps must be > 0");
+    if (!(std::isfinite(z0) && std::isfinite(z1) && z0 > z1 && z1 > 0.0))
+        return fail(c, MC_LYA_EINVAL, "need finite z0 > z1 > 0");
+    if (!n_packets || !x_e) return fail(c, MC_LYA_EINVAL, "n_packets and x_e must not be NULL");
+    const int nb = c->n_boxes;
+    for (int b = 0; b < nb; ++b)
+        if (!x_e[b] || x_e[b] != c->desc[b].x_e)
+            return fail(c, MC_LYA_EINVAL, "box " + std::to_string(b) + ": x_e must be its descriptor's x_e field");
+    const size_t n = c->total_cells;
+    if (!c->d_ev) {
+        hipError_t e = dalloc(&c->d_ev, 6 * n);
+        if (e == hipSuccess) e = dalloc(&c->d_ev_coef, (size_t)nb);
+        if (e != hipSuccess) return hip_fail(c, e, "evolution buffers");
+    }
+    double *y0 = c->d_ev, *ndot = c->d_ev + 5 * n;
+    double *k[4] = {c->d_ev + n, c->d_ev + 2 * n, c->d_ev + 3 * n, c->d_ev + 4 * n};
+    HIP_TRY(c, launch_xe_load(c->d_pack, nb, c->max_blk, y0, c->stream));
+    if (X_out) {
+        mc_lya_status st = global_xe(c, X_out);
+        if (st != MC_LYA_OK) return st;
+    }
+    const double h = (z1 - z0) / n_steps;
+    const double cz[4] = {0.0, 0.5, 0.5, 1.0};            // stage redshift offsets
+    std::vector<uint64_t> seeds(nb);
+    std::vector<double> coef(nb);
+    for (int32_t i = 0; i < n_steps; ++i) {
+        const double z = z0 + i * h;
+        for (int s = 0; s < 4; ++s) {
+            if (s > 0) {                                  // the stage's x_e: y0 + c_s h k_{s-1}
+                const double w = cz[s] * h;
+                const double *kk[1] = {k[s - 1]};
+                HIP_TRY(c, launch_xe_combine(c->d_pack, nb, c->max_blk, y0, kk, &w, 1, nullptr, true, c->stream));
+            }
+            const double zs = z + cz[s] * h;
+            mc_lya_status st = set_epoch(c, zs);
+            if (st == MC_LYA_OK) st = do_refresh(c);
+            for (int b = 0; b < nb; ++b) seeds[b] = seed + (((uint64_t)(4 * (uint64_t)i + s)) << 20) + (uint64_t)b;
+            if (st == MC_LYA_OK) st = mc_lya_emit(c, seeds.data(), n_packets);
+            if (st == MC_LYA_OK) st = launch_walk(c, 0, c->total_packets);
+            if (st == MC_LYA_OK) st = mc_lya_feed(c, ndot, nullptr, nullptr);
+            if (st != MC_LYA_OK) return st;
+            for (int b = 0; b < nb; ++b) coef[b] = -1.0 / (c->ph[b].nH * (1.0 + zs) * c->ph[b].H);
+            HIP_TRY(c, hipMemcpyAsync(c->d_ev_coef, coef.data(), sizeof(double) * nb, hipMemcpyHostToDevice,
+                                      c->stream));
+            HIP_TRY(c, launch_xe_rate(c->d_pack, nb, c->max_blk, c->d_ev_coef, ndot, k[s], c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));   // coef is reused by the next stage
+        }
+        const double w[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0};
+        const double *kk[4] = {k[0], k[1], k[2], k[3]};
+        HIP_TRY(c, launch_xe_combine(c->d_pack, nb, c->max_blk, y0, kk, w, 4, y0, true, c->stream));
+        if (X_out) {
+            mc_lya_status st = global_xe(c, X_out + (size_t)(i + 1) * nb);
+            if (st != MC_LYA_OK) return st;
+        }
+    }
+    // leave the context at z1, re-packed from the final fields
+    mc_lya_status st = set_epoch(c, z1);
+    if (st == MC_LYA_OK) st = do_refresh(c);
+    return st;
 }
 
 mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)

@@ -185,6 +185,14 @@ struct ScatterParams {
 };
 hipError_t launch_scatter(const ScatterParams &p, int block, int grid, hipStream_t s);
 
+// ---- recombination history ---------------------------------------------------
+hipError_t launch_xe_load(const PackBox *pb_dev, int n_boxes, int max_blk, double *y, hipStream_t s);
+hipError_t launch_xe_rate(const PackBox *pb_dev, int n_boxes, int max_blk, const double *coef, const double *ndot,
+                          double *k, hipStream_t s);
+hipError_t launch_xe_combine(const PackBox *pb_dev, int n_boxes, int max_blk, const double *y0,
+                             const double *const *k, const double *w, int nk, double *y_out, bool field,
+                             hipStream_t s);
+
 // ---- tile-decomposed walk -------------------------------------------------
 // Tile extent in cells along x, y, z (the last tiles along an axis may be
 // thinner) and the workgroup that walks one tile.

@@ -72,6 +72,7 @@ class Simulation:
         self.device = torch.device(device)
         self._keep = []
         descs = [desc_from_spec(s, self._keep, self.device) for s in self.specs]
+        self._descs = descs
         self.ncells = [s.ncells for s in self.specs]
         self.total_cells = int(sum(self.ncells))
         self.cell_off = np.concatenate([[0], np.cumsum(self.ncells)]).astype(np.int64)
@@ -139,6 +140,30 @@ class Simulation:
             torch.cuda.synchronize(self.device)
             return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=SCATTER_DTYPE)[:count]
         return None
+
+    def x_e_field(self, b=0):
+        """The device x_e array of box b (the one its descriptor points to)."""
+        ptr = self._descs[b].x_e
+        for t in self._keep:
+            if t.data_ptr() == ptr:
+                return t
+        raise ValueError(f"box {b} has no x_e field")
+
+    def evolve(self, z0, z1, n_steps, n_packets=None, seed=1):
+        """Recombination history driven by the Monte Carlo: every cell's x_e
+        from z0 to z1 by fourth-order Runge-Kutta in z, each stage a whole
+        emit - transport - feed. Every box needs an x_e field; the fields are
+        updated in place. Returns the global X_e of each box after each step,
+        numpy [n_steps + 1, n_boxes]."""
+        n_packets = [s.n_packets for s in self.specs] if n_packets is None else list(n_packets)
+        ptrs = [self._descs[b].x_e for b in range(len(self.specs))]
+        for b, p in enumerate(ptrs):
+            if not p:
+                raise ValueError(f"box {b} has no x_e field (give the spec an x_e array)")
+        X = np.zeros((int(n_steps) + 1, len(self.specs)))
+        A.mc_lya_evolve(self.ctx, z0, z1, n_steps, n_packets, seed, ptrs, X)
+        self.n_packets = [0] * len(self.specs)
+        return X
 
     def set_option(self, option, value):
         A.mc_lya_set_option(self.ctx, option, value)
