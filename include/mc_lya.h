@@ -293,7 +293,8 @@ mc_lya_status mc_lya_feed(mc_lya_ctx *ctx, double *ndot_e, float *mix_corr,
 typedef struct mc_lya_scatter_opts {
     double x_inert;               /* > 0; 0 selects 300 (well past x_50 ~ 60 of App. A) */
     double p_destroy;             /* destruction probability per scattering; < 0 selects each
-                                     box's p_ab (test problems raise it to shorten histories) */
+                                     box's p_ab (test problems raise it to shorten histories;
+                                     0 never destroys) */
     uint64_t max_events;          /* scatterings before a photon is stopped as capped;
                                      0 selects 2^32 - 1 */
     int32_t fixed_x0;             /* 1: every photon is injected at x0 (App. A step 1 injects at
@@ -317,7 +318,8 @@ typedef struct mc_lya_scatter_record {
 /* Scatters photons [first, first + count) of the current emission into the
  * tallies (as mc_lya_transport_range does for the walk; disjoint ranges add
  * up to the whole).
- *   opts     host, or NULL for the defaults
+ *   opts     host, or NULL for the defaults (x_inert 300, each box's p_ab, 2^32 - 1 events,
+ *            the emission's frequencies, no return test)
  *   records  dev [count], or NULL
  * Asynchronous on the context's stream. Errors: EINVAL (range, options),
  * ESTATE, ENOMEM, EDEVICE. */

@@ -1274,6 +1274,7 @@ mc_lya_status mc_lya_scatter(mc_lya_ctx *c, uint64_t first, uint64_t count, cons
     if (first > c->total_packets || count > c->total_packets - first)
         return fail(c, MC_LYA_EINVAL, "packet range outside the emitted packets");
     mc_lya_scatter_opts o{};
+    o.p_destroy = -1.0;                                   // NULL options: each box's p_ab
     if (opts) o = *opts;
     if (o.x_inert == 0.0) o.x_inert = 300.0;
     if (!(o.x_inert > 0.0) || !std::isfinite(o.x_inert)) return fail(c, MC_LYA_EINVAL, "x_inert must be > 0");

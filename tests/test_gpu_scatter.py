@@ -149,3 +149,50 @@ def test_scatter_clumpy_box_with_flow():
     assert mismatch <= 2 * parted + 1e-12
     assert parted < 0.1
     assert abs(st.escaped - ref["escaped"]) <= 2 * parted * w0 * spec.n_packets + 1
+
+
+def test_scatter_batch_equals_boxes_alone():
+    """Two boxes in one context (the multi-box kernel) give, box by box, the
+    same tallies, totals and histories as each box scattered alone (a
+    photon's random numbers depend on its box's seed and its id in the box)."""
+    a = W.make_box("c2", n=12, n_packets=3000, profile="voigt", zeta=1e3, field_seed=8, seed=11)
+    b = homog_box(zeta=1e5, profile="doppler", n_packets=2000, seed=12, n=6)
+    alone = []
+    for spec in (a, b):
+        with M.Simulation(spec) as sim:
+            sim.emit()
+            rec = sim.scatter(p_destroy=2e-4, records=True)
+            t = sim.tally()
+            alone.append((t["absorbed"].cpu().numpy(), t["stats"][0], rec))
+    with M.Simulation([a, b]) as sim:
+        sim.emit()
+        rec = sim.scatter(p_destroy=2e-4, records=True)
+        t = sim.tally()
+        A = t["absorbed"].cpu().numpy()
+        off = sim.cell_off
+    for i, (A1, st1, rec1) in enumerate(alone):
+        st = t["stats"][i]
+        assert np.array_equal(A[off[i]:off[i + 1]], A1), i
+        assert (st.escaped, st.wing, st.scatterings, st.crossings) == (st1.escaped, st1.wing, st1.scatterings,
+                                                                       st1.crossings), i
+        assert st.conserved == 1
+    n0 = a.n_packets
+    for f in ("fate", "scatterings", "crossings", "x_end"):
+        assert np.array_equal(rec[f][:n0], alone[0][2][f]) and np.array_equal(rec[f][n0:], alone[1][2][f]), f
+
+
+def test_scatter_default_options_use_p_ab():
+    """NULL options: each box's own p_ab, the same as asking for it."""
+    spec = homog_box(zeta=1e5, n_packets=20000, seed=3)
+    out = []
+    for opts in (None, -1.0):
+        with M.Simulation(spec) as sim:
+            sim.emit()
+            if opts is None:
+                M.mc_lya_scatter(sim.ctx, 0, spec.n_packets)
+            else:
+                sim.scatter(p_destroy=opts)
+            t = sim.tally()
+            out.append((t["absorbed"].cpu().numpy(), t["stats"][0].escaped, t["stats"][0].scatterings))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+    assert out[0][0].sum() > 0                       # some photons are destroyed
