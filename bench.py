@@ -414,6 +414,7 @@ def main():
         "config": {"workload": workload_name(a.config, specs), "cells": sum(x.ncells for x in specs),
                    "packets": sum(npk), "graph": graph, "autotuned": tuned,
                    "crossings_per_step": cross_per_step,
+                   "packets_per_s": sum(npk) * a.steps / dt,
                    "walk_ms": walk_s * 1e3,
                    "walk_launches_per_step": launches / a.steps,
                    "walk_launch_avg_us": kms * 1e3 / max(1, launches),
