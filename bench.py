@@ -110,7 +110,7 @@ def summarize_counters(a):
             raise SystemExit(f"no walk rows in {path}")
         per[name] = scale[name] * sum(vals) / n
         launches[name] = n
-    out = {"config": a.config, "kernel": " + ".join(WALK_LAUNCH_KERNELS), "launches": launches,
+    out = {"config": a.config, "profile": a.profile, "kernel": " + ".join(WALK_LAUNCH_KERNELS), "launches": launches,
            "fetch_scale": scale["fetch"], "write_scale": scale["write"],
            "fetch_bytes_per_launch": per["fetch"], "write_bytes_per_launch": per["write"],
            "bytes_per_launch": per["fetch"] + per["write"], "source_sha256": walk_source_hash()}
@@ -396,7 +396,8 @@ def main():
     if os.path.exists(a.traffic):
         with open(a.traffic) as fh:
             tr = json.load(fh)
-        if tr.get("config") == a.config and tr.get("source_sha256") == walk_source_hash():
+        if (tr.get("config") == a.config and tr.get("profile", "doppler") == a.profile
+                and tr.get("source_sha256") == walk_source_hash()):
             traffic = tr.get("bytes_per_launch")
     out = {
         "metric": "photon cell-crossings/s",
