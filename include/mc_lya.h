@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MC_LYA_ABI_VERSION 2
+#define MC_LYA_ABI_VERSION 3
 
 typedef struct mc_lya_ctx mc_lya_ctx;
 
@@ -305,7 +305,7 @@ typedef struct mc_lya_scatter_opts {
                                      tallies are then not conserved. 0: off */
 } mc_lya_scatter_opts;
 
-/* One photon's history from mc_lya_scatter (56 bytes). */
+/* One photon's history from mc_lya_scatter (72 bytes). */
 typedef struct mc_lya_scatter_record {
     uint32_t cell0, cell_end;     /* global emission cell; cell of the last event */
     float x0, x_end;              /* injection frequency; frequency at the end (-x_inert if lost) */
@@ -313,6 +313,12 @@ typedef struct mc_lya_scatter_record {
     uint32_t crossings;
     int32_t fate;                 /* 0 destroyed, 1 lost to the line, 2 capped, 3 returned */
     int64_t escaped, absorbed, wing;
+    float dx, dy, dz;             /* displacement from the emission point to the last event
+                                     (the destruction point of a destroyed photon), in cell
+                                     widths along x, y, z, unwrapped over the periodic box:
+                                     the distance a photon travels between creation and
+                                     destruction (Fig. MCtravel) */
+    int32_t reserved;
 } mc_lya_scatter_record;
 
 /* Scatters photons [first, first + count) of the current emission into the

@@ -461,6 +461,8 @@ typedef struct {
     double x0, x_end;
     int64_t scatterings, crossings;
     int64_t escaped, absorbed, wing;
+    double d[3];         /* displacement from the emission point to the last event, in cell
+                            widths, unwrapped over the periodic box */
     int32_t fate;        /* 0 destroyed, 1 lost to the line, 2 capped, 3 returned (test hook) */
     int32_t pad;
 } orc_scatter_rec;
@@ -613,6 +615,7 @@ static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, cons
     int fate = 2;
     double x_stop = 0.0;
     int64_t c = cell0;
+    int64_t moved[3] = {0, 0, 0};                             /* net face crossings per axis */
     rec->cell0 = cell0;
     rec->x0 = x;
     for (;;) {
@@ -640,7 +643,14 @@ static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, cons
             const double slim = inert ? (x + sp->x_inert) / b->delta : sf;
             const double dtau = kap * orc_swept(b, x, inert ? x + sp->x_inert : b->delta * sf);
             if (dtau < tau) {
-                if (inert) { lost = 1; break; }
+                if (inert) {                                  /* lost where x reaches -x_inert */
+                    for (int a = 0; a < 3; ++a) {
+                        const double g = f[a] + k[a] * slim;
+                        f[a] = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
+                    }
+                    lost = 1;
+                    break;
+                }
                 tau -= dtau;
                 for (int a = 0; a < 3; ++a) {
                     if (a == axis) continue;
@@ -648,8 +658,8 @@ static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, cons
                     f[a] = g < 0.0 ? 0.0 : (g > 1.0 ? 1.0 : g);
                 }
                 const int64_t old = c;
-                if (k[axis] > 0.0) { f[axis] = 0.0; ci[axis] = orc_wrap(ci[axis] + 1, n[axis]); }
-                else { f[axis] = 1.0; ci[axis] = orc_wrap(ci[axis] - 1, n[axis]); }
+                if (k[axis] > 0.0) { f[axis] = 0.0; ci[axis] = orc_wrap(ci[axis] + 1, n[axis]); ++moved[axis]; }
+                else { f[axis] = 1.0; ci[axis] = orc_wrap(ci[axis] - 1, n[axis]); --moved[axis]; }
                 x = xf;
                 ++ncross;
                 if (b->has_vel) {
@@ -686,6 +696,7 @@ static void orc_scatter_one(const orc_box *b, const orc_scatter_params *sp, cons
     rec->escaped = (fate == 1 || fate == 2) ? w : 0;
     rec->absorbed = fate == 0 ? w : 0;
     rec->wing = wing;
+    for (int a = 0; a < 3; ++a) rec->d[a] = (double)moved[a] + f[a] - u[a];
     rec->fate = fate;
     rec->pad = 0;
 }

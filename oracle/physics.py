@@ -179,6 +179,22 @@ def escape_homogeneous(tau, X):
     return px + (-math.expm1(-tau * (1.0 - px))) / tau
 
 
+def escape_uniform_gradient(tau, g, X):
+    """Escaped fraction in a homogeneous medium whose bulk flow along one axis
+    has the uniform gradient dv_x/dx = g H (g > -1): along a direction at
+    cosine mu to that axis a packet's gas-frame frequency drifts (1 + g mu^2)
+    times as fast as by the expansion alone, so its depth per unit of swept
+    profile is tau / (1 + g mu^2). The static closed form averaged over the
+    isotropic directions; g = 0 is that closed form, and for tau >> 1 the
+    result is (1 + g/3) / tau: H -> H + div v / 3 (Fig. MCescape caption)."""
+    if not g > -1.0:
+        raise ValueError("a converging flow with g <= -1 traps packets along the flow axis")
+    from scipy import integrate
+    f = lambda mu: escape_homogeneous(tau / (1.0 + g * mu * mu), X)
+    val, _ = integrate.quad(f, 0.0, 1.0, epsabs=0.0, epsrel=1e-13, limit=200)
+    return val
+
+
 def sobolev_p_esc(H, n1s):
     """P_esc = 8 pi H / (3 lambda^3 n_1s A) (Sec. III.A.1)."""
     return 8.0 * math.pi * H / (3.0 * LAMBDA_ALPHA ** 3 * n1s * A_2P1S)

@@ -31,7 +31,8 @@ class OrcScatterParams(C.Structure):
 SCATTER_REC_DTYPE = np.dtype([("cell0", np.int64), ("cell_end", np.int64), ("x0", np.float64),
                               ("x_end", np.float64), ("scatterings", np.int64),
                               ("crossings", np.int64), ("escaped", np.int64), ("absorbed", np.int64),
-                              ("wing", np.int64), ("fate", np.int32), ("pad", np.int32)])
+                              ("wing", np.int64), ("dx", np.float64), ("dy", np.float64),
+                              ("dz", np.float64), ("fate", np.int32), ("pad", np.int32)])
 
 
 REC_DTYPE = np.dtype([("cell0", np.int64), ("fx", np.float64), ("fy", np.float64),

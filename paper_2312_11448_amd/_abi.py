@@ -55,7 +55,8 @@ class mc_lya_scatter_opts(C.Structure):
 class mc_lya_scatter_record(C.Structure):
     _fields_ = [("cell0", C.c_uint32), ("cell_end", C.c_uint32), ("x0", C.c_float), ("x_end", C.c_float),
                 ("scatterings", C.c_uint64), ("crossings", C.c_uint32), ("fate", C.c_int32),
-                ("escaped", C.c_int64), ("absorbed", C.c_int64), ("wing", C.c_int64)]
+                ("escaped", C.c_int64), ("absorbed", C.c_int64), ("wing", C.c_int64),
+                ("dx", C.c_float), ("dy", C.c_float), ("dz", C.c_float), ("reserved", C.c_int32)]
 
 
 class mc_lya_feed_stats(C.Structure):

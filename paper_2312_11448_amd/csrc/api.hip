@@ -16,7 +16,7 @@ using namespace mclya;
 
 static_assert(sizeof(mc_lya_box_desc) == 152, "mc_lya_box_desc layout");
 static_assert(sizeof(mc_lya_box_stats) == 112, "mc_lya_box_stats layout");
-static_assert(sizeof(mc_lya_scatter_record) == 56, "mc_lya_scatter_record layout");
+static_assert(sizeof(mc_lya_scatter_record) == 72, "mc_lya_scatter_record layout");
 static_assert(sizeof(mc_lya_scatter_opts) == 40, "mc_lya_scatter_opts layout");
 static_assert(sizeof(mc_lya_feed_stats) == 56, "mc_lya_feed_stats layout");
 static_assert(sizeof(mc_lya_packet_trace) == 64, "mc_lya_packet_trace layout");

@@ -55,25 +55,35 @@ __device__ __forceinline__ float swept(float x, float dx, float damp)
 
 // Length s in (0, s_max] with kap * swept(x, delta s) = tau: Newton's method
 // inside a shrinking bracket (the swept mass grows with s), from the linear
-// estimate tau / (kap delta phi(x)). `found` is false when the depth over
-// the whole of (0, s_max] stays below tau (no root was bracketed).
+// estimate tau / (kap delta phi(x)). A Newton step that leaves the closed
+// bracket is replaced by its midpoint; one that lands on an end of it (a
+// step below binary32 resolution) ends the search, as does a residual of
+// exactly zero. Most flights take two to four steps; a flight from the wing
+// across the core (high zeta) takes up to about twenty, as the swept mass
+// turns from flat to steep there. `found` is false when the depth over the
+// whole of (0, s_max] stays below tau (no root was bracketed).
 __device__ __forceinline__ float flight_length(float kap, float delta, float damp, float x, float tau, float s_max,
                                                bool &found)
 {
     float lo = 0.0f, hi = s_max;
     float s = tau * __builtin_amdgcn_rcpf(kap * delta * line_density(x, damp));
     if (!(s > lo && s < hi)) s = 0.5f * (lo + hi);
+    bool root = false;
 #pragma unroll 1
-    for (int it = 0; it < 12; ++it) {
+    for (int it = 0; it < 32; ++it) {
         const float g = kap * swept(x, delta * s, damp) - tau;
+        if (g == 0.0f) {
+            root = true;
+            break;
+        }
         if (g > 0.0f) hi = s; else lo = s;
         float sn = s - g * __builtin_amdgcn_rcpf(kap * delta * line_density(x - delta * s, damp));
-        if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
+        if (!(sn >= lo && sn <= hi)) sn = 0.5f * (lo + hi);
         const bool done = fabsf(sn - s) <= 1e-6f * s;
         s = sn;
         if (done) break;
     }
-    found = hi < s_max;
+    found = root || hi < s_max;
     return s;
 }
 
@@ -139,6 +149,7 @@ struct Photon {
     float tau;                // optical depth left to the next scattering
     Rec r;                    // the cell's record
     uint32_t nscat, ncross;
+    int32_t mx, my, mz;       // net face crossings per axis (the unwrapped cell offset)
     uint64_t p;               // box-local photon id
     uint32_t cell0;
     float x0;
@@ -185,6 +196,7 @@ __device__ __forceinline__ void init_photon(Photon &P, const WalkBox &B, float a
     P.r = load_rec<VEL>(rec, gcell);
     P.nscat = 0;
     P.ncross = 0;
+    P.mx = P.my = P.mz = 0;
     P.p = p;
     P.need_event = true;
 }
@@ -258,6 +270,11 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
     const float dtau = kap * swept(P.x, dx, S.damp);
     if (dtau < P.tau) {
         if (inert) {
+            // lost where the frequency reaches -x_inert, inside this cell
+            const double sl = (double)((P.x + S.x_inert) / B.delta);
+            P.fx = fmin(fmax(P.fx + P.kx * sl, 0.0), 1.0);
+            P.fy = fmin(fmax(P.fy + P.ky * sl, 0.0), 1.0);
+            P.fz = fmin(fmax(P.fz + P.kz * sl, 0.0), 1.0);
             x_stop = -S.x_inert;
             return kSLost;
         }
@@ -270,14 +287,14 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
         P.fy = nfy;
         P.fz = nfz;
         if (bx) {
-            if (P.kx > 0.0) { P.fx = 0.0; P.ix = P.ix + 1 == B.nx ? 0 : P.ix + 1; }
-            else { P.fx = 1.0; P.ix = P.ix == 0 ? B.nx - 1 : P.ix - 1; }
+            if (P.kx > 0.0) { P.fx = 0.0; P.ix = P.ix + 1 == B.nx ? 0 : P.ix + 1; ++P.mx; }
+            else { P.fx = 1.0; P.ix = P.ix == 0 ? B.nx - 1 : P.ix - 1; --P.mx; }
         } else if (by) {
-            if (P.ky > 0.0) { P.fy = 0.0; P.iy = P.iy + 1 == B.ny ? 0 : P.iy + 1; }
-            else { P.fy = 1.0; P.iy = P.iy == 0 ? B.ny - 1 : P.iy - 1; }
+            if (P.ky > 0.0) { P.fy = 0.0; P.iy = P.iy + 1 == B.ny ? 0 : P.iy + 1; ++P.my; }
+            else { P.fy = 1.0; P.iy = P.iy == 0 ? B.ny - 1 : P.iy - 1; --P.my; }
         } else {
-            if (P.kz > 0.0) { P.fz = 0.0; P.iz = P.iz + 1 == B.nz ? 0 : P.iz + 1; }
-            else { P.fz = 1.0; P.iz = P.iz == 0 ? B.nz - 1 : P.iz - 1; }
+            if (P.kz > 0.0) { P.fz = 0.0; P.iz = P.iz + 1 == B.nz ? 0 : P.iz + 1; ++P.mz; }
+            else { P.fz = 1.0; P.iz = P.iz == 0 ? B.nz - 1 : P.iz - 1; --P.mz; }
         }
         P.c = B.cell_off + (uint32_t)P.ix + (uint32_t)B.nx * ((uint32_t)P.iy + (uint32_t)B.ny * (uint32_t)P.iz);
         const Rec nr = load_rec<VEL>(rec, P.c);
@@ -366,6 +383,13 @@ __device__ __forceinline__ void finish_photon(const Photon &P, const WalkBox &B,
         o.escaped = out ? (int64_t)B.w0 : 0;
         o.absorbed = st == kSDestroyed ? (int64_t)B.w0 : 0;
         o.wing = (int64_t)wing;
+        // the emission point's place in its cell: the emission's own Philox words
+        uint32_t wa[4] = {(uint32_t)P.p, (uint32_t)(P.p >> 32), 0u, 0u};
+        philox4x32_10(wa, (uint32_t)B.seed, (uint32_t)(B.seed >> 32));
+        o.dx = (float)((double)P.mx + P.fx - (double)u01(wa[0]));
+        o.dy = (float)((double)P.my + P.fy - (double)u01(wa[1]));
+        o.dz = (float)((double)P.mz + P.fz - (double)u01(wa[2]));
+        o.reserved = 0;
     }
 }
 

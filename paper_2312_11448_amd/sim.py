@@ -21,7 +21,8 @@ assert TRACE_DTYPE.itemsize == C.sizeof(A.mc_lya_packet_trace)
 SCATTER_DTYPE = np.dtype([("cell0", np.uint32), ("cell_end", np.uint32), ("x0", np.float32),
                           ("x_end", np.float32), ("scatterings", np.uint64), ("crossings", np.uint32),
                           ("fate", np.int32), ("escaped", np.int64), ("absorbed", np.int64),
-                          ("wing", np.int64)])
+                          ("wing", np.int64), ("dx", np.float32), ("dy", np.float32), ("dz", np.float32),
+                          ("reserved", np.int32)])
 assert SCATTER_DTYPE.itemsize == C.sizeof(A.mc_lya_scatter_record)
 
 

@@ -37,7 +37,7 @@ def test_struct_sizes_match_header_layout():
     M = _lib()
     assert C.sizeof(M.mc_lya_packet_trace) == 64
     assert C.sizeof(M.mc_lya_box_stats) == 112
-    assert C.sizeof(M.mc_lya_scatter_record) == 56
+    assert C.sizeof(M.mc_lya_scatter_record) == 72
     assert C.sizeof(M.mc_lya_scatter_opts) == 40
     assert C.sizeof(M.mc_lya_feed_stats) == 56
     assert C.sizeof(M.mc_lya_tune_result) == 88

@@ -62,6 +62,16 @@ def test_scatter_histories_match_oracle(profile):
     both = same & (rec["fate"] == 1)
     assert np.all(np.abs(rec["x_end"][both] - ref["x_end"][both]) <= 1e-3 * (1 + np.abs(ref["x_end"][both])))
     assert rec["scatterings"].sum() == t["stats"][0].scatterings
+    # the unwrapped displacement from emission to the last event: the counts
+    # above do not pin a photon's path (a destroyed photon's scattering count
+    # is set by its destruction words alone), so a trajectory that parted
+    # after a flipped rejection trial can still count as the same history
+    dg = np.stack([rec["dx"], rec["dy"], rec["dz"]], axis=1).astype(np.float64)
+    do = np.stack([ref["dx"], ref["dy"], ref["dz"]], axis=1)
+    scale = np.linalg.norm(do, axis=1)[:, None]
+    close = np.all(np.abs(dg - do) <= 1e-3 * scale + 1e-7, axis=1)         # 1e-7 cell: 0.01 pc
+    _say(f"  displacements within 1e-3: {close[same].mean():.4f} of the same histories")
+    assert close[same].mean() > 0.98
 
 
 @pytest.mark.parametrize("profile,ptau", [("doppler", 1.0), ("voigt", 10.0)])

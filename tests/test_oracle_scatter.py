@@ -162,3 +162,54 @@ def test_scatter_galilean_invariance():
     a, b = rest.scatter(p, p_destroy=2e-3), moving.scatter(p, p_destroy=2e-3)
     assert np.array_equal(a["A"], b["A"])
     assert (a["escaped"], a["scatterings"], a["crossings"]) == (b["escaped"], b["scatterings"], b["crossings"])
+
+
+def _custom(kappa, delta, n_packets, seed, n=4):
+    nc = n ** 3
+    return walker.Prepared.custom((n, n, n), np.full(nc, float(kappa)), np.ones(nc), n_packets, seed, delta, 6.0)
+
+
+def _disp(r):
+    return np.stack([r["dx"], r["dy"], r["dz"]], axis=1)
+
+
+def test_displacement_free_streaming():
+    """Without line opacity a photon streams straight until the expansion
+    redshifts it to -x_inert: its recorded displacement is (x0 + x_inert) /
+    delta cell widths along its emission direction, unwrapped across the ten
+    or so periodic wraps of a 4^3 box."""
+    prep = _custom(0.0, 0.5, 500, 3)
+    r = prep.scatter(1.0, x_inert=20.0, p_destroy=0.0, records=True)["records"]
+    assert np.all(r["fate"] == 1) and np.all(r["scatterings"] == 0)
+    d = _disp(r)
+    L = np.linalg.norm(d, axis=1)
+    assert np.allclose(L, (r["x0"] + 20.0) / 0.5, rtol=1e-12, atol=1e-9)
+    w = prep.records(np.arange(500))                      # the emission's directions
+    k = np.stack([w["kx"], w["ky"], w["kz"]], axis=1)
+    assert np.allclose(d, L[:, None] * k, atol=1e-9)
+
+
+@pytest.mark.parametrize("kap,delta", [(5.0, 0.1), (6e4, 192.0)])
+def test_displacement_first_flight(kap, delta):
+    """A photon destroyed at its first scattering has traveled the free path
+    s of kappa_sc (Phi(x0) - Phi(x0 - delta s)) = -ln u (Doppler profile,
+    static homogeneous medium), u from the first word of its event block
+    (p, 0, 1): the root found here by bisection on erfc against the oracle's
+    Newton step, face walk and unwrapping. The second case is the line of
+    the zeta = 1e4 test problem, where flights from the wing cross the core."""
+    from scipy.optimize import brentq
+    seed = 4
+    prep = _custom(kap, delta, 400, seed)
+    r = prep.scatter(1.0, p_destroy=1.0 - 1e-9, records=True)["records"]
+    first = np.nonzero((r["fate"] == 0) & (r["scatterings"] == 1))[0]
+    assert first.size > 280                                # the rest escape on their first flight
+    L = np.linalg.norm(_disp(r), axis=1)
+    for p in first[:150]:
+        w = walker.philox4x32_10([int(p) & 0xFFFFFFFF, int(p) >> 32, 0, 1], [seed, 0])
+        tau = -math.log(((int(w[0]) >> 9) + 0.5) * 2.0 ** -23)
+        x0 = float(r["x0"][p])
+        f = lambda s: kap * (P.Phi(x0) - P.Phi(x0 - delta * s)) - tau
+        s = brentq(f, 0.0, (x0 + 40.0) / delta, xtol=1e-300, rtol=1e-13)
+        assert L[p] == pytest.approx(s, rel=1e-9, abs=1e-14)       # positions are O(1) doubles
+    if delta < 1.0:
+        assert L[first].max() > 4.0                        # some flights wrap the box

@@ -104,3 +104,24 @@ def batch_specs(n_boxes=64, packets_each=1_000_000, seed=1000, nmin=16, nmax=96)
                              temp_K=t0 * (1.0 + z), n_packets=packets_each, seed=b,
                              name=f"batch box {b}: {n}^3 z={z:.0f} rms={rms:.2f}"))
     return boxes
+
+
+def escape_slab(wavelength_cells, amplitude, cell_cm, n_packets, seed=1, ny=1, nz=1, **overrides):
+    """The flow test of Fig. MCescape on the grid: a homogeneous box one
+    wavelength long in x with the bulk flow U_x = amplitude sin(2 pi x / L)
+    (v_th units, cell-centred), packets emitted only in the two cells that
+    meet at x = 0, where the flow's gradient is largest: 2 pi amplitude / L
+    per cell. ``ny`` x ``nz`` cells across (the medium is uniform across, so
+    1 x 1 suffices)."""
+    nx = int(wavelength_cells)
+    od = np.ones((nz, ny, nx), dtype=np.float32)
+    vel = np.zeros((3, nz, ny, nx), dtype=np.float32)
+    vel[0] = F.sinusoidal_profile(nx, amplitude)[None, None, :]
+    src = np.zeros((nz, ny, nx), dtype=np.float32)
+    src[:, :, 0] = 1.0
+    src[:, :, nx - 1] = 1.0
+    box = BoxSpec(n=(nx, ny, nz), overdensity=od, velocity=vel, source=src, cell_cm=float(cell_cm),
+                  n_packets=int(n_packets), seed=int(seed),
+                  name=f"escape slab: {nx} cells of {cell_cm / KPC_CM * 1e3:.4g} pc, flow amplitude "
+                       f"{amplitude:.4g} v_th")
+    return replace(box, **overrides) if overrides else box

@@ -74,14 +74,19 @@ def uniform_box(n, value=1.0):
     return np.full((n, n, n), value, dtype=np.float32)
 
 
+def sinusoidal_profile(n, amplitude, periods=1):
+    """amplitude * sin(2 pi periods x / L) at the n cell centres, float64."""
+    x = (np.arange(n) + 0.5) / n
+    return amplitude * np.sin(2.0 * np.pi * periods * x)
+
+
 def sinusoidal_flow(n, amplitude, periods=1, axis=0):
     """Bulk flow v = amplitude * sin(2 pi periods x / L) along one axis.
 
     The flow family of the paper's escape test (Fig. MCescape caption), on the
     grid. Returns float32 [3,n,n,n] with only component ``axis`` non-zero.
     """
-    x = (np.arange(n) + 0.5) / n
-    prof = amplitude * np.sin(2.0 * np.pi * periods * x)
+    prof = sinusoidal_profile(n, amplitude, periods)
     v = np.zeros((3, n, n, n), dtype=np.float64)
     shape = [1, 1, 1]
     shape[2 - axis] = n
