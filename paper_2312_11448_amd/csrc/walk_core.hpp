@@ -146,22 +146,22 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
 }
 
 // Swept profile mass Phi(x) - Phi(x - dx) for dx > 0, Phi the cumulative
-// Doppler profile. Segments are short (dx = delta * length, a few hundredths
-// of a Doppler width for the paper's cells), so the integral of
-// exp(-y^2)/sqrt(pi) over the segment is taken by 3-point Gauss-Legendre
-// (relative error < 5e-8 for dx <= 0.05, < 3e-6 for dx <= 0.1); longer
+// Doppler profile. Segments are short (dx = delta * length, at most 0.033
+// Doppler widths for the paper's cells), so the integral of
+// exp(-y^2)/sqrt(pi) over the segment is taken by 2-point Gauss-Legendre:
+// relative error below 3e-7 for dx <= 0.033 and |x| <= 3 (1e-6 to |x| = 4),
+// below 5e-6 for dx <= 0.05 and |x| <= 4, against binary32's 6e-8. Longer
 // segments use the difference of complementary error functions, each taken
 // where it is small. Never negative.
 __device__ __forceinline__ float swept_profile(float x, float dx)
 {
-    if (dx <= 0.1f) {
+    if (dx <= 0.05f) {
         const float h = 0.5f * dx;
         const float m = x - h;
-        const float a = h * 0.7745966692414834f;          // sqrt(3/5)
-        const float y0 = m - a, y2 = m + a;
-        const float e0 = __expf(-y0 * y0), e1 = __expf(-m * m), e2 = __expf(-y2 * y2);
-        // (5 e0 + 8 e1 + 5 e2) / 9 * h / sqrt(pi)
-        return h * 0.06268937721449021f * (5.0f * (e0 + e2) + 8.0f * e1);
+        const float a = h * 0.5773502691896258f;          // 1 / sqrt(3)
+        const float y0 = m - a, y1 = m + a;
+        // (e0 + e1) h / sqrt(pi)
+        return h * 0.5641895835477563f * (__expf(-y0 * y0) + __expf(-y1 * y1));
     }
     const float lo = x - dx;
     const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(x)) : 0.5f * (erfcf(-x) - erfcf(-lo));
