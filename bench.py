@@ -79,6 +79,10 @@ def parse():
                          "of the benchmark, then of --calibrate-copy) into the walk's HBM bytes per launch, "
                          "written to --traffic")
     ap.add_argument("--calibration-mib", type=int, default=1024)
+    ap.add_argument("--summarize-valu", nargs=3, metavar=("CSV", "LOG", "OUT"),
+                    help="only turn a rocprofv3 counter_collection.csv with SQ_INSTS_VALU / SQ_INSTS_SALU of "
+                         "a benchmark run, and that run's JSON line (LOG), into wave instructions per crossing "
+                         "(walk) or per scattering (--config scatter), written to OUT")
     return ap.parse_args()
 
 
@@ -115,6 +119,39 @@ def summarize_counters(a):
            "fetch_bytes_per_launch": per["fetch"], "write_bytes_per_launch": per["write"],
            "bytes_per_launch": per["fetch"] + per["write"], "source_sha256": walk_source_hash()}
     with open(a.traffic, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out), flush=True)
+
+
+def summarize_valu(a):
+    """Vector and scalar wave instructions per unit of work of the dominant
+    kernel, from SQ_INSTS_VALU / SQ_INSTS_SALU summed over its dispatches of a
+    profiled benchmark run, divided by the work that run did (its warm-up
+    and timed steps, from its JSON line)."""
+    csv_path, log_path, out_path = a.summarize_valu
+    with open(log_path) as fh:
+        line = [json.loads(t) for t in fh if t.startswith("{")][-1]
+    runs = line["steps"] + line["warmup"]
+    scatter = line["metric"].startswith("resonant")
+    kernels = ("scatter_kernel",) if scatter else WALK_BYTE_KERNELS
+    units = runs * (line["config"]["scatterings_per_step"] if scatter else line["config"]["crossings_per_step"])
+    tot = {}
+    for name in ("SQ_INSTS_VALU", "SQ_INSTS_SALU"):
+        rows = [r for r in _counter_rows(csv_path, name) if any(k in r["Kernel_Name"] for k in kernels)]
+        if not rows:
+            raise SystemExit(f"no {name} rows of {kernels} in {csv_path}")
+        tot[name] = sum(float(r["Counter_Value"]) for r in rows)
+    unit = "scattering" if scatter else "crossing"
+    out = {"kernel": " + ".join(kernels), "workload": line["config"]["workload"], "unit": unit,
+           f"valu_wave_instr_per_{unit}": tot["SQ_INSTS_VALU"] / units,
+           f"salu_wave_instr_per_{unit}": tot["SQ_INSTS_SALU"] / units,
+           "source_sha256": scatter_source_hash() if scatter else walk_source_hash()}
+    if scatter:
+        out.update(photons=line["config"]["photons"], zeta=a.zeta)
+    else:
+        out.update(config=a.config, profile=a.profile)
+    with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps(out), flush=True)
@@ -332,6 +369,9 @@ def main():
     if a.summarize_counters:
         summarize_counters(a)
         return
+    if a.summarize_valu:
+        summarize_valu(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -399,6 +439,16 @@ def main():
         if (tr.get("config") == a.config and tr.get("profile", "doppler") == a.profile
                 and tr.get("source_sha256") == walk_source_hash()):
             traffic = tr.get("bytes_per_launch")
+    # the walk's issue rate: measured VALU instructions per crossing (rocprofv3
+    # SQ_INSTS_VALU over the same workload and sources) times this run's rate
+    valu = None
+    vpath = os.path.join(ROOT, "profiles", "walk_valu.json")
+    if os.path.exists(vpath):
+        with open(vpath) as fh:
+            pv = json.load(fh)
+        if (pv.get("config") == a.config and pv.get("profile") == a.profile
+                and pv.get("source_sha256") == walk_source_hash()):
+            valu = pv["valu_wave_instr_per_crossing"] * cross_per_step / walk_s / 1e9
     out = {
         "metric": "photon cell-crossings/s",
         "value": cross / dt,
@@ -424,6 +474,9 @@ def main():
                    "f_absorbed": f["stats"][0].f_absorbed, "c_mc": f["stats"][0].c_mc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline_valu": {"bound": "alu", "achieved": valu, "peak": VALU_PEAK_GINSTR,
+                          "unit": "G wave-instr/s (VALU issue)",
+                          "frac": None if valu is None else valu / VALU_PEAK_GINSTR},
     }
     sim.close()
     if not a.no_cpu_baseline:

@@ -55,18 +55,22 @@ __device__ __forceinline__ float swept(float x, float dx, float damp)
 
 // Length s in (0, s_max] with kap * swept(x, delta s) = tau: Newton's method
 // inside a shrinking bracket (the swept mass grows with s), from the linear
-// estimate tau / (kap delta phi(x)). A Newton step that leaves the closed
+// estimate s_lin = tau / (kap delta phi(x)). A Newton step that leaves the closed
 // bracket is replaced by its midpoint; one that lands on an end of it (a
 // step below binary32 resolution) ends the search, as does a residual of
-// exactly zero. Most flights take two to four steps; a flight from the wing
-// across the core (high zeta) takes up to about twenty, as the swept mass
-// turns from flat to steep there. `found` is false when the depth over the
-// whole of (0, s_max] stays below tau (no root was bracketed).
-__device__ __forceinline__ float flight_length(float kap, float delta, float damp, float x, float tau, float s_max,
-                                               bool &found)
+// exactly zero. Over a short segment (delta s <= 0.05) a step below 3e-4 of
+// s also ends it: the error after a Newton step is about |y| delta s times
+// the square of the step's relative size (y the frequency, for the Gaussian
+// core), below 1e-8 |y| there, so the search usually ends after one step.
+// A flight from the wing across the core (high zeta) takes up to about
+// twenty, as the swept mass turns from flat to steep there. `found` is false
+// when the depth over the whole of (0, s_max] stays below tau (no root was
+// bracketed).
+__device__ __forceinline__ float flight_length(float kap, float delta, float damp, float x, float tau, float s_lin,
+                                               float s_max, bool &found)
 {
     float lo = 0.0f, hi = s_max;
-    float s = tau * __builtin_amdgcn_rcpf(kap * delta * line_density(x, damp));
+    float s = s_lin;
     if (!(s > lo && s < hi)) s = 0.5f * (lo + hi);
     bool root = false;
 #pragma unroll 1
@@ -79,7 +83,8 @@ __device__ __forceinline__ float flight_length(float kap, float delta, float dam
         if (g > 0.0f) hi = s; else lo = s;
         float sn = s - g * __builtin_amdgcn_rcpf(kap * delta * line_density(x - delta * s, damp));
         if (!(sn >= lo && sn <= hi)) sn = 0.5f * (lo + hi);
-        const bool done = fabsf(sn - s) <= 1e-6f * s;
+        const float step = fabsf(sn - s);
+        const bool done = step <= 1e-6f * s || (step <= 3e-4f * s && delta * sn <= 0.05f);
         s = sn;
         if (done) break;
     }
@@ -244,16 +249,16 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
     // flight and the cell-independent bound on how much it can grow over
     // delta s <= 1e-3 (phi changes by under 1 %) decide it without the face
     // search, and the root is then sought in (0, r_safe].
+    const float s_lin = P.tau * __builtin_amdgcn_rcpf(kap * B.delta * line_density(P.x, S.damp));
     {
         const double rsafe = fmin(fmin(fmin(P.fx, 1.0 - P.fx), fmin(P.fy, 1.0 - P.fy)), fmin(P.fz, 1.0 - P.fz));
-        const float s_lin = P.tau * __builtin_amdgcn_rcpf(kap * B.delta * line_density(P.x, S.damp));
         if (B.delta * s_lin <= 1e-3f && 1.02f * s_lin < (float)rsafe && P.x - 2e-3f > -S.x_inert) {
             // over delta s < 1e-6 the density changes by about 1e-5 of itself
             // at most (|phi'/phi| = 2|x| in the thermal core, 2/|x| in the
             // damping wing): the linear estimate is the flight
             if (B.delta * s_lin < 1e-6f) return scatter_at<VEL>(P, B, S, A, SP, s_lin);
             bool found = false;
-            const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, (float)rsafe, found);
+            const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, s_lin, (float)rsafe, found);
             if (found) return scatter_at<VEL>(P, B, S, A, SP, s);
         }
     }
@@ -310,7 +315,7 @@ __device__ __forceinline__ int scatter_event(Photon &P, const WalkBox &B, const 
     // the scattering point inside this cell
     const float slim = inert ? (P.x + S.x_inert) / B.delta : (float)sf;
     bool found = false;
-    const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, slim, found);
+    const float s = flight_length(kap, B.delta, S.damp, P.x, P.tau, s_lin, slim, found);
     return scatter_at<VEL>(P, B, S, A, SP, s);
 }
 

@@ -1,0 +1,67 @@
+"""Host logic of the benchmark's counter summaries (CPU only): the HBM bytes
+per walk launch from FETCH_SIZE / WRITE_SIZE scaled by a copy's calibration,
+and the wave instructions per unit of work from SQ_INSTS_VALU / SQ_INSTS_SALU,
+on small hand-made counter files."""
+import csv
+import json
+import subprocess
+import sys
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _csv(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(("Kernel_Name", "Counter_Name", "Counter_Value"), r)))
+
+
+def _bench(*args):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                       cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_summarize_counters_scales_by_the_copy(tmp_path):
+    f, w, cf, cw = (str(tmp_path / n) for n in ("f.csv", "w.csv", "cf.csv", "cw.csv"))
+    # two walk launches (and a prefix kernel counted in the bytes only), 1000 and 3000 KiB fetched
+    _csv(f, [("tile_walk_kernel<true>", "FETCH_SIZE", 1000), ("tail_prefix_kernel", "FETCH_SIZE", 500),
+             ("tail_walk_kernel<true>", "FETCH_SIZE", 2500), ("pack_kernel", "FETCH_SIZE", 99999)])
+    _csv(w, [("tile_walk_kernel<true>", "WRITE_SIZE", 10), ("tail_walk_kernel<true>", "WRITE_SIZE", 30)])
+    # a 1 MiB copy whose fetch counter reads half of what it moves
+    _csv(cf, [("neg_kernel", "FETCH_SIZE", 512)])
+    _csv(cw, [("neg_kernel", "WRITE_SIZE", 1024)])
+    out = str(tmp_path / "traffic.json")
+    r = _bench("--summarize-counters", f, w, cf, cw, "--calibration-mib", "1", "--traffic", out)
+    assert r["fetch_scale"] == pytest.approx(2.0) and r["write_scale"] == pytest.approx(1.0)
+    assert r["fetch_bytes_per_launch"] == pytest.approx(2.0 * 4000 * 1024 / 2)
+    assert r["write_bytes_per_launch"] == pytest.approx(40 * 1024 / 2)
+    assert json.load(open(out))["bytes_per_launch"] == pytest.approx(r["bytes_per_launch"])
+
+
+def test_summarize_valu_divides_by_the_profiled_work(tmp_path):
+    c = str(tmp_path / "c.csv")
+    _csv(c, [("tile_walk_kernel<true>", "SQ_INSTS_VALU", 6e9), ("tail_walk_kernel", "SQ_INSTS_VALU", 3e9),
+             ("tile_walk_kernel<true>", "SQ_INSTS_SALU", 1e9), ("pack_kernel", "SQ_INSTS_VALU", 5e12)])
+    log = str(tmp_path / "b.log")
+    with open(log, "w") as fh:
+        fh.write("noise\n" + json.dumps({"metric": "photon cell-crossings/s", "steps": 2, "warmup": 1,
+                                         "config": {"workload": "w", "crossings_per_step": 1e8}}) + "\n")
+    out = str(tmp_path / "v.json")
+    r = _bench("--summarize-valu", c, log, out)
+    assert r["valu_wave_instr_per_crossing"] == pytest.approx(9e9 / 3e8)
+    assert r["salu_wave_instr_per_crossing"] == pytest.approx(1e9 / 3e8)
+    assert r["config"] == "c2" and r["profile"] == "doppler"
+    with open(log, "w") as fh:
+        fh.write(json.dumps({"metric": "resonant scatterings/s", "steps": 1, "warmup": 0,
+                             "config": {"workload": "s", "scatterings_per_step": 2e9, "photons": 64}}) + "\n")
+    _csv(c, [("scatter_kernel<false, true>", "SQ_INSTS_VALU", 1e11), ("scatter_kernel<false, true>",
+                                                                       "SQ_INSTS_SALU", 2e10)])
+    r = _bench("--summarize-valu", c, log, out)
+    assert r["valu_wave_instr_per_scattering"] == pytest.approx(50.0) and r["photons"] == 64
