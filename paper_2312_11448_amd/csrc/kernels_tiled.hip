@@ -69,6 +69,26 @@ struct TileSink {
     }
 };
 
+// L = take ? N : L, field by field (selects, not a branch).
+__device__ __forceinline__ void keep_or_take(Lane &L, const Lane &N, bool take)
+{
+    L.ix = take ? N.ix : L.ix;
+    L.iy = take ? N.iy : L.iy;
+    L.iz = take ? N.iz : L.iz;
+    L.c = take ? N.c : L.c;
+    L.tmx = take ? N.tmx : L.tmx;
+    L.tmy = take ? N.tmy : L.tmy;
+    L.tmz = take ? N.tmz : L.tmz;
+    L.t = take ? N.t : L.t;
+    L.x = take ? N.x : L.x;
+    L.kap = take ? N.kap : L.kap;
+    L.ux = take ? N.ux : L.ux;
+    L.uy = take ? N.uy : L.uy;
+    L.uz = take ? N.uz : L.uz;
+    L.w = take ? N.w : L.w;
+    L.ncross = take ? N.ncross : L.ncross;
+}
+
 __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -344,12 +364,11 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             idle = __ballot(!alive);
         }
         const uint64_t live = __ballot(alive);
-        if (!live) {
-            if (!more) {
-                flush_exits();
-                break;
-            }
-            continue;
+        // no live lane after the refill means the input is used up (a wave
+        // with idle lanes refills while there is input)
+        if (!live && !more) {
+            flush_exits();
+            break;
         }
         // (only after a step, so every deferred packet has moved in this generation)
         if (!more && !fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
@@ -363,21 +382,24 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             break;
         }
         fresh = false;
-        if (alive) {
+        {
+            // Every lane steps, by selects rather than branches: an idle lane's
+            // step deposits nothing and reads an in-tile record, and the idle
+            // lane keeps its state. Branches here made the compiler copy the
+            // lane state and the totals on every step.
             uint64_t dep = 0;
             uint32_t wing = 0;
-            const int fate = walk_step<VEL, VOIGT>(L, P.rec, sink, P.max_cross, dep, ln, wing);
-            if (fate == kExit) {
-                pending = true;
-                alive = false;
-            } else if (fate != kAlive) {
-                a_cross += L.ncross;
-                a_esc += fate == kEscaped ? L.w : 0;
-                a_capn += fate == kCapped ? 1 : 0;
-                a_capw += fate == kCapped ? L.w : 0;
-                if (VOIGT) a_wing += wing;
-                alive = false;
-            }
+            Lane Ln = L;
+            const int fate = walk_step<VEL, VOIGT>(Ln, P.rec, sink, P.max_cross, dep, ln, wing, alive);
+            keep_or_take(L, Ln, alive);
+            const bool fin = alive && fate != kAlive && fate != kExit;
+            a_cross += fin ? L.ncross : 0u;
+            a_esc += alive && fate == kEscaped ? L.w : 0u;
+            a_capn += alive && fate == kCapped ? 1u : 0u;
+            a_capw += alive && fate == kCapped ? L.w : 0u;
+            if (VOIGT) a_wing += fin ? wing : 0u;
+            pending = pending || (alive && fate == kExit);
+            alive = alive && fate == kAlive;
         }
     }
 

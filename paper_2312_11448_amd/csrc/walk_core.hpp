@@ -267,12 +267,12 @@ enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
 template <bool VEL, bool VOIGT, class Sink>
 __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, const Sink &sink,
                                          uint32_t max_cross, uint64_t &deposited, const Line &ln,
-                                         uint32_t &wing)
+                                         uint32_t &wing, bool act = true)
 {
     // redshifted out of the line (or, Voigt, emitted blue of the walked window)
     const bool gone = VOIGT ? (L.x <= -L.xeff) | (L.x > ln.xblue) : L.x <= -L.xeff;
     const bool capped = !gone && L.ncross >= max_cross;
-    const bool walk = !gone && !capped;
+    const bool walk = act && !gone && !capped;
 
     // next face (ties: x, then y, then z) and the neighbour behind it
     const bool bx = L.tmx <= L.tmy && L.tmx <= L.tmz;
