@@ -69,26 +69,6 @@ struct TileSink {
     }
 };
 
-// L = take ? N : L, field by field (selects, not a branch).
-__device__ __forceinline__ void keep_or_take(Lane &L, const Lane &N, bool take)
-{
-    L.ix = take ? N.ix : L.ix;
-    L.iy = take ? N.iy : L.iy;
-    L.iz = take ? N.iz : L.iz;
-    L.c = take ? N.c : L.c;
-    L.tmx = take ? N.tmx : L.tmx;
-    L.tmy = take ? N.tmy : L.tmy;
-    L.tmz = take ? N.tmz : L.tmz;
-    L.t = take ? N.t : L.t;
-    L.x = take ? N.x : L.x;
-    L.kap = take ? N.kap : L.kap;
-    L.ux = take ? N.ux : L.ux;
-    L.uy = take ? N.uy : L.uy;
-    L.uz = take ? N.uz : L.uz;
-    L.w = take ? N.w : L.w;
-    L.ncross = take ? N.ncross : L.ncross;
-}
-
 __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

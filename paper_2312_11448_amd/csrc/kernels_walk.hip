@@ -122,6 +122,7 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
     const uint32_t lane = lane_id();
     const uint32_t max_cross = (uint32_t)P.max_cross;
     Lane L;
+    idle_lane(L);
     Line ln{0.0f, 0.0f, 0.0f};
     Acc acc{-1, 0, 0, 0, 0, 0};
     bool alive = false;
@@ -178,18 +179,25 @@ __global__ __launch_bounds__(256) void walk_persistent_kernel(WalkParams P)
                 idle = __ballot(!alive);
             }
         }
-        if (!__ballot(alive)) {
-            if (!more) break;
-            continue;
-        }
-        if (alive) {
+        // no live lane after a refill means the queue is drained
+        if (!__ballot(alive) && !more) break;
+        {
+            // Every lane steps, by selects rather than branches (an idle lane
+            // holds its last packet's state, or idle_lane's: its step deposits
+            // nothing and reads a cell of its box), so that the lane state
+            // stays in the same registers across the loop.
             uint64_t dep = 0;
             uint32_t wing = 0;
-            const int fate = walk_step<VEL, VOIGT>(L, P.rec, GlobalSink{P.A}, max_cross, dep, ln, wing);
-            if (fate != kAlive) {
-                account(acc, L, fate, wing);
-                alive = false;
-            }
+            Lane Ln = L;
+            const int fate = walk_step<VEL, VOIGT>(Ln, P.rec, GlobalSink{P.A}, max_cross, dep, ln, wing, alive);
+            keep_or_take(L, Ln, alive);
+            const bool fin = alive && fate != kAlive;
+            acc.cross += fin ? L.ncross : 0u;
+            acc.esc += fin && fate == kEscaped ? L.w : 0u;
+            acc.capn += fin && fate == kCapped ? 1u : 0u;
+            acc.capw += fin && fate == kCapped ? L.w : 0u;
+            acc.wing += fin ? wing : 0u;
+            alive = alive && fate == kAlive;
         }
     }
     flush(acc, true, P.tot);

@@ -248,6 +248,48 @@ struct NullSink {
     }
 };
 
+// L = take ? N : L, field by field (selects, not a branch).
+__device__ __forceinline__ void keep_or_take(Lane &L, const Lane &N, bool take)
+{
+    L.ix = take ? N.ix : L.ix;
+    L.iy = take ? N.iy : L.iy;
+    L.iz = take ? N.iz : L.iz;
+    L.c = take ? N.c : L.c;
+    L.tmx = take ? N.tmx : L.tmx;
+    L.tmy = take ? N.tmy : L.tmy;
+    L.tmz = take ? N.tmz : L.tmz;
+    L.t = take ? N.t : L.t;
+    L.x = take ? N.x : L.x;
+    L.kap = take ? N.kap : L.kap;
+    L.ux = take ? N.ux : L.ux;
+    L.uy = take ? N.uy : L.uy;
+    L.uz = take ? N.uz : L.uz;
+    L.w = take ? N.w : L.w;
+    L.ncross = take ? N.ncross : L.ncross;
+}
+
+// A lane state on which a step is harmless: cell 0 of a 1-cell grid (the
+// first cell of the first box), no weight, far below any escape threshold.
+__device__ __forceinline__ void idle_lane(Lane &L)
+{
+    L.ix = L.iy = L.iz = 0;
+    L.nx = L.ny = L.nz = 1;
+    L.coff = 0u;
+    L.c = 0u;
+    L.tmx = L.tmy = L.tmz = 1.0;
+    L.tdx = L.tdy = L.tdz = 1.0;
+    L.t = 0.0;
+    L.kx = 1.0f;
+    L.ky = L.kz = 0.0f;
+    L.x = -3.0e38f;
+    L.kap = 0.0f;
+    L.ux = L.uy = L.uz = 0.0f;
+    L.w = 0u;
+    L.ncross = 0u;
+    L.delta = 1.0f;
+    L.xeff = 0.0f;
+}
+
 enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
 
 // One (packet, cell) segment. Returns kAlive, or the packet's fate, or kExit
