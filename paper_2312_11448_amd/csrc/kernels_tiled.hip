@@ -30,16 +30,28 @@ constexpr int BLK = kTileBlock;
 static_assert(TC % BLK == 0, "tile cells must be a multiple of the workgroup size");
 constexpr int kWaves = BLK / 64;
 
+// LDS slot of a tile cell: a 16 x 16 x kTileZ layout whatever the tile's
+// extent (a tile at a box edge may be smaller), so that the slot is a shift
+// and an or of the cell's offsets in the tile, not two multiplies.
+static_assert(kTileX == 16 && kTileY == 16, "tile slots assume 16 x 16 cells across");
+__device__ __forceinline__ int tile_slot(int32_t lx, int32_t ly, int32_t lz)
+{
+    return lx | (ly << 4) | (lz << 8);
+}
+
 // Deposits and opacity/velocity records of the cells of one tile, both in LDS.
+// The packets' global cell index is not kept up to date inside the tile
+// (kCell): the tiled walk sets it when a packet leaves.
 template <bool VEL>
 struct TileSink {
+    static constexpr bool kCell = false;
     unsigned long long *tally;
     const float4 *rec4;          // VEL: (kappa, U) per cell
     const float *reck;           // !VEL: kappa per cell
     int32_t ox, oy, oz, sx, sy, sz;
     __device__ __forceinline__ int local(int32_t ix, int32_t iy, int32_t iz) const
     {
-        return (ix - ox) + sx * ((iy - oy) + sy * (iz - oz));
+        return tile_slot(ix - ox, iy - oy, iz - oz);
     }
     __device__ __forceinline__ bool inside(int32_t jx, int32_t jy, int32_t jz) const
     {
@@ -251,13 +263,15 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
         return;
     }
-    for (int lc = tid; lc < ncell; lc += BLK) {
-        tally[lc] = 0ull;
-        const int lx = lc % ti.sx, ly = (lc / ti.sx) % ti.sy, lz = lc / (ti.sx * ti.sy);
-        const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
-                            (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
-        if (VEL) srec4[lc] = static_cast<const float4 *>(P.rec)[gc];
-        else sreck[lc] = static_cast<const float *>(P.rec)[gc];
+    for (int q = tid; q < TC; q += BLK) {
+        tally[q] = 0ull;
+        const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
+        if (lx < ti.sx && ly < ti.sy && lz < ti.sz) {
+            const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                                (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+            if (VEL) srec4[q] = static_cast<const float4 *>(P.rec)[gc];
+            else sreck[q] = static_cast<const float *>(P.rec)[gc];
+        }
     }
     if (tid == 0) {
         s_next = 0;
@@ -279,6 +293,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     auto flush_exits = [&]() {
         if (pending) {
             const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
+            L.c = cell_of(L);
             save_state(P.out_state[g], L);
             // the face it left through: the one coordinate now outside the tile
             uint32_t f;
@@ -355,6 +370,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             flush_exits();
             if (alive) {
                 const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
+                L.c = cell_of(L);
                 save_state(P.out_state[g], L);
                 P.out_face[g] = (uint8_t)kDeferred;
                 atomicAdd(&s_fcnt[kDeferred], 1u);
@@ -398,10 +414,10 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     }
     __threadfence_block();
     __syncthreads();
-    for (int lc = tid; lc < ncell; lc += BLK) {
-        const unsigned long long v = tally[lc];
+    for (int q = tid; q < TC; q += BLK) {
+        const unsigned long long v = tally[q];
         if (v) {
-            const int lx = lc % ti.sx, ly = (lc / ti.sx) % ti.sy, lz = lc / (ti.sx * ti.sy);
+            const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
             const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
                                 (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
             P.A[gc] += v;    // this workgroup alone owns these cells in this generation

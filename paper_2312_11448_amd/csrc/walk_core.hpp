@@ -220,8 +220,15 @@ __device__ __forceinline__ void finish_entry(Lane &L, const Rec &nr)
     L.kap = nr.kap;
 }
 
+// Global cell index of a lane's cell.
+__device__ __forceinline__ uint32_t cell_of(const Lane &L)
+{
+    return L.coff + (uint32_t)L.ix + (uint32_t)L.nx * ((uint32_t)L.iy + (uint32_t)L.ny * (uint32_t)L.iz);
+}
+
 // Deposits go straight to the per-cell int64 tallies in device memory.
 struct GlobalSink {
+    static constexpr bool kCell = true;   // keeps each lane's global cell index
     unsigned long long *A;
     __device__ __forceinline__ void deposit(const Lane &L, uint32_t d) const
     {
@@ -238,6 +245,7 @@ struct GlobalSink {
 
 // Histories only: nothing is tallied.
 struct NullSink {
+    static constexpr bool kCell = true;
     __device__ __forceinline__ void deposit(const Lane &, uint32_t) const {}
     __device__ __forceinline__ bool inside(int32_t, int32_t, int32_t) const { return true; }
     template <bool VEL>
@@ -335,7 +343,10 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     mi = mi == ni ? 0 : mi;
     mi = mi < 0 ? ni - 1 : mi;
     const int32_t jx = bx ? mi : L.ix, jy = by ? mi : L.iy, jz = bz ? mi : L.iz;
-    const uint32_t cn = L.coff + (uint32_t)jx + (uint32_t)L.nx * ((uint32_t)jy + (uint32_t)L.ny * (uint32_t)jz);
+    // the neighbour's global index, for sinks that address global memory by it
+    const uint32_t cn = Sink::kCell
+                            ? L.coff + (uint32_t)jx + (uint32_t)L.nx * ((uint32_t)jy + (uint32_t)L.ny * (uint32_t)jz)
+                            : 0u;
     const bool stay = sink.inside(jx, jy, jz);
     const Rec nr = sink.template fetch<VEL>(rec, cn, jx, jy, jz, stay);   // in flight during the profile arithmetic
 
@@ -372,7 +383,7 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     L.ix = jx;
     L.iy = jy;
     L.iz = jz;
-    L.c = cn;
+    if (Sink::kCell) L.c = cn;
     // entering a cell owned by the same region: the bulk term of Eq. (inout)
     // and the new cell's opacity; leaving it: keep the pre-jump frequency
     if (VEL) {
