@@ -69,8 +69,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "walk_traffic.json"),
-                    help="measured HBM bytes per launch of the walk kernel (rocprofv3 counters)")
+    ap.add_argument("--traffic", default=None,
+                    help="measured HBM bytes per launch of the walk kernel (rocprofv3 counters); default "
+                         "profiles/walk_traffic.json, or walk_traffic_voigt.json with --profile voigt")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy of MIB MiB (float32 negation, "
                          "reads and writes MIB MiB) five times, to scale byte counters")
@@ -78,12 +79,21 @@ def parse():
                     help="only turn four rocprofv3 counter_collection.csv files (FETCH_SIZE and WRITE_SIZE "
                          "of the benchmark, then of --calibrate-copy) into the walk's HBM bytes per launch, "
                          "written to --traffic")
+    ap.add_argument("--valu", default=None,
+                    help="measured VALU instructions per crossing of the walk (rocprofv3 counters); default "
+                         "profiles/walk_valu.json, or walk_valu_voigt.json with --profile voigt")
     ap.add_argument("--calibration-mib", type=int, default=1024)
     ap.add_argument("--summarize-valu", nargs=3, metavar=("CSV", "LOG", "OUT"),
                     help="only turn a rocprofv3 counter_collection.csv with SQ_INSTS_VALU / SQ_INSTS_SALU of "
                          "a benchmark run, and that run's JSON line (LOG), into wave instructions per crossing "
                          "(walk) or per scattering (--config scatter), written to OUT")
-    return ap.parse_args()
+    a = ap.parse_args()
+    suffix = "_voigt" if a.profile == "voigt" else ""
+    if a.traffic is None:
+        a.traffic = os.path.join(ROOT, "profiles", f"walk_traffic{suffix}.json")
+    if a.valu is None:
+        a.valu = os.path.join(ROOT, "profiles", f"walk_valu{suffix}.json")
+    return a
 
 
 def _counter_rows(path, counter):
@@ -442,9 +452,8 @@ def main():
     # the walk's issue rate: measured VALU instructions per crossing (rocprofv3
     # SQ_INSTS_VALU over the same workload and sources) times this run's rate
     valu = None
-    vpath = os.path.join(ROOT, "profiles", "walk_valu.json")
-    if os.path.exists(vpath):
-        with open(vpath) as fh:
+    if os.path.exists(a.valu):
+        with open(a.valu) as fh:
             pv = json.load(fh)
         if (pv.get("config") == a.config and pv.get("profile") == a.profile
                 and pv.get("source_sha256") == walk_source_hash()):
