@@ -284,6 +284,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     // ---- walk -------------------------------------------------------------
     const TileSink<VEL> sink{tally, srec4, sreck, ti.ox, ti.oy, ti.oz, ti.sx, ti.sy, ti.sz};
     Lane L;
+    idle_lane(L);               // every lane steps, so none starts undefined
     bool alive = false, more = true;
     bool fresh = false;          // wave-uniform: packets loaded since the wave's last step
     // A packet that leaves the tile parks in its lane (pending) and is written
