@@ -206,3 +206,26 @@ def test_scatter_default_options_use_p_ab():
             out.append((t["absorbed"].cpu().numpy(), t["stats"][0].escaped, t["stats"][0].scatterings))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
     assert out[0][0].sum() > 0                       # some photons are destroyed
+
+
+def test_scatter_errors():
+    """Invalid calls return an error status, leave the context usable, and
+    scatter nothing."""
+    spec = homog_box(zeta=1e5, n_packets=500, seed=2)
+    with M.Simulation(spec) as sim:
+        with pytest.raises(M.MCLyaError):
+            sim.scatter()                                       # before any emission
+        sim.emit()
+        bad = [dict(first=400, count=101), dict(x_inert=-1.0), dict(x_inert=float("inf")),
+               dict(p_destroy=1.5), dict(p_destroy=float("nan")), dict(max_events=1 << 33),
+               dict(x_return=-0.5), dict(x0=float("nan"))]
+        for kw in bad:
+            with pytest.raises(M.MCLyaError):
+                sim.scatter(**kw)
+        t = sim.tally()
+        assert t["stats"][0].scatterings == 0 and int(t["absorbed"].sum().item()) == 0
+        sim.scatter(0, 0)                                       # an empty range is fine
+        rec = sim.scatter(p_destroy=1.0, records=True)          # every photon destroyed at its first scattering
+        assert np.all((rec["fate"] == 0) | (rec["fate"] == 1))
+        assert np.all(rec["scatterings"][rec["fate"] == 0] == 1)
+        assert sim.tally()["stats"][0].conserved == 1
