@@ -50,7 +50,7 @@ def grf_k2(n, rms, kmax, seed, clip=(1e-2, 1e2), vel_rms=0.1):
     kmag = np.sqrt(k2)
     amp = np.where((kmag >= 1.0) & (kmag <= kmax), kmag, 0.0)   # sqrt(P) ~ k
     dk = wk * amp
-    delta = np.fft.irfftn(dk, s=(n, n, n))
+    delta = np.fft.irfftn(dk, s=(n, n, n), axes=(0, 1, 2))
     scale = rms / np.sqrt(np.mean(delta * delta))
     delta *= scale
     dk *= scale
@@ -62,7 +62,7 @@ def grf_k2(n, rms, kmax, seed, clip=(1e-2, 1e2), vel_rms=0.1):
         comps = []
         for kc in (kx, ky, kz):
             vk = 1j * np.broadcast_to(kc, dk.shape) * dk / safe
-            comps.append(np.fft.irfftn(vk, s=(n, n, n)))
+            comps.append(np.fft.irfftn(vk, s=(n, n, n), axes=(0, 1, 2)))
         v = np.stack(comps)
         v *= vel_rms / np.sqrt(np.mean(np.sum(v * v, axis=0)))
         vel = v.astype(np.float32)
