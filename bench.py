@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy of MIB MiB (float32 negation, "
                          "reads and writes MIB MiB) five times, to scale byte counters")
+    ap.add_argument("--probe-bandwidth", action="store_true",
+                    help="only measure the achievable streaming HBM bandwidth (a copy far larger than the caches)")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
                     help="only turn four rocprofv3 counter_collection.csv files (FETCH_SIZE and WRITE_SIZE "
                          "of the benchmark, then of --calibrate-copy) into the walk's HBM bytes per launch, "
@@ -177,6 +179,33 @@ def calibrate_copy(mib):
     torch.cuda.synchronize()
     print(json.dumps({"calibration": "neg", "bytes_read": n * 4, "bytes_written": n * 4,
                       "launches": 5}), flush=True)
+
+
+def probe_bandwidth():
+    """Achievable streaming HBM bandwidth: a float32 negation (one read, one
+    write per element) repeated over working sets well beyond the 256 MB
+    last-level cache, timed with events on the current stream. Prints one JSON
+    line per size (read + written bytes per second). (Cache-resident sizes
+    cannot be measured this way: one launch per pass, and a launch's few
+    microseconds of overhead exceed a cache-sized pass.)"""
+    import torch
+    for mib in (1024, 4096):
+        n = mib * (1 << 20) // 8           # two buffers of mib / 2 MiB each
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        reps = max(20, min(2000, (8 << 30) // (8 * n)))
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            torch.neg(src, out=dst)
+        t1.record()
+        t1.synchronize()
+        s = t0.elapsed_time(t1) / 1e3
+        print(json.dumps({"probe": "neg", "working_set_mib": mib, "reps": reps,
+                          "GB_per_s": 8.0 * n * reps / s / 1e9}), flush=True)
+        del src, dst
 
 
 def workload_name(config, specs):
@@ -375,6 +404,9 @@ def main():
     a = parse()
     if a.calibrate_copy:
         calibrate_copy(a.calibrate_copy)
+        return
+    if a.probe_bandwidth:
+        probe_bandwidth()
         return
     if a.summarize_counters:
         summarize_counters(a)
