@@ -18,6 +18,7 @@ import hashlib
 import dataclasses
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,12 +39,24 @@ WALK_LAUNCH_KERNELS = ("tile_walk_kernel", "tail_walk_kernel")
 WALK_BYTE_KERNELS = ("tile_walk_kernel", "tail_walk_kernel", "tail_prefix_kernel")
 
 
-def walk_source_hash():
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def source_hash(paths):
+    """SHA-256 of the code of the given sources, with comments and whitespace
+    runs removed: a stored counter figure stays valid across comment edits
+    and goes stale when the code changes. (The sources hold no string literal
+    with a comment marker.)"""
     h = hashlib.sha256()
-    for rel in WALK_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+    for rel in paths:
+        with open(os.path.join(ROOT, rel)) as fh:
+            code = _COMMENT.sub(" ", fh.read())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
+
+
+def walk_source_hash():
+    return source_hash(WALK_SOURCES)
 
 
 def parse():
@@ -258,11 +271,7 @@ SCATTER_SOURCES = ("paper_2312_11448_amd/csrc/kernels_scatter.hip", "paper_2312_
 
 
 def scatter_source_hash():
-    h = hashlib.sha256()
-    for rel in SCATTER_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    return source_hash(SCATTER_SOURCES)
 
 
 def bench_scatter(a):

@@ -314,6 +314,10 @@ enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
 // VOIGT: the Voigt profile of the box's Line; `wing` receives the far-wing
 // share of an escaping packet's weight (0 otherwise). The packet's own weight
 // L.w is left whole: the share is part of the escaped weight.
+//
+// act = false steps a lane that holds no packet (its state a finished
+// packet's, or idle_lane's): it deposits and counts nothing, and the caller
+// discards the state it leaves and the fate it returns.
 template <bool VEL, bool VOIGT, class Sink>
 __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, const Sink &sink,
                                          uint32_t max_cross, uint64_t &deposited, const Line &ln,
