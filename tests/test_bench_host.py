@@ -65,3 +65,14 @@ def test_summarize_valu_divides_by_the_profiled_work(tmp_path):
                                                                        "SQ_INSTS_SALU", 2e10)])
     r = _bench("--summarize-valu", c, log, out)
     assert r["valu_wave_instr_per_scattering"] == pytest.approx(50.0) and r["photons"] == 64
+
+
+def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    import bench
+    a, b, c = (tmp_path / n for n in ("a.hip", "b.hip", "c.hip"))
+    a.write_text("// header\nint f(int x) { return x + 1; }  /* done */\n")
+    b.write_text("int f(int x)\n{\n    return x + 1;   // one more\n}\n")
+    c.write_text("int f(int x) { return x + 2; }\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.source_hash(["a.hip"]) == bench.source_hash(["b.hip"])
+    assert bench.source_hash(["a.hip"]) != bench.source_hash(["c.hip"])
