@@ -35,7 +35,7 @@ import numpy as np
 
 from .sim import Simulation
 
-KPC_CM = 3.0856775814913673e21
+KPC_CM = 3.0856775814913673e21           # cm per comoving kpc
 
 
 def _stats(spec):
@@ -109,13 +109,14 @@ def global_loss(spec, echo=None):
     return rows
 
 
-def travel_box(z, x_e, n_photons, seed=1, cell_kpc=1.0, n=4, t_cmb0=2.7255):
+def travel_box(z, x_e, n_photons, seed=1, cell_kpc=1.0, n=4):
     """The medium of Fig. MCtravel: homogeneous hydrogen at the mean density,
     at rest in the Hubble flow, at redshift z with matter and radiation at
     T = T_cmb0 (1 + z), free-electron fraction x_e, the Voigt profile and the
     physical expansion rate (zeta = 1). The periodic box is n cells of
     ``cell_kpc`` comoving on a side; the displacements are unwrapped."""
     import workloads as W
+    t_cmb0 = W.CosmoParams().t_cmb0
     return W.BoxSpec(n=(n, n, n), overdensity=W.uniform_box(n), x_e_uniform=float(x_e), z=float(z),
                      temp_K=t_cmb0 * (1.0 + z), profile="voigt", zeta=1.0, cell_cm=cell_kpc * KPC_CM,
                      n_packets=int(n_photons), seed=int(seed),
