@@ -115,9 +115,12 @@ __device__ __forceinline__ float atom_upar(float x, float a, uint64_t seed, uint
         const float q = fmaxf(xa - 1.0f, 0.0f);
         u0 = fmaxf(xa - 0.02f - 0.1f * q * q, 0.0f);
     }
-    const float th0 = atanf((u0 - xa) / a);
-    const float m2 = expf(-u0 * u0) * (kHalfPi - th0);
-    const float m1 = wing ? 0.886226925452758f * erfcf(-u0) * a / ((xa - u0) * (xa - u0)) : th0 + kHalfPi;
+    // phi0: the Cauchy angle of the split measured from -pi/2, atan(a / (x - u0))
+    // (taken directly, not as atan((u0 - x) / a) + pi/2, which cancels in
+    // binary32 where the split sits far below resonance)
+    const float phi0 = atanf(a / (xa - u0));
+    const float m2 = expf(-u0 * u0) * (2.0f * kHalfPi - phi0);
+    const float m1 = wing ? 0.886226925452758f * erfcf(-u0) * a / ((xa - u0) * (xa - u0)) : phi0;
     const float p1 = m1 / (m1 + m2);
 #pragma unroll 1
     for (uint32_t j = 0; j < 4096u; ++j) {       // at worst ~14 trials are expected
@@ -131,12 +134,12 @@ __device__ __forceinline__ float atom_upar(float x, float a, uint64_t seed, uint
                 if (u > u0) continue;
                 acc = (xa - u0) * (xa - u0) / fmaf(xa - u, xa - u, a * a);
             } else {
-                const float th = fmaf(th0 + kHalfPi, r1, -kHalfPi);
-                u = fmaf(a, tanf(th), xa);
+                // angle psi = phi0 r1 above -pi/2: tan(psi - pi/2) = -1 / tan(psi)
+                u = xa - a / tanf(phi0 * r1);
                 acc = expf(-u * u);
             }
         } else {
-            const float th = fmaf(kHalfPi - th0, r1, th0);
+            const float th = fmaf(2.0f * kHalfPi - phi0, r1, phi0 - kHalfPi);
             u = fmaf(a, tanf(th), xa);
             acc = expf(u0 * u0 - u * u);
         }
