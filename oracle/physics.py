@@ -74,10 +74,23 @@ def n_h0(cosmo):
 
 
 # --- atomic rates (Sec. III.A.1) ---------------------------------------------
-def alpha_e(T):
-    """alpha_e = 1.14 x case-B coefficient (Pequignot et al. 1991 fit), cm^3/s."""
+# Case-B fit A_B(T) = 1e-13 a t^b / (1 + c t^d) cm^3/s, t = T / 1e4 K
+# (Pequignot, Petitjean & Boisson 1991, the fit RecFast uses; the paper cites
+# it without printing the coefficients). Module-level so that the pins can
+# plant a perturbed coefficient and see it caught.
+CASE_B_FIT = (4.309, -0.6166, 0.6703, 0.5300)
+
+
+def case_b(T):
+    """Case-B recombination coefficient of hydrogen from the fit, cm^3/s."""
+    a, b, c, d = CASE_B_FIT
     t = T / 1.0e4
-    return 1.14 * 1.0e-13 * 4.309 * t ** (-0.6166) / (1.0 + 0.6703 * t ** 0.5300)
+    return 1.0e-13 * a * t ** b / (1.0 + c * t ** d)
+
+
+def alpha_e(T):
+    """alpha_e = 1.14 x case-B coefficient (Sec. III.A.1), cm^3/s."""
+    return 1.14 * case_b(T)
 
 
 def beta_e(T):

@@ -67,10 +67,45 @@ def test_hydrogen_density():
     assert P.n_h0(COSMO) == pytest.approx(0.76 * nb * 1.67262e-24 / P.M_H, rel=1e-12)
 
 
+def _case_b_table():
+    rows = []
+    with open(os.path.join(GOLDEN, "case_b_recombination.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            T, a = line.split()[:2]
+            rows.append((float(T), float(a)))
+    return rows
+
+
+# the fit reproduces the tabulated coefficients to better than 1 %; the table
+# is printed to three figures
+CASE_B_REL = 0.01
+
+
+def _case_b_misses():
+    return [abs(P.alpha_e(T) / 1.14 - a) / a for T, a in _case_b_table()]
+
+
 def test_case_b_coefficient_textbook():
-    # case-B recombination coefficient of hydrogen at 1e4 K: 2.59e-13 cm^3/s
-    # (Osterbrock & Ferland, Table 2.1); alpha_e carries the 1.14 fudge factor
-    assert abs(P.alpha_e(1.0e4) / 1.14 - 2.59e-13) < 0.01 * 2.59e-13
+    """alpha_e / 1.14 against the textbook case-B coefficients at 5000, 10^4
+    and 2 x 10^4 K (tests/golden/case_b_recombination.txt): the amplitude and
+    both temperature exponents of the fit are pinned, and with them alpha_e,
+    beta_e, p_ab and kappa_c at the paper's 3000 K."""
+    misses = _case_b_misses()
+    assert max(misses) < CASE_B_REL, misses
+
+
+@pytest.mark.parametrize("which,delta", [(1, 0.05), (1, -0.05), (3, 0.05), (3, -0.05),
+                                         (2, 0.05), (2, -0.05), (0, 0.1)])
+def test_case_b_pin_catches_a_perturbed_coefficient(monkeypatch, which, delta):
+    """A fit coefficient mistyped by a few hundredths (the exponent b or d, the
+    denominator's c, the amplitude a) moves the fit off the table by more than
+    the tolerance at one of the three temperatures."""
+    fit = list(P.CASE_B_FIT)
+    fit[which] += delta
+    monkeypatch.setattr(P, "CASE_B_FIT", tuple(fit))
+    assert max(_case_b_misses()) > CASE_B_REL
 
 
 def test_detailed_balance_saha():
