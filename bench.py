@@ -4,8 +4,9 @@ One step is the full hot path over one batch of synthetic input already
 resident in HBM: pack the fields (kappa_c, velocity, emission weight),
 allocate the packets to cells, walk every packet (emission, drift, deposits,
 escape), finish the tallies (conservation check) and compute the
-recombination feed. Workload: the 128^3 k^2 Gaussian field with its
-curl-free flow at z = 1100, 1e7 packets.
+recombination feed. Workload: the 256^3 k^2 Gaussian field of rms contrast 2
+(clipped to 1e-2..1e2) with its curl-free flow at z = 1100, 2^28 packets (the
+largest single-box workload; --config c2 runs the 128^3 box with 1e7 packets).
 
 Prints one JSON line (rank 0). The dominant kernel's roofline uses the walk
 kernel's duration measured with HIP events on the library's stream and the
@@ -64,8 +65,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "batch", "surrogate", "scatter"],
-                    help="c2: the 128^3 workload (default); batch: 64 uneven boxes in one context; "
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "batch", "surrogate", "scatter"],
+                    help="c3: the 256^3 workload, 2^28 packets (default); c2: the 128^3 box, 1e7 packets; "
+                         "batch: 64 uneven boxes in one context; "
                          "surrogate: train the mixing-correction network on Monte-Carlo boxes, evaluate it "
                          "on held-out boxes and time its inference on the 256^3 box")
     ap.add_argument("--profile", default="doppler", choices=["doppler", "voigt"],

@@ -115,7 +115,9 @@ typedef struct mc_lya_box_stats {
     int64_t crossings;            /* (packet, cell) segments walked */
     int64_t packets;              /* packets emitted in the box */
     int32_t conserved;            /* 1 iff absorbed + escaped + capped_weight == emitted */
-    int32_t reserved;
+    int32_t tiled;                /* 1 if the last walk of the box's packets was the tile-decomposed
+                                     walk, 0 if the persistent or one-thread-per-packet walk (or the
+                                     scattering Monte Carlo) took them */
     double delta;                 /* red drift per cell width, Doppler units (App. A step 4) */
     double x_eff;                 /* escape threshold used (x_esc + velocity margin) */
     double tau_ab_mean;           /* <kappa_c>: mean optical depth to true absorption */

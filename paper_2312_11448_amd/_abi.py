@@ -42,7 +42,7 @@ class mc_lya_box_stats(C.Structure):
     _fields_ = [("emitted", C.c_int64), ("absorbed", C.c_int64), ("escaped", C.c_int64),
                 ("capped_weight", C.c_int64), ("capped_packets", C.c_int64),
                 ("crossings", C.c_int64), ("packets", C.c_int64), ("conserved", C.c_int32),
-                ("reserved", C.c_int32), ("delta", C.c_double), ("x_eff", C.c_double),
+                ("tiled", C.c_int32), ("delta", C.c_double), ("x_eff", C.c_double),
                 ("tau_ab_mean", C.c_double), ("damping", C.c_double), ("wing", C.c_int64),
                 ("scatterings", C.c_int64)]
 
@@ -329,3 +329,4 @@ def mc_lya_mlp_train_step(mlp, feat_ptr, t_ptr, w_ptr, n, lr, beta1=0.9, beta2=0
 def mc_lya_mlp_destroy(mlp):
     if mlp:
         load().mc_lya_mlp_destroy(mlp)
+

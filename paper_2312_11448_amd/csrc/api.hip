@@ -101,6 +101,7 @@ struct mc_lya_ctx {
     std::vector<WalkBox> walk;
     std::vector<BoxRed> red;
     std::vector<uint64_t> walked;     // packets walked per box since the last emit
+    std::vector<uint8_t> walked_tiled;  // per box: the last walk of its packets was the tiled walk
     uint64_t total_cells = 0;
     uint64_t total_packets = 0;
     int max_blk = 1;
@@ -757,12 +758,17 @@ mc_lya_status plan_walk(mc_lya_ctx *c, uint64_t first, uint64_t count, WalkPlan 
     return MC_LYA_OK;
 }
 
-void account_walked(mc_lya_ctx *c, uint64_t first, uint64_t count)
+// tiled: the walk that took the range was kernel 2 (per box, the tile table's
+// choice); false for the other walks and the scattering Monte Carlo
+void account_walked(mc_lya_ctx *c, uint64_t first, uint64_t count, bool tiled)
 {
     for (int b = 0; b < c->n_boxes; ++b) {
         const uint64_t lo = std::max(first, c->walk[b].pkt_off);
         const uint64_t hi = std::min(first + count, c->walk[b].pkt_off + c->walk[b].npkt);
-        if (hi > lo) c->walked[b] += hi - lo;
+        if (hi > lo) {
+            c->walked[b] += hi - lo;
+            c->walked_tiled[b] = tiled && c->tiled[b] ? 1 : 0;
+        }
     }
     c->state = 2;
 }
@@ -879,7 +885,7 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
     }
     if (st == MC_LYA_OK && coarse_end) st = timed_end(c, coarse_end);
     if (st != MC_LYA_OK) return st;
-    account_walked(c, first, count);
+    account_walked(c, first, count, c->kernel == 2);
     return MC_LYA_OK;
 }
 
@@ -954,6 +960,7 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
     c->walk.resize(n_boxes);
     c->red.resize(n_boxes);
     c->walked.assign(n_boxes, 0);
+    c->walked_tiled.assign(n_boxes, 0);
     c->ph.resize(n_boxes);
     uint64_t off = 0;
     int max_blk = 1;
@@ -1062,6 +1069,7 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *
         c->walk[b].seed = seeds[b];
         off += n_packets[b];
         c->walked[b] = 0;
+        c->walked_tiled[b] = 0;
     }
     c->total_packets = ntot;
     const int nb = c->n_boxes;
@@ -1125,6 +1133,7 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, m
             s.crossings = (int64_t)tot[b].crossings;
             s.packets = (int64_t)c->walked[b];
             s.conserved = ok ? 1 : 0;
+            s.tiled = c->walked_tiled[b];
             s.delta = c->walk[b].delta;
             s.x_eff = c->walk[b].x_eff;
             s.tau_ab_mean = c->red[b].kappa_sum / (double)c->walk[b].cells();
@@ -1336,7 +1345,7 @@ mc_lya_status mc_lya_scatter(mc_lya_ctx *c, uint64_t first, uint64_t count, cons
     HIP_TRY(c, launch_scatter(p, 256, grid, c->stream));
     st = timed_end(c, e1);
     if (st != MC_LYA_OK) return st;
-    account_walked(c, first, count);
+    account_walked(c, first, count, false);
     return MC_LYA_OK;
 }
 
@@ -1551,6 +1560,7 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
         HIP_TRY(c, hipMemsetAsync(c->d_A, 0, sizeof(unsigned long long) * c->total_cells, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->d_tot, 0, sizeof(BoxTot) * c->n_boxes, c->stream));
         std::fill(c->walked.begin(), c->walked.end(), 0);
+        std::fill(c->walked_tiled.begin(), c->walked_tiled.end(), 0);
         c->state = 1;
         return MC_LYA_OK;
     };

@@ -366,8 +366,7 @@ __device__ __forceinline__ void finish_photon(const Photon &P, const WalkBox &B,
 {
     uint32_t wing = 0;
     if (st == kSLost && B.kfar > 0.0f) {
-        const float pw = one_minus_exp(B.kfar * cumulative_voigt(x_stop, B.damp));
-        wing = min((uint32_t)rintf((float)B.w0 * pw), B.w0);
+        wing = absorbed_share(B.w0, B.kfar * cumulative_voigt(x_stop, B.damp));
     }
     BoxTot &t = SP.tot[box];
     const bool out = st == kSLost || st == kSCapped;

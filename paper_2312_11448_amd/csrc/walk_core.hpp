@@ -189,13 +189,23 @@ __device__ __forceinline__ float cumulative_voigt(float x, float damp)
     return fmaxf(0.5f * erfcf(-x) - damp * dawson_f32(x), 0.0f);
 }
 
-// 1 - exp(-tau) for tau >= 0 without cancellation (series below 0.1).
-__device__ __forceinline__ float one_minus_exp(float tau)
+// The integer weight that a packet of weight w < 2^32 leaves in a segment of
+// true-absorption depth tau >= 0: rint(w (1 - e^-tau)), never more than w.
+// A thin segment (tau < 0.1) takes the absorbed fraction from its Taylor
+// series (no cancellation). A thicker one rounds the weight that passes,
+// rint(w e^-tau), and deposits the rest: past tau ~ 17 the passing fraction
+// is below binary32's resolution of 1 - e^-tau, yet w e^-tau can still be
+// some units of weight that the packet carries into the next cell. The
+// products are at most 0.1 w and 0.905 w, so both conversions stay inside
+// the unsigned range and the result inside [0, w].
+__device__ __forceinline__ uint32_t absorbed_share(uint32_t w, float tau)
 {
+    const bool thin = tau < 0.1f;
     const float series = tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f -
-                                              tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
-    const float direct = 1.0f - __expf(-tau);
-    return tau < 0.1f ? series : direct;
+                                          tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
+    const float pass = __expf(-tau);
+    const uint32_t k = (uint32_t)rintf((float)w * (thin ? series : pass));
+    return thin ? k : w - k;
 }
 
 // k . (U_new - U_old) in thermal units: the frequency shift of Eq. (inout)
@@ -360,8 +370,7 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     const bool esc = xo <= -L.xeff;
     const float dx = esc ? L.x + L.xeff : L.delta * s;
     const float dphi = VOIGT ? swept_profile_voigt(L.x, dx, ln.damp) : swept_profile(L.x, dx);
-    const float pabs = one_minus_exp(L.kap * dphi);
-    const uint32_t d = walk ? min((uint32_t)rintf((float)L.w * pabs), L.w) : 0u;
+    const uint32_t d = walk ? absorbed_share(L.w, L.kap * dphi) : 0u;
     if (d) sink.deposit(L, d);
     L.w -= d;
     deposited += d;
@@ -375,8 +384,7 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     if (VOIGT && fate == kEscaped) {
         // the far damping wing beyond the stopping frequency
         const float xs = gone ? L.x : -L.xeff;
-        const float pw = one_minus_exp(ln.kfar * cumulative_voigt(xs, ln.damp));
-        wing = min((uint32_t)rintf((float)L.w * pw), L.w);
+        wing = absorbed_share(L.w, ln.kfar * cumulative_voigt(xs, ln.damp));
     }
 
     // cross the face

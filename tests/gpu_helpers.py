@@ -31,5 +31,7 @@ def compare_cells(gpu_A, orc_A, w_total):
     bad = diff > tol
     f_g = gpu_A.sum() / w_total
     f_o = orc_A.sum() / w_total
+    # a box that absorbs nothing (x_e = 1) compares its fractions exactly
+    f_rel = abs(f_g - f_o) / f_o if f_o > 0 else (0.0 if f_g == f_o else float("inf"))
     return dict(bad=int(bad.sum()), worst=float((diff / np.maximum(tol, 1)).max()),
-                f_gpu=f_g, f_orc=f_o, f_rel=abs(f_g - f_o) / f_o)
+                f_gpu=f_g, f_orc=f_o, f_rel=f_rel)

@@ -57,7 +57,7 @@ def test_summarize_valu_divides_by_the_profiled_work(tmp_path):
     r = _bench("--summarize-valu", c, log, out)
     assert r["valu_wave_instr_per_crossing"] == pytest.approx(9e9 / 3e8)
     assert r["salu_wave_instr_per_crossing"] == pytest.approx(1e9 / 3e8)
-    assert r["config"] == "c2" and r["profile"] == "doppler"
+    assert r["config"] == "c3" and r["profile"] == "doppler"
     with open(log, "w") as fh:
         fh.write(json.dumps({"metric": "resonant scatterings/s", "steps": 1, "warmup": 0,
                              "config": {"workload": "s", "scatterings_per_step": 2e9, "photons": 64}}) + "\n")

@@ -76,10 +76,15 @@ def test_packet_initial_states_match_oracle():
     assert esc_diff.max() < 1e-3
 
 
-@pytest.mark.parametrize("case", ["c1", "ragged_flow_source", "c2_small"])
+@pytest.mark.parametrize("case", ["c1", "ragged_flow_source", "c2_small", "max_weight"])
 def test_tallies_match_oracle(case):
     if case == "c1":
         spec = W.make_box("c1")
+    elif case == "max_weight":
+        # the largest packet weight the ABI takes, 2^32 - 1: its binary32 value
+        # is 2^32 itself, so every deposit of a whole packet must be capped
+        # at the integer weight without leaving the unsigned range
+        spec = W.make_box("c2", n=24, n_packets=200_000, w0=(1 << 32) - 1, zeta=0.3)
     elif case == "ragged_flow_source":
         rng = np.random.default_rng(12)
         n = (13, 7, 11)
