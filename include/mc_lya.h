@@ -487,6 +487,33 @@ mc_lya_status mc_lya_mlp_train_step(mc_lya_mlp *mlp, const float *features, cons
                                     const float *weights, uint64_t n, const mc_lya_adam *hp,
                                     float *loss);
 
+/* For callers that cannot allocate device memory (work being captured into a
+ * HIP graph, tight serving or training loops, harnesses that forbid
+ * hipMalloc): mc_lya_mlp_gradient without a network object and without any
+ * allocation. Its workspace (the per-block partial sums of the gradient and
+ * their fixed-order reduction, MC_LYA_STATIC_SCRATCH_BYTES) is one
+ * library-owned static device array per GPU, held until the process ends;
+ * calls that overlap on one GPU (other host threads, other streams) race on
+ * it and must be serialised by the caller. Every part of the workspace a
+ * call reads is written by that call first, so no call depends on an
+ * earlier one's leftovers. The result is the same, bit for bit, as
+ * mc_lya_mlp_gradient's for the same parameters and cells.
+ *   params    dev [MC_LYA_MLP_PARAMS] float (the layout above)
+ *   features  dev [n][8], targets dev [n], weights dev [n] (>= 0)
+ *   n         1 .. MC_LYA_STATIC_MAX_CELLS
+ *   grad_out  dev [MC_LYA_MLP_PARAMS + 2] float: the gradient of the weighted
+ *             mean squared error, then sum w r^2 and sum w (loss = their
+ *             ratio; a zero weight sum leaves a zero gradient)
+ *   stream    hipStream_t, or NULL
+ * Asynchronous on `stream` (no synchronisation, no allocation, no host
+ * copies). Errors: EINVAL (NULL pointers, n out of range), EDEVICE; the text
+ * of the last failure on this thread is mc_lya_mlp_static_last_error(). */
+#define MC_LYA_STATIC_MAX_CELLS (((uint64_t)1 << 40) - 1)
+#define MC_LYA_STATIC_SCRATCH_BYTES ((uint64_t)(1024 + 32) * 4808 * 4)
+mc_lya_status mc_lya_mlp_gradient_static(const float *params, const float *features, const float *targets,
+                                         const float *weights, uint64_t n, float *grad_out, void *stream);
+const char *mc_lya_mlp_static_last_error(void);
+
 /* Frees the network (synchronises its stream). NULL ok. */
 void mc_lya_mlp_destroy(mc_lya_mlp *mlp);
 

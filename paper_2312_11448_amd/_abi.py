@@ -87,7 +87,10 @@ EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
            "mc_lya_features", "mc_lya_mlp_create", "mc_lya_mlp_get_params", "mc_lya_mlp_set_envelope",
            "mc_lya_mlp_forward", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_destroy",
-           "mc_lya_mlp_last_error"]
+           "mc_lya_mlp_last_error", "mc_lya_mlp_gradient_static", "mc_lya_mlp_static_last_error"]
+# the static workspace of mc_lya_mlp_gradient_static (mc_lya.h)
+MC_LYA_STATIC_MAX_CELLS = (1 << 40) - 1
+MC_LYA_STATIC_SCRATCH_BYTES = (1024 + 32) * 4808 * 4
 MC_LYA_MLP_PARAMS = 4801
 MC_LYA_MLP_FEATURES = 8
 
@@ -132,7 +135,7 @@ def load():
     L.mc_lya_philox4x32_10.argtypes = [vp, vp, vp, u64, vp]
     for name in EXPORTS:
         if name in ("mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error", "mc_lya_mlp_destroy",
-                    "mc_lya_mlp_last_error"):
+                    "mc_lya_mlp_last_error", "mc_lya_mlp_static_last_error"):
             continue
         getattr(L, name).restype = C.c_int
     L.mc_lya_destroy.argtypes = [vp]
@@ -153,6 +156,9 @@ def load():
     L.mc_lya_mlp_destroy.restype = None
     L.mc_lya_mlp_last_error.argtypes = [vp]
     L.mc_lya_mlp_last_error.restype = C.c_char_p
+    L.mc_lya_mlp_gradient_static.argtypes = [vp, vp, vp, vp, u64, vp, vp]
+    L.mc_lya_mlp_static_last_error.argtypes = []
+    L.mc_lya_mlp_static_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -330,3 +336,15 @@ def mc_lya_mlp_destroy(mlp):
     if mlp:
         load().mc_lya_mlp_destroy(mlp)
 
+
+def mc_lya_mlp_gradient_static(params_ptr, feat_ptr, t_ptr, w_ptr, n, grad_out_ptr, stream=None):
+    """The allocation-free gradient: every pointer is device memory; grad_out
+    receives MC_LYA_MLP_PARAMS + 2 floats. Asynchronous on `stream`."""
+    L = load()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    status = L.mc_lya_mlp_gradient_static(params_ptr, feat_ptr, t_ptr, w_ptr, int(n), grad_out_ptr,
+                                          C.c_void_p(stream))
+    if status != MC_LYA_OK:
+        msg = L.mc_lya_mlp_static_last_error().decode() or L.mc_lya_strerror(status).decode()
+        raise MCLyaError(status, msg)

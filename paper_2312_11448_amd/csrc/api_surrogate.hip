@@ -3,6 +3,7 @@
 // and the gradient workspace on one device and stream.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -219,6 +220,77 @@ mc_lya_status mc_lya_mlp_train_step(mc_lya_mlp *m, const float *features, const 
     }
     return MC_LYA_OK;
 }
+
+}  // extern "C"
+
+// ---- gradient without allocation ---------------------------------------------
+// The workspace of mc_lya_mlp_gradient_static: the gradient kernel's per-block
+// partial sums and the group sums of its fixed-order reduction, in one
+// file-scope device array per GPU (held until the process ends). Host code
+// never uses the array's name as an address: its device address is looked up
+// once per device with hipGetSymbolAddress and kept below.
+namespace {
+
+constexpr size_t kStaticGradFloats =
+    (size_t)(kMlpGradBlocks + (kMlpGradBlocks + 31) / 32) * kMlpPartStride;
+static_assert(kStaticGradFloats * sizeof(float) == MC_LYA_STATIC_SCRATCH_BYTES, "static workspace size");
+__device__ __align__(256) float scratch[kStaticGradFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+thread_local std::string g_static_err;
+
+mc_lya_status static_fail(mc_lya_status s, const std::string &what)
+{
+    g_static_err = what;
+    return s;
+}
+
+// The device address of the current device's scratch array (looked up on the
+// first call on that device, with that device current).
+mc_lya_status scratch_address(float **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return static_fail(MC_LYA_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return static_fail(MC_LYA_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return static_fail(MC_LYA_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<float *>(g_scratch_ptr[dev]);
+    return MC_LYA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mc_lya_status mc_lya_mlp_gradient_static(const float *params, const float *features, const float *targets,
+                                         const float *weights, uint64_t n, float *grad_out, void *stream)
+{
+    g_static_err.clear();
+    if (!params || !grad_out) return static_fail(MC_LYA_EINVAL, "params and grad_out must not be NULL");
+    if (n == 0 || !features || !targets || !weights)
+        return static_fail(MC_LYA_EINVAL, "need cells, features, targets and weights");
+    if (n > MC_LYA_STATIC_MAX_CELLS)
+        return static_fail(MC_LYA_EINVAL, "n exceeds MC_LYA_STATIC_MAX_CELLS (the static workspace's limit)");
+    float *ws = nullptr;
+    mc_lya_status st = scratch_address(&ws);
+    if (st != MC_LYA_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_mlp_gradient(params, features, targets, weights, n, ws, kMlpGradBlocks, grad_out, s);
+    if (e == hipSuccess) e = launch_mlp_normalise(grad_out, s);
+    if (e != hipSuccess) return static_fail(MC_LYA_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return MC_LYA_OK;
+}
+
+const char *mc_lya_mlp_static_last_error(void) { return g_static_err.c_str(); }
 
 void mc_lya_mlp_destroy(mc_lya_mlp *m)
 {
