@@ -358,7 +358,10 @@ void build_tiles(mc_lya_ctx *c)
                     t.sy = e[1];
                     t.sz = e[2];
                     for (int a = 0; a < 3; ++a) {
-                        if (nt[a] == 1) continue;
+                        if (nt[a] == 1) {
+                            t.span |= 1u << a;
+                            continue;
+                        }
                         for (int dir = -1; dir <= 1; dir += 2) {
                             int q[3] = {tx, ty, tz};
                             q[a] = (q[a] + dir + nt[a]) % nt[a];

@@ -213,7 +213,8 @@ struct TileInfo {
     int32_t nsrc;            // exit lists this tile pulls from (0..6)
     int32_t src_tile[6];     // tile whose exits through face src_face[k] enter this tile
     uint32_t src_faces;      // 4 bits per source: the face (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z)
-    int32_t pad;
+    uint32_t span;           // bit a: the tile spans the box along axis a (a packet wraps
+                             // round inside the tile instead of leaving it)
 };
 static_assert(sizeof(TileInfo) == 64, "TileInfo layout");
 

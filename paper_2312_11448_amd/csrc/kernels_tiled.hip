@@ -39,65 +39,270 @@ __device__ __forceinline__ int tile_slot(int32_t lx, int32_t ly, int32_t lz)
     return lx | (ly << 4) | (lz << 8);
 }
 
-// Deposits and opacity/velocity records of the cells of one tile, both in LDS.
-// The packets' global cell index is not kept up to date inside the tile
-// (kCell): the tiled walk sets it when a packet leaves.
-template <bool VEL>
-struct TileSink {
-    static constexpr bool kCell = false;
-    unsigned long long *tally;
-    const float4 *rec4;          // VEL: (kappa, U) per cell
-    const float *reck;           // !VEL: kappa per cell
+// Faces left along an axis the tile spans: a packet never leaves that way.
+constexpr int32_t kNoFace = 1 << 30;
+
+// The tile a workgroup walks, uniform over it: the box's drift, escape
+// threshold and line constants, the tile's origin and extent, and the axes
+// along which it spans the whole box (the grid wraps round inside it).
+struct TileCtx {
+    float delta, xeff;
+    uint32_t max_cross;
+    Line ln;
     int32_t ox, oy, oz, sx, sy, sz;
-    __device__ __forceinline__ int local(int32_t ix, int32_t iy, int32_t iz) const
-    {
-        return tile_slot(ix - ox, iy - oy, iz - oz);
-    }
-    __device__ __forceinline__ bool inside(int32_t jx, int32_t jy, int32_t jz) const
-    {
-        return ((uint32_t)(jx - ox) < (uint32_t)sx) & ((uint32_t)(jy - oy) < (uint32_t)sy) &
-               ((uint32_t)(jz - oz) < (uint32_t)sz);
-    }
-    __device__ __forceinline__ void deposit(const Lane &L, uint32_t d) const
-    {
-        atomicAdd(&tally[local(L.ix, L.iy, L.iz)], (unsigned long long)d);
-    }
-    template <bool V>
-    __device__ __forceinline__ Rec fetch(const void *, uint32_t, int32_t jx, int32_t jy, int32_t jz, bool stay) const
-    {
-        Rec r;
-        const int lc = stay ? local(jx, jy, jz) : 0;    // leaving: the record is not used
-        if (V) {
-            const float4 v = rec4[lc];
-            r.kap = v.x;
-            r.ux = v.y;
-            r.uy = v.z;
-            r.uz = v.w;
-        } else {
-            r.kap = reck[lc];
-            r.ux = r.uy = r.uz = 0.0f;
-        }
-        return r;
-    }
+    uint32_t span;
 };
 
-__device__ __forceinline__ uint32_t rank_in(uint64_t mask)
+// A packet inside a tile. Ray geometry and line state are a Lane's; the cell
+// is tracked by its record's byte offset q in the tile's LDS (RS bytes per
+// record), with the change of q for a step along each axis and the number
+// of faces the packet can still cross along each axis before it reaches the
+// tile's edge. A step is then an add and three compares, where global cell
+// coordinates would need the box's periodic wrap, the neighbour's index and
+// an in-tile test; they are formed only when the packet leaves the tile.
+struct TLane {
+    double tmx, tmy, tmz, tdx, tdy, tdz, t;
+    float kx, ky, kz;
+    float x, kap, ux, uy, uz;
+    uint32_t w, ncross;
+    int32_t q;
+    int32_t dqx, dqy, dqz;
+    int32_t rx, ry, rz;
+};
+
+// The LDS tally of the cell whose record is at byte offset q (8-byte tallies).
+template <int RS>
+__device__ __forceinline__ unsigned long long *tally_of(unsigned long long *tally, int32_t q)
 {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const uint32_t b = RS >= 8 ? (uint32_t)q / (uint32_t)(RS / 8) : (uint32_t)q * (uint32_t)(8 / RS);
+    return reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(tally) + b);
 }
 
-__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+template <bool VEL>
+__device__ __forceinline__ Rec rec_at(const char *recs, int32_t q)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    Rec r;
+    if (VEL) {
+        const float4 v = *reinterpret_cast<const float4 *>(recs + q);
+        r.kap = v.x;
+        r.ux = v.y;
+        r.uy = v.z;
+        r.uz = v.w;
+    } else {
+        r.kap = *reinterpret_cast<const float *>(recs + q);
+        r.ux = r.uy = r.uz = 0.0f;
+    }
+    return r;
 }
 
-__device__ __forceinline__ void save_state(PState &o, const Lane &L)
+// A packet standing in cell (L.ix, L.iy, L.iz) of this tile, as a TLane.
+template <int RS>
+__device__ __forceinline__ void to_tile(TLane &T, const Lane &L, const TileCtx &C)
 {
+    T.tmx = L.tmx;
+    T.tmy = L.tmy;
+    T.tmz = L.tmz;
+    T.tdx = L.tdx;
+    T.tdy = L.tdy;
+    T.tdz = L.tdz;
+    T.t = L.t;
+    T.kx = L.kx;
+    T.ky = L.ky;
+    T.kz = L.kz;
+    T.x = L.x;
+    T.kap = L.kap;
+    T.ux = L.ux;
+    T.uy = L.uy;
+    T.uz = L.uz;
+    T.w = L.w;
+    T.ncross = L.ncross;
+    const int32_t lx = L.ix - C.ox, ly = L.iy - C.oy, lz = L.iz - C.oz;
+    T.q = tile_slot(lx, ly, lz) * RS;
+    // the walk steps +1 along an axis when the direction's component is > 0, else -1
+    const bool px = L.kx > 0.0f, py = L.ky > 0.0f, pz = L.kz > 0.0f;
+    T.dqx = px ? RS : -RS;
+    T.dqy = py ? 16 * RS : -16 * RS;
+    T.dqz = pz ? 256 * RS : -256 * RS;
+    T.rx = (C.span & 1u) ? kNoFace : (px ? C.sx - 1 - lx : lx);
+    T.ry = (C.span & 2u) ? kNoFace : (py ? C.sy - 1 - ly : ly);
+    T.rz = (C.span & 4u) ? kNoFace : (pz ? C.sz - 1 - lz : lz);
+}
+
+// Global coordinates of a TLane's cell.
+template <int RS>
+__device__ __forceinline__ void tile_cell(const TLane &T, const TileCtx &C, int32_t &ix, int32_t &iy, int32_t &iz)
+{
+    const int32_t s = (int32_t)((uint32_t)T.q / (uint32_t)RS);
+    ix = C.ox + (s & 15);
+    iy = C.oy + ((s >> 4) & 15);
+    iz = C.oz + (s >> 8);
+}
+
+// Along an axis the tile spans, one cell past either end of the tile is its
+// other end (the box is periodic and the tile is the whole box that way).
+template <int RS>
+__device__ __forceinline__ int32_t wrap_slot(const TLane &L, int32_t qn, const Face &f, const TileCtx &C)
+{
+    const int32_t s = (int32_t)((uint32_t)L.q / (uint32_t)RS);
+    if (f.bx && (C.span & 1u)) {
+        const int32_t l = s & 15;
+        const int32_t m = L.kx > 0.0f ? (l + 1 == C.sx ? 0 : l + 1) : (l == 0 ? C.sx - 1 : l - 1);
+        qn = L.q + (m - l) * RS;
+    } else if (f.by && (C.span & 2u)) {
+        const int32_t l = (s >> 4) & 15;
+        const int32_t m = L.ky > 0.0f ? (l + 1 == C.sy ? 0 : l + 1) : (l == 0 ? C.sy - 1 : l - 1);
+        qn = L.q + (m - l) * (16 * RS);
+    } else if (f.bz && (C.span & 4u)) {
+        const int32_t l = s >> 8;
+        const int32_t m = L.kz > 0.0f ? (l + 1 == C.sz ? 0 : l + 1) : (l == 0 ? C.sz - 1 : l - 1);
+        qn = L.q + (m - l) * (256 * RS);
+    }
+    return qn;
+}
+
+// Outcome of one step of a TLane.
+struct TStep {
+    bool alive;      // walks on inside the tile
+    bool exit;       // stands on the tile's edge, to be handed to the neighbour
+    bool fin;        // finished: absorbed, escaped or capped
+    bool escaped;    // finished by escape (its weight escapes)
+    bool capped;     // finished at the crossing cap
+    uint32_t wing;   // Voigt: the far wing's share of an escaping packet's weight
+};
+
+// One (packet, cell) segment inside a tile: the same face choice, line
+// physics, deposit and face jump as walk_step, so that the integers are the
+// same bits as those of every other driver. A packet whose next cell lies
+// outside the tile stops on the face with its geometry not yet advanced, its
+// drifted pre-jump frequency and its cell's velocity (save_exit completes the
+// crossing). act = false leaves the lane's state as it is (an idle lane, or
+// one waiting to be written out) and deposits nothing.
+// The deposit of a step is issued at the start of the next one (dep_q, dep_w:
+// the cell's record offset and the weight, 0 for none): its LDS atomic then
+// runs while the step computes, instead of delaying the wait for the
+// neighbour's record at the end of the step it was computed in.
+template <bool VEL, bool VOIGT, bool WRAP, int RS>
+__device__ __forceinline__ TStep tile_step(TLane &L, bool act, const TileCtx &C, const char *recs,
+                                           unsigned long long *tally, int32_t &dep_q, uint32_t &dep_w)
+{
+    if (dep_w) atomicAdd(tally_of<RS>(tally, dep_q), (unsigned long long)dep_w);
+    TStep o;
+    const bool gone = VOIGT ? (L.x <= -C.xeff) | (L.x > C.ln.xblue) : L.x <= -C.xeff;
+    const bool capped = !gone && L.ncross >= C.max_cross;
+    const bool walk = act && !gone && !capped;
+    const Face f = next_face(L.tmx, L.tmy, L.tmz);
+    const bool stay = (f.bx & (L.rx != 0)) | (f.by & (L.ry != 0)) | (f.bz & (L.rz != 0));
+    // sums of field-or-zero terms: a choice between fields would make the
+    // compiler address the lane state in (scratch) memory
+    int32_t qn = L.q + (f.bx ? L.dqx : 0) + (f.by ? L.dqy : 0) + (f.bz ? L.dqz : 0);
+    if (WRAP) qn = wrap_slot<RS>(L, qn, f, C);
+    // the neighbour's record, in flight during the profile arithmetic (a
+    // packet leaving the tile reads its own cell's instead: not used)
+    const Rec nr = rec_at<VEL>(recs, stay ? qn : L.q);
+    const Segment g = segment<VOIGT>(L.x, (float)(f.tn - L.t), C.delta, C.xeff, L.kap, L.w, walk, C.ln);
+    dep_q = L.q;                 // the deposit goes into the cell being left
+    dep_w = g.d;
+    L.w -= g.d;
+    L.ncross += walk ? 1u : 0u;
+    const bool live = walk && !g.esc && L.w != 0u;
+    o.alive = live && stay;
+    o.exit = live && !stay;
+    o.fin = act && !live;
+    o.escaped = act && (gone || (walk && g.esc));
+    o.capped = act && capped;
+    o.wing = 0u;
+    if (VOIGT && o.escaped) o.wing = wing_share(L.w, gone ? L.x : -C.xeff, C.ln);
+    // cross the face (packets that walk on inside the tile)
+    const bool mv = o.alive;
+    L.tmx = (mv && f.bx) ? L.tmx + L.tdx : L.tmx;
+    L.tmy = (mv && f.by) ? L.tmy + L.tdy : L.tmy;
+    L.tmz = (mv && f.bz) ? L.tmz + L.tdz : L.tmz;
+    L.t = mv ? f.tn : L.t;
+    L.q = mv ? qn : L.q;
+    L.rx -= (mv && f.bx) ? 1 : 0;
+    L.ry -= (mv && f.by) ? 1 : 0;
+    L.rz -= (mv && f.bz) ? 1 : 0;
+    // the bulk term of Eq. (inout) on entering the new cell; a packet that
+    // leaves keeps its pre-jump frequency
+    if (VEL) {
+        const float xj = g.xo - bulk_jump(L, nr);
+        L.x = act ? (mv ? xj : g.xo) : L.x;
+        L.ux = mv ? nr.ux : L.ux;
+        L.uy = mv ? nr.uy : L.uy;
+        L.uz = mv ? nr.uz : L.uz;
+    } else {
+        L.x = act ? g.xo : L.x;
+    }
+    L.kap = mv ? nr.kap : L.kap;
+    return o;
+}
+
+// A lane that holds no packet: no weight, far below any escape threshold.
+__device__ __forceinline__ void idle_tlane(TLane &T, int32_t rs)
+{
+    T.tmx = T.tmy = T.tmz = 1.0;
+    T.tdx = T.tdy = T.tdz = 1.0;
+    T.t = 0.0;
+    T.kx = 1.0f;
+    T.ky = T.kz = 0.0f;
+    T.x = -3.0e38f;
+    T.kap = 0.0f;
+    T.ux = T.uy = T.uz = 0.0f;
+    T.w = 0u;
+    T.ncross = 0u;
+    T.q = 0;
+    T.dqx = rs;
+    T.dqy = 16 * rs;
+    T.dqz = 256 * rs;
+    T.rx = T.ry = T.rz = 0;
+}
+
+// A packet standing on the tile's edge, written for the neighbouring tile:
+// the face crossing that tile_step left undone (the same face choice and
+// FP64 advance as walk_step, and the next cell with the box's periodic wrap),
+// with the pre-jump frequency and the velocity of the cell it leaves.
+template <int RS>
+__device__ __forceinline__ uint32_t save_exit(PState &o, const TLane &L, const TileCtx &C, const WalkBox &B)
+{
+    const Face f = next_face(L.tmx, L.tmy, L.tmz);
+    int32_t ix, iy, iz;
+    tile_cell<RS>(L, C, ix, iy, iz);
+    const int32_t ci = (f.bx ? ix : 0) + (f.by ? iy : 0) + (f.bz ? iz : 0);
+    const int32_t ni = (f.bx ? B.nx : 0) + (f.by ? B.ny : 0) + (f.bz ? B.nz : 0);
+    const bool up = (f.bx & (L.kx > 0.0f)) | (f.by & (L.ky > 0.0f)) | (f.bz & (L.kz > 0.0f));
+    int32_t mi = ci + (up ? 1 : -1);
+    mi = mi == ni ? 0 : mi;
+    mi = mi < 0 ? ni - 1 : mi;
+    const int32_t jx = f.bx ? mi : ix, jy = f.by ? mi : iy, jz = f.bz ? mi : iz;
+    o.tmx = f.bx ? L.tmx + L.tdx : L.tmx;
+    o.tmy = f.by ? L.tmy + L.tdy : L.tmy;
+    o.tmz = f.bz ? L.tmz + L.tdz : L.tmz;
+    o.tdx = L.tdx;
+    o.tdy = L.tdy;
+    o.tdz = L.tdz;
+    o.t = f.tn;
+    o.w = L.w;
+    o.x = L.x;
+    o.kx = L.kx;
+    o.ky = L.ky;
+    o.kz = L.kz;
+    o.ux = L.ux;
+    o.uy = L.uy;
+    o.uz = L.uz;
+    o.cell = B.cell_off + (uint32_t)jx + (uint32_t)B.nx * ((uint32_t)jy + (uint32_t)B.ny * (uint32_t)jz);
+    o.ncross = L.ncross;
+    o.ix = jx;
+    o.iy = jy;
+    o.iz = jz;
+    return (f.bx ? 0u : (f.by ? 2u : 4u)) + (up ? 1u : 0u);   // the face it leaves through
+}
+
+// A packet deferred to the tile's next generation, standing inside its cell.
+template <int RS>
+__device__ __forceinline__ void save_here(PState &o, const TLane &L, const TileCtx &C, const WalkBox &B)
+{
+    int32_t ix, iy, iz;
+    tile_cell<RS>(L, C, ix, iy, iz);
     o.tmx = L.tmx;
     o.tmy = L.tmy;
     o.tmz = L.tmz;
@@ -113,11 +318,26 @@ __device__ __forceinline__ void save_state(PState &o, const Lane &L)
     o.ux = L.ux;
     o.uy = L.uy;
     o.uz = L.uz;
-    o.cell = L.c;
+    o.cell = B.cell_off + (uint32_t)ix + (uint32_t)B.nx * ((uint32_t)iy + (uint32_t)B.ny * (uint32_t)iz);
     o.ncross = L.ncross;
-    o.ix = L.ix;
-    o.iy = L.iy;
-    o.iz = L.iz;
+    o.ix = ix;
+    o.iy = iy;
+    o.iz = iz;
+}
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkBox &B)
@@ -150,6 +370,141 @@ __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkB
     L.xeff = B.x_eff;
 }
 
+// Per-wave running totals of finished packets.
+struct TileAcc {
+    uint64_t esc, cross, capn, capw, wing;
+};
+
+// The walk of one tile's input by one workgroup (all its waves): refill
+// idle lanes from the input list, step every lane, park packets that reach
+// the tile's edge and write them out at the next refill, defer thin waves.
+// The walk of one tile's input by one workgroup (all its waves): refill
+// idle lanes from the input list, step every lane, park packets that reach
+// the tile's edge and write them out at the next refill, defer thin waves.
+template <bool VEL, bool GEN0, bool VOIGT, bool WRAP>
+__device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &ti, const WalkBox &B,
+                                          const TileCtx &C, uint32_t n_in, const uint32_t *pre, const uint32_t *lst,
+                                          const char *recs, unsigned long long *tally, uint32_t *s_next,
+                                          uint32_t *s_exit, uint32_t s_base, uint32_t *s_fcnt, TileAcc &acc)
+{
+    constexpr int RS = VEL ? 16 : 4;
+    const int ncell = ti.sx * ti.sy * ti.sz;
+    const uint32_t lane = __lane_id();
+    const uint64_t r_lo = P.first;
+    TLane L;
+    idle_tlane(L, RS);          // every lane steps, so none starts undefined
+    bool alive = false, more = true;
+    bool fresh = false;          // wave-uniform: packets loaded since the wave's last step
+    // A packet that reaches the tile's edge parks in its lane (pending) and is
+    // written out when the wave next refills or stops: one exit-writing pass
+    // for many lanes instead of one per step for a few.
+    bool pending = false;
+    auto flush_exits = [&]() {
+        if (pending) {
+            const uint32_t g = s_base + atomicAdd(s_exit, 1u);
+            const uint32_t f = save_exit<RS>(P.out_state[g], L, C, B);
+            P.out_face[g] = (uint8_t)f;
+            atomicAdd(&s_fcnt[f], 1u);
+            pending = false;
+        }
+    };
+    uint32_t cur = 0, end = 0;
+    const uint32_t chunk = (uint32_t)P.chunk;
+    const uint32_t refill = (uint32_t)P.refill;
+    int32_t dep_q = 0;           // the last step's deposit, not yet issued
+    uint32_t dep_w = 0;
+    for (;;) {
+        uint64_t idle = __ballot(!alive);
+        // refilling stalls the whole wave on the new packets' loads: wait until
+        // enough lanes are idle (or all are)
+        if ((uint32_t)__popcll(idle) < refill && idle != ~0ull) idle = 0;
+        if (idle && more) flush_exits();
+        while (idle && more) {
+            if (cur >= end) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(s_next, chunk);
+                base = uniform_u32(__shfl(base, 0, 64));
+                if (base >= n_in) {
+                    more = false;
+                    break;
+                }
+                cur = base;
+                end = base + chunk < n_in ? base + chunk : n_in;
+            }
+            const uint32_t take = min((uint32_t)__popcll(idle), end - cur);
+            const uint32_t r = rank_in(idle);
+            if (!alive && r < take) {
+                const uint32_t j = cur + r;
+                Lane N;
+                if (GEN0) {
+                    int lo = 0, hi = ncell - 1;             // largest cell with pre <= j
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                    }
+                    const int lx = lo % ti.sx, ly = (lo / ti.sx) % ti.sy, lz = lo / (ti.sx * ti.sy);
+                    const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                                        (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+                    const uint64_t pf = P.pfirst[gc];
+                    const uint64_t gp = (pf > r_lo ? pf : r_lo) + (j - pre[lo]);
+                    emit_packet<VOIGT>(N, B, gp - B.pkt_off, gc);
+                    const Rec rc = rec_at<VEL>(recs, tile_slot(lx, ly, lz) * RS);   // the emission cell's record
+                    N.kap = rc.kap;
+                    N.ux = rc.ux;
+                    N.uy = rc.uy;
+                    N.uz = rc.uz;
+                } else {
+                    int k = 0;
+                    while (k + 1 <= ti.nsrc && pre[k + 1] <= j) ++k;
+                    const uint32_t g = P.in_idx[lst[k] + (j - pre[k])];
+                    load_state(N, P.in_state[g], B);
+                    const Rec rc = rec_at<VEL>(recs, tile_slot(N.ix - ti.ox, N.iy - ti.oy, N.iz - ti.oz) * RS);
+                    if (k < ti.nsrc) finish_entry<VEL>(N, rc);   // entering through a face
+                    else N.kap = rc.kap;                         // deferred inside its cell
+                }
+                to_tile<RS>(L, N, C);
+                alive = true;
+            }
+            fresh = true;
+            cur += take;
+            idle = __ballot(!alive);
+        }
+        const uint64_t live = __ballot(alive);
+        // no live lane after the refill means the input is used up (a wave
+        // with idle lanes refills while there is input)
+        if (!live && !more) {
+            flush_exits();
+            break;
+        }
+        // (only after a step, so every deferred packet has moved in this generation)
+        if (!more && !fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
+            flush_exits();
+            if (alive) {
+                const uint32_t g = s_base + atomicAdd(s_exit, 1u);
+                save_here<RS>(P.out_state[g], L, C, B);
+                P.out_face[g] = (uint8_t)kDeferred;
+                atomicAdd(&s_fcnt[kDeferred], 1u);
+            }
+            break;
+        }
+        fresh = false;
+        // Every lane steps: an idle or parked lane's step changes nothing and
+        // deposits nothing (selects, not branches, keep the lane state in the
+        // same registers round the loop).
+        const TStep o = tile_step<VEL, VOIGT, WRAP, RS>(L, alive, C, recs, tally, dep_q, dep_w);
+        acc.cross += o.fin ? L.ncross : 0u;
+        acc.esc += o.escaped ? L.w : 0u;
+        if (VOIGT) acc.wing += o.escaped ? o.wing : 0u;
+        if (__ballot(o.capped)) {
+            acc.capn += o.capped ? 1u : 0u;
+            acc.capw += o.capped ? L.w : 0u;
+        }
+        pending = pending || o.exit;
+        alive = o.alive;
+    }
+    if (dep_w) atomicAdd(tally_of<RS>(tally, dep_q), (unsigned long long)dep_w);
+}
+
 // One generation. GEN0: the tile's input is the packets emitted in its cells
 // (within the requested packet range); otherwise it is the face lists of the
 // previous generation that point at this tile.
@@ -180,7 +535,6 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     }
     const TileInfo ti = P.tiles[T];
     const WalkBox B = P.boxes[ti.box];
-    const Line ln = line_of(B);       // tile-uniform
     const int ncell = ti.sx * ti.sy * ti.sz;
     const uint32_t lane = __lane_id();
     const uint64_t r_lo = P.first, r_hi = P.first + P.count;
@@ -282,130 +636,31 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     __syncthreads();
 
     // ---- walk -------------------------------------------------------------
-    const TileSink<VEL> sink{tally, srec4, sreck, ti.ox, ti.oy, ti.oz, ti.sx, ti.sy, ti.sz};
-    Lane L;
-    idle_lane(L);               // every lane steps, so none starts undefined
-    bool alive = false, more = true;
-    bool fresh = false;          // wave-uniform: packets loaded since the wave's last step
-    // A packet that leaves the tile parks in its lane (pending) and is written
-    // out when the wave next refills or stops: one exit-writing pass for many
-    // lanes instead of one per step for a few.
-    bool pending = false;
-    auto flush_exits = [&]() {
-        if (pending) {
-            const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
-            L.c = cell_of(L);
-            save_state(P.out_state[g], L);
-            // the face it left through: the one coordinate now outside the tile
-            uint32_t f;
-            if ((uint32_t)(L.ix - ti.ox) >= (uint32_t)ti.sx) f = L.kx > 0.0f ? 1u : 0u;
-            else if ((uint32_t)(L.iy - ti.oy) >= (uint32_t)ti.sy) f = L.ky > 0.0f ? 3u : 2u;
-            else f = L.kz > 0.0f ? 5u : 4u;
-            P.out_face[g] = (uint8_t)f;
-            atomicAdd(&s_fcnt[f], 1u);
-            pending = false;
-        }
-    };
-    uint32_t cur = 0, end = 0;
-    uint64_t a_esc = 0, a_cross = 0, a_capn = 0, a_capw = 0, a_wing = 0;
-    const uint32_t chunk = (uint32_t)P.chunk;
-    const uint32_t refill = (uint32_t)P.refill;
-    for (;;) {
-        uint64_t idle = __ballot(!alive);
-        // refilling stalls the whole wave on the new packets' loads: wait until
-        // enough lanes are idle (or all are)
-        if ((uint32_t)__popcll(idle) < refill && idle != ~0ull) idle = 0;
-        if (idle && more) flush_exits();
-        while (idle && more) {
-            if (cur >= end) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&s_next, chunk);
-                base = uniform_u32(__shfl(base, 0, 64));
-                if (base >= n_in) {
-                    more = false;
-                    break;
-                }
-                cur = base;
-                end = base + chunk < n_in ? base + chunk : n_in;
-            }
-            const uint32_t take = min((uint32_t)__popcll(idle), end - cur);
-            const uint32_t r = rank_in(idle);
-            if (!alive && r < take) {
-                const uint32_t j = cur + r;
-                if (GEN0) {
-                    int lo = 0, hi = ncell - 1;             // largest cell with pre <= j
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (pre[mid] <= j) lo = mid; else hi = mid - 1;
-                    }
-                    const int lx = lo % ti.sx, ly = (lo / ti.sx) % ti.sy, lz = lo / (ti.sx * ti.sy);
-                    const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
-                                        (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
-                    const uint64_t pf = P.pfirst[gc];
-                    const uint64_t gp = (pf > r_lo ? pf : r_lo) + (j - pre[lo]);
-                    init_packet<VEL, VOIGT>(L, B, gp - B.pkt_off, gc, P.rec);
-                } else {
-                    int k = 0;
-                    while (k + 1 <= ti.nsrc && pre[k + 1] <= j) ++k;
-                    const uint32_t g = P.in_idx[lst[k] + (j - pre[k])];
-                    load_state(L, P.in_state[g], B);
-                    const Rec r = sink.template fetch<VEL>(P.rec, L.c, L.ix, L.iy, L.iz, true);
-                    if (k < ti.nsrc) finish_entry<VEL>(L, r);   // entering through a face
-                    else L.kap = r.kap;                         // deferred inside its cell
-                }
-                alive = true;
-            }
-            fresh = true;
-            cur += take;
-            idle = __ballot(!alive);
-        }
-        const uint64_t live = __ballot(alive);
-        // no live lane after the refill means the input is used up (a wave
-        // with idle lanes refills while there is input)
-        if (!live && !more) {
-            flush_exits();
-            break;
-        }
-        // (only after a step, so every deferred packet has moved in this generation)
-        if (!more && !fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
-            flush_exits();
-            if (alive) {
-                const uint32_t g = s_base + atomicAdd(&s_exit, 1u);
-                L.c = cell_of(L);
-                save_state(P.out_state[g], L);
-                P.out_face[g] = (uint8_t)kDeferred;
-                atomicAdd(&s_fcnt[kDeferred], 1u);
-            }
-            break;
-        }
-        fresh = false;
-        {
-            // Every lane steps, by selects rather than branches: an idle lane's
-            // step deposits nothing and reads an in-tile record, and the idle
-            // lane keeps its state. Branches here made the compiler copy the
-            // lane state and the totals on every step.
-            uint64_t dep = 0;
-            uint32_t wing = 0;
-            Lane Ln = L;
-            const int fate = walk_step<VEL, VOIGT>(Ln, P.rec, sink, P.max_cross, dep, ln, wing, alive);
-            keep_or_take(L, Ln, alive);
-            const bool fin = alive && fate != kAlive && fate != kExit;
-            a_cross += fin ? L.ncross : 0u;
-            a_esc += alive && fate == kEscaped ? L.w : 0u;
-            a_capn += alive && fate == kCapped ? 1u : 0u;
-            a_capw += alive && fate == kCapped ? L.w : 0u;
-            if (VOIGT) a_wing += fin ? wing : 0u;
-            pending = pending || (alive && fate == kExit);
-            alive = alive && fate == kAlive;
-        }
-    }
+    TileCtx C;
+    C.delta = B.delta;
+    C.xeff = B.x_eff;
+    C.max_cross = P.max_cross;
+    C.ln = line_of(B);
+    C.ox = ti.ox;
+    C.oy = ti.oy;
+    C.oz = ti.oz;
+    C.sx = ti.sx;
+    C.sy = ti.sy;
+    C.sz = ti.sz;
+    C.span = ti.span;
+    const char *recs = VEL ? reinterpret_cast<const char *>(srec4) : reinterpret_cast<const char *>(sreck);
+    TileAcc acc{0, 0, 0, 0, 0};
+    // a tile that spans the box along some axis wraps round inside itself
+    if (ti.span)
+        walk_tile<VEL, GEN0, VOIGT, true>(P, ti, B, C, n_in, pre, lst, recs, tally, &s_next, &s_exit, s_base, s_fcnt,
+                                          acc);
+    else
+        walk_tile<VEL, GEN0, VOIGT, false>(P, ti, B, C, n_in, pre, lst, recs, tally, &s_next, &s_exit, s_base, s_fcnt,
+                                           acc);
 
     // ---- finish: tally, totals, face lists of the exits ----------------------
-    a_esc = wave_sum(a_esc);
-    a_cross = wave_sum(a_cross);
-    a_capn = wave_sum(a_capn);
-    a_capw = wave_sum(a_capw);
-    if (VOIGT) a_wing = wave_sum(a_wing);
+    const uint64_t a_esc = wave_sum(acc.esc), a_cross = wave_sum(acc.cross), a_capn = wave_sum(acc.capn),
+                   a_capw = wave_sum(acc.capw), a_wing = VOIGT ? wave_sum(acc.wing) : 0;
     if (lane == 0) {
         s_red[tid >> 6][0] = a_esc;
         s_red[tid >> 6][1] = a_cross;

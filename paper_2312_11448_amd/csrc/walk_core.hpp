@@ -88,9 +88,9 @@ __device__ __forceinline__ Line line_of(const WalkBox &B)
 // the Cauchy deviate of the natural line from the eighth uniform. Optionally
 // returns the initial state (position inside the cell and direction) for
 // traces.
-template <bool VEL, bool VOIGT = false>
-__device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t p, uint32_t gcell,
-                                            const void *__restrict__ rec, float *state = nullptr)
+template <bool VOIGT>
+__device__ __forceinline__ void emit_packet(Lane &L, const WalkBox &B, uint64_t p, uint32_t gcell,
+                                            float *state = nullptr)
 {
     const uint32_t k0 = (uint32_t)B.seed, k1 = (uint32_t)(B.seed >> 32);
     uint32_t a[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, 0u};
@@ -133,16 +133,25 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
     }
     L.w = (uint32_t)B.w0;
     L.ncross = 0;
-    const Rec r = load_rec<VEL>(rec, gcell);
-    L.kap = r.kap;
-    L.ux = r.ux;
-    L.uy = r.uy;
-    L.uz = r.uz;
     if (state) {
         state[0] = (float)fx;
         state[1] = (float)fy;
         state[2] = (float)fz;
     }
+}
+
+// Emission (emit_packet) with the emission cell's opacity and velocity read
+// from the packed records.
+template <bool VEL, bool VOIGT = false>
+__device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t p, uint32_t gcell,
+                                            const void *__restrict__ rec, float *state = nullptr)
+{
+    emit_packet<VOIGT>(L, B, p, gcell, state);
+    const Rec r = load_rec<VEL>(rec, gcell);
+    L.kap = r.kap;
+    L.ux = r.ux;
+    L.uy = r.uy;
+    L.uz = r.uz;
 }
 
 // Swept profile mass Phi(x) - Phi(x - dx) for dx > 0, Phi the cumulative
@@ -211,7 +220,8 @@ __device__ __forceinline__ uint32_t absorbed_share(uint32_t w, float tau)
 // k . (U_new - U_old) in thermal units: the frequency shift of Eq. (inout)
 // at a face. One expression, shared by every place that applies the jump, so
 // that the rounding is the same wherever the face is crossed.
-__device__ __forceinline__ float bulk_jump(const Lane &L, const Rec &nr)
+template <class LaneT>
+__device__ __forceinline__ float bulk_jump(const LaneT &L, const Rec &nr)
 {
     return L.kx * (nr.ux - L.ux) + L.ky * (nr.uy - L.uy) + L.kz * (nr.uz - L.uz);
 }
@@ -310,6 +320,59 @@ __device__ __forceinline__ void idle_lane(Lane &L)
 
 enum : int { kAlive = 0, kEscaped = 1, kAbsorbed = 2, kCapped = 3, kExit = 4 };
 
+// The next face a ray crosses (Amanatides & Woo): the axis with the smallest
+// face distance (ties: x, then y, then z) and that distance. Shared by every
+// driver, so that each packet takes the same faces whichever driver walks it.
+struct Face {
+    bool bx, by, bz;
+    double tn;
+};
+
+__device__ __forceinline__ Face next_face(double tmx, double tmy, double tmz)
+{
+    Face f;
+    f.bx = tmx <= tmy && tmx <= tmz;
+    f.by = !f.bx && tmy <= tmz;
+    f.bz = !f.bx && !f.by;
+    // the chosen distance, selected on the bit patterns (fmin would
+    // canonicalise its operands with three extra FP64 instructions)
+    const long long ux = __double_as_longlong(tmx), uy = __double_as_longlong(tmy), uz = __double_as_longlong(tmz);
+    f.tn = __longlong_as_double(f.bx ? ux : (f.by ? uy : uz));
+    return f;
+}
+
+// The line physics of one segment of length s (cells) through a cell of
+// true-absorption depth kap per unit swept profile: the Hubble drift to
+// xo = x - delta s (App. A step 4), the stop at -x_eff on the last segment
+// (esc), and the expected-value deposit d of the absorbed weight (zero unless
+// walk). One function for every driver: the same bits wherever a packet
+// crosses a cell.
+struct Segment {
+    float xo;
+    bool esc;
+    uint32_t d;
+};
+
+template <bool VOIGT>
+__device__ __forceinline__ Segment segment(float x, float s, float delta, float xeff, float kap, uint32_t w,
+                                           bool walk, const Line &ln)
+{
+    Segment g;
+    g.xo = fmaf(-delta, s, x);
+    g.esc = g.xo <= -xeff;
+    const float dx = g.esc ? x + xeff : delta * s;
+    const float dphi = VOIGT ? swept_profile_voigt(x, dx, ln.damp) : swept_profile(x, dx);
+    g.d = walk ? absorbed_share(w, kap * dphi) : 0u;
+    return g;
+}
+
+// The far damping wing's share of an escaping packet's weight (Voigt): the
+// wing beyond the stopping frequency xs, crossed at the box's mean kappa.
+__device__ __forceinline__ uint32_t wing_share(uint32_t w, float xs, const Line &ln)
+{
+    return absorbed_share(w, ln.kfar * cumulative_voigt(xs, ln.damp));
+}
+
 // One (packet, cell) segment. Returns kAlive, or the packet's fate, or kExit
 // when the next cell is outside the sink's region: the packet then stands on
 // the face with its pre-jump frequency and the old cell's velocity, and the
@@ -338,15 +401,10 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     const bool capped = !gone && L.ncross >= max_cross;
     const bool walk = act && !gone && !capped;
 
-    // next face (ties: x, then y, then z) and the neighbour behind it
-    const bool bx = L.tmx <= L.tmy && L.tmx <= L.tmz;
-    const bool by = !bx && L.tmy <= L.tmz;
-    const bool bz = !bx && !by;
-    // the chosen face's distance, selected on the bit patterns (fmin would
-    // canonicalise its operands with three extra FP64 instructions)
-    const long long ux = __double_as_longlong(L.tmx), uy = __double_as_longlong(L.tmy),
-                    uz = __double_as_longlong(L.tmz);
-    const double tn = __longlong_as_double(bx ? ux : (by ? uy : uz));
+    // next face and the neighbour behind it
+    const Face f = next_face(L.tmx, L.tmy, L.tmz);
+    const bool bx = f.bx, by = f.by, bz = f.bz;
+    const double tn = f.tn;
     // only the coordinate on the chosen axis moves, by one cell (periodic);
     // sums of field-or-zero terms: a choice between fields would make the
     // compiler address the lane state in memory
@@ -364,13 +422,11 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     const bool stay = sink.inside(jx, jy, jz);
     const Rec nr = sink.template fetch<VEL>(rec, cn, jx, jy, jz, stay);   // in flight during the profile arithmetic
 
-    // Hubble drift across the segment; the last one stops at -x_eff
-    const float s = (float)(tn - L.t);
-    const float xo = fmaf(-L.delta, s, L.x);
-    const bool esc = xo <= -L.xeff;
-    const float dx = esc ? L.x + L.xeff : L.delta * s;
-    const float dphi = VOIGT ? swept_profile_voigt(L.x, dx, ln.damp) : swept_profile(L.x, dx);
-    const uint32_t d = walk ? absorbed_share(L.w, L.kap * dphi) : 0u;
+    // Hubble drift across the segment (the last one stops at -x_eff) and the deposit
+    const Segment g = segment<VOIGT>(L.x, (float)(tn - L.t), L.delta, L.xeff, L.kap, L.w, walk, ln);
+    const float xo = g.xo;
+    const bool esc = g.esc;
+    const uint32_t d = g.d;
     if (d) sink.deposit(L, d);
     L.w -= d;
     deposited += d;
@@ -383,8 +439,7 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     wing = 0u;
     if (VOIGT && fate == kEscaped) {
         // the far damping wing beyond the stopping frequency
-        const float xs = gone ? L.x : -L.xeff;
-        wing = absorbed_share(L.w, ln.kfar * cumulative_voigt(xs, ln.damp));
+        wing = wing_share(L.w, gone ? L.x : -L.xeff, ln);
     }
 
     // cross the face
