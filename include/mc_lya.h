@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MC_LYA_ABI_VERSION 3
+#define MC_LYA_ABI_VERSION 4
 
 typedef struct mc_lya_ctx mc_lya_ctx;
 
@@ -201,19 +201,43 @@ enum {
                                      generations */
 };
 
+/* What a context reserves at mc_lya_init. Every device buffer of the
+ * context is allocated there, sized by the boxes and by these limits; no later
+ * call allocates device memory (a HIP graph captured with MC_LYA_OPT_GRAPH is
+ * the HIP runtime's own). The sizing rule, for C cells in all boxes, T tiles
+ * of 16^3 cells and N = max_packets:
+ *   per cell    the packed record (4 bytes, 16 with a velocity field), the
+ *               emission weight, quantised weight, packet count, first packet
+ *               and absorbed tally (36 bytes), plus 48 bytes with evolve = 1;
+ *   per packet  its cell (4 bytes) and two generations of tiled-walk
+ *               hand-over state (234 bytes): about 238 bytes x N; if that much
+ *               cannot be allocated, init halves the hand-over part down to
+ *               2^25 packets and the tiled walk then walks larger emissions in
+ *               batches of that size;
+ *   per tile    its table entry and exit lists (about 140 bytes);
+ *   per box     a few hundred bytes of tables and per-block partial sums. */
+typedef struct mc_lya_limits {
+    uint64_t max_packets;         /* most packets one mc_lya_emit may emit over all boxes,
+                                     1 <= max_packets < 2^40 */
+    int32_t evolve;               /* 1: reserve mc_lya_evolve's six doubles per cell; 0: that
+                                     call returns ESTATE */
+    int32_t reserved;             /* 0 */
+} mc_lya_limits;
+
 /* Creates a context for n_boxes boxes, validates and packs their fields
  * (Sec. III.A.1 quantities per cell: n_1s, the true-absorption depth kappa_c
  * of Eq. (<fnu>), the bulk velocity, the emission weight) and allocates every
- * device buffer except the per-packet queue (sized by mc_lya_emit).
+ * device buffer the context will use (mc_lya_limits states the sizes).
  *   out      host, receives the context (set to NULL on failure)
  *   boxes    host [n_boxes]; the field pointers must stay valid and unchanged
  *            until mc_lya_destroy, or until they are refreshed
  *   n_boxes  1 to 1024
+ *   limits   host, or NULL for max_packets = 2^20 and no evolve buffers
  *   stream   hipStream_t to run on (NULL = the default stream)
  * Synchronises the stream (to report invalid fields). Errors: EINVAL,
  * ENOMEM, EOVERFLOW, EDEVICE. */
 mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_t n_boxes,
-                          void *stream);
+                          const mc_lya_limits *limits, void *stream);
 
 /* Re-reads the field arrays of every box (same pointers, new contents) and
  * repacks them. Synchronises the stream. Afterwards mc_lya_emit must be called. */
@@ -223,10 +247,11 @@ mc_lya_status mc_lya_refresh(mc_lya_ctx *ctx);
  * the emission weight (systematic integer allocation: cell c receives
  * floor-based counts with |N_c - N q_c / sum q| < 1, q_c = floor(2^32 S_c /
  * max S)), zeroes the tallies, and keys packet p of box b to the Philox4x32-10
- * stream (key = seeds[b], counter = (p, s)). May (re)allocate the packet queue
- * when the total packet count grows.
- *   seeds, n_packets  host [n_boxes]; n_packets[b] may be 0
- * Errors: EINVAL, EOVERFLOW (w0 * packets >= 2^63), ENOMEM, ESTATE, EDEVICE. */
+ * stream (key = seeds[b], counter = (p, s)).
+ *   seeds, n_packets  host [n_boxes]; n_packets[b] may be 0, their sum at most
+ *                     the context's max_packets
+ * Errors: EINVAL (also: more packets than max_packets), EOVERFLOW (w0 *
+ * packets >= 2^63), ESTATE, EDEVICE. */
 mc_lya_status mc_lya_emit(mc_lya_ctx *ctx, const uint64_t *seeds, const uint64_t *n_packets);
 
 /* Walks every emitted packet (App. A steps 1-4 and the red-wing exit) and
@@ -234,9 +259,7 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *ctx, const uint64_t *seeds, const uint64_t
  * Asynchronous on the context's stream, except that the tiled walk (kernel 2)
  * synchronises to learn whether packets are still in flight: after a first
  * round of as many generations as the previous transport needed, then after
- * every 16 more. It may allocate its packet-state buffers on first use (the
- * whole emission's, if they fit a third of the free device memory).
- * Errors: ESTATE, ENOMEM, EDEVICE. */
+ * every 16 more. Errors: ESTATE, EDEVICE. */
 mc_lya_status mc_lya_transport(mc_lya_ctx *ctx);
 
 /* As mc_lya_transport, for global packet ids [first, first + count) only.
@@ -330,7 +353,7 @@ typedef struct mc_lya_scatter_record {
  *            the emission's frequencies, no return test)
  *   records  dev [count], or NULL
  * Asynchronous on the context's stream. Errors: EINVAL (range, options),
- * ESTATE, ENOMEM, EDEVICE. */
+ * ESTATE, EDEVICE. */
 mc_lya_status mc_lya_scatter(mc_lya_ctx *ctx, uint64_t first, uint64_t count,
                              const mc_lya_scatter_opts *opts, mc_lya_scatter_record *records);
 
@@ -350,9 +373,9 @@ mc_lya_status mc_lya_scatter(mc_lya_ctx *ctx, uint64_t first, uint64_t count,
  *   X_out  host [n_steps + 1][n_boxes], or NULL: the global X_e = <n_e>/<n_H>
  *          of each box at z0 and after every step.
  * The context is left at z1 and re-packed (emit before transporting again).
- * The call allocates 6 doubles per cell on first use and synchronises the
- * stream at every stage. Errors: EINVAL, ESTATE, ENOMEM, EDEVICE, and those of
- * the emission and transport. */
+ * It uses the six doubles per cell reserved with limits.evolve = 1 (ESTATE
+ * without them) and synchronises the stream at every stage. Errors: EINVAL,
+ * ESTATE, EDEVICE, and those of the emission and transport. */
 mc_lya_status mc_lya_evolve(mc_lya_ctx *ctx, double z0, double z1, int32_t n_steps, const uint64_t *n_packets,
                             uint64_t seed, float *const *x_e, double *X_out);
 
@@ -390,7 +413,8 @@ typedef struct mc_lya_tune_result {
  * the context as after mc_lya_emit (tallies zero), ready for mc_lya_transport.
  * Costs about (reps + 1) x 12 transports. result: host, or NULL.
  * Synchronises the stream. Errors: EINVAL (reps outside [1, 100]), ESTATE
- * (before mc_lya_emit), EDEVICE. */
+ * (before mc_lya_emit), EDEVICE; after an error the options are those the call
+ * started with. */
 mc_lya_status mc_lya_autotune(mc_lya_ctx *ctx, int32_t reps, mc_lya_tune_result *result);
 
 /* Sum of the durations of the transport kernels since the last call (ms),

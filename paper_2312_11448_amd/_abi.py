@@ -38,6 +38,10 @@ class mc_lya_box_desc(C.Structure):
                 ("x_e_uniform", C.c_float), ("profile", C.c_int32), ("source", C.c_void_p)]
 
 
+class mc_lya_limits(C.Structure):
+    _fields_ = [("max_packets", C.c_uint64), ("evolve", C.c_int32), ("reserved", C.c_int32)]
+
+
 class mc_lya_box_stats(C.Structure):
     _fields_ = [("emitted", C.c_int64), ("absorbed", C.c_int64), ("escaped", C.c_int64),
                 ("capped_weight", C.c_int64), ("capped_packets", C.c_int64),
@@ -119,7 +123,7 @@ def load():
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     vp, u64, i32, i64 = C.c_void_p, C.c_uint64, C.c_int32, C.c_int64
-    L.mc_lya_init.argtypes = [P(vp), P(mc_lya_box_desc), i32, vp]
+    L.mc_lya_init.argtypes = [P(vp), P(mc_lya_box_desc), i32, P(mc_lya_limits), vp]
     L.mc_lya_refresh.argtypes = [vp]
     L.mc_lya_emit.argtypes = [vp, P(u64), P(u64)]
     L.mc_lya_transport.argtypes = [vp]
@@ -176,15 +180,21 @@ def _arr(ctype, values):
     return (ctype * len(values))(*values)
 
 
-def mc_lya_init(boxes, stream=None):
+def mc_lya_init(boxes, stream=None, max_packets=None, evolve=False):
     """boxes: sequence of mc_lya_box_desc; stream: hipStream_t as int (None =
-    torch's current stream). Returns the context handle."""
+    torch's current stream); max_packets / evolve: the mc_lya_limits (None:
+    the library's defaults). Returns the context handle."""
     L = load()
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     arr = (mc_lya_box_desc * len(boxes))(*boxes)
     ctx = C.c_void_p()
-    _check(L.mc_lya_init(C.byref(ctx), arr, len(boxes), C.c_void_p(stream)))
+    lim = None
+    if max_packets is not None or evolve:
+        lim = mc_lya_limits(max_packets=int(max_packets if max_packets is not None else 1 << 20),
+                            evolve=1 if evolve else 0, reserved=0)
+    _check(L.mc_lya_init(C.byref(ctx), arr, len(boxes), None if lim is None else C.byref(lim),
+                         C.c_void_p(stream)))
     return ctx
 
 

@@ -21,6 +21,7 @@ static_assert(sizeof(mc_lya_scatter_opts) == 40, "mc_lya_scatter_opts layout");
 static_assert(sizeof(mc_lya_feed_stats) == 56, "mc_lya_feed_stats layout");
 static_assert(sizeof(mc_lya_packet_trace) == 64, "mc_lya_packet_trace layout");
 static_assert(sizeof(mc_lya_tune_result) == 88, "mc_lya_tune_result layout");
+static_assert(sizeof(mc_lya_limits) == 16, "mc_lya_limits layout");
 
 namespace {
 
@@ -91,6 +92,7 @@ hipError_t dalloc(T **p, size_t n)
 }  // namespace
 
 constexpr int kEagerGens = 16;
+constexpr uint64_t kDefaultMaxPackets = 1ull << 20;   // limits == NULL
 
 struct mc_lya_ctx {
     hipStream_t stream = nullptr;
@@ -121,14 +123,14 @@ struct mc_lya_ctx {
     uint32_t *d_npk = nullptr;
     unsigned long long *d_A = nullptr;
     unsigned long long *d_queue = nullptr;
-    ScatBox *d_sbox = nullptr;               // scattering constants per box (allocated on first use)
-    double *d_ev = nullptr;                  // evolution: y0, k0..k3, ndot [6][total cells] (first use)
+    ScatBox *d_sbox = nullptr;               // scattering constants per box
+    double *d_ev = nullptr;                  // evolution: y0, k0..k3, ndot [6][total cells] (limits.evolve)
     double *d_ev_coef = nullptr;             // evolution: -1 / (n_H (1+z) H) per box
+    uint64_t max_packets = 0;                // packet capacity reserved at init (limits.max_packets)
     unsigned long long *d_boxabs = nullptr;
     double *d_fsum = nullptr;
     FeedBox *d_feed = nullptr;
-    uint32_t *d_cop = nullptr;
-    uint64_t cop_cap = 0;
+    uint32_t *d_cop = nullptr;               // [max_packets] cell of each packet
     bool cop_valid = false;      // d_cop holds the cells of the current emission
     uint64_t *d_pfirst = nullptr;
 
@@ -417,11 +419,13 @@ mc_lya_status classify_boxes(mc_lya_ctx *c)
     return MC_LYA_OK;
 }
 
-// Packets per tiled batch: the whole emission when the packet-state buffers
-// for it (two generations' states, faces and indices) fit in a third of the
-// free device memory, else as many as do, at least 2^25. Fewer batches mean
-// fewer per-generation tile loads and flushes; the 2^28 packets of the 256^3
-// workload (63 GB of state) are one batch on a 288 GB device.
+// Packets per tiled batch: the packet-state buffers (two generations'
+// states, faces and indices) are reserved at init for max_packets packets,
+// or, if that much memory cannot be had, for as many as fit in halving steps
+// down to 2^25; a larger emission then walks in batches. Every batch repeats
+// the per-generation tile loads and flushes, so fewer batches are faster;
+// the 2^28 packets of the 256^3 workload (63 GB of state) are one batch on a
+// 288 GB device.
 constexpr uint64_t kMinTiledBatch = 1ull << 25;
 constexpr int kGenRound = 16;                  // generations queued between two checks
 constexpr uint64_t kStateBytes = 2 * (sizeof(PState) + sizeof(uint8_t) + sizeof(uint32_t));
@@ -437,20 +441,12 @@ void free_tile_buffers(mc_lya_ctx *c)
         c->d_idx[i] = nullptr;
     }
     c->state_cap = 0;
-    ++c->epoch;
 }
 
-mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
+// The packet-state buffers of the tiled walk (init only).
+hipError_t alloc_tile_buffers(mc_lya_ctx *c, uint64_t packets)
 {
-    packets = std::max<uint64_t>(1, packets);
-    if (packets <= c->state_cap) return MC_LYA_OK;             // one batch already
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    size_t free_b = 0, total_b = 0;
-    HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
-    const uint64_t avail = (uint64_t)free_b + c->state_cap * kStateBytes;   // the current buffers are released
-    uint64_t cap = std::min(packets, std::max(kMinTiledBatch, avail / 3 / kStateBytes));
-    if (cap <= c->state_cap) return MC_LYA_OK;                 // no larger batch possible: keep batching
-    free_tile_buffers(c);
+    uint64_t cap = std::max<uint64_t>(1, packets);
     for (;;) {
         hipError_t e = hipSuccess;
         for (int i = 0; i < 2 && e == hipSuccess; ++i) {
@@ -460,12 +456,11 @@ mc_lya_status ensure_tile_buffers(mc_lya_ctx *c, uint64_t packets)
         if (e == hipSuccess) break;
         free_tile_buffers(c);
         (void)hipGetLastError();
-        if (e != hipErrorOutOfMemory || cap <= kMinTiledBatch) return hip_fail(c, e, "packet-state buffers");
-        cap = std::max(kMinTiledBatch, cap / 2);               // fragmented memory: smaller batches
+        if (e != hipErrorOutOfMemory || cap <= kMinTiledBatch) return e;
+        cap = std::max(kMinTiledBatch, cap / 2);               // smaller batches
     }
     c->state_cap = cap;
-    ++c->epoch;
-    return MC_LYA_OK;
+    return hipSuccess;
 }
 
 // Event pairs: one per walk launch (timing 1), or one per transport with the
@@ -662,21 +657,12 @@ mc_lya_status walk_tiled(mc_lya_ctx *c, uint64_t first, uint64_t count)
 }
 
 // The per-packet cell list, built on first use after an emission (the
-// persistent, per-packet and trace kernels take packets by id).
+// persistent, per-packet and trace kernels take packets by id) in the buffer
+// reserved at init.
 mc_lya_status ensure_cell_of_packet(mc_lya_ctx *c)
 {
     if (c->cop_valid) return MC_LYA_OK;
     const uint64_t ntot = c->total_packets;
-    if (ntot > c->cop_cap) {
-        uint32_t *np = nullptr;
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&np), ntot * sizeof(uint32_t));
-        if (e != hipSuccess) return hip_fail(c, e, "packet queue allocation");
-        if (c->d_cop) (void)hipFree(c->d_cop);
-        c->d_cop = np;
-        c->cop_cap = ntot;
-        ++c->epoch;
-    }
     if (ntot) HIP_TRY(c, launch_cell_of_packet(c->d_pack, c->n_boxes, c->max_blk, c->d_npk, c->d_pfirst, c->d_cop,
                                                c->stream));
     c->cop_valid = true;
@@ -721,10 +707,6 @@ mc_lya_status plan_walk(mc_lya_ctx *c, uint64_t first, uint64_t count, WalkPlan 
         mc_lya_status st = classify_boxes(c);
         if (st != MC_LYA_OK) return st;
         w->tiled = !c->tiles.empty();
-        if (w->tiled) {
-            st = ensure_tile_buffers(c, c->total_packets);
-            if (st != MC_LYA_OK) return st;
-        }
         std::vector<uint64_t> starts, ids;
         uint64_t n = 0;
         for (int b = 0; b < c->n_boxes; ++b) {
@@ -939,13 +921,20 @@ const char *mc_lya_strerror(mc_lya_status s)
 
 const char *mc_lya_last_error(const mc_lya_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_err.c_str(); }
 
-mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_t n_boxes, void *stream)
+mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_t n_boxes,
+                          const mc_lya_limits *limits, void *stream)
 {
     g_init_err.clear();
     if (!out) return fail(nullptr, MC_LYA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!boxes || n_boxes < 1 || n_boxes > 1024)
         return fail(nullptr, MC_LYA_EINVAL, "need 1 to 1024 box descriptors");
+    mc_lya_limits lim{};
+    lim.max_packets = kDefaultMaxPackets;
+    if (limits) lim = *limits;
+    if (lim.max_packets == 0 || lim.max_packets >= (1ull << 40))
+        return fail(nullptr, MC_LYA_EINVAL, "limits.max_packets must be in [1, 2^40)");
+    if (lim.evolve != 0 && lim.evolve != 1) return fail(nullptr, MC_LYA_EINVAL, "limits.evolve must be 0 or 1");
     uint64_t cells = 0;
     for (int b = 0; b < n_boxes; ++b) {
         const std::string why = check_desc(boxes[b], b);
@@ -957,6 +946,7 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
     if (!c) return fail(nullptr, MC_LYA_ENOMEM, "host allocation failed");
     c->stream = static_cast<hipStream_t>(stream);
     c->n_boxes = n_boxes;
+    c->max_packets = lim.max_packets;
     c->desc.assign(boxes, boxes + n_boxes);
     c->total_cells = cells;
     c->pack.resize(n_boxes);
@@ -1019,7 +1009,12 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         (e = dalloc(&c->d_queue, kMaxQueues)) != hipSuccess || (e = dalloc(&c->d_boxabs, n_boxes)) != hipSuccess ||
         (e = dalloc(&c->d_fsum, (size_t)4 * n_boxes)) != hipSuccess ||
         (e = dalloc(&c->d_feed, n_boxes)) != hipSuccess || (e = dalloc(&c->d_pfirst, cells)) != hipSuccess ||
-        (e = dalloc(&c->d_seg, 2 * ((size_t)n_boxes + 1))) != hipSuccess)
+        (e = dalloc(&c->d_seg, 2 * ((size_t)n_boxes + 1))) != hipSuccess ||
+        (e = dalloc(&c->d_featbox, n_boxes)) != hipSuccess || (e = dalloc(&c->d_sbox, n_boxes)) != hipSuccess ||
+        (e = dalloc(&c->d_cop, lim.max_packets)) != hipSuccess ||
+        (lim.evolve && ((e = dalloc(&c->d_ev, 6 * cells)) != hipSuccess ||
+                        (e = dalloc(&c->d_ev_coef, (size_t)n_boxes)) != hipSuccess)) ||
+        (e = alloc_tile_buffers(c, lim.max_packets)) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
     c->cpp.assign(n_boxes, 1.0);
     c->tiled.assign(n_boxes, 1);         // the tile table starts with every box; emit narrows it
@@ -1064,6 +1059,9 @@ mc_lya_status mc_lya_emit(mc_lya_ctx *c, const uint64_t *seeds, const uint64_t *
     }
     if (weight >= ((unsigned __int128)1 << 63) || total >= ((unsigned __int128)1 << 40))
         return fail(c, MC_LYA_EOVERFLOW, "total packets or total weight too large");
+    if (total > c->max_packets)
+        return fail(c, MC_LYA_EINVAL, "more packets than the max_packets reserved at mc_lya_init (" +
+                                          std::to_string(c->max_packets) + ")");
     const uint64_t ntot = (uint64_t)total;
     uint64_t off = 0;
     for (int b = 0; b < c->n_boxes; ++b) {
@@ -1156,10 +1154,6 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
     if (!out) return fail(c, MC_LYA_EINVAL, "out is NULL");
     if (c->state < 0) return fail(c, MC_LYA_ESTATE, "fields failed validation; call mc_lya_refresh");
     const int nb = c->n_boxes;
-    if (!c->d_featbox) {
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&c->d_featbox), sizeof(FeatBox) * nb);
-        if (e != hipSuccess) return hip_fail(c, e, "feature table allocation");
-    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
     c->featbox.resize(nb);
     for (int b = 0; b < nb; ++b) {
@@ -1300,10 +1294,6 @@ mc_lya_status mc_lya_scatter(mc_lya_ctx *c, uint64_t first, uint64_t count, cons
     mc_lya_status st = ensure_cell_of_packet(c);
     if (st != MC_LYA_OK) return st;
     const int nb = c->n_boxes;
-    if (!c->d_sbox) {
-        hipError_t e = dalloc(&c->d_sbox, (size_t)nb);
-        if (e != hipSuccess) return hip_fail(c, e, "scattering table allocation");
-    }
     std::vector<ScatBox> sb(nb);
     for (int b = 0; b < nb; ++b) {
         const phys::Box &ph = c->ph[b];
@@ -1398,11 +1388,7 @@ mc_lya_status mc_lya_evolve(mc_lya_ctx *c, double z0, double z1, int32_t n_steps
         if (!x_e[b] || x_e[b] != c->desc[b].x_e)
             return fail(c, MC_LYA_EINVAL, "box " + std::to_string(b) + ": x_e must be its descriptor's x_e field");
     const size_t n = c->total_cells;
-    if (!c->d_ev) {
-        hipError_t e = dalloc(&c->d_ev, 6 * n);
-        if (e == hipSuccess) e = dalloc(&c->d_ev_coef, (size_t)nb);
-        if (e != hipSuccess) return hip_fail(c, e, "evolution buffers");
-    }
+    if (!c->d_ev) return fail(c, MC_LYA_ESTATE, "mc_lya_evolve needs limits.evolve = 1 at mc_lya_init");
     double *y0 = c->d_ev, *ndot = c->d_ev + 5 * n;
     double *k[4] = {c->d_ev + n, c->d_ev + 2 * n, c->d_ev + 3 * n, c->d_ev + 4 * n};
     HIP_TRY(c, launch_xe_load(c->d_pack, nb, c->max_blk, y0, c->stream));
@@ -1555,6 +1541,17 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto finish = [&](mc_lya_status st) {
         c->timing = timing;
+        if (st != MC_LYA_OK) {
+            // a failed tuning leaves the options it started with
+            c->kernel = start.kernel;
+            c->tile_share = start.share;
+            c->block = start.block;
+            c->waves_per_cu = start.waves;
+            c->chunk = start.chunk;
+            c->refill = start.refill;
+            c->tile_chunk = start.tchunk;
+            c->tile_refill = start.trefill;
+        }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         return st;

@@ -64,9 +64,12 @@ _PROFILES = {"doppler": A.MC_LYA_PROFILE_DOPPLER, "voigt": A.MC_LYA_PROFILE_VOIG
 
 
 class Simulation:
-    """One context over ``specs`` (a box spec or a list of them)."""
+    """One context over ``specs`` (a box spec or a list of them). The context
+    reserves its device memory here: room for ``max_packets`` packets per
+    emission (default: the specs' packet counts summed) and, with
+    ``evolve=True``, the buffers of the recombination history."""
 
-    def __init__(self, specs, device="cuda", stream=None):
+    def __init__(self, specs, device="cuda", stream=None, max_packets=None, evolve=False):
         if not isinstance(specs, (list, tuple)):
             specs = [specs]
         self.specs = list(specs)
@@ -78,7 +81,10 @@ class Simulation:
         self.total_cells = int(sum(self.ncells))
         self.cell_off = np.concatenate([[0], np.cumsum(self.ncells)]).astype(np.int64)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        self.ctx = A.mc_lya_init(descs, self.stream)
+        if max_packets is None:
+            max_packets = max(1, sum(int(s.n_packets) for s in self.specs))
+        self.max_packets = int(max_packets)
+        self.ctx = A.mc_lya_init(descs, self.stream, max_packets=self.max_packets, evolve=evolve)
         self.n_packets = [0] * len(self.specs)
 
     # -- C calls --------------------------------------------------------------

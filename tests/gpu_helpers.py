@@ -10,7 +10,8 @@ CELL_REL, CELL_FLOOR, GLOBAL_REL = 1e-3, 1e-6, 1e-5
 
 def gpu_run(spec, options=None, ranges=None, seeds=None, n_packets=None):
     import paper_2312_11448_amd as M
-    with M.Simulation(spec) as sim:
+    cap = None if n_packets is None else max(1, sum(int(n) for n in n_packets))
+    with M.Simulation(spec, max_packets=cap) as sim:
         for k, v in (options or {}).items():
             sim.set_option(k, v)
         sim.emit(seeds, n_packets)

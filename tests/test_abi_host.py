@@ -41,6 +41,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(M.mc_lya_scatter_opts) == 40
     assert C.sizeof(M.mc_lya_feed_stats) == 56
     assert C.sizeof(M.mc_lya_tune_result) == 88
+    assert C.sizeof(M.mc_lya_limits) == 16
     # 4 int32, 11 doubles, w0, 3 pointers, float + int32, 1 pointer
     assert C.sizeof(M.mc_lya_box_desc) == 16 + 88 + 8 + 24 + 8 + 8
 
@@ -74,6 +75,20 @@ def test_init_rejects_bad_descriptors_before_any_device_call(bad, msg):
         M.mc_lya_init([_desc(M, **bad)], stream=0)
     assert e.value.status == M.MC_LYA_EINVAL
     assert msg in str(e.value)
+
+
+@pytest.mark.parametrize("limits,msg", [(dict(max_packets=0), "max_packets"),
+                                        (dict(max_packets=1 << 40), "max_packets"),
+                                        (dict(max_packets=10, evolve=2), "evolve")])
+def test_init_rejects_bad_limits_before_any_device_call(limits, msg):
+    M = _lib()
+    L = M.load()
+    lim = M.mc_lya_limits(**limits)
+    arr = (M.mc_lya_box_desc * 1)(_desc(M))
+    ctx = C.c_void_p()
+    assert L.mc_lya_init(C.byref(ctx), arr, 1, C.byref(lim), None) == M.MC_LYA_EINVAL
+    assert not ctx.value
+    assert msg in L.mc_lya_last_error(None).decode()
 
 
 def test_null_context_calls():

@@ -60,7 +60,7 @@ def test_evolve_matches_oracle_driven_history():
     spec = W.BoxSpec(n=(2, 1, 1), overdensity=od, x_e=xe, z=1300.0, temp_K=COSMO.t_cmb0 * 1301.0,
                      n_packets=5000, seed=5)
     xo, Xo = R.evolve_mc(spec, 1300.0, 1297.0, 3, 5000, 5)
-    with M.Simulation(spec) as sim:
+    with M.Simulation(spec, evolve=True) as sim:
         X = sim.evolve(1300.0, 1297.0, 3, [5000], 5)
         xg = sim.x_e_field(0).cpu().numpy().reshape(-1)
     _say(f"  gpu {xg} oracle {xo}; X gpu {X[:, 0]} oracle {Xo}")
@@ -76,7 +76,7 @@ def test_evolve_full_mixing_regime():
     y0 = _start("full_mixing")
     spec, plus = two_zone_box(10.0, y0, 20000)
     z1, steps = 1100.0, 400
-    with M.Simulation(spec) as sim:
+    with M.Simulation(spec, evolve=True) as sim:
         X = sim.evolve(1300.0, z1, steps, [20000], 7)
         xe = sim.x_e_field(0).cpu().numpy().reshape(spec.overdensity.shape)
     zp, zm = xe[:, :, plus].mean(), xe[:, :, ~plus].mean()
@@ -98,7 +98,7 @@ def test_evolve_local_regime_global_xe():
     y0 = _start("no_mixing")
     spec, plus = two_zone_box(1e4, y0, 20000)
     z1, steps = 1100.0, 400
-    with M.Simulation(spec) as sim:
+    with M.Simulation(spec, evolve=True) as sim:
         X = sim.evolve(1300.0, z1, steps, [20000], 7)
     ze = np.linspace(1300.0, z1, steps + 1)
     for mode in ("no_mixing", "full_mixing"):
@@ -110,12 +110,17 @@ def test_evolve_local_regime_global_xe():
 
 def test_evolve_errors():
     spec, _ = two_zone_box(10.0, (0.5, 0.5), 100, n=2)
-    with M.Simulation(spec) as sim:
+    with M.Simulation(spec, evolve=True) as sim:
         with pytest.raises(M.MCLyaError):
             sim.evolve(1100.0, 1300.0, 1)                       # backwards in time
         with pytest.raises(M.MCLyaError):
             sim.evolve(1300.0, 1200.0, 0)
+    # a context reserved without the evolve buffers refuses the call
+    with M.Simulation(spec) as sim:
+        with pytest.raises(M.MCLyaError) as e:
+            sim.evolve(1300.0, 1299.0, 1)
+        assert e.value.status == M.MC_LYA_ESTATE and "evolve" in str(e.value)
     uniform = W.make_box("c1", n=4, n_packets=100)
-    with M.Simulation(uniform) as sim:
+    with M.Simulation(uniform, evolve=True) as sim:
         with pytest.raises((M.MCLyaError, ValueError)):
             sim.evolve(1300.0, 1200.0, 1)                       # no x_e field

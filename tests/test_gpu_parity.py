@@ -257,6 +257,10 @@ def test_errors_and_cap():
         with pytest.raises(M.MCLyaError) as e:
             sim.emit(n_packets=[1 << 33])
         assert e.value.status == M.MC_LYA_EOVERFLOW
+        # more packets than the context reserved room for at init
+        with pytest.raises(M.MCLyaError) as e:
+            sim.emit(n_packets=[1001])
+        assert e.value.status == M.MC_LYA_EINVAL and "max_packets" in str(e.value)
         sim.emit(n_packets=[0])
         sim.transport()
         t = sim.tally()
