@@ -482,9 +482,10 @@ mc_lya_status mc_lya_mlp_get_params(mc_lya_mlp *mlp, float *params);
  * Errors: EINVAL, EDEVICE. */
 mc_lya_status mc_lya_mlp_set_envelope(mc_lya_mlp *mlp, const float *lo, const float *hi);
 
-/* Inference: y = network(features) for n cells, on the matrix cores with
- * BF16 weights and activations and FP32 accumulation (biases, activations and
- * the last layer in FP32).
+/* Inference: y = network(features) for n cells, on the matrix cores: W1, W2,
+ * the features and the layer-1 activations in BF16, FP32 accumulation, each
+ * of b1 and b2 as the BF16 pair hi = bf16(b), lo = bf16(b - hi) (b to 2^-16),
+ * the last layer (w3, b3) in FP32. Training differentiates this same function.
  *   features  dev [n][8] float
  *   y         dev [n] float
  *   outside   dev [n] uint8 (1 = some feature outside the envelope), or NULL
@@ -494,8 +495,12 @@ mc_lya_status mc_lya_mlp_forward(mc_lya_mlp *mlp, const float *features, uint64_
                                  uint8_t *outside, uint64_t *n_outside);
 
 /* The weighted mean squared error L = sum w_i (y_i - t_i)^2 / sum w_i over n
- * cells and its gradient with respect to the parameters, in FP32 (cells are
- * summed in a fixed order: the result is reproducible bit for bit).
+ * cells of the network mc_lya_mlp_forward evaluates, and its gradient with
+ * respect to the FP32 parameters (each BF16 rounding passed through
+ * unchanged), on the matrix cores: the forward and backward products in BF16
+ * with FP32 accumulation, the error signals dL/dz rounded to BF16, the w3, b2
+ * and b3 gradients summed in FP32. Cells are summed in a fixed order: the
+ * result is reproducible bit for bit.
  *   features dev [n][8], targets dev [n], weights dev [n] (>= 0, not all 0)
  *   grad     host [MC_LYA_MLP_PARAMS], or NULL;  loss host, or NULL
  * Synchronises. Errors: EINVAL, EDEVICE. */

@@ -32,6 +32,13 @@ Parameters are one flat vector of 4801 numbers:
   w3 [64] at 4736, b3 at 4800;  row-major [out][in].
 Loss: weighted mean squared error sum_i w_i (y_i - t_i)^2 / sum_i w_i.
 Optimiser: Adam (Kingma & Ba 2015, Algorithm 1) with bias correction.
+
+The network as the matrix cores evaluate it ("bf16" below): the features, W1,
+W2 and the layer-1 activations rounded to bfloat16 (8 significant bits, ties
+to even), each of b1 and b2 as the two bfloat16 terms hi = bf16(b),
+lo = bf16(b - hi) (their sum is b to 2^-16 relative), w3, b3 and the last
+layer exact. Its gradient with respect to the unrounded parameters passes
+every rounding through unchanged (the straight-through derivative).
 """
 import numpy as np
 
@@ -149,3 +156,63 @@ def adam_step(params, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** step)
     vhat = v / (1.0 - beta2 ** step)
     return _f64(params) - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# --- the bfloat16 network ----------------------------------------------------
+def bf16(a):
+    """Round to bfloat16, ties to even, after rounding to binary32 (returned
+    as float64): on the binary32 bit pattern, add 0x7FFF plus the lowest kept
+    bit (bit 16), then clear the 16 low bits. Finite inputs only."""
+    a = np.asarray(a, dtype=np.float64)
+    f = np.ascontiguousarray(a.astype(np.float32)).reshape(-1)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(a.shape)
+
+
+def bias_split(b):
+    """b as hi + lo, hi = bf16(b), lo = bf16(b - hi) (b - hi is exact in
+    binary32 and in float64)."""
+    b32 = _f64(np.asarray(b, dtype=np.float64).astype(np.float32))
+    hi = bf16(b32)
+    return hi, bf16(b32 - hi)
+
+
+def forward_bf16(params, X):
+    """y [n] and the intermediate values of the bfloat16 network."""
+    W1, b1, W2, b2, w3, b3 = unpack(params)
+    Xb, W1b, W2b = bf16(X), bf16(W1), bf16(W2)
+    b1e, b2e = sum(bias_split(b1)), sum(bias_split(b2))
+    z1 = Xb @ W1b.T + b1e
+    h1 = bf16(relu(z1))
+    z2 = h1 @ W2b.T + b2e
+    h2 = relu(z2)
+    w3 = _f64(np.asarray(w3).astype(np.float32))
+    y = h2 @ w3 + float(np.float32(b3))
+    return y, dict(X=Xb, W2=W2b, w3=w3, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def loss_and_grad_bf16(params, X, t, w, abs_bound=False):
+    """Weighted MSE of the bfloat16 network and its straight-through gradient
+    (the chain rule of loss_and_grad with the rounded operands). With
+    abs_bound, also the same chain taken with absolute values of every factor
+    (and of dL/dy), the scale of the rounding errors of each gradient entry."""
+    y, c = forward_bf16(params, X)
+    w = _f64(w)
+    sw = w.sum()
+    r = y - _f64(t)
+    L = float((w * r * r).sum() / sw)
+    gy = 2.0 * w * r / sw
+
+    def chain(gy, w3, W2, h1, h2, X, m1, m2):
+        gz2 = np.outer(gy, w3) * m2
+        gz1 = (gz2 @ W2) * m1
+        return pack(gz1.T @ X, gz1.sum(axis=0), gz2.T @ h1, gz2.sum(axis=0), h2.T @ gy, gy.sum())
+
+    m1 = (c["z1"] > 0.0).astype(np.float64)
+    m2 = (c["z2"] > 0.0).astype(np.float64)
+    g = chain(gy, c["w3"], c["W2"], c["h1"], c["h2"], c["X"], m1, m2)
+    if not abs_bound:
+        return L, g
+    gabs = chain(np.abs(gy), np.abs(c["w3"]), np.abs(c["W2"]), c["h1"], c["h2"], np.abs(c["X"]), m1, m2)
+    return L, g, gabs

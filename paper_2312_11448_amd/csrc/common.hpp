@@ -347,7 +347,7 @@ struct FeatBox {
 
 constexpr int kMlpParams = 4801;         // 8-64-64-1 network
 constexpr int kMlpPartStride = 4808;     // floats per block of gradient partial sums (params, sum w r^2, sum w)
-constexpr int kMlpGradBlocks = 1024;     // blocks of the gradient kernel
+constexpr int kMlpGradBlocks = 1024;     // most blocks of the gradient kernel (partial-sum slots)
 
 struct MlpAdam {
     float lr, beta1, beta2, eps;
@@ -358,9 +358,9 @@ hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, floa
 hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, float *y, uint8_t *outside,
                               const float *lo, const float *hi, unsigned long long *n_out, int grid,
                               hipStream_t s);
-// partial: [blocks + ceil(blocks / 32)][kMlpPartStride] floats of workspace
+// partial: [max_blocks + ceil(max_blocks / 32)][kMlpPartStride] floats of workspace
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
-                               float *partial, int blocks, float *grad, hipStream_t s);
+                               float *partial, int max_blocks, float *grad, hipStream_t s);
 hipError_t launch_mlp_normalise(float *grad, hipStream_t s);
 hipError_t launch_mlp_adam(float *params, float *m, float *v, float *grad, const MlpAdam &a, hipStream_t s);
 

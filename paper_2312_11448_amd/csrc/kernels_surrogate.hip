@@ -1,6 +1,6 @@
 // The mixing-correction surrogate: per-cell features, the 8-64-64-1 ReLU
-// network on BF16 matrix cores (inference), and its FP32 training step
-// (weighted-MSE gradient, Adam).
+// network on BF16 matrix cores (inference and the weighted-MSE gradient of
+// training, FP32 accumulation), and Adam on the FP32 master parameters.
 //
 // The quantity approximated is y = ln M_c, M_c = A_c / A_c^fm, the ratio of a
 // cell's Monte-Carlo absorption to its full-mixing share (Sec. IV.B,
@@ -21,7 +21,8 @@ constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 47
 // max(z, 0) as one v_med3_f32 (median of z, 0 and the largest float); fmaxf
 // would first canonicalise z with a second instruction
 __device__ __forceinline__ float relu(float z) { return __builtin_amdgcn_fmed3f(z, 0.0f, 3.402823466e38f); }
-__device__ __forceinline__ float relu_grad(float z) { return z > 0.0f ? 1.0f : 0.0f; }
+// ReLU's derivative (0 at z = 0)
+__device__ __forceinline__ float step(float z) { return z > 0.0f ? 1.0f : 0.0f; }
 
 // ---- features ---------------------------------------------------------------
 // Per cell: ln Delta, mean and variance of Delta over the 27 cells around it
@@ -78,29 +79,123 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict
     o[1] = make_float4(fb.ln_t, xe, fb.z_feat, fb.ln_clump);
 }
 
-// ---- inference on matrix cores ---------------------------------------------
-// One wave evaluates 32 cells at a time with the activations held transposed
-// (hidden units along the matrix rows, cells along the columns), so the
-// layer-1 results a lane holds for its cell are the layer-2 operands it must
-// supply, and no data moves between lanes until the final dot product.
-//   Layer 1: v_mfma_f32_32x32x8_bf16 (K = the 8 features). Lane l holds
-//   A[l%32][4(l/32)+e], B[4(l/32)+e][l%32] (e = 0..3) and
-//   D[8q + 4(l/32) + t][l%32] in register 4q + t.
-//   Layer 2: v_mfma_f32_32x32x16_bf16, K = 16 hidden units per step, lane
-//   half l/32 and element e (0..7) of the A and B operands naming the same
-//   K index. Step s takes its B elements straight from the layer-1 registers,
-//   element e of lane half hb being hidden unit
-//   16 s + 8 (e / 4) + 4 hb + e % 4 (a permutation of 0..63), and the A
-//   operand (W2) is gathered in that same order.
-// Biases enter as the accumulators' initial values.
+// ---- the network on the matrix cores ----------------------------------------
+// Inference and training evaluate one function: W1, W2, the features and the
+// layer-1 activations in BF16, products accumulated in FP32, each bias b1, b2
+// entering as the two BF16 terms hi = bf16(b), lo = bf16(b - hi) (their sum
+// is b to 2^-16 relative), w3 and b3 in FP32 (the last layer on the VALU).
+//
+// An MFMA D = A B reads A with its rows on the lanes (lane % 32) and B with
+// its columns on the lanes, both with the K index in the registers: lane
+// half hb = lane / 32 and element e (0..7) of v_mfma_f32_32x32x16_bf16 name
+// K index 8 hb + e in both operands. D comes back with its columns on the
+// lanes and row 8 (r / 4) + 4 hb + r % 4 in register r.
+//   Layer 1, K = 16: the 8 features in lane half 0, and in half 1 the pair
+//   (1, 1) against the pair (hi, lo) of b1, so the bias is part of the product.
+//   Layer 2, K = 64 hidden units in four steps plus a fifth with the b2 pair.
+//   Step s takes its B elements straight from the layer-1 registers: element
+//   e of lane half hb is hidden unit l2_unit(s, hb, e) = 16 s + 8 (e / 4) +
+//   4 hb + e % 4, a permutation of 0..63, and W2 is gathered in that order.
+// Evaluated with the cells as the columns ("C": D1 = W1 X^T, D2 = W2 H1) a
+// lane holds one cell and the hidden units in its registers, which is what
+// the next layer's B operand needs, so no data moves between lanes until the
+// final dot product. Swapping A and B transposes a product ("H": D1' = X W1^T,
+// D2' = H1^T W2^T, hidden unit per lane, cells in the registers): the same
+// operand registers serve both.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// binary32 -> bfloat16, round to nearest even (one v_cvt_pk_bf16_f32 per pair)
-__device__ __forceinline__ short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
-
 __device__ __forceinline__ int l2_unit(int s, int hb, int e) { return 16 * s + 8 * (e / 4) + 4 * hb + (e % 4); }
+// row of register r of a 32x32 result, in lane half `half`
+__device__ __forceinline__ int d_row(int r, int half) { return 8 * (r >> 2) + 4 * half + (r & 3); }
+// the layer-1 register of hidden unit l2_unit(s, hb, e) (in block s / 2)
+__device__ __forceinline__ int l1_reg(int s, int e) { return 4 * (2 * (s % 2) + e / 4) + e % 4; }
+
+__device__ __forceinline__ f32x16 mfma16(const bf16x8 &a, const bf16x8 &b, const f32x16 &c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x16 zero16()
+{
+    f32x16 z;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = 0.0f;
+    return z;
+}
+
+// (hi, lo, 0, ...) in lane half 0 when `in_half0`, else in half 1; zeros in
+// the other half
+__device__ __forceinline__ bf16x8 bias_pair(float b, bool here)
+{
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.0f;
+    if (here) {
+        const __bf16 hi = (__bf16)b;
+        v[0] = hi;
+        v[1] = (__bf16)(b - (float)hi);
+    }
+    return v;
+}
+
+__device__ __forceinline__ bf16x8 ones_pair(bool here)
+{
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (__bf16)(here && e < 2 ? 1.0f : 0.0f);
+    return v;
+}
+
+// The weight operands of lane (half, col): a1[T] for unit u = 32 T + col
+// (W1[u][0..7] in half 0, the b1 pair in half 1) and a2[T][s] (W2[u][unit
+// l2_unit(s, half, e)] for s < 4, the b2 pair in half 0 for s = 4).
+struct NetOps {
+    bf16x8 a1[2];
+    bf16x8 a2[2][5];
+};
+
+__device__ __forceinline__ void load_ops(const float *__restrict__ P, int half, int col, NetOps &o)
+{
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        const int u = 32 * T + col;
+        if (half == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) o.a1[T][e] = (__bf16)P[OFF_W1 + u * kFeat + e];
+        } else {
+            o.a1[T] = bias_pair(P[OFF_B1 + u], true);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) o.a2[T][s][e] = (__bf16)P[OFF_W2 + u * kHid + l2_unit(s, half, e)];
+        o.a2[T][4] = bias_pair(P[OFF_B2 + u], half == 0);
+    }
+}
+
+// The K operand of a cell's features: the features in lane half 0, the pair
+// (1, 1) that meets the b1 pair in half 1.
+__device__ __forceinline__ bf16x8 feature_operand(const float (&x)[kFeat], int half)
+{
+    if (half == 0) {
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)x[e];
+        return v;
+    }
+    return ones_pair(true);
+}
+
+// h1 = relu(D1) as the four K steps of layer 2
+__device__ __forceinline__ void hidden_operand(const f32x16 (&d1)[2], bf16x8 (&h1)[4])
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h1[s][e] = (__bf16)relu(d1[s / 2][l1_reg(s, e)]);
+}
 
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restrict__ P, const float *__restrict__ X,
                                                           uint64_t n, float *__restrict__ y,
@@ -112,73 +207,63 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
     __shared__ unsigned long long s_cnt;
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
     if (threadIdx.x == 0) s_cnt = 0;
-    bf16x4 a1[2];
-    bf16x8 a2[2][4];
-    f32x16 c1[2], c2[2];
+    NetOps o;
+    load_ops(P, half, col, o);
+    const bf16x8 ones = ones_pair(half == 0);
     float w3r[2][16];
 #pragma unroll
-    for (int T = 0; T < 2; ++T) {
+    for (int T = 0; T < 2; ++T)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a1[T][e] = to_bf16(P[OFF_W1 + (32 * T + col) * kFeat + 4 * half + e]);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) a2[T][s][e] = (__bf16)P[OFF_W2 + (32 * T + col) * kHid + l2_unit(s, half, e)];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 32 * T + 8 * (r / 4) + 4 * half + (r % 4);
-            c1[T][r] = P[OFF_B1 + row];
-            c2[T][r] = P[OFF_B2 + row];
-            w3r[T][r] = P[OFF_W3 + row];
-        }
-    }
+        for (int r = 0; r < 16; ++r) w3r[T][r] = P[OFF_W3 + 32 * T + d_row(r, half)];
     const float b3 = P[OFF_B3];
-    float flo[4], fhi[4];
+    float flo[kFeat], fhi[kFeat];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        flo[e] = lo ? lo[4 * half + e] : -3.0e38f;
-        fhi[e] = hi ? hi[4 * half + e] : 3.0e38f;
+    for (int e = 0; e < kFeat; ++e) {
+        flo[e] = lo ? lo[e] : -3.0e38f;
+        fhi[e] = hi ? hi[e] : 3.0e38f;
     }
     __syncthreads();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const uint64_t tiles = (n + 31) / 32;
     uint32_t n_outside = 0;
-    // the next tile's features are loaded while this one is computed
-    auto load = [&](uint64_t tile) {
+    // lane half 0 loads the cell's 8 features; the next tile's while this
+    // one is computed
+    auto load = [&](uint64_t tile, float (&x)[kFeat]) {
         const uint64_t cell = tile * 32 + (uint64_t)col;
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (cell < n) v = *reinterpret_cast<const float4 *>(X + cell * kFeat + 4 * half);
-        return v;
+        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+        if (half == 0 && cell < n) {
+            a = *reinterpret_cast<const float4 *>(X + cell * kFeat);
+            b = *reinterpret_cast<const float4 *>(X + cell * kFeat + 4);
+        }
+        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
     };
-    float4 next = load(wave);
+    float next[kFeat];
+    load(wave, next);
     for (uint64_t tile = wave; tile < tiles; tile += waves) {
         const uint64_t cell = tile * 32 + (uint64_t)col;
         const bool valid = cell < n;
-        const float4 xv = next;
-        next = load(tile + waves);
-        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-        int out_env = 0;
-        bf16x4 bx;
+        float x[kFeat];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            out_env |= (xs[e] < flo[e]) | (xs[e] > fhi[e]);
-            bx[e] = to_bf16(xs[e]);
-        }
-        out_env |= __shfl_xor(out_env, 32, 64);
+        for (int e = 0; e < kFeat; ++e) x[e] = next[e];
+        load(tile + waves, next);
+        int out_env = 0;
+#pragma unroll
+        for (int e = 0; e < kFeat; ++e) out_env |= (x[e] < flo[e]) | (x[e] > fhi[e]);
+        const bf16x8 bx = feature_operand(x, half);
         f32x16 d1[2];
 #pragma unroll
-        for (int T = 0; T < 2; ++T) d1[T] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[T], bx, c1[T], 0, 0, 0);
-        bf16x8 b2[4];
+        for (int T = 0; T < 2; ++T) d1[T] = mfma16(o.a1[T], bx, zero16());
+        bf16x8 h1[4];
+        hidden_operand(d1, h1);
+        f32x16 d2[2];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int T = 0; T < 2; ++T) {
+            d2[T] = mfma16(o.a2[T][4], ones, zero16());
 #pragma unroll
-            for (int e = 0; e < 8; ++e) b2[s][e] = (__bf16)relu(d1[s / 2][4 * (2 * (s % 2) + e / 4) + e % 4]);
-        f32x16 d2[2] = {c2[0], c2[1]};
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int T = 0; T < 2; ++T) d2[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[T][s], b2[s], d2[T], 0, 0, 0);
+            for (int s = 0; s < 4; ++s) d2[T] = mfma16(o.a2[T][s], h1[s], d2[T]);
+        }
         float part = 0.0f;
 #pragma unroll
         for (int T = 0; T < 2; ++T)
@@ -201,87 +286,278 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
     }
 }
 
-// ---- training: weighted-MSE gradient in FP32 --------------------------------
-// One wave per block; lane h is hidden unit h of both layers. Each block
-// walks cells blockIdx.x, blockIdx.x + gridDim.x, ... and writes its partial
-// sums (the unnormalised gradient sum_i 2 w_i r_i dy_i/dtheta, sum w r^2,
-// sum w) to its own slot; a second kernel adds the slots in block order, so
-// the result does not depend on timing.
-__global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ P, const float *__restrict__ X,
-                                                      const float *__restrict__ tgt, const float *__restrict__ wgt,
-                                                      uint64_t n, float *__restrict__ partial)
+// ---- training: weighted-MSE gradient on the matrix cores --------------------
+// The gradient of the function above with respect to the FP32 master
+// parameters (every rounding passed through unchanged). Each tile of 32
+// cells is evaluated in both orientations:
+//   "C" gives y per lane and dL/dz2 with the output units in the registers,
+//       the A operand of dL/dh1 = (dL/dz2)^T W2;
+//   "H" gives h1 and dL/dz2 with the cells in the registers, the operands of
+//       the weight gradients, which are sums over cells (K = cells):
+//       dL/dW2 = (dL/dz2) H1^T and [dL/dW1 dL/db1] = (dL/dz1) [X 1].
+// The error signals dL/dz2, dL/dz1 are rounded to BF16 for the matrix cores;
+// the w3, b2 and b3 gradients are FP32 sums. X^T (feature per lane) and
+// dL/dy per cell pass through a few hundred bytes of wave-private LDS, and
+// the B operand of dL/dh1 (W2 with the output units in the registers) is
+// read from the block's LDS.
+//
+// Each block of kGradWaves waves writes the sum of its waves' partial sums
+// (in wave order) to its own slot; two more kernels add the slots in block
+// order, so the result does not depend on timing.
+constexpr int kGradWaves = 2;
+
+struct GradLds {
+    float w3[kHid];                              // by row, for "C"
+    __bf16 w2[2][5][2][32][8];                   // a2[T][s] of lane (h, c) at [T][s][h][c]
+    __bf16 w2t[2][4][2][32][8];                  // w3[o] W2[o][32 T + c], o = l2_unit(s, h, e), at [T][s][h][c][e]
+    union {
+        struct {
+            __bf16 xs[kGradWaves][kFeat][32];    // the tile's features, [feature][cell]
+            float gy[kGradWaves][32];            // dL/dy of the tile's cells
+        } t;
+        float part[kMlpPartStride];              // another wave's partial sums
+    } u;
+};
+
+__global__ __launch_bounds__(64 * kGradWaves, 2) void mlp_grad_kernel(const float *__restrict__ P,
+                                                                      const float *__restrict__ X,
+                                                                      const float *__restrict__ tgt,
+                                                                      const float *__restrict__ wgt, uint64_t n,
+                                                                      float *__restrict__ partial)
 {
-    __shared__ float s_h1[kHid], s_gz2[kHid], s_x[kFeat];
-    const int h = threadIdx.x;
-    float w1[kFeat], w2r[kHid], w2c[kHid];
-#pragma unroll
-    for (int k = 0; k < kFeat; ++k) w1[k] = P[OFF_W1 + h * kFeat + k];
-#pragma unroll
-    for (int k = 0; k < kHid; ++k) {
-        w2r[k] = P[OFF_W2 + h * kHid + k];
-        w2c[k] = P[OFF_W2 + k * kHid + h];
+    __shared__ GradLds L;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    for (int j = threadIdx.x; j < kHid; j += blockDim.x) L.w3[j] = P[OFF_W3 + j];
+    for (int j = threadIdx.x; j < kHid * kHid; j += blockDim.x) {
+        const int e = j & 7, c = (j >> 3) & 31, h = (j >> 8) & 1, s = (j >> 9) & 3, T = j >> 11;
+        const int o = l2_unit(s, h, e);
+        L.w2t[T][s][h][c][e] = (__bf16)(P[OFF_W3 + o] * P[OFF_W2 + o * kHid + 32 * T + c]);
     }
-    const float b1 = P[OFF_B1 + h], b2 = P[OFF_B2 + h], w3 = P[OFF_W3 + h], b3 = P[OFF_B3];
-    float gW1[kFeat], gW2[kHid];
+    // the weight operands: layer 1 in registers, layer 2 in LDS (read as
+    // needed; registers are short)
+    NetOps o;
+    load_ops(P, half, col, o);
 #pragma unroll
-    for (int k = 0; k < kFeat; ++k) gW1[k] = 0.0f;
+    for (int T = 0; T < 2; ++T)
 #pragma unroll
-    for (int k = 0; k < kHid; ++k) gW2[k] = 0.0f;
-    float gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f, gb3 = 0.0f, loss = 0.0f, wsum = 0.0f;
-    for (uint64_t c = blockIdx.x; c < n; c += gridDim.x) {
-        __syncthreads();
-        if (h < kFeat) s_x[h] = X[c * kFeat + h];
-        __syncthreads();
+        for (int s = 0; s < 5; ++s)
+            if (wid == 0) *reinterpret_cast<bf16x8 *>(&L.w2[T][s][half][col][0]) = o.a2[T][s];
+    const bf16x8 ones = ones_pair(half == 0);
+    auto a2 = [&](int T, int s) { return *reinterpret_cast<const bf16x8 *>(&L.w2[T][s][half][col][0]); };
+    float w3h[2];                                // unit 32 T + col, for "H"
+    w3h[0] = P[OFF_W3 + col];
+    w3h[1] = P[OFF_W3 + 32 + col];
+    const float b3 = P[OFF_B3];
+    f32x16 gW2[2][2], gW1[2];
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        gW1[T] = zero16();
+        gW2[T][0] = zero16();
+        gW2[T][1] = zero16();
+    }
+    float gw3[2] = {0.0f, 0.0f}, gb2[2] = {0.0f, 0.0f}, gb3 = 0.0f, loss = 0.0f, wsum = 0.0f;
+    __syncthreads();
+
+    __bf16(*xs)[32] = L.u.t.xs[wid];
+    float *gys = L.u.t.gy[wid];
+    const uint64_t waves = (uint64_t)gridDim.x * kGradWaves;
+    const uint64_t tiles = (n + 31) / 32;
+    for (uint64_t tile = (uint64_t)blockIdx.x * kGradWaves + wid; tile < tiles; tile += waves) {
+        // the LDS tables are read in each tile, not held in registers across
+        // tiles (the compiler may not hoist them past this)
+        asm volatile("" ::: "memory");
+        const uint64_t cell = tile * 32 + (uint64_t)col;
+        const bool valid = cell < n;
         float x[kFeat];
+        float tv = 0.0f, wv = 0.0f;                  // cells past n weigh nothing
+        {
+            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+            if (half == 0 && valid) {
+                a = *reinterpret_cast<const float4 *>(X + cell * kFeat);
+                b = *reinterpret_cast<const float4 *>(X + cell * kFeat + 4);
+            }
+            if (valid) {
+                tv = tgt[cell];
+                wv = wgt[cell];
+            }
+            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+            x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+        }
+        const bf16x8 bx = feature_operand(x, half);
+        if (half == 0)
 #pragma unroll
-        for (int k = 0; k < kFeat; ++k) x[k] = s_x[k];
-        float z1 = b1;
+            for (int e = 0; e < kFeat; ++e) xs[e][col] = bx[e];
+
+        // forward, "C"
+        bf16x8 h1c[4];
+        {
+            f32x16 d1[2];
 #pragma unroll
-        for (int k = 0; k < kFeat; ++k) z1 += w1[k] * x[k];
-        const float h1 = relu(z1);
-        s_h1[h] = h1;
-        __syncthreads();
-        float z2 = b2;
+            for (int T = 0; T < 2; ++T) d1[T] = mfma16(o.a1[T], bx, zero16());
+            hidden_operand(d1, h1c);
+        }
+        bf16x8 gzc[4];                 // dL/dz2 / w3, K operand of dL/dh1 (unit l2_unit(s, half, e))
+        {
+            f32x16 d2[2];
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) z2 += w2r[k] * s_h1[k];
-        const float h2 = relu(z2);
-        float yv = w3 * h2;
+            for (int T = 0; T < 2; ++T) {
+                d2[T] = mfma16(a2(T, 4), ones, zero16());
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) yv += __shfl_xor(yv, off, 64);
-        yv += b3;
-        const float wc = wgt[c];
-        const float r = yv - tgt[c];
-        loss += wc * r * r;
-        wsum += wc;
-        const float gy = 2.0f * wc * r;
-        gw3 += gy * h2;
-        gb3 += gy;
-        const float gz2 = gy * w3 * relu_grad(z2);
-        gb2 += gz2;
+                for (int s = 0; s < 4; ++s) d2[T] = mfma16(a2(T, s), h1c[s], d2[T]);
+            }
+            float w3r[2][16];
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) gW2[k] += gz2 * s_h1[k];
-        s_gz2[h] = gz2;
-        __syncthreads();
-        float gh1 = 0.0f;
+            for (int T = 0; T < 2; ++T)
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) gh1 += w2c[k] * s_gz2[k];
-        const float gz1 = gh1 * relu_grad(z1);
-        gb1 += gz1;
+                for (int r = 0; r < 16; ++r) w3r[T][r] = L.w3[32 * T + d_row(r, half)];
+            float part = 0.0f;
 #pragma unroll
-        for (int k = 0; k < kFeat; ++k) gW1[k] += gz1 * x[k];
+            for (int T = 0; T < 2; ++T)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) part += w3r[T][r] * relu(d2[T][r]);
+            part += __shfl_xor(part, 32, 64);
+            const float res = part + b3 - tv;
+            const float gy = 2.0f * wv * res;          // d(sum w r^2)/dy
+            if (half == 0) {
+                loss += wv * res * res;
+                wsum += wv;
+                gb3 += gy;
+                gys[col] = gy;
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) gzc[s][e] = (__bf16)(d2[s / 2][l1_reg(s, e)] > 0.0f ? gy : 0.0f);
+        }
+
+        // dL/dh1 = (dL/dz2)^T W2 ("H": cells in the registers), with w3
+        // carried by the W2 operand
+        f32x16 gh1[2];
+#pragma unroll
+        for (int T = 0; T < 2; ++T) {
+            gh1[T] = zero16();
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                gh1[T] = mfma16(gzc[s], *reinterpret_cast<const bf16x8 *>(&L.w2t[T][s][half][col][0]), gh1[T]);
+        }
+
+        // X^T (feature per lane, element e of K step s' = cell
+        // d_row(8 s' + e, half)) from the staged tile, with a column of ones
+        bf16x8 xb[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (col < kFeat) {
+                // (read as the type it was written with: no type punning, so
+                // the compiler keeps these loads after the stores above)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xb[s][e] = xs[col][16 * s + 4 * half + e];
+                    xb[s][4 + e] = xs[col][16 * s + 8 + 4 * half + e];
+                }
+            } else {
+                const __bf16 v = (__bf16)(col == kFeat ? 1.0f : 0.0f);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xb[s][e] = v;
+            }
+        }
+
+        // forward layer 1, "H": h1 with the cells in the registers (element e
+        // of K step s' = register 8 s' + e); dL/dz1 through ReLU's derivative,
+        // and [dL/dW1 dL/db1] += (dL/dz1) [X 1]
+        bf16x8 h1h[2][2];
+#pragma unroll
+        for (int T = 0; T < 2; ++T) {
+            const f32x16 d = mfma16(bx, o.a1[T], zero16());
+            bf16x8 gz1[2];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                h1h[T][r / 8][r % 8] = (__bf16)relu(d[r]);
+                gz1[r / 8][r % 8] = (__bf16)(d[r] > 0.0f ? gh1[T][r] : 0.0f);
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) gW1[T] = mfma16(gz1[s], xb[s], gW1[T]);
+        }
+
+        // forward layer 2, "H": dL/dz2 / w3 with the cells in the registers
+        // and the FP32 sums of the w3 and b2 gradients (w3, a factor of each
+        // output unit's row, is applied to the dL/dW2 and dL/db2 sums at the
+        // end)
+        float gyr[16];                 // dL/dy of cell d_row(r, half)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) gyr[r] = gys[d_row(r, half)];
+#pragma unroll
+        for (int To = 0; To < 2; ++To) {
+            f32x16 d = mfma16(ones, a2(To, 4), zero16());
+#pragma unroll
+            for (int s = 0; s < 4; ++s) d = mfma16(h1c[s], a2(To, s), d);
+            bf16x8 gzh[2];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float g = d[r] > 0.0f ? gyr[r] : 0.0f;
+                gw3[To] += g * d[r];
+                gb2[To] += g;
+                gzh[r / 8][r % 8] = (__bf16)g;
+            }
+            // dL/dW2 += (dL/dz2) H1^T, K = the 32 cells in two steps
+#pragma unroll
+            for (int Ti = 0; Ti < 2; ++Ti)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) gW2[To][Ti] = mfma16(gzh[s], h1h[Ti][s], gW2[To][Ti]);
+        }
     }
-    float *p = partial + (size_t)blockIdx.x * kMlpPartStride;
+
+    // this wave's sums: lanes col and col + 32 hold the two halves of the
+    // cells of the unit sums; half 0 alone holds the per-cell sums
+    gw3[0] += __shfl_xor(gw3[0], 32, 64);
+    gw3[1] += __shfl_xor(gw3[1], 32, 64);
+    gb2[0] = w3h[0] * (gb2[0] + __shfl_xor(gb2[0], 32, 64));
+    gb2[1] = w3h[1] * (gb2[1] + __shfl_xor(gb2[1], 32, 64));
 #pragma unroll
-    for (int k = 0; k < kFeat; ++k) p[OFF_W1 + h * kFeat + k] = gW1[k];
-    p[OFF_B1 + h] = gb1;
+    for (int off = 32; off > 0; off >>= 1) {
+        gb3 += __shfl_down(gb3, off, 64);
+        loss += __shfl_down(loss, off, 64);
+        wsum += __shfl_down(wsum, off, 64);
+    }
+    // Every lane visits the entries it owns in the same order in every wave,
+    // and the waves are added in index order through LDS.
+    auto visit = [&](auto &&f) {
 #pragma unroll
-    for (int k = 0; k < kHid; ++k) p[OFF_W2 + h * kHid + k] = gW2[k];
-    p[OFF_B2 + h] = gb2;
-    p[OFF_W3 + h] = gw3;
-    if (h == 0) {
-        p[OFF_B3] = gb3;
-        p[kMlpParams] = loss;
-        p[kMlpParams + 1] = wsum;
+        for (int To = 0; To < 2; ++To)
+#pragma unroll
+            for (int Ti = 0; Ti < 2; ++Ti)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int o = 32 * To + d_row(r, half);
+                    f(OFF_W2 + o * kHid + 32 * Ti + col, L.w3[o] * gW2[To][Ti][r]);
+                }
+        if (col <= kFeat)
+#pragma unroll
+            for (int T = 0; T < 2; ++T)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int u = 32 * T + d_row(r, half);
+                    f(col < kFeat ? OFF_W1 + u * kFeat + col : OFF_B1 + u, gW1[T][r]);
+                }
+        if (half == 0)
+#pragma unroll
+            for (int T = 0; T < 2; ++T) {
+                f(OFF_W3 + 32 * T + col, gw3[T]);
+                f(OFF_B2 + 32 * T + col, gb2[T]);
+            }
+        if (lane == 0) {
+            f(OFF_B3, gb3);
+            f(kMlpParams, loss);
+            f(kMlpParams + 1, wsum);
+        }
+    };
+    __syncthreads();                                  // staging no longer in use
+    for (int w = kGradWaves - 1; w > 0; --w) {
+        if (wid == w) visit([&](int j, float v) { L.u.part[j] = (w == kGradWaves - 1 ? 0.0f : L.u.part[j]) + v; });
+        __syncthreads();
+    }
+    if (wid == 0) {
+        float *p = partial + (size_t)blockIdx.x * kMlpPartStride;
+        visit([&](int j, float v) { p[j] = kGradWaves > 1 ? v + L.u.part[j] : v; });
     }
 }
 
@@ -356,11 +632,19 @@ hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, f
 }
 
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
-                               float *partial, int blocks, float *grad, hipStream_t s)
+                               float *partial, int max_blocks, float *grad, hipStream_t s)
 {
+    // as many blocks as give every wave kGradMinTiles tiles, up to max_blocks:
+    // fewer partial-sum slots to add for small batches (the count is a
+    // function of n alone, so the summation order is too)
+    constexpr uint64_t kGradMinTiles = 4;
+    const uint64_t tiles = (n + 31) / 32;
+    const int blocks = (int)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)max_blocks, tiles / (kGradWaves * kGradMinTiles)));
     const int groups = (blocks + kMlpGroup - 1) / kMlpGroup;
     float *tmp = partial + (size_t)blocks * kMlpPartStride;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)blocks), dim3(64), 0, s, params, X, t, w, n, partial);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)blocks), dim3(64 * kGradWaves), 0, s, params, X, t, w, n,
+                       partial);
     hipLaunchKernelGGL(mlp_reduce_groups_kernel, dim3((unsigned)((kMlpParams + 2 + 255) / 256), (unsigned)groups),
                        dim3(256), 0, s, partial, blocks, tmp);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)((kMlpParams + 2 + 255) / 256)), dim3(256), 0, s, tmp,

@@ -183,3 +183,85 @@ def test_adam_reaches_minimum_of_quadratic():
         lr = 0.05 if step < 2000 else 0.005
         x, m, v = S.adam_step(x, m, v, a * (x - c), step, lr)
     assert np.max(np.abs(x - c)) < 1e-3
+
+
+# --- the bfloat16 network ----------------------------------------------------
+def test_bf16_rounding_matches_torch_and_ties_to_even():
+    """bf16() against torch's float32 -> bfloat16 conversion (round to nearest
+    even) over many magnitudes, and hand-made ties: with 8 significant bits,
+    1 + 2^-8 lies halfway between 1 and 1 + 2^-7 and goes to the even 1;
+    1 + 3 2^-8 lies halfway between 1 + 2^-7 and 1 + 2^-6 and goes to
+    1 + 2^-6."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(12)
+    x = (rng.normal(size=20000) * 10.0 ** rng.uniform(-30, 30, size=20000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(S.bf16(x), ref)
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 2.0 ** 10 * (1 + 2.0 ** -8)])
+    assert np.array_equal(S.bf16(ties), [1.0, 1 + 2.0 ** -6, -1.0, 2.0 ** 10])
+    assert np.array_equal(S.bf16(1 + 2.0 ** -8 + 2.0 ** -20), 1 + 2.0 ** -7)   # just above the tie
+
+
+def test_bias_split_is_exact_to_two_to_minus_sixteen():
+    rng = np.random.default_rng(13)
+    b = rng.normal(size=5000).astype(np.float32).astype(np.float64)
+    hi, lo = S.bias_split(b)
+    assert np.array_equal(S.bf16(hi), hi) and np.array_equal(S.bf16(lo), lo)
+    assert np.all(np.abs(hi + lo - b) <= 2.0 ** -16 * np.abs(b))
+    exact = S.bf16(b)                                # representable biases: lo = 0
+    assert np.all(S.bias_split(exact)[1] == 0.0)
+
+
+def _representable_net(seed):
+    """Weights, biases and features on coarse dyadic grids, so every
+    product and sum of the network is exact in bfloat16: the rounded network
+    is then the plain one."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.choice([-1.0, -0.5, 0.0, 0.5, 1.0], size=(64, 8))
+    W2 = rng.choice([-0.25, 0.0, 0.125, 0.25], size=(64, 64)) * (rng.random((64, 64)) < 0.1)
+    b1 = rng.choice([-1.0, 0.0, 0.5, 2.0], size=64)
+    b2 = rng.choice([-0.5, 0.0, 0.25], size=64)
+    w3 = rng.normal(size=64)
+    p = S.pack(W1, b1, W2, b2, w3.astype(np.float32), np.float32(0.3))
+    X = rng.integers(-3, 4, size=(200, 8)).astype(np.float64)
+    return p, X
+
+
+def test_bf16_network_reduces_to_the_plain_one_on_representable_values():
+    p, X = _representable_net(14)
+    y, c = S.forward(p, X)
+    yb, cb = S.forward_bf16(p, X)
+    assert np.array_equal(cb["h1"], c["h1"])         # every activation exact
+    assert np.allclose(yb, y, rtol=1e-14, atol=1e-14)
+    rng = np.random.default_rng(15)
+    t = rng.normal(size=200)
+    w = rng.uniform(0.1, 1.0, size=200)
+    L, g = S.loss_and_grad(p, X, t, w)
+    Lb, gb, gabs = S.loss_and_grad_bf16(p, X, t, w, abs_bound=True)
+    assert abs(Lb - L) <= 1e-13 * L
+    assert np.allclose(gb, g, rtol=1e-12, atol=1e-14)
+    assert np.all(gabs >= np.abs(gb) - 1e-12)
+
+
+def test_bf16_network_rounds_where_stated():
+    """Generic parameters: the rounded network differs from the plain one by
+    no more than its roundings allow (W1, x, W2 and h1 at 2^-8 relative each,
+    first order), and its gradient equals the plain gradient evaluated with
+    the rounded operands: bf16 weights and features give the same network as
+    the rounded parameters fed to the plain forward, up to the h1 rounding."""
+    rng = np.random.default_rng(16)
+    p = _random_params(4)
+    X = rng.normal(size=(300, 8))
+    y, c = S.forward(p, X)
+    yb, cb = S.forward_bf16(p, X)
+    W1, b1, W2, b2, w3, b3 = S.unpack(p)
+    e1 = 2.0 ** -7 * (np.abs(X) @ np.abs(W1).T) + 2.0 ** -16 * np.abs(b1)
+    e2 = (e1 + 2.0 ** -8 * np.abs(c["h1"])) @ np.abs(W2).T + 2.0 ** -8 * (np.abs(c["h1"]) @ np.abs(W2).T)
+    bound = 1.1 * (e2 @ np.abs(w3)) + 1e-12
+    assert np.all(np.abs(yb - y) <= bound)
+    assert np.any(yb != y)                          # the roundings do act
+    # with X and the weights already rounded, only h1 and the biases still round
+    W1r, W2r = S.bf16(W1), S.bf16(W2)
+    pr = S.pack(W1r, np.float32(b1), W2r, np.float32(b2), np.float32(w3), np.float32(b3))
+    yr, cr = S.forward_bf16(pr, S.bf16(X))
+    assert np.array_equal(yr, yb)
