@@ -224,7 +224,8 @@ struct alignas(16) PState {
     uint32_t w;
     uint32_t pad;
     float x, kx, ky, kz;     // pre-jump frequency and direction
-    float ux, uy, uz;        // velocity of the cell it leaves
+    float ku;                // k . U of the cell it leaves (Doppler units)
+    uint32_t pad2[2];
     uint32_t cell;           // cell it enters (global)
     uint32_t ncross;
     int32_t ix, iy, iz;      // coordinates of that cell

@@ -30,17 +30,30 @@ constexpr int BLK = kTileBlock;
 static_assert(TC % BLK == 0, "tile cells must be a multiple of the workgroup size");
 constexpr int kWaves = BLK / 64;
 
-// LDS slot of a tile cell: a 16 x 16 x kTileZ layout whatever the tile's
-// extent (a tile at a box edge may be smaller), so that the slot is a shift
-// and an or of the cell's offsets in the tile, not two multiplies.
-static_assert(kTileX == 16 && kTileY == 16, "tile slots assume 16 x 16 cells across");
+// LDS slots: the tile's cells with a ring of one slot round them, in a
+// (kTileX + 2) x (kTileY + 2) x (kTileZ + 2) layout whatever the tile's extent
+// (a tile at a box edge may be smaller). Every slot that is not a cell of the
+// tile (the ring, and the rest of the layout in a smaller tile) holds the
+// record kOutside, so a packet about to step out of the tile finds out by
+// reading the record of the slot it would enter: no per-packet count of the
+// faces left before the tile's edge.
+static_assert(kTileX == 16 && kTileY == 16, "the cell loops take rows and planes of 16 cells");
+constexpr int kSX = kTileX + 2, kSY = kTileY + 2, kSZ = kTileZ + 2;
+constexpr int kSlots = kSX * kSY * kSZ;
+constexpr uint32_t kOutside = 0xFFFFFFFFu;   // kappa bits of a slot outside the tile (a NaN)
 __device__ __forceinline__ int tile_slot(int32_t lx, int32_t ly, int32_t lz)
 {
-    return lx | (ly << 4) | (lz << 8);
+    return (lx + 1) + kSX * ((ly + 1) + kSY * (lz + 1));
 }
 
-// Faces left along an axis the tile spans: a packet never leaves that way.
-constexpr int32_t kNoFace = 1 << 30;
+// The cell offsets in the tile of slot s (-1 or the extent on the ring).
+__device__ __forceinline__ void slot_cell(int32_t s, int32_t &lx, int32_t &ly, int32_t &lz)
+{
+    const int32_t r = s % (kSX * kSY);
+    lz = s / (kSX * kSY) - 1;
+    ly = r / kSX - 1;
+    lx = r % kSX - 1;
+}
 
 // The tile a workgroup walks, uniform over it: the box's drift, escape
 // threshold and line constants, the tile's origin and extent, and the axes
@@ -55,19 +68,17 @@ struct TileCtx {
 
 // A packet inside a tile. Ray geometry and line state are a Lane's; the cell
 // is tracked by its record's byte offset q in the tile's LDS (RS bytes per
-// record), with the change of q for a step along each axis and the number
-// of faces the packet can still cross along each axis before it reaches the
-// tile's edge. A step is then an add and three compares, where global cell
-// coordinates would need the box's periodic wrap, the neighbour's index and
-// an in-tile test; they are formed only when the packet leaves the tile.
+// record), with the change of q for a step along each axis. A step is then an
+// add, where global cell coordinates would need the box's periodic wrap and
+// the neighbour's index; they are formed only when the packet leaves the
+// tile (found from the record of the slot it steps into, kOutside).
 struct TLane {
     double tmx, tmy, tmz, tdx, tdy, tdz, t;
     float kx, ky, kz;
-    float x, kap, ux, uy, uz;
+    float x, kap, ku;
     uint32_t w, ncross;
     int32_t q;
     int32_t dqx, dqy, dqz;
-    int32_t rx, ry, rz;
 };
 
 // The LDS tally of the cell whose record is at byte offset q (8-byte tallies).
@@ -111,31 +122,25 @@ __device__ __forceinline__ void to_tile(TLane &T, const Lane &L, const TileCtx &
     T.kz = L.kz;
     T.x = L.x;
     T.kap = L.kap;
-    T.ux = L.ux;
-    T.uy = L.uy;
-    T.uz = L.uz;
+    T.ku = L.ku;
     T.w = L.w;
     T.ncross = L.ncross;
-    const int32_t lx = L.ix - C.ox, ly = L.iy - C.oy, lz = L.iz - C.oz;
-    T.q = tile_slot(lx, ly, lz) * RS;
+    T.q = tile_slot(L.ix - C.ox, L.iy - C.oy, L.iz - C.oz) * RS;
     // the walk steps +1 along an axis when the direction's component is > 0, else -1
-    const bool px = L.kx > 0.0f, py = L.ky > 0.0f, pz = L.kz > 0.0f;
-    T.dqx = px ? RS : -RS;
-    T.dqy = py ? 16 * RS : -16 * RS;
-    T.dqz = pz ? 256 * RS : -256 * RS;
-    T.rx = (C.span & 1u) ? kNoFace : (px ? C.sx - 1 - lx : lx);
-    T.ry = (C.span & 2u) ? kNoFace : (py ? C.sy - 1 - ly : ly);
-    T.rz = (C.span & 4u) ? kNoFace : (pz ? C.sz - 1 - lz : lz);
+    T.dqx = L.kx > 0.0f ? RS : -RS;
+    T.dqy = L.ky > 0.0f ? kSX * RS : -kSX * RS;
+    T.dqz = L.kz > 0.0f ? kSX * kSY * RS : -kSX * kSY * RS;
 }
 
 // Global coordinates of a TLane's cell.
 template <int RS>
 __device__ __forceinline__ void tile_cell(const TLane &T, const TileCtx &C, int32_t &ix, int32_t &iy, int32_t &iz)
 {
-    const int32_t s = (int32_t)((uint32_t)T.q / (uint32_t)RS);
-    ix = C.ox + (s & 15);
-    iy = C.oy + ((s >> 4) & 15);
-    iz = C.oz + (s >> 8);
+    int32_t lx, ly, lz;
+    slot_cell((int32_t)((uint32_t)T.q / (uint32_t)RS), lx, ly, lz);
+    ix = C.ox + lx;
+    iy = C.oy + ly;
+    iz = C.oz + lz;
 }
 
 // Along an axis the tile spans, one cell past either end of the tile is its
@@ -143,25 +148,24 @@ __device__ __forceinline__ void tile_cell(const TLane &T, const TileCtx &C, int3
 template <int RS>
 __device__ __forceinline__ int32_t wrap_slot(const TLane &L, int32_t qn, const Face &f, const TileCtx &C)
 {
-    const int32_t s = (int32_t)((uint32_t)L.q / (uint32_t)RS);
+    int32_t lx, ly, lz;
+    slot_cell((int32_t)((uint32_t)L.q / (uint32_t)RS), lx, ly, lz);
     if (f.bx && (C.span & 1u)) {
-        const int32_t l = s & 15;
-        const int32_t m = L.kx > 0.0f ? (l + 1 == C.sx ? 0 : l + 1) : (l == 0 ? C.sx - 1 : l - 1);
-        qn = L.q + (m - l) * RS;
+        const int32_t m = L.kx > 0.0f ? (lx + 1 == C.sx ? 0 : lx + 1) : (lx == 0 ? C.sx - 1 : lx - 1);
+        qn = L.q + (m - lx) * RS;
     } else if (f.by && (C.span & 2u)) {
-        const int32_t l = (s >> 4) & 15;
-        const int32_t m = L.ky > 0.0f ? (l + 1 == C.sy ? 0 : l + 1) : (l == 0 ? C.sy - 1 : l - 1);
-        qn = L.q + (m - l) * (16 * RS);
+        const int32_t m = L.ky > 0.0f ? (ly + 1 == C.sy ? 0 : ly + 1) : (ly == 0 ? C.sy - 1 : ly - 1);
+        qn = L.q + (m - ly) * (kSX * RS);
     } else if (f.bz && (C.span & 4u)) {
-        const int32_t l = s >> 8;
-        const int32_t m = L.kz > 0.0f ? (l + 1 == C.sz ? 0 : l + 1) : (l == 0 ? C.sz - 1 : l - 1);
-        qn = L.q + (m - l) * (256 * RS);
+        const int32_t m = L.kz > 0.0f ? (lz + 1 == C.sz ? 0 : lz + 1) : (lz == 0 ? C.sz - 1 : lz - 1);
+        qn = L.q + (m - lz) * (kSX * kSY * RS);
     }
     return qn;
 }
 
 // Outcome of one step of a TLane.
 struct TStep {
+    bool walked;     // crossed a cell (deposited and counted)
     bool alive;      // walks on inside the tile
     bool exit;       // stands on the tile's edge, to be handed to the neighbour
     bool fin;        // finished: absorbed, escaped or capped
@@ -191,19 +195,21 @@ __device__ __forceinline__ TStep tile_step(TLane &L, bool act, const TileCtx &C,
     const bool capped = !gone && L.ncross >= C.max_cross;
     const bool walk = act && !gone && !capped;
     const Face f = next_face(L.tmx, L.tmy, L.tmz);
-    const bool stay = (f.bx & (L.rx != 0)) | (f.by & (L.ry != 0)) | (f.bz & (L.rz != 0));
     // sums of field-or-zero terms: a choice between fields would make the
     // compiler address the lane state in (scratch) memory
     int32_t qn = L.q + (f.bx ? L.dqx : 0) + (f.by ? L.dqy : 0) + (f.bz ? L.dqz : 0);
+    // along an axis the tile spans, the step wraps round to the tile's other end
     if (WRAP) qn = wrap_slot<RS>(L, qn, f, C);
-    // the neighbour's record, in flight during the profile arithmetic (a
-    // packet leaving the tile reads its own cell's instead: not used)
-    const Rec nr = rec_at<VEL>(recs, stay ? qn : L.q);
+    // the next slot's record, in flight during the profile arithmetic; the
+    // ring round the tile holds kOutside
+    const Rec nr = rec_at<VEL>(recs, qn);
     const Segment g = segment<VOIGT>(L.x, (float)(f.tn - L.t), C.delta, C.xeff, L.kap, L.w, walk, C.ln);
     dep_q = L.q;                 // the deposit goes into the cell being left
     dep_w = g.d;
     L.w -= g.d;
     L.ncross += walk ? 1u : 0u;
+    o.walked = walk;
+    const bool stay = __float_as_uint(nr.kap) != kOutside;
     const bool live = walk && !g.esc && L.w != 0u;
     o.alive = live && stay;
     o.exit = live && !stay;
@@ -212,24 +218,23 @@ __device__ __forceinline__ TStep tile_step(TLane &L, bool act, const TileCtx &C,
     o.capped = act && capped;
     o.wing = 0u;
     if (VOIGT && o.escaped) o.wing = wing_share(L.w, gone ? L.x : -C.xeff, C.ln);
-    // cross the face (packets that walk on inside the tile)
+    // cross the face (packets that walk on inside the tile). The path length
+    // walked advances for every lane: a packet that stops here is written out
+    // from its face distances (save_exit), not from t, and an idle lane's
+    // next segment is then empty.
     const bool mv = o.alive;
     L.tmx = (mv && f.bx) ? L.tmx + L.tdx : L.tmx;
     L.tmy = (mv && f.by) ? L.tmy + L.tdy : L.tmy;
     L.tmz = (mv && f.bz) ? L.tmz + L.tdz : L.tmz;
-    L.t = mv ? f.tn : L.t;
+    L.t = f.tn;
     L.q = mv ? qn : L.q;
-    L.rx -= (mv && f.bx) ? 1 : 0;
-    L.ry -= (mv && f.by) ? 1 : 0;
-    L.rz -= (mv && f.bz) ? 1 : 0;
     // the bulk term of Eq. (inout) on entering the new cell; a packet that
     // leaves keeps its pre-jump frequency
     if (VEL) {
-        const float xj = g.xo - bulk_jump(L, nr);
+        const float kn = ray_velocity(L.kx, L.ky, L.kz, nr);
+        const float xj = g.xo - (kn - L.ku);
         L.x = act ? (mv ? xj : g.xo) : L.x;
-        L.ux = mv ? nr.ux : L.ux;
-        L.uy = mv ? nr.uy : L.uy;
-        L.uz = mv ? nr.uz : L.uz;
+        L.ku = mv ? kn : L.ku;
     } else {
         L.x = act ? g.xo : L.x;
     }
@@ -247,14 +252,13 @@ __device__ __forceinline__ void idle_tlane(TLane &T, int32_t rs)
     T.ky = T.kz = 0.0f;
     T.x = -3.0e38f;
     T.kap = 0.0f;
-    T.ux = T.uy = T.uz = 0.0f;
+    T.ku = 0.0f;
     T.w = 0u;
     T.ncross = 0u;
-    T.q = 0;
+    T.q = tile_slot(0, 0, 0) * rs;    // a cell of every tile
     T.dqx = rs;
-    T.dqy = 16 * rs;
-    T.dqz = 256 * rs;
-    T.rx = T.ry = T.rz = 0;
+    T.dqy = kSX * rs;
+    T.dqz = kSX * kSY * rs;
 }
 
 // A packet standing on the tile's edge, written for the neighbouring tile:
@@ -286,9 +290,7 @@ __device__ __forceinline__ uint32_t save_exit(PState &o, const TLane &L, const T
     o.kx = L.kx;
     o.ky = L.ky;
     o.kz = L.kz;
-    o.ux = L.ux;
-    o.uy = L.uy;
-    o.uz = L.uz;
+    o.ku = L.ku;
     o.cell = B.cell_off + (uint32_t)jx + (uint32_t)B.nx * ((uint32_t)jy + (uint32_t)B.ny * (uint32_t)jz);
     o.ncross = L.ncross;
     o.ix = jx;
@@ -315,9 +317,7 @@ __device__ __forceinline__ void save_here(PState &o, const TLane &L, const TileC
     o.kx = L.kx;
     o.ky = L.ky;
     o.kz = L.kz;
-    o.ux = L.ux;
-    o.uy = L.uy;
-    o.uz = L.uz;
+    o.ku = L.ku;
     o.cell = B.cell_off + (uint32_t)ix + (uint32_t)B.nx * ((uint32_t)iy + (uint32_t)B.ny * (uint32_t)iz);
     o.ncross = L.ncross;
     o.ix = ix;
@@ -354,9 +354,7 @@ __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkB
     L.kx = o.kx;
     L.ky = o.ky;
     L.kz = o.kz;
-    L.ux = o.ux;
-    L.uy = o.uy;
-    L.uz = o.uz;
+    L.ku = o.ku;
     L.c = o.cell;
     L.ncross = o.ncross;
     L.ix = o.ix;
@@ -370,14 +368,14 @@ __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkB
     L.xeff = B.x_eff;
 }
 
-// Per-wave running totals of finished packets.
+// Per-lane running totals: crossings walked in this generation, and the
+// weights of the packets that escaped (capped packets, which are rare, go to
+// the tile's LDS totals).
 struct TileAcc {
-    uint64_t esc, cross, capn, capw, wing;
+    uint32_t cross;
+    uint64_t esc, wing;
 };
 
-// The walk of one tile's input by one workgroup (all its waves): refill
-// idle lanes from the input list, step every lane, park packets that reach
-// the tile's edge and write them out at the next refill, defer thin waves.
 // The walk of one tile's input by one workgroup (all its waves): refill
 // idle lanes from the input list, step every lane, park packets that reach
 // the tile's edge and write them out at the next refill, defer thin waves.
@@ -385,7 +383,8 @@ template <bool VEL, bool GEN0, bool VOIGT, bool WRAP>
 __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &ti, const WalkBox &B,
                                           const TileCtx &C, uint32_t n_in, const uint32_t *pre, const uint32_t *lst,
                                           const char *recs, unsigned long long *tally, uint32_t *s_next,
-                                          uint32_t *s_exit, uint32_t s_base, uint32_t *s_fcnt, TileAcc &acc)
+                                          uint32_t *s_exit, uint32_t s_base, uint32_t *s_fcnt,
+                                          unsigned long long *s_cap, TileAcc &acc)
 {
     constexpr int RS = VEL ? 16 : 4;
     const int ncell = ti.sx * ti.sy * ti.sz;
@@ -410,15 +409,15 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
     };
     uint32_t cur = 0, end = 0;
     const uint32_t chunk = (uint32_t)P.chunk;
-    const uint32_t refill = (uint32_t)P.refill;
+    // refilling stalls the whole wave on the new packets' loads: wait until
+    // this many lanes are idle (1..64; 64 waits for all)
+    const uint32_t refill = (uint32_t)min(max(P.refill, 1), 64);
     int32_t dep_q = 0;           // the last step's deposit, not yet issued
     uint32_t dep_w = 0;
     for (;;) {
         uint64_t idle = __ballot(!alive);
-        // refilling stalls the whole wave on the new packets' loads: wait until
-        // enough lanes are idle (or all are)
-        if ((uint32_t)__popcll(idle) < refill && idle != ~0ull) idle = 0;
-        if (idle && more) flush_exits();
+        if (more && (uint32_t)__popcll(idle) >= refill) {
+        flush_exits();
         while (idle && more) {
             if (cur >= end) {
                 uint32_t base = 0;
@@ -450,9 +449,7 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
                     emit_packet<VOIGT>(N, B, gp - B.pkt_off, gc);
                     const Rec rc = rec_at<VEL>(recs, tile_slot(lx, ly, lz) * RS);   // the emission cell's record
                     N.kap = rc.kap;
-                    N.ux = rc.ux;
-                    N.uy = rc.uy;
-                    N.uz = rc.uz;
+                    N.ku = VEL ? ray_velocity(N.kx, N.ky, N.kz, rc) : 0.0f;
                 } else {
                     int k = 0;
                     while (k + 1 <= ti.nsrc && pre[k + 1] <= j) ++k;
@@ -469,35 +466,38 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
             cur += take;
             idle = __ballot(!alive);
         }
-        const uint64_t live = __ballot(alive);
-        // no live lane after the refill means the input is used up (a wave
-        // with idle lanes refills while there is input)
-        if (!live && !more) {
-            flush_exits();
-            break;
         }
-        // (only after a step, so every deferred packet has moved in this generation)
-        if (!more && !fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
-            flush_exits();
-            if (alive) {
-                const uint32_t g = s_base + atomicAdd(s_exit, 1u);
-                save_here<RS>(P.out_state[g], L, C, B);
-                P.out_face[g] = (uint8_t)kDeferred;
-                atomicAdd(&s_fcnt[kDeferred], 1u);
+        if (!more) {
+            const uint64_t live = __ballot(alive);
+            // no live lane once the input is used up: done (while there is
+            // input, a wave with every lane idle refills)
+            if (!live) {
+                flush_exits();
+                break;
             }
-            break;
+            // (only after a step, so every deferred packet has moved in this generation)
+            if (!fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
+                flush_exits();
+                if (alive) {
+                    const uint32_t g = s_base + atomicAdd(s_exit, 1u);
+                    save_here<RS>(P.out_state[g], L, C, B);
+                    P.out_face[g] = (uint8_t)kDeferred;
+                    atomicAdd(&s_fcnt[kDeferred], 1u);
+                }
+                break;
+            }
         }
         fresh = false;
         // Every lane steps: an idle or parked lane's step changes nothing and
         // deposits nothing (selects, not branches, keep the lane state in the
         // same registers round the loop).
         const TStep o = tile_step<VEL, VOIGT, WRAP, RS>(L, alive, C, recs, tally, dep_q, dep_w);
-        acc.cross += o.fin ? L.ncross : 0u;
+        acc.cross += o.walked ? 1u : 0u;
         acc.esc += o.escaped ? L.w : 0u;
         if (VOIGT) acc.wing += o.escaped ? o.wing : 0u;
-        if (__ballot(o.capped)) {
-            acc.capn += o.capped ? 1u : 0u;
-            acc.capw += o.capped ? L.w : 0u;
+        if (o.capped) {          // rare: the tile's LDS totals
+            atomicAdd(&s_cap[0], 1ull);
+            atomicAdd(&s_cap[1], (unsigned long long)L.w);
         }
         pending = pending || o.exit;
         alive = o.alive;
@@ -511,15 +511,16 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
 template <bool VEL, bool GEN0, bool VOIGT>
 __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
 {
-    __shared__ unsigned long long tally[TC];
-    __shared__ float4 srec4[VEL ? TC : 1];
-    __shared__ float sreck[VEL ? 1 : TC];
+    __shared__ unsigned long long tally[kSlots];   // slots of the tile's cells are used
+    __shared__ float4 srec4[VEL ? kSlots : 1];
+    __shared__ float sreck[VEL ? 1 : kSlots];
     __shared__ uint32_t pre[GEN0 ? TC + 1 : 8];   // GEN0: cell prefix of packet counts; else list prefix
     __shared__ uint32_t lst[8];                    // pull: first index of each source list
     __shared__ uint32_t s_tsum[kWaves];
     __shared__ uint32_t s_next, s_exit, s_total, s_base;
     __shared__ uint32_t s_fcnt[8], s_fcur[8];
     __shared__ unsigned long long s_red[kWaves][5];
+    __shared__ unsigned long long s_cap[2];        // capped packets and their weight
 
     const int T = blockIdx.x;
     const int tid = threadIdx.x;
@@ -617,14 +618,26 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
         return;
     }
+    // the tile's records (rows of 16 cells read together) and zero tallies
     for (int q = tid; q < TC; q += BLK) {
-        tally[q] = 0ull;
         const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
         if (lx < ti.sx && ly < ti.sy && lz < ti.sz) {
+            const int sl = tile_slot(lx, ly, lz);
             const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
                                 (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
-            if (VEL) srec4[q] = static_cast<const float4 *>(P.rec)[gc];
-            else sreck[q] = static_cast<const float *>(P.rec)[gc];
+            tally[sl] = 0ull;
+            if (VEL) srec4[sl] = static_cast<const float4 *>(P.rec)[gc];
+            else sreck[sl] = static_cast<const float *>(P.rec)[gc];
+        }
+    }
+    // every other slot reads as outside the tile
+    for (int sl = tid; sl < kSlots; sl += BLK) {
+        int32_t lx, ly, lz;
+        slot_cell(sl, lx, ly, lz);
+        const bool in = (uint32_t)lx < (uint32_t)ti.sx && (uint32_t)ly < (uint32_t)ti.sy && (uint32_t)lz < (uint32_t)ti.sz;
+        if (!in) {
+            if (VEL) srec4[sl] = make_float4(__uint_as_float(kOutside), 0.0f, 0.0f, 0.0f);
+            else sreck[sl] = __uint_as_float(kOutside);
         }
     }
     if (tid == 0) {
@@ -633,6 +646,7 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         s_base = (uint32_t)atomicAdd(P.bump, (unsigned long long)n_in);
     }
     if (tid < 8) s_fcnt[tid] = 0;
+    if (tid < 2) s_cap[tid] = 0;
     __syncthreads();
 
     // ---- walk -------------------------------------------------------------
@@ -649,38 +663,39 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     C.sz = ti.sz;
     C.span = ti.span;
     const char *recs = VEL ? reinterpret_cast<const char *>(srec4) : reinterpret_cast<const char *>(sreck);
-    TileAcc acc{0, 0, 0, 0, 0};
+    TileAcc acc{0, 0, 0};
     // a tile that spans the box along some axis wraps round inside itself
     if (ti.span)
         walk_tile<VEL, GEN0, VOIGT, true>(P, ti, B, C, n_in, pre, lst, recs, tally, &s_next, &s_exit, s_base, s_fcnt,
-                                          acc);
+                                          s_cap, acc);
     else
         walk_tile<VEL, GEN0, VOIGT, false>(P, ti, B, C, n_in, pre, lst, recs, tally, &s_next, &s_exit, s_base, s_fcnt,
-                                           acc);
+                                           s_cap, acc);
 
     // ---- finish: tally, totals, face lists of the exits ----------------------
-    const uint64_t a_esc = wave_sum(acc.esc), a_cross = wave_sum(acc.cross), a_capn = wave_sum(acc.capn),
-                   a_capw = wave_sum(acc.capw), a_wing = VOIGT ? wave_sum(acc.wing) : 0;
+    const uint64_t a_esc = wave_sum(acc.esc), a_cross = wave_sum((uint64_t)acc.cross),
+                   a_wing = VOIGT ? wave_sum(acc.wing) : 0;
     if (lane == 0) {
         s_red[tid >> 6][0] = a_esc;
         s_red[tid >> 6][1] = a_cross;
-        s_red[tid >> 6][2] = a_capn;
-        s_red[tid >> 6][3] = a_capw;
+        s_red[tid >> 6][2] = 0;
+        s_red[tid >> 6][3] = 0;
         s_red[tid >> 6][4] = a_wing;
     }
     __threadfence_block();
     __syncthreads();
     for (int q = tid; q < TC; q += BLK) {
-        const unsigned long long v = tally[q];
+        const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
+        const unsigned long long v = (lx < ti.sx && ly < ti.sy && lz < ti.sz) ? tally[tile_slot(lx, ly, lz)] : 0ull;
         if (v) {
-            const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
             const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
                                 (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
             P.A[gc] += v;    // this workgroup alone owns these cells in this generation
         }
     }
     if (tid < (VOIGT ? 5 : 4)) {
-        unsigned long long t = 0;
+        // (after the barrier: every wave's walk has ended, so s_cap is final)
+        unsigned long long t = tid == 2 ? s_cap[0] : tid == 3 ? s_cap[1] : 0ull;
         for (int w = 0; w < kWaves; ++w) t += s_red[w][tid];
         if (t) {
             unsigned long long *dst = tid == 0 ? &P.tot[ti.box].escaped
@@ -773,6 +788,7 @@ __global__ __launch_bounds__(256) void tail_walk_kernel(TailParams P)
         const WalkBox B = P.boxes[box];
         Lane L;
         load_state(L, P.state[q][k], B);
+        const uint32_t cross0 = L.ncross;          // crossings walked by the tile generations
         const Rec r = load_rec<VEL>(P.rec, L.c);
         if (P.face[q][k] == kDeferred) L.kap = r.kap;   // deferred inside its cell
         else finish_entry<VEL>(L, r);                   // entering through a face
@@ -783,7 +799,7 @@ __global__ __launch_bounds__(256) void tail_walk_kernel(TailParams P)
         do {
             fate = walk_step<VEL, VOIGT>(L, P.rec, GlobalSink{P.A}, P.max_cross, dep, ln, wing);
         } while (fate == kAlive);
-        cross = L.ncross;
+        cross = L.ncross - cross0;                 // the generations counted theirs
         esc = fate == kEscaped ? L.w : 0;
         capn = fate == kCapped ? 1 : 0;
         capw = fate == kCapped ? L.w : 0;

@@ -41,7 +41,7 @@ struct Lane {
     float kx, ky, kz;    // direction (binary32: velocity terms only)
     float x;             // gas-frame frequency, Doppler widths
     float kap;           // kappa of the current cell
-    float ux, uy, uz;    // bulk velocity of the current cell (Doppler units)
+    float ku;            // k . U of the current cell (bulk velocity along the ray, Doppler units)
     uint32_t w;          // remaining weight (w0 < 2^32)
     uint32_t ncross;
     int32_t nx, ny, nz;
@@ -68,6 +68,16 @@ __device__ __forceinline__ Rec load_rec(const void *__restrict__ rec, uint32_t c
         r.ux = r.uy = r.uz = 0.0f;
     }
     return r;
+}
+
+// k . U of a cell for a ray of direction k (Doppler units). The frequency
+// shift of Eq. (inout) at a face is the change of this projection,
+// x_new = x_old - (k.U_new - k.U_old). One expression, shared by every place
+// that forms it, so that the rounding is the same wherever a face is crossed
+// (a uniform flow gives exactly equal projections and no shift).
+__device__ __forceinline__ float ray_velocity(float kx, float ky, float kz, const Rec &r)
+{
+    return fmaf(kz, r.uz, fmaf(ky, r.uy, kx * r.ux));
 }
 
 // Profile constants of a box for the Voigt walk (uniform over a tile).
@@ -149,28 +159,34 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
     emit_packet<VOIGT>(L, B, p, gcell, state);
     const Rec r = load_rec<VEL>(rec, gcell);
     L.kap = r.kap;
-    L.ux = r.ux;
-    L.uy = r.uy;
-    L.uz = r.uz;
+    L.ku = VEL ? ray_velocity(L.kx, L.ky, L.kz, r) : 0.0f;
 }
 
 // Swept profile mass Phi(x) - Phi(x - dx) for dx > 0, Phi the cumulative
 // Doppler profile. Segments are short (dx = delta * length, at most 0.033
 // Doppler widths for the paper's cells), so the integral of
-// exp(-y^2)/sqrt(pi) over the segment is taken by 2-point Gauss-Legendre:
-// relative error below 3e-7 for dx <= 0.033 and |x| <= 3 (1e-6 to |x| = 4),
-// below 5e-6 for dx <= 0.05 and |x| <= 4, against binary32's 6e-8. Longer
-// segments use the difference of complementary error functions, each taken
-// where it is small. Never negative.
+// f(y) = exp(-y^2)/sqrt(pi) over the segment is taken from the Taylor series
+// of f about the midpoint m = x - h, h = dx/2:
+//   integral = 2h f(m) [1 + (h^2/6) f2(m) + (h^4/120) f4(m)],
+//   f2 = f''/f = 4m^2 - 2,   f4 = f''''/f = 16m^4 - 48m^2 + 12,
+// with one exponential per segment. The next term of the series is below
+// 3e-7 of the result for dx <= 0.05 and |x| <= 7, so the error is that of the
+// binary32 exponential of -m^2 (about 6e-8 m^2 relative, as for any
+// single-precision evaluation of the profile). Longer segments use the
+// difference of complementary error functions, each taken where it is small.
+// Never negative.
 __device__ __forceinline__ float swept_profile(float x, float dx)
 {
     if (dx <= 0.05f) {
         const float h = 0.5f * dx;
         const float m = x - h;
-        const float a = h * 0.5773502691896258f;          // 1 / sqrt(3)
-        const float y0 = m - a, y1 = m + a;
-        // (e0 + e1) h / sqrt(pi)
-        return h * 0.5641895835477563f * (__expf(-y0 * y0) + __expf(-y1 * y1));
+        const float m2 = m * m;
+        const float h2 = h * h;
+        const float c2 = fmaf(m2, 2.0f / 3.0f, -1.0f / 3.0f);                 // f2 / 6
+        const float c4 = fmaf(m2, fmaf(m2, 2.0f / 15.0f, -0.4f), 0.1f);       // f4 / 120
+        const float br = fmaf(h2, fmaf(h2, c4, c2), 1.0f);
+        // 2h / sqrt(pi) = dx / sqrt(pi)
+        return (dx * 0.5641895835477563f) * __expf(-m2) * br;
     }
     const float lo = x - dx;
     const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(x)) : 0.5f * (erfcf(-x) - erfcf(-lo));
@@ -217,25 +233,15 @@ __device__ __forceinline__ uint32_t absorbed_share(uint32_t w, float tau)
     return thin ? k : w - k;
 }
 
-// k . (U_new - U_old) in thermal units: the frequency shift of Eq. (inout)
-// at a face. One expression, shared by every place that applies the jump, so
-// that the rounding is the same wherever the face is crossed.
-template <class LaneT>
-__device__ __forceinline__ float bulk_jump(const LaneT &L, const Rec &nr)
-{
-    return L.kx * (nr.ux - L.ux) + L.ky * (nr.uy - L.uy) + L.kz * (nr.uz - L.uz);
-}
-
-// Entering a cell: the bulk term of Eq. (inout), x_new = x_old - k.(U_new -
-// U_old), then the new cell's opacity and velocity.
+// Entering a cell: the bulk term of Eq. (inout), x_new = x_old - (k.U_new -
+// k.U_old), then the new cell's opacity and velocity projection.
 template <bool VEL>
 __device__ __forceinline__ void finish_entry(Lane &L, const Rec &nr)
 {
     if (VEL) {
-        L.x = L.x - bulk_jump(L, nr);
-        L.ux = nr.ux;
-        L.uy = nr.uy;
-        L.uz = nr.uz;
+        const float kn = ray_velocity(L.kx, L.ky, L.kz, nr);
+        L.x = L.x - (kn - L.ku);
+        L.ku = kn;
     }
     L.kap = nr.kap;
 }
@@ -289,9 +295,7 @@ __device__ __forceinline__ void keep_or_take(Lane &L, const Lane &N, bool take)
     L.t = take ? N.t : L.t;
     L.x = take ? N.x : L.x;
     L.kap = take ? N.kap : L.kap;
-    L.ux = take ? N.ux : L.ux;
-    L.uy = take ? N.uy : L.uy;
-    L.uz = take ? N.uz : L.uz;
+    L.ku = take ? N.ku : L.ku;
     L.w = take ? N.w : L.w;
     L.ncross = take ? N.ncross : L.ncross;
 }
@@ -311,7 +315,7 @@ __device__ __forceinline__ void idle_lane(Lane &L)
     L.ky = L.kz = 0.0f;
     L.x = -3.0e38f;
     L.kap = 0.0f;
-    L.ux = L.uy = L.uz = 0.0f;
+    L.ku = 0.0f;
     L.w = 0u;
     L.ncross = 0u;
     L.delta = 1.0f;
@@ -454,10 +458,9 @@ __device__ __forceinline__ int walk_step(Lane &L, const void *__restrict__ rec, 
     // entering a cell owned by the same region: the bulk term of Eq. (inout)
     // and the new cell's opacity; leaving it: keep the pre-jump frequency
     if (VEL) {
-        L.x = stay ? xo - bulk_jump(L, nr) : xo;
-        L.ux = stay ? nr.ux : L.ux;
-        L.uy = stay ? nr.uy : L.uy;
-        L.uz = stay ? nr.uz : L.uz;
+        const float kn = ray_velocity(L.kx, L.ky, L.kz, nr);
+        L.x = stay ? xo - (kn - L.ku) : xo;
+        L.ku = stay ? kn : L.ku;
     } else {
         L.x = xo;
     }
