@@ -159,14 +159,14 @@ struct mc_lya_ctx {
     std::vector<uint64_t> graph_key;
     int graph_gens = 64;                     // tile generations inside the graph
     int eager_gens = kEagerGens;             // tile generations in the first eager round
-    int tail = 100000;                       // MC_LYA_OPT_TAIL (millionths of a batch)
+    int tail = 20000;                        // MC_LYA_OPT_TAIL (millionths of a batch)
     uint32_t *d_tail_prefix = nullptr;       // [tiles] first tail packet of each tile
     uint64_t epoch = 0;                      // bumped whenever a buffer a graph reads is reallocated
 
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
     int kernel = 2, block = 256, waves_per_cu = 32, chunk = 256, refill = 16, nqueues = 8;
-    int tile_chunk = 64, tile_refill = 24;   // the tiled walk's own chunk and refill
+    int tile_chunk = 64, tile_refill = 48;   // the tiled walk's own chunk and refill
     int64_t max_cross = 1000000;
     int timing = 0;                          // 0 off, 1 per launch, 2 per transport
     int64_t coarse_launches = 0;

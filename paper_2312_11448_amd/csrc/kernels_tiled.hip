@@ -451,8 +451,11 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
                     N.kap = rc.kap;
                     N.ku = VEL ? ray_velocity(N.kx, N.ky, N.kz, rc) : 0.0f;
                 } else {
+                    // the list holding position j (independent reads of the
+                    // list prefix, not a chain)
                     int k = 0;
-                    while (k + 1 <= ti.nsrc && pre[k + 1] <= j) ++k;
+#pragma unroll
+                    for (int m = 1; m <= 6; ++m) k += (m <= ti.nsrc && pre[m] <= j) ? 1 : 0;
                     const uint32_t g = P.in_idx[lst[k] + (j - pre[k])];
                     load_state(N, P.in_state[g], B);
                     const Rec rc = rec_at<VEL>(recs, tile_slot(N.ix - ti.ox, N.iy - ti.oy, N.iz - ti.oz) * RS);

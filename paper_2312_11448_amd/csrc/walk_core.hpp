@@ -80,16 +80,23 @@ __device__ __forceinline__ float ray_velocity(float kx, float ky, float kz, cons
     return fmaf(kz, r.uz, fmaf(ky, r.uy, kx * r.ux));
 }
 
-// Profile constants of a box for the Voigt walk (uniform over a tile).
+// Line constants of a box (uniform over a tile): the Voigt walk's, and
+// whether every segment is short. A segment is at most a cell's diagonal
+// long (sqrt 3 cells; its binary32 length rounds below 1.75), so its swept
+// frequency dx = delta * length (or less, when it stops at -x_eff) stays
+// below 0.05 Doppler widths in every box with delta <= 0.05 / 1.75; there the
+// short-segment form of the swept profile is taken without a per-segment
+// test (the same form the test would choose, so the same bits).
 struct Line {
     float damp;     // 2a/pi
     float kfar;     // mean kappa of the box
     float xblue;    // packets above it are not walked
+    bool short_seg; // delta * 1.75 <= 0.05
 };
 
 __device__ __forceinline__ Line line_of(const WalkBox &B)
 {
-    return Line{B.damp, B.kfar, B.xblue};
+    return Line{B.damp, B.kfar, B.xblue, B.delta * 1.75f <= 0.05f};
 }
 
 // Emission of packet p (box-local id) in global cell gcell: position uniform
@@ -175,19 +182,23 @@ __device__ __forceinline__ void init_packet(Lane &L, const WalkBox &B, uint64_t 
 // single-precision evaluation of the profile). Longer segments use the
 // difference of complementary error functions, each taken where it is small.
 // Never negative.
-__device__ __forceinline__ float swept_profile(float x, float dx)
+__device__ __forceinline__ float swept_short(float x, float dx)
 {
-    if (dx <= 0.05f) {
-        const float h = 0.5f * dx;
-        const float m = x - h;
-        const float m2 = m * m;
-        const float h2 = h * h;
-        const float c2 = fmaf(m2, 2.0f / 3.0f, -1.0f / 3.0f);                 // f2 / 6
-        const float c4 = fmaf(m2, fmaf(m2, 2.0f / 15.0f, -0.4f), 0.1f);       // f4 / 120
-        const float br = fmaf(h2, fmaf(h2, c4, c2), 1.0f);
-        // 2h / sqrt(pi) = dx / sqrt(pi)
-        return (dx * 0.5641895835477563f) * __expf(-m2) * br;
-    }
+    const float h = 0.5f * dx;
+    const float m = x - h;
+    const float m2 = m * m;
+    const float h2 = h * h;
+    const float c2 = fmaf(m2, 2.0f / 3.0f, -1.0f / 3.0f);                 // f2 / 6
+    const float c4 = fmaf(m2, fmaf(m2, 2.0f / 15.0f, -0.4f), 0.1f);       // f4 / 120
+    const float br = fmaf(h2, fmaf(h2, c4, c2), 1.0f);
+    // 2h / sqrt(pi) = dx / sqrt(pi)
+    return (dx * 0.5641895835477563f) * __expf(-m2) * br;
+}
+
+__device__ __forceinline__ float swept_profile(float x, float dx, bool short_seg = false)
+{
+    if (short_seg) return swept_short(x, dx);   // (uniform over a tile: no per-lane branch)
+    if (dx <= 0.05f) return swept_short(x, dx);
     const float lo = x - dx;
     const float d = lo >= 0.0f ? 0.5f * (erfcf(lo) - erfcf(x)) : 0.5f * (erfcf(-x) - erfcf(-lo));
     return fmaxf(d, 0.0f);
@@ -201,11 +212,11 @@ __device__ __forceinline__ float swept_profile(float x, float dx)
 // dx <= 0.1 at |y| >= 3 and 3e-5 for the paper's cells (dx <= 0.033); in the
 // core the thermal part dominates. Longer segments use the difference
 // F(x - dx) - F(x). Never negative.
-__device__ __forceinline__ float swept_profile_voigt(float x, float dx, float damp)
+__device__ __forceinline__ float swept_profile_voigt(float x, float dx, float damp, bool short_seg = false)
 {
-    const float corr = dx <= 0.1f ? -dx * dawson_deriv_f32(x - 0.5f * dx)
-                                  : dawson_f32(x - dx) - dawson_f32(x);
-    return fmaxf(fmaf(damp, corr, swept_profile(x, dx)), 0.0f);
+    const float corr = (short_seg || dx <= 0.1f) ? -dx * dawson_deriv_f32(x - 0.5f * dx)
+                                                 : dawson_f32(x - dx) - dawson_f32(x);
+    return fmaxf(fmaf(damp, corr, swept_profile(x, dx, short_seg)), 0.0f);
 }
 
 // Cumulative Voigt profile to first order in a (the far-wing share).
@@ -365,7 +376,7 @@ __device__ __forceinline__ Segment segment(float x, float s, float delta, float 
     g.xo = fmaf(-delta, s, x);
     g.esc = g.xo <= -xeff;
     const float dx = g.esc ? x + xeff : delta * s;
-    const float dphi = VOIGT ? swept_profile_voigt(x, dx, ln.damp) : swept_profile(x, dx);
+    const float dphi = VOIGT ? swept_profile_voigt(x, dx, ln.damp, ln.short_seg) : swept_profile(x, dx, ln.short_seg);
     g.d = walk ? absorbed_share(w, kap * dphi) : 0u;
     return g;
 }
