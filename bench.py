@@ -72,7 +72,9 @@ def parse():
                          "on held-out boxes and time its inference on the 256^3 box")
     ap.add_argument("--profile", default="doppler", choices=["doppler", "voigt"],
                     help="line profile of every box (voigt: Eq. (MC) with its damping wing)")
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--ref-runs", type=int, default=8,
+                    help="surrogate: transports of 128 packets per cell averaged into each reference")
     ap.add_argument("--photons", type=int, default=1 << 20, help="scatter: photons per step")
     ap.add_argument("--zeta", type=float, default=1e4,
                     help="scatter: expansion-rate factor of the App. A test problem (1e4: tau_S = 6e4, "
@@ -346,7 +348,9 @@ def bench_scatter(a):
 
 def bench_surrogate(a):
     """Surrogate cells per second (features + inference over the 256^3 box),
-    with its accuracy against held-out Monte-Carlo references."""
+    with its accuracy against a high-statistics Monte-Carlo reference of
+    held-out 256^3 boxes. Training: 200 field seeds of the three single-box
+    workloads (each box's own Monte Carlo, 2^17 cells kept per box)."""
     import numpy as np
     import torch
     import workloads as W
@@ -355,24 +359,52 @@ def bench_surrogate(a):
     from paper_2312_11448_amd import surrogate as SG
 
     t_start = time.perf_counter()
-    train_specs = WS.training_specs()
-    data = SG.mc_cells(train_specs)
+    parts = []
+    boxes = WS.training_boxes()
+    t_fields = 0.0
+    sims = {}            # one context per workload family; each new box's fields are loaded into it
+    for i, (key, fseed, ppc, pseed) in enumerate(boxes):
+        t0 = time.perf_counter()
+        spec = WS.family_box(key, fseed, ppc, pseed, device="cuda")
+        t_fields += time.perf_counter() - t0
+        if key not in sims:
+            for k in list(sims):
+                sims.pop(k).close()
+            sims[key] = M.Simulation(spec, max_packets=spec.n_packets,
+                                     batch_packets=min(spec.n_packets, SG.BATCH))
+        parts.append(SG.mc_cells([spec], keep=1 << 17, pick_seed=i, sim=sims[key]))
+        del spec
+        if i % 10 == 9 or i == len(boxes) - 1:
+            print(f"surrogate: training box {i + 1}/{len(boxes)} ({key}), {time.perf_counter() - t_start:.0f} s",
+                  flush=True)
+    for k in list(sims):
+        sims.pop(k).close()
+    data = SG.concat(parts)
+    del parts
+    n_train = int(data["features"].shape[0])
     with M.Mlp(WS.initial_params(1)) as mlp:
+        t0 = time.perf_counter()
         losses = SG.train(mlp, data, steps=a.train_steps, log_every=max(1, a.train_steps // 10))
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
         lo, hi = SG.envelope(data["features"][data["w"] > 0])
         mlp.set_envelope(lo, hi)
         del data
-        eval_specs = WS.evaluation_specs()
-        ref = SG.mc_cells(eval_specs)
-        ref2 = SG.mc_cells(eval_specs, seeds=[s.seed + 1000 for s in eval_specs])
-        acc = SG.evaluate(mlp, ref, ref2)
-        _, _, n_out = mlp.forward(ref["features"], outside=True, count=True)
-        del ref, ref2
+        print(f"surrogate: trained {a.train_steps} steps in {t_train:.1f} s", flush=True)
+        eval_specs = [WS.family_box(k, fs, 16, ps, device="cuda") for k, fs, ps in WS.evaluation_boxes()]
+        ref = SG.reference(eval_specs, runs=a.ref_runs, packets_per_cell=128, seed0=5000)
+        print(f"surrogate: reference 1 done, {time.perf_counter() - t_start:.0f} s", flush=True)
+        ref2 = SG.reference(eval_specs, runs=a.ref_runs, packets_per_cell=128, seed0=6000)
+        print(f"surrogate: reference 2 done, {time.perf_counter() - t_start:.0f} s", flush=True)
+        pred = SG.predict(mlp, eval_specs)
+        acc = SG.evaluate(pred["M"], ref, ref2)
+        n_out = pred["n_outside"]
+        del ref, ref2, pred
         big = W.make_box("c3")
         with M.Simulation(big) as sim:
             t_all, t_inf, n, _ = SG.time_inference(mlp, sim)
-            # the Monte Carlo of the same box, timed after a first transport
-            # (which allocates the packet-state buffers)
+            # the Monte Carlo of the same box and packet count, timed after a
+            # first transport
             sim.emit()
             sim.transport()
             sim.emit()
@@ -392,11 +424,13 @@ def bench_surrogate(a):
         "steps": 5, "warmup": 2, "ms_per_step": t_all * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "8-64-64-1 ReLU network on the 256^3 k^2 field (features + inference); "
-                               "trained on 24 64^3 boxes (128 packets/cell, z 800-1400, rms 0.2-2), "
-                               "evaluated on 3 held-out 128^3 boxes (256 packets/cell)",
+                               "trained on 200 field seeds of the 32^3, 128^3 and 256^3 workloads "
+                               "(512, 128 and 64 packets per cell), evaluated on 3 held-out 256^3 seeds "
+                               f"against the mean of {a.ref_runs} transports of 128 packets per cell",
                    "cells": n, "inference_ms": t_inf * 1e3, "features_ms": (t_all - t_inf) * 1e3,
                    "mc_transport_s_same_box": t_mc, "mc_crossings": st.crossings,
-                   "speedup_vs_mc": t_mc / t_all, "train_steps": a.train_steps,
+                   "speedup_vs_mc": t_mc / t_all, "train_steps": a.train_steps, "train_cells": n_train,
+                   "train_s": t_train, "field_generation_s": t_fields,
                    "train_loss": losses, "eval_cells_outside_envelope": n_out,
                    "accuracy_vs_reference_mc": acc, "wall_s": time.perf_counter() - t_start},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",

@@ -210,10 +210,10 @@ enum {
  *               emission weight, quantised weight, packet count, first packet
  *               and absorbed tally (36 bytes), plus 48 bytes with evolve = 1;
  *   per packet  its cell (4 bytes) and two generations of tiled-walk
- *               hand-over state (234 bytes): about 238 bytes x N; if that much
- *               cannot be allocated, init halves the hand-over part down to
- *               2^25 packets and the tiled walk then walks larger emissions in
- *               batches of that size;
+ *               hand-over state (234 bytes) for B = batch_packets packets (N
+ *               if 0): 4 N + 234 B bytes; if the hand-over part cannot be
+ *               allocated, init halves B down to 2^25 packets; the tiled
+ *               walk walks emissions larger than B in batches of B;
  *   per tile    its table entry and exit lists (about 140 bytes);
  *   per box     a few hundred bytes of tables and per-block partial sums. */
 typedef struct mc_lya_limits {
@@ -222,6 +222,9 @@ typedef struct mc_lya_limits {
     int32_t evolve;               /* 1: reserve mc_lya_evolve's six doubles per cell; 0: that
                                      call returns ESTATE */
     int32_t reserved;             /* 0 */
+    uint64_t batch_packets;       /* packets of one tiled-walk batch (0 = max_packets): the
+                                     hand-over state reserved for it is 234 bytes a packet;
+                                     larger emissions walk in batches (the same integers) */
 } mc_lya_limits;
 
 /* Creates a context for n_boxes boxes, validates and packs their fields
@@ -457,6 +460,17 @@ mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uin
  * Asynchronous on the context's stream. Errors: EINVAL, ESTATE, EDEVICE. */
 mc_lya_status mc_lya_features(mc_lya_ctx *ctx, float *out);
 
+/* The surrogate's regression data from the last transport (after
+ * mc_lya_transport; the same tallies mc_lya_feed reads), per cell:
+ *   y  dev [total cells] float: ln M_c, the log of the mixing correction of
+ *      mc_lya_feed (Sec. IV.B, Eq. (dotne-mix));
+ *   w  dev [total cells] float: the cell's share S_c / sum_box(S) of its box's
+ *      recombination source (Eq. (rec0)), the weight of the cell in the loss.
+ * Cells with M_c = 0 (nothing absorbed) get y = 0 and w = 0. Synchronises the
+ * stream once (per-box sums), then asynchronous. Errors: EINVAL, ESTATE,
+ * EDEVICE. */
+mc_lya_status mc_lya_surrogate_targets(mc_lya_ctx *ctx, float *y, float *w);
+
 typedef struct mc_lya_mlp mc_lya_mlp;
 
 /* Adam hyper-parameters (Kingma & Ba 2015, Algorithm 1, bias-corrected). */
@@ -493,6 +507,21 @@ mc_lya_status mc_lya_mlp_set_envelope(mc_lya_mlp *mlp, const float *lo, const fl
  * Asynchronous otherwise. Errors: EINVAL, EDEVICE. */
 mc_lya_status mc_lya_mlp_forward(mc_lya_mlp *mlp, const float *features, uint64_t n, float *y,
                                  uint8_t *outside, uint64_t *n_outside);
+
+/* The mixing correction the surrogate gives, with the Monte Carlo as
+ * fallback: mc_lya_mlp_forward's y for n cells, then per cell
+ *   M = fallback[i]  where the cell's features are outside the envelope and
+ *                    a fallback is given (the Monte Carlo's M_c, mc_lya_feed),
+ *   M = exp(y)       otherwise.
+ *   features  dev [n][8] float
+ *   fallback  dev [n] float, or NULL (no fallback: M = exp(y) everywhere)
+ *   y         dev [n] float (out: the network's ln M)
+ *   M         dev [n] float (out)
+ *   outside   dev [n] uint8 (out), or NULL; n_outside host (out), or NULL
+ *             (then synchronises)
+ * Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_mlp_correction(mc_lya_mlp *mlp, const float *features, uint64_t n, const float *fallback,
+                                    float *y, float *M, uint8_t *outside, uint64_t *n_outside);
 
 /* The weighted mean squared error L = sum w_i (y_i - t_i)^2 / sum w_i over n
  * cells of the network mc_lya_mlp_forward evaluates, and its gradient with

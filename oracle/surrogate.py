@@ -92,6 +92,21 @@ def features(overdensity, velocity=None, x_e=0.1, temp_K=3000.0, z=1100.0):
 
 
 # --- network -----------------------------------------------------------------
+def targets(spec, A, E, n_packets, wing=0):
+    """Regression data of the surrogate from a box's tallies: y = ln M_c
+    (M_c = A_c / A_c^fm, the mixing correction of Sec. IV.B, Eq. (dotne-mix),
+    as the feed forms it) and the loss weight of the cell, its share
+    S_c / sum(S) of the box's recombination source. Cells with M_c = 0 have no
+    logarithm: y = 0, weight 0."""
+    from . import physics as P
+    mix = P.feed(spec, A, E, n_packets, wing)["mix_corr"]
+    S = P.emission_weights(spec)
+    ok = mix > 0
+    y = np.where(ok, np.log(np.where(ok, mix, 1.0)), 0.0)
+    w = np.where(ok, S / S.sum(), 0.0)
+    return y, w
+
+
 def unpack(params):
     p = _f64(params)
     W1 = p[OFF_W1:OFF_B1].reshape(HIDDEN, N_FEAT)

@@ -39,7 +39,8 @@ class mc_lya_box_desc(C.Structure):
 
 
 class mc_lya_limits(C.Structure):
-    _fields_ = [("max_packets", C.c_uint64), ("evolve", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("max_packets", C.c_uint64), ("evolve", C.c_int32), ("reserved", C.c_int32),
+                ("batch_packets", C.c_uint64)]
 
 
 class mc_lya_box_stats(C.Structure):
@@ -89,8 +90,8 @@ EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_evolve",
            "mc_lya_set_option", "mc_lya_autotune", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
-           "mc_lya_features", "mc_lya_mlp_create", "mc_lya_mlp_get_params", "mc_lya_mlp_set_envelope",
-           "mc_lya_mlp_forward", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_destroy",
+           "mc_lya_features", "mc_lya_surrogate_targets", "mc_lya_mlp_create", "mc_lya_mlp_get_params",
+           "mc_lya_mlp_set_envelope", "mc_lya_mlp_forward", "mc_lya_mlp_correction", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_destroy",
            "mc_lya_mlp_last_error", "mc_lya_mlp_gradient_static", "mc_lya_mlp_static_last_error"]
 # the static workspace of mc_lya_mlp_gradient_static (mc_lya.h)
 MC_LYA_STATIC_MAX_CELLS = (1 << 40) - 1
@@ -150,6 +151,8 @@ def load():
     L.mc_lya_last_error.restype = C.c_char_p
     fp = P(C.c_float)
     L.mc_lya_features.argtypes = [vp, vp]
+    L.mc_lya_surrogate_targets.argtypes = [vp, vp, vp]
+    L.mc_lya_mlp_correction.argtypes = [vp, vp, u64, vp, vp, vp, vp, P(u64)]
     L.mc_lya_mlp_create.argtypes = [P(vp), fp, vp]
     L.mc_lya_mlp_get_params.argtypes = [vp, fp]
     L.mc_lya_mlp_set_envelope.argtypes = [vp, fp, fp]
@@ -180,19 +183,19 @@ def _arr(ctype, values):
     return (ctype * len(values))(*values)
 
 
-def mc_lya_init(boxes, stream=None, max_packets=None, evolve=False):
+def mc_lya_init(boxes, stream=None, max_packets=None, evolve=False, batch_packets=0):
     """boxes: sequence of mc_lya_box_desc; stream: hipStream_t as int (None =
-    torch's current stream); max_packets / evolve: the mc_lya_limits (None:
-    the library's defaults). Returns the context handle."""
+    torch's current stream); max_packets / evolve / batch_packets: the
+    mc_lya_limits (None: the library's defaults). Returns the context handle."""
     L = load()
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     arr = (mc_lya_box_desc * len(boxes))(*boxes)
     ctx = C.c_void_p()
     lim = None
-    if max_packets is not None or evolve:
+    if max_packets is not None or evolve or batch_packets:
         lim = mc_lya_limits(max_packets=int(max_packets if max_packets is not None else 1 << 20),
-                            evolve=1 if evolve else 0, reserved=0)
+                            evolve=1 if evolve else 0, reserved=0, batch_packets=int(batch_packets))
     _check(L.mc_lya_init(C.byref(ctx), arr, len(boxes), None if lim is None else C.byref(lim),
                          C.c_void_p(stream)))
     return ctx
@@ -289,6 +292,10 @@ def mc_lya_features(ctx, out_ptr):
     return _check(load().mc_lya_features(ctx, out_ptr), ctx)
 
 
+def mc_lya_surrogate_targets(ctx, y_ptr, w_ptr):
+    return _check(load().mc_lya_surrogate_targets(ctx, y_ptr, w_ptr), ctx)
+
+
 def _check_mlp(status, mlp=None):
     if status != MC_LYA_OK:
         L = load()
@@ -324,6 +331,13 @@ def mc_lya_mlp_forward(mlp, feat_ptr, n, y_ptr, outside_ptr=None, count=False):
     c = C.c_uint64()
     _check_mlp(load().mc_lya_mlp_forward(mlp, feat_ptr, int(n), y_ptr, outside_ptr,
                                          C.byref(c) if count else None), mlp)
+    return c.value if count else None
+
+
+def mc_lya_mlp_correction(mlp, feat_ptr, n, fallback_ptr, y_ptr, m_ptr, outside_ptr=None, count=False):
+    c = C.c_uint64()
+    _check_mlp(load().mc_lya_mlp_correction(mlp, feat_ptr, int(n), fallback_ptr, y_ptr, m_ptr, outside_ptr,
+                                            C.byref(c) if count else None), mlp)
     return c.value if count else None
 
 

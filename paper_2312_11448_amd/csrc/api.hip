@@ -21,7 +21,7 @@ static_assert(sizeof(mc_lya_scatter_opts) == 40, "mc_lya_scatter_opts layout");
 static_assert(sizeof(mc_lya_feed_stats) == 56, "mc_lya_feed_stats layout");
 static_assert(sizeof(mc_lya_packet_trace) == 64, "mc_lya_packet_trace layout");
 static_assert(sizeof(mc_lya_tune_result) == 88, "mc_lya_tune_result layout");
-static_assert(sizeof(mc_lya_limits) == 16, "mc_lya_limits layout");
+static_assert(sizeof(mc_lya_limits) == 24, "mc_lya_limits layout");
 
 namespace {
 
@@ -935,6 +935,8 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
     if (lim.max_packets == 0 || lim.max_packets >= (1ull << 40))
         return fail(nullptr, MC_LYA_EINVAL, "limits.max_packets must be in [1, 2^40)");
     if (lim.evolve != 0 && lim.evolve != 1) return fail(nullptr, MC_LYA_EINVAL, "limits.evolve must be 0 or 1");
+    if (lim.reserved != 0) return fail(nullptr, MC_LYA_EINVAL, "limits.reserved must be 0");
+    if (lim.batch_packets == 0 || lim.batch_packets > lim.max_packets) lim.batch_packets = lim.max_packets;
     uint64_t cells = 0;
     for (int b = 0; b < n_boxes; ++b) {
         const std::string why = check_desc(boxes[b], b);
@@ -1014,7 +1016,7 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         (e = dalloc(&c->d_cop, lim.max_packets)) != hipSuccess ||
         (lim.evolve && ((e = dalloc(&c->d_ev, 6 * cells)) != hipSuccess ||
                         (e = dalloc(&c->d_ev_coef, (size_t)n_boxes)) != hipSuccess)) ||
-        (e = alloc_tile_buffers(c, lim.max_packets)) != hipSuccess)
+        (e = alloc_tile_buffers(c, lim.batch_packets)) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
     c->cpp.assign(n_boxes, 1.0);
     c->tiled.assign(n_boxes, 1);         // the tile table starts with every box; emit narrows it
@@ -1182,10 +1184,10 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
     return MC_LYA_OK;
 }
 
-mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya_feed_stats *stats)
+// Per-box scalars of the feed from the last transport's tallies (uploaded to
+// c->d_feed, queued on the stream) and, optionally, its statistics.
+static mc_lya_status feed_prepare(mc_lya_ctx *c, mc_lya_feed_stats *stats)
 {
-    if (!c) return MC_LYA_EINVAL;
-    if (c->state < 2) return fail(c, MC_LYA_ESTATE, "mc_lya_feed before mc_lya_transport");
     const int nb = c->n_boxes;
     HIP_TRY(c, launch_tally(c->d_walk, nb, c->max_blk, c->d_A, c->d_npk, nullptr, nullptr, c->d_part,
                             c->d_boxabs, c->stream));
@@ -1222,6 +1224,7 @@ mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya
         fb[b].thermal = c_mc * ph.beta * ph.boltz;
         fb[b].fm_norm = sum_n1s > 0.0 ? sum_A / sum_n1s : 0.0;
         fb[b].wing_n1s = sum_n1s > 0.0 ? wing / sum_n1s : 0.0;
+        fb[b].w_inv = sums[4 * b + 0] > 0.0 ? 1.0 / sums[4 * b + 0] : 0.0;
         if (stats) {
             mc_lya_feed_stats &s = stats[b];
             const double n1s_mean = sum_n1s / ncell;
@@ -1237,12 +1240,34 @@ mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya
             s.ndot_e_mean = (-sum_s + reion * sum_A * fb[b].a_norm + fb[b].thermal * sum_n1s) / ncell;
         }
     }
+    // (fb is host memory the copy reads: synchronise before it goes)
+    HIP_TRY(c, hipMemcpyAsync(c->d_feed, fb.data(), sizeof(FeedBox) * nb, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_feed(mc_lya_ctx *c, double *ndot_e, float *mix_corr, mc_lya_feed_stats *stats)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 2) return fail(c, MC_LYA_ESTATE, "mc_lya_feed before mc_lya_transport");
+    mc_lya_status st = feed_prepare(c, stats);
+    if (st != MC_LYA_OK) return st;
     if (ndot_e || mix_corr) {
-        HIP_TRY(c, hipMemcpyAsync(c->d_feed, fb.data(), sizeof(FeedBox) * nb, hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, launch_feed(c->d_pack, c->d_feed, nb, c->max_blk, c->d_wgt, c->d_A, ndot_e, mix_corr,
+        HIP_TRY(c, launch_feed(c->d_pack, c->d_feed, c->n_boxes, c->max_blk, c->d_wgt, c->d_A, ndot_e, mix_corr,
                                c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_surrogate_targets(mc_lya_ctx *c, float *y, float *w)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (c->state < 2) return fail(c, MC_LYA_ESTATE, "mc_lya_surrogate_targets before mc_lya_transport");
+    if (!y || !w) return fail(c, MC_LYA_EINVAL, "y or w is NULL");
+    mc_lya_status st = feed_prepare(c, nullptr);
+    if (st != MC_LYA_OK) return st;
+    HIP_TRY(c, launch_targets(c->d_pack, c->d_feed, c->n_boxes, c->max_blk, c->d_wgt, c->d_A, y, w, c->stream));
     return MC_LYA_OK;
 }
 

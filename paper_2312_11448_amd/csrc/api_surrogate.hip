@@ -171,6 +171,18 @@ mc_lya_status mc_lya_mlp_forward(mc_lya_mlp *m, const float *features, uint64_t 
     return MC_LYA_OK;
 }
 
+mc_lya_status mc_lya_mlp_correction(mc_lya_mlp *m, const float *features, uint64_t n, const float *fallback,
+                                    float *y, float *M, uint8_t *outside, uint64_t *n_outside)
+{
+    if (!m) return MC_LYA_EINVAL;
+    if (n > 0 && !M) return mlp_fail(m, MC_LYA_EINVAL, "M is NULL");
+    if (n > 0 && (uint64_t)(n + 255) / 256 > 0x7fffffffull) return mlp_fail(m, MC_LYA_EINVAL, "too many cells");
+    mc_lya_status st = mc_lya_mlp_forward(m, features, n, y, outside, n_outside);
+    if (st != MC_LYA_OK || n == 0) return st;
+    MLP_TRY(m, launch_mlp_correction(y, outside, fallback, n, M, m->stream));
+    return MC_LYA_OK;
+}
+
 mc_lya_status mc_lya_mlp_gradient(mc_lya_mlp *m, const float *features, const float *targets, const float *weights,
                                   uint64_t n, float *grad, float *loss)
 {

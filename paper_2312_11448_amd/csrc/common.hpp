@@ -322,11 +322,16 @@ struct FeedBox {
     double thermal;          // C_MC beta exp(-E_alpha/kT)
     double fm_norm;          // (sum(A) + wing) / sum(n_1s)
     double wing_n1s;         // wing / sum(n_1s): the far damping wing's absorption per unit n_1s
+    double w_inv;            // 1 / sum(weight): a cell's share of the box's emission is weight * w_inv
 };
 hipError_t launch_feed_sums(const PackBox *pb_dev, int n_boxes, int max_blk, const double *wgt,
                             double *partials, hipStream_t s);
 hipError_t launch_feed_reduce(int n_boxes, int max_blk, const PackBox *pb_dev, const double *partials,
                               double *sums, hipStream_t s);
+// The surrogate's regression data per cell: y = ln M_c and the cell's share
+// of its box's emission (both 0 where M_c = 0).
+hipError_t launch_targets(const PackBox *pb_dev, const FeedBox *fb_dev, int n_boxes, int max_blk,
+                          const double *wgt, const unsigned long long *A, float *y, float *w, hipStream_t s);
 hipError_t launch_feed(const PackBox *pb_dev, const FeedBox *fb_dev, int n_boxes, int max_blk,
                        const double *wgt, const unsigned long long *A, double *ndot,
                        float *mix, hipStream_t s);
@@ -363,6 +368,8 @@ hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, f
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
                                float *partial, int max_blocks, float *grad, hipStream_t s);
 hipError_t launch_mlp_normalise(float *grad, hipStream_t s);
+hipError_t launch_mlp_correction(const float *y, const uint8_t *outside, const float *fallback, uint64_t n,
+                                 float *M, hipStream_t s);
 hipError_t launch_mlp_adam(float *params, float *m, float *v, float *grad, const MlpAdam &a, hipStream_t s);
 
 }  // namespace mclya

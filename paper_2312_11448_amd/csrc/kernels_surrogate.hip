@@ -606,6 +606,19 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ P, fl
     P[j] -= a.lr * mhat / (sqrtf(vhat) + a.eps);
 }
 
+// The correction with the Monte Carlo as fallback: a cell flagged outside the
+// training envelope takes the Monte Carlo's M, every other exp(y).
+__global__ __launch_bounds__(256) void mlp_correction_kernel(const float *__restrict__ y,
+                                                             const uint8_t *__restrict__ outside,
+                                                             const float *__restrict__ fallback, uint64_t n,
+                                                             float *__restrict__ M)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const bool mc = fallback && outside && outside[i];
+    M[i] = mc ? fallback[i] : expf(y[i]);
+}
+
 __global__ __launch_bounds__(256) void mlp_normalise_kernel(float *__restrict__ grad)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
@@ -649,6 +662,14 @@ hipError_t launch_mlp_gradient(const float *params, const float *X, const float 
                        dim3(256), 0, s, partial, blocks, tmp);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)((kMlpParams + 2 + 255) / 256)), dim3(256), 0, s, tmp,
                        groups, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_correction(const float *y, const uint8_t *outside, const float *fallback, uint64_t n,
+                                 float *M, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_correction_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, outside,
+                       fallback, n, M);
     return hipGetLastError();
 }
 

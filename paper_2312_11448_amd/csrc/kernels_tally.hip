@@ -154,6 +154,35 @@ __global__ __launch_bounds__(B) void feed_kernel(const PackBox *__restrict__ pbs
     }
 }
 
+// The surrogate's regression data: the log of the mixing correction the
+// feed forms (M_c = A_c / A_c^fm) and the weight of the cell in the loss, its
+// share of the box's emission S_c / sum(S) (the cells that feed recombination
+// most count most). A cell with M_c = 0 (nothing absorbed there) has no
+// logarithm and gets weight 0.
+__global__ __launch_bounds__(B) void targets_kernel(const PackBox *__restrict__ pbs,
+                                                    const FeedBox *__restrict__ fbs,
+                                                    const double *__restrict__ wgt,
+                                                    const unsigned long long *__restrict__ A,
+                                                    float *__restrict__ y, float *__restrict__ w)
+{
+    const int b = blockIdx.y;
+    const PackBox pb = pbs[b];
+    if ((int)blockIdx.x >= pb.nblk) return;
+    const uint32_t i = blockIdx.x * B + threadIdx.x;
+    if (i >= pb.ncells) return;
+    const FeedBox fb = fbs[b];
+    const size_t g = (size_t)pb.cell_off + i;
+    const double od = (double)pb.od[i];
+    const double xe = (double)(pb.xe ? pb.xe[i] : pb.xe_uniform);
+    const double n1s = fb.n_h * (1.0 - xe) * od;
+    const double a = (double)A[g] + fb.wing_n1s * n1s;
+    const double fm = fb.fm_norm * n1s;
+    const double m = fm > 0.0 ? a / fm : 0.0;
+    const bool ok = m > 0.0;
+    y[g] = ok ? (float)log(m) : 0.0f;
+    w[g] = ok ? (float)(wgt[g] * fb.w_inv) : 0.0f;
+}
+
 inline dim3 grid2(int max_blk, int n_boxes) { return dim3((unsigned)max_blk, (unsigned)n_boxes, 1); }
 
 }  // namespace
@@ -182,6 +211,13 @@ hipError_t launch_feed_reduce(int n_boxes, int max_blk, const PackBox *pb_dev, c
 {
     hipLaunchKernelGGL(reduce4_kernel, dim3((unsigned)n_boxes), dim3(B), 0, s, pb_dev, partials, sums,
                        max_blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(const PackBox *pb_dev, const FeedBox *fb_dev, int n_boxes, int max_blk,
+                          const double *wgt, const unsigned long long *A, float *y, float *w, hipStream_t s)
+{
+    hipLaunchKernelGGL(targets_kernel, grid2(max_blk, n_boxes), dim3(B), 0, s, pb_dev, fb_dev, wgt, A, y, w);
     return hipGetLastError();
 }
 

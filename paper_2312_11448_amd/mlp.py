@@ -35,6 +35,23 @@ class Mlp:
             out.append(c)
         return out[0] if len(out) == 1 else tuple(out)
 
+    def correction(self, features, fallback=None):
+        """The mixing correction M per cell, with the Monte Carlo's M
+        (`fallback`, float32 [n]) taken where the features leave the training
+        envelope. Returns (M, y, outside flags, number outside)."""
+        f = features.contiguous()
+        n = f.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=self.device)
+        m = torch.empty_like(y)
+        flags = torch.empty(n, dtype=torch.uint8, device=self.device)
+        fb = None
+        if fallback is not None:
+            fallback = fallback.contiguous()
+            assert fallback.dtype == torch.float32 and fallback.shape[0] == n
+            fb = fallback.data_ptr()
+        c = A.mc_lya_mlp_correction(self.h, f.data_ptr(), n, fb, y.data_ptr(), m.data_ptr(), flags.data_ptr(), True)
+        return m, y, flags, c
+
     def gradient(self, features, targets, weights):
         """(gradient [4801] as a list, loss) of the weighted MSE."""
         return A.mc_lya_mlp_gradient(self.h, features.contiguous().data_ptr(), targets.contiguous().data_ptr(),

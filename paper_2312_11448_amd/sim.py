@@ -69,13 +69,19 @@ class Simulation:
     emission (default: the specs' packet counts summed) and, with
     ``evolve=True``, the buffers of the recombination history."""
 
-    def __init__(self, specs, device="cuda", stream=None, max_packets=None, evolve=False):
+    def __init__(self, specs, device="cuda", stream=None, max_packets=None, evolve=False, batch_packets=0):
         if not isinstance(specs, (list, tuple)):
             specs = [specs]
         self.specs = list(specs)
         self.device = torch.device(device)
         self._keep = []
-        descs = [desc_from_spec(s, self._keep, self.device) for s in self.specs]
+        self._fields = []        # per box: its device field tensors (overdensity, flow, x_e, source: those given)
+        descs = []
+        for s in self.specs:
+            keep = []
+            descs.append(desc_from_spec(s, keep, self.device))
+            self._fields.append(keep)
+            self._keep.extend(keep)
         self._descs = descs
         self.ncells = [s.ncells for s in self.specs]
         self.total_cells = int(sum(self.ncells))
@@ -84,12 +90,35 @@ class Simulation:
         if max_packets is None:
             max_packets = max(1, sum(int(s.n_packets) for s in self.specs))
         self.max_packets = int(max_packets)
-        self.ctx = A.mc_lya_init(descs, self.stream, max_packets=self.max_packets, evolve=evolve)
+        self.ctx = A.mc_lya_init(descs, self.stream, max_packets=self.max_packets, evolve=evolve,
+                                 batch_packets=batch_packets)
         self.n_packets = [0] * len(self.specs)
 
     # -- C calls --------------------------------------------------------------
     def refresh(self):
         A.mc_lya_refresh(self.ctx)
+
+    def load_fields(self, specs):
+        """New field contents for every box (the same shapes and the same
+        fields given as at init; the boxes' physics stay those of init), copied
+        into the context's device arrays, then mc_lya_refresh. The packet
+        seeds and counts become those of `specs`."""
+        specs = list(specs) if isinstance(specs, (list, tuple)) else [specs]
+        if len(specs) != len(self.specs):
+            raise ValueError("load_fields needs one spec per box")
+        for b, s in enumerate(specs):
+            new = [a for a in (s.overdensity, s.velocity, s.x_e, s.source) if a is not None]
+            if len(new) != len(self._fields[b]):
+                raise ValueError("load_fields: box %d gives other fields than at init" % b)
+            for t, a in zip(self._fields[b], new):
+                src = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+                if tuple(src.shape) != tuple(t.shape):
+                    raise ValueError("load_fields: box %d field shape %s, expected %s" % (b, tuple(src.shape),
+                                                                                       tuple(t.shape)))
+                t.copy_(src.to(dtype=t.dtype))
+        torch.cuda.synchronize(self.device)
+        self.specs = specs
+        self.refresh()
 
     def emit(self, seeds=None, n_packets=None):
         seeds = [s.seed for s in self.specs] if seeds is None else list(seeds)
@@ -123,6 +152,14 @@ class Simulation:
         out = torch.empty((self.total_cells, A.MC_LYA_MLP_FEATURES), dtype=torch.float32, device=self.device)
         A.mc_lya_features(self.ctx, out.data_ptr())
         return out
+
+    def targets(self):
+        """The surrogate's regression data from the last transport: ln M_c and
+        each cell's share of its box's emission (float32 tensors [cells])."""
+        y = torch.empty(self.total_cells, dtype=torch.float32, device=self.device)
+        w = torch.empty_like(y)
+        A.mc_lya_surrogate_targets(self.ctx, y.data_ptr(), w.data_ptr())
+        return y, w
 
     def trace(self, first, count):
         buf = torch.empty(int(count) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=self.device)

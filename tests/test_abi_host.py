@@ -41,7 +41,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(M.mc_lya_scatter_opts) == 40
     assert C.sizeof(M.mc_lya_feed_stats) == 56
     assert C.sizeof(M.mc_lya_tune_result) == 88
-    assert C.sizeof(M.mc_lya_limits) == 16
+    assert C.sizeof(M.mc_lya_limits) == 24
     # 4 int32, 11 doubles, w0, 3 pointers, float + int32, 1 pointer
     assert C.sizeof(M.mc_lya_box_desc) == 16 + 88 + 8 + 24 + 8 + 8
 
@@ -79,7 +79,8 @@ def test_init_rejects_bad_descriptors_before_any_device_call(bad, msg):
 
 @pytest.mark.parametrize("limits,msg", [(dict(max_packets=0), "max_packets"),
                                         (dict(max_packets=1 << 40), "max_packets"),
-                                        (dict(max_packets=10, evolve=2), "evolve")])
+                                        (dict(max_packets=10, evolve=2), "evolve"),
+                                        (dict(max_packets=10, reserved=1), "reserved")])
 def test_init_rejects_bad_limits_before_any_device_call(limits, msg):
     M = _lib()
     L = M.load()

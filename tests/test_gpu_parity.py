@@ -155,6 +155,22 @@ def test_launch_configuration_and_ranges_bitwise():
     assert np.array_equal(again["A"], base["A"])
 
 
+def test_tiled_batches_give_the_same_integers():
+    """A context that reserves hand-over state for fewer packets than an
+    emission (mc_lya_limits.batch_packets) walks it in batches: the same
+    integers as one batch."""
+    spec = W.make_box("c2", n=32, n_packets=200_000)
+    tiled = {M.MC_LYA_OPT_TILE_SHARE: ALL_TILED}
+    base = gpu_run(spec, options=tiled)
+    with M.Simulation(spec, batch_packets=47_000) as sim:
+        sim.set_option(M.MC_LYA_OPT_TILE_SHARE, ALL_TILED)
+        sim.emit()
+        sim.transport()
+        t = sim.tally()
+    assert np.array_equal(t["absorbed"].cpu().numpy(), base["A"])
+    assert t["stats"][0].escaped == base["escaped"] and t["stats"][0].crossings == base["crossings"]
+
+
 def test_batch_equals_boxes_alone():
     boxes = [W.make_box("c2", n=n, n_packets=p, field_seed=fs, seed=s)
              for n, p, fs, s in ((12, 20000, 5, 1), (20, 50000, 6, 2), (9, 7000, 7, 3))]
@@ -495,3 +511,21 @@ def test_largest_batch_of_boxes():
             alone = gpu_run(boxes[b])
             lo, hi = sim.cell_off[b], sim.cell_off[b + 1]
             assert np.array_equal(A[lo:hi], alone["A"]) and t["stats"][b].escaped == alone["escaped"]
+
+
+def test_loaded_fields_give_a_fresh_contexts_integers():
+    """Fields loaded into an open context (mc_lya_refresh over the same device
+    arrays) walk to the same integers as a context made for them."""
+    a = W.make_box("c2", n=24, n_packets=40_000, field_seed=11, seed=5)
+    b = W.make_box("c2", n=24, n_packets=40_000, field_seed=12, seed=6)
+    fresh = gpu_run(b)
+    with M.Simulation(a) as sim:
+        sim.emit()
+        sim.transport()
+        sim.tally()
+        sim.load_fields(b)
+        sim.emit()
+        sim.transport()
+        t = sim.tally()
+    assert np.array_equal(t["absorbed"].cpu().numpy(), fresh["A"])
+    assert t["stats"][0].escaped == fresh["escaped"]

@@ -264,3 +264,28 @@ def test_mlp_errors():
         with pytest.raises(M.MCLyaError):
             mlp.train_step(X, torch.zeros(4, device="cuda"), torch.ones(4, device="cuda"), lr=-1.0)
         assert mlp.forward(X[:0]).numel() == 0
+
+
+def test_targets_match_oracle():
+    """ln M_c and the emission-share weights from the library's tallies
+    against the oracle's targets from the oracle's own walk of the same box.
+    y differs by the tallies' difference (per cell within 1e-3 of A_c plus
+    1e-6 of the mean, so |dy| <= ~1e-3 where A_c is not tiny); the weights
+    depend only on the fields (FP32 products against FP64: 1e-6)."""
+    from oracle import walker
+    spec = W.make_box("c2", n=24, n_packets=60_000)
+    with M.Simulation(spec) as sim:
+        sim.emit()
+        sim.transport()
+        sim.tally()
+        y, w = sim.targets()
+    y, w = y.cpu().numpy().astype(np.float64), w.cpu().numpy().astype(np.float64)
+    ref = walker.run_box(spec)
+    y_o, w_o = S.targets(spec, ref["A"], ref["escaped"], spec.n_packets)
+    assert np.array_equal(w > 0, w_o > 0)
+    assert np.allclose(w, w_o, rtol=1e-6, atol=0.0)
+    A_o = ref["A"].astype(np.float64)
+    big = A_o > 1e-2 * A_o.mean()
+    _say(f"  worst |dy| where A_c > 1% of the mean: {np.abs(y - y_o)[big].max():.2e}")
+    assert np.abs(y - y_o)[big].max() <= 2e-3
+    assert np.sum(w_o) <= 1.0 + 1e-12

@@ -265,3 +265,31 @@ def test_bf16_network_rounds_where_stated():
     pr = S.pack(W1r, np.float32(b1), W2r, np.float32(b2), np.float32(w3), np.float32(b3))
     yr, cr = S.forward_bf16(pr, S.bf16(X))
     assert np.array_equal(yr, yb)
+
+
+def test_targets_reduce_to_definitions():
+    """ln M and the emission-share weights (Sec. IV.B, Eq. (dotne-mix)):
+    tallies spread exactly like n_1s give M = 1 (y = 0) in every cell; one
+    cell holding twice its full-mixing share (the others scaled to keep the
+    total) gives y = ln 2 there; a cell that absorbed nothing gets weight 0;
+    the weights are S_c / sum(S)."""
+    import workloads as W
+    from oracle import physics as P
+    spec = W.make_box("c2", n=6, n_packets=1000)
+    n1s = P.n1s_field(spec)
+    S_w = P.emission_weights(spec)
+    A_fm = n1s / n1s.sum() * 1e12
+    y, w = S.targets(spec, A_fm, 0, spec.n_packets)
+    assert np.abs(y).max() < 1e-12
+    assert np.allclose(w, S_w / S_w.sum(), rtol=1e-14)
+    A2 = A_fm.copy()
+    A2[5] *= 2.0
+    y2, _ = S.targets(spec, A2, 0, spec.n_packets)
+    tot = A2.sum()
+    expect5 = np.log(A2[5] / (tot * n1s[5] / n1s.sum()))
+    assert y2[5] == pytest.approx(expect5, rel=1e-12)
+    assert y2[5] == pytest.approx(np.log(2.0) + np.log(A_fm.sum() / tot), rel=1e-12)
+    A3 = A_fm.copy()
+    A3[7] = 0.0
+    y3, w3 = S.targets(spec, A3, 0, spec.n_packets)
+    assert y3[7] == 0.0 and w3[7] == 0.0 and (w3[np.arange(w3.size) != 7] > 0).all()

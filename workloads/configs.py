@@ -68,8 +68,9 @@ CONFIGS = {
 }
 
 
-def make_box(key, n=None, n_packets=None, field_seed=None, seed=None, **overrides):
-    """Build the BoxSpec for preset ``key`` ("c1", "c2", "c3"), optionally resized."""
+def make_box(key, n=None, n_packets=None, field_seed=None, seed=None, device=None, **overrides):
+    """Build the BoxSpec for preset ``key`` ("c1", "c2", "c3"), optionally resized
+    (device: a torch GPU device for the k^2 field's FFTs)."""
     cfg = dict(CONFIGS[key])
     n = int(n or cfg["n"])
     fs = cfg["field_seed"] if field_seed is None else field_seed
@@ -78,7 +79,7 @@ def make_box(key, n=None, n_packets=None, field_seed=None, seed=None, **override
         vel = None
     else:
         kmax = max(1, int(round(cfg["kmax"] * n / cfg["n"])))
-        od, vel = F.grf_k2(n, cfg["rms"], kmax, fs, vel_rms=cfg["vel_rms"])
+        od, vel = F.grf_k2(n, cfg["rms"], kmax, fs, vel_rms=cfg["vel_rms"], device=device)
     box = BoxSpec(n=(n, n, n), overdensity=od, velocity=vel,
                   n_packets=int(n_packets if n_packets is not None else cfg["n_packets"]),
                   seed=int(cfg["seed"] if seed is None else seed), name=cfg["name"])

@@ -32,7 +32,7 @@ def _kgrid(n):
     return kx, ky, kz
 
 
-def grf_k2(n, rms, kmax, seed, clip=(1e-2, 1e2), vel_rms=0.1):
+def grf_k2(n, rms, kmax, seed, clip=(1e-2, 1e2), vel_rms=0.1, device=None):
     """Gaussian random field with a k^2 power spectrum and a matching flow.
 
     The spectrum P(k) ~ k^2 on integer wavenumbers 1 <= |k| <= kmax mirrors the
@@ -41,9 +41,14 @@ def grf_k2(n, rms, kmax, seed, clip=(1e-2, 1e2), vel_rms=0.1):
     The velocity is the curl-free flow v_k = i k delta_k / k^2 (infall into
     overdensities, div v = -delta), scaled to a 3-D rms of ``vel_rms``.
     Returns (overdensity float32 [n,n,n], velocity float32 [3,n,n,n]).
+    device: a torch GPU device to take the same steps in float64 on it (the
+    same seeded white noise; only the FFTs' rounding differs, far below the
+    float32 result's).
     """
     rng = _rng(seed)
     white = rng.standard_normal((n, n, n))
+    if device is not None:
+        return _grf_k2_torch(white, n, rms, kmax, clip, vel_rms, device)
     wk = np.fft.rfftn(white)
     kx, ky, kz = _kgrid(n)
     k2 = kx * kx + ky * ky + kz * kz
@@ -67,6 +72,31 @@ def grf_k2(n, rms, kmax, seed, clip=(1e-2, 1e2), vel_rms=0.1):
         v *= vel_rms / np.sqrt(np.mean(np.sum(v * v, axis=0)))
         vel = v.astype(np.float32)
     return od.astype(np.float32), vel
+
+
+def _grf_k2_torch(white, n, rms, kmax, clip, vel_rms, device):
+    import torch
+    w = torch.from_numpy(white).to(device)
+    wk = torch.fft.rfftn(w)
+    kx, ky, kz = (torch.from_numpy(np.ascontiguousarray(k)).to(device) for k in _kgrid(n))
+    k2 = kx * kx + ky * ky + kz * kz
+    kmag = torch.sqrt(k2)
+    amp = torch.where((kmag >= 1.0) & (kmag <= kmax), kmag, torch.zeros_like(kmag))
+    dk = wk * amp
+    delta = torch.fft.irfftn(dk, s=(n, n, n), dim=(0, 1, 2))
+    scale = rms / torch.sqrt(torch.mean(delta * delta))
+    delta = delta * scale
+    dk = dk * scale
+    od = torch.clamp(1.0 + delta, clip[0], clip[1])
+    od = od / od.mean()
+    vel = None
+    if vel_rms is not None and vel_rms > 0:
+        safe = torch.where(k2 > 0, k2, torch.ones_like(k2))
+        comps = [torch.fft.irfftn(1j * kc * dk / safe, s=(n, n, n), dim=(0, 1, 2)) for kc in (kx, ky, kz)]
+        v = torch.stack(comps)
+        v = v * (vel_rms / torch.sqrt(torch.mean(torch.sum(v * v, dim=0))))
+        vel = v.to(torch.float32).cpu().numpy()
+    return od.to(torch.float32).cpu().numpy(), vel
 
 
 def uniform_box(n, value=1.0):
