@@ -120,9 +120,22 @@ def _counter_rows(path, counter):
         return [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
 
 
+def _first_generation(name):
+    """True for a dispatch of the first tile generation, tile_walk_kernel<VEL,
+    GEN0 = true, VOIGT>."""
+    if WALK_KERNEL + "<" not in name:
+        return False
+    args = name.split(WALK_KERNEL + "<", 1)[1].split(">", 1)[0].split(",")
+    return len(args) == 3 and args[1].strip() == "true"
+
+
 def summarize_counters(a):
-    """HBM bytes per walk launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
-    each scaled by what the same counter reads for a copy of known size."""
+    """HBM bytes per walk (one transport) from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for a copy of known
+    size. Transports are counted by their first tile generation (one per
+    single-batch transport); the benchmark divides by its own launch count,
+    since the number of (empty) generation launches after the tail walk
+    varies from run to run."""
     f_csv, w_csv, cf_csv, cw_csv = a.summarize_counters
     known = a.calibration_mib * (1 << 20)
     scale = {}
@@ -139,14 +152,15 @@ def summarize_counters(a):
         vals = [float(r["Counter_Value"]) * 1024.0 for r in rows
                 if any(k in r["Kernel_Name"] for k in WALK_BYTE_KERNELS)]
         n = sum(1 for r in rows if any(k in r["Kernel_Name"] for k in WALK_LAUNCH_KERNELS))
-        if not vals or not n:
+        walks = sum(1 for r in rows if _first_generation(r["Kernel_Name"]))
+        if not vals or not n or not walks:
             raise SystemExit(f"no walk rows in {path}")
-        per[name] = scale[name] * sum(vals) / n
-        launches[name] = n
-    out = {"config": a.config, "profile": a.profile, "kernel": " + ".join(WALK_LAUNCH_KERNELS), "launches": launches,
+        per[name] = scale[name] * sum(vals) / walks
+        launches[name] = {"launches": n, "walks": walks}
+    out = {"config": a.config, "profile": a.profile, "kernel": " + ".join(WALK_BYTE_KERNELS), "counted": launches,
            "fetch_scale": scale["fetch"], "write_scale": scale["write"],
-           "fetch_bytes_per_launch": per["fetch"], "write_bytes_per_launch": per["write"],
-           "bytes_per_launch": per["fetch"] + per["write"], "source_sha256": walk_source_hash()}
+           "fetch_bytes_per_walk": per["fetch"], "write_bytes_per_walk": per["write"],
+           "bytes_per_walk": per["fetch"] + per["write"], "source_sha256": walk_source_hash()}
     with open(a.traffic, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
@@ -529,7 +543,7 @@ def main():
             tr = json.load(fh)
         if (tr.get("config") == a.config and tr.get("profile", "doppler") == a.profile
                 and tr.get("source_sha256") == walk_source_hash()):
-            traffic = tr.get("bytes_per_launch")
+            traffic = tr.get("bytes_per_walk")     # per launch below, with this run's launch count
     # the walk's issue rate: measured VALU instructions per crossing (rocprofv3
     # SQ_INSTS_VALU over the same workload and sources) times this run's rate
     valu = None
@@ -563,7 +577,8 @@ def main():
                    "walk_crossings_per_s": cross_per_step / walk_s,
                    "f_absorbed": f["stats"][0].f_absorbed, "c_mc": f["stats"][0].c_mc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic * a.steps / max(1, launches)},
         "roofline_valu": {"bound": "alu", "achieved": valu, "peak": VALU_PEAK_GINSTR,
                           "unit": "G wave-instr/s (VALU issue)",
                           "frac": None if valu is None else valu / VALU_PEAK_GINSTR},

@@ -1,5 +1,5 @@
 """Host logic of the benchmark's counter summaries (CPU only): the HBM bytes
-per walk launch from FETCH_SIZE / WRITE_SIZE scaled by a copy's calibration,
+per walk from FETCH_SIZE / WRITE_SIZE scaled by a copy's calibration,
 and the wave instructions per unit of work from SQ_INSTS_VALU / SQ_INSTS_SALU,
 on small hand-made counter files."""
 import csv
@@ -30,19 +30,24 @@ def _bench(*args):
 
 def test_summarize_counters_scales_by_the_copy(tmp_path):
     f, w, cf, cw = (str(tmp_path / n) for n in ("f.csv", "w.csv", "cf.csv", "cw.csv"))
-    # two walk launches (and a prefix kernel counted in the bytes only), 1000 and 3000 KiB fetched
-    _csv(f, [("tile_walk_kernel<true>", "FETCH_SIZE", 1000), ("tail_prefix_kernel", "FETCH_SIZE", 500),
-             ("tail_walk_kernel<true>", "FETCH_SIZE", 2500), ("pack_kernel", "FETCH_SIZE", 99999)])
-    _csv(w, [("tile_walk_kernel<true>", "WRITE_SIZE", 10), ("tail_walk_kernel<true>", "WRITE_SIZE", 30)])
+    # two walks (each opened by a first tile generation), a later generation,
+    # a tail walk and its prefix kernel: 1000 + 250 + 500 + 2500 + 750 KiB fetched
+    gen0, gen = "tile_walk_kernel<true, true, false>(P)", "tile_walk_kernel<true, false, false>(P)"
+    _csv(f, [(gen0, "FETCH_SIZE", 1000), (gen, "FETCH_SIZE", 250), ("tail_prefix_kernel", "FETCH_SIZE", 500),
+             ("tail_walk_kernel<true, false>", "FETCH_SIZE", 2500), (gen0, "FETCH_SIZE", 750),
+             ("pack_kernel", "FETCH_SIZE", 99999)])
+    _csv(w, [(gen0, "WRITE_SIZE", 10), ("tail_walk_kernel<true, false>", "WRITE_SIZE", 30),
+             (gen0, "WRITE_SIZE", 0)])
     # a 1 MiB copy whose fetch counter reads half of what it moves
     _csv(cf, [("neg_kernel", "FETCH_SIZE", 512)])
     _csv(cw, [("neg_kernel", "WRITE_SIZE", 1024)])
     out = str(tmp_path / "traffic.json")
     r = _bench("--summarize-counters", f, w, cf, cw, "--calibration-mib", "1", "--traffic", out)
     assert r["fetch_scale"] == pytest.approx(2.0) and r["write_scale"] == pytest.approx(1.0)
-    assert r["fetch_bytes_per_launch"] == pytest.approx(2.0 * 4000 * 1024 / 2)
-    assert r["write_bytes_per_launch"] == pytest.approx(40 * 1024 / 2)
-    assert json.load(open(out))["bytes_per_launch"] == pytest.approx(r["bytes_per_launch"])
+    assert r["counted"]["fetch"] == {"launches": 4, "walks": 2}
+    assert r["fetch_bytes_per_walk"] == pytest.approx(2.0 * 5000 * 1024 / 2)
+    assert r["write_bytes_per_walk"] == pytest.approx(40 * 1024 / 2)
+    assert json.load(open(out))["bytes_per_walk"] == pytest.approx(r["bytes_per_walk"])
 
 
 def test_summarize_valu_divides_by_the_profiled_work(tmp_path):
