@@ -93,7 +93,8 @@ def parse():
                     help="only run a plain elementwise copy of MIB MiB (float32 negation, "
                          "reads and writes MIB MiB) five times, to scale byte counters")
     ap.add_argument("--probe-bandwidth", action="store_true",
-                    help="only measure the achievable streaming HBM bandwidth (a copy far larger than the caches)")
+                    help="only measure the achievable read bandwidth by working-set size (L2, MALL, HBM) and "
+                         "the streaming copy's")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
                     help="only turn four rocprofv3 counter_collection.csv files (FETCH_SIZE and WRITE_SIZE "
                          "of the benchmark, then of --calibrate-copy) into the walk's HBM bytes per launch, "
@@ -213,13 +214,32 @@ def calibrate_copy(mib):
 
 
 def probe_bandwidth():
-    """Achievable streaming HBM bandwidth: a float32 negation (one read, one
-    write per element) repeated over working sets well beyond the 256 MB
-    last-level cache, timed with events on the current stream. Prints one JSON
-    line per size (read + written bytes per second). (Cache-resident sizes
-    cannot be measured this way: one launch per pass, and a launch's few
-    microseconds of overhead exceed a cache-sized pass.)"""
+    """Achievable read bandwidth by working-set size: the library's read probe
+    (mc_lya_probe_read: one launch reads the buffer many times over, each
+    thread the same positions every pass) from a few MiB (served by the
+    XCDs' L2 caches) through the 256 MB last-level cache (MALL) to GiB sizes
+    (HBM), timed with events on the current stream, plus the streaming copy
+    (torch's negation: one read and one write per element) at HBM sizes.
+    Prints one JSON line per measurement."""
     import torch
+    import paper_2312_11448_amd as M
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    for mib in (4, 16, 32, 64, 128, 192, 256, 512, 1024, 4096):
+        nbytes = mib << 20
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        passes = max(2, min(4096, (16 << 30) // nbytes))
+        grid = cus * 8
+        M.mc_lya_probe_read(buf.data_ptr(), nbytes, 1, grid, sink.data_ptr())
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        M.mc_lya_probe_read(buf.data_ptr(), nbytes, passes, grid, sink.data_ptr())
+        t1.record()
+        t1.synchronize()
+        s = t0.elapsed_time(t1) / 1e3
+        print(json.dumps({"probe": "read", "working_set_mib": mib, "passes": passes,
+                          "GB_per_s": nbytes * passes / s / 1e9}), flush=True)
+        del buf
     for mib in (1024, 4096):
         n = mib * (1 << 20) // 8           # two buffers of mib / 2 MiB each
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")

@@ -436,6 +436,18 @@ mc_lya_status mc_lya_kernel_time(mc_lya_ctx *ctx, double *ms, int64_t *launches)
 mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                                    uint64_t n, void *stream);
 
+/* Measurement utility (not part of the transport): reads `bytes` of device
+ * memory at `buf` `passes` times over in one launch of `grid` workgroups of
+ * 256 threads, each thread the same 16-byte positions in every pass, so a
+ * buffer that fits a cache level is served from it after the first pass.
+ * Timing is the caller's (events on `stream`); read bandwidth = bytes *
+ * passes / time. The data must be finite floats; `sink` (dev, 1 float) is
+ * never written for such data.
+ *   bytes  a multiple of 16, >= 16;  passes, grid >= 1
+ * Asynchronous. Errors: EINVAL, EDEVICE. */
+mc_lya_status mc_lya_probe_read(const void *buf, uint64_t bytes, int32_t passes, int32_t grid, float *sink,
+                                void *stream);
+
 /* ---- mixing-correction surrogate ------------------------------------------
  * A per-cell regression of y = ln M_c, the log of the mixing correction that
  * mc_lya_feed returns (M_c = A_c / A_c^fm, Sec. IV.B, Eq. (dotne-mix); M = 1

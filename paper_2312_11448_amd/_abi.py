@@ -89,6 +89,7 @@ EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_transport_range", "mc_lya_tally", "mc_lya_feed", "mc_lya_trace", "mc_lya_scatter",
            "mc_lya_evolve",
            "mc_lya_set_option", "mc_lya_autotune", "mc_lya_kernel_time", "mc_lya_philox4x32_10",
+           "mc_lya_probe_read",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
            "mc_lya_features", "mc_lya_surrogate_targets", "mc_lya_mlp_create", "mc_lya_mlp_get_params",
            "mc_lya_mlp_set_envelope", "mc_lya_mlp_forward", "mc_lya_mlp_correction", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_destroy",
@@ -151,6 +152,7 @@ def load():
     L.mc_lya_last_error.restype = C.c_char_p
     fp = P(C.c_float)
     L.mc_lya_features.argtypes = [vp, vp]
+    L.mc_lya_probe_read.argtypes = [vp, u64, i32, i32, vp, vp]
     L.mc_lya_surrogate_targets.argtypes = [vp, vp, vp]
     L.mc_lya_mlp_correction.argtypes = [vp, vp, u64, vp, vp, vp, vp, P(u64)]
     L.mc_lya_mlp_create.argtypes = [P(vp), fp, vp]
@@ -290,6 +292,14 @@ def mc_lya_last_error(ctx=None):
 # ---- mixing-correction surrogate --------------------------------------------
 def mc_lya_features(ctx, out_ptr):
     return _check(load().mc_lya_features(ctx, out_ptr), ctx)
+
+
+def mc_lya_probe_read(buf_ptr, nbytes, passes, grid, sink_ptr, stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = load().mc_lya_probe_read(buf_ptr, int(nbytes), int(passes), int(grid), sink_ptr, C.c_void_p(stream))
+    if st != MC_LYA_OK:
+        raise MCLyaError(st, load().mc_lya_strerror(st).decode())
 
 
 def mc_lya_surrogate_targets(ctx, y_ptr, w_ptr):

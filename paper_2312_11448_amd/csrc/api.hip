@@ -1666,6 +1666,24 @@ mc_lya_status mc_lya_kernel_time(mc_lya_ctx *c, double *ms, int64_t *launches)
     return MC_LYA_OK;
 }
 
+}  // extern "C"
+
+namespace mclya {
+// the read probe (kernels_probe.hip), a measurement utility
+hipError_t launch_probe_read(const void *buf, uint64_t bytes, int passes, int grid, float *sink, hipStream_t s);
+}  // namespace mclya
+
+extern "C" {
+
+mc_lya_status mc_lya_probe_read(const void *buf, uint64_t bytes, int32_t passes, int32_t grid, float *sink,
+                                void *stream)
+{
+    if (!buf || !sink || bytes < 16 || bytes % 16 != 0 || passes < 1 || grid < 1) return MC_LYA_EINVAL;
+    if (launch_probe_read(buf, bytes, passes, grid, sink, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return MC_LYA_EDEVICE;
+    return MC_LYA_OK;
+}
+
 mc_lya_status mc_lya_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, uint64_t n,
                                    void *stream)
 {

@@ -81,3 +81,16 @@ def test_no_device_allocation_after_init():
 
         _every_call(sim, bufs, check)
     print(f"  device memory taken after init: {seen}", flush=True)
+
+
+def test_read_probe_checks_its_arguments_and_runs():
+    """The read-bandwidth probe (a measurement utility): bad sizes are
+    rejected; a valid call reads and leaves the sink alone (finite data)."""
+    buf = torch.ones(1 << 20, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    M.mc_lya_probe_read(buf.data_ptr(), buf.numel() * 4, 3, 64, sink.data_ptr())
+    torch.cuda.synchronize()
+    assert sink.item() == 0.0
+    for nbytes, passes, grid in ((12, 1, 1), (buf.numel() * 4, 0, 1), (buf.numel() * 4, 1, 0)):
+        with pytest.raises(M.MCLyaError):
+            M.mc_lya_probe_read(buf.data_ptr(), nbytes, passes, grid, sink.data_ptr())

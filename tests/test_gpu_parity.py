@@ -204,25 +204,36 @@ def test_uniform_flow_changes_nothing():
 
 
 def test_feed_matches_oracle_feed():
+    """The feed (ndot_e, M_c, C_MC, C^mix, x_e) from the library's own
+    transport against the oracle's feed from the oracle's own walk of the same
+    box (no input of the oracle comes from the GPU). The tallies agree per cell
+    within 1e-3 A_c + 1e-6 mean(A) and globally within 1e-5, so: M_c within
+    2e-3 relative where A_c is not tiny, ndot_e per cell within 2e-3 of its
+    absorbed term plus 2e-3 of the thermal term, C_MC within 1e-3 relative;
+    C^mix and x_e depend on the fields only (1e-9)."""
     from oracle import physics as P
     spec = W.make_box("c2", n=24, n_packets=50000)
     with M.Simulation(spec) as sim:
         sim.emit()
         sim.transport()
-        t = sim.tally()
+        sim.tally()
         f = sim.feed()
-    A = t["absorbed"].cpu().numpy()
-    E = t["stats"][0].escaped
-    ref = P.feed(spec, A, E, spec.n_packets)
+    orc = walker.run_box(spec)
+    ref = P.feed(spec, orc["A"], orc["escaped"], spec.n_packets)
     nd = f["ndot_e"].cpu().numpy()
-    assert np.allclose(nd, ref["ndot_e"], rtol=1e-9, atol=1e-12 * np.abs(ref["ndot_e"]).max())
-    mix = f["mix_corr"].cpu().numpy()
-    assert np.allclose(mix, ref["mix_corr"], rtol=2e-7)
+    sc = P.box_scalars(spec)
+    reion = sc["beta"] / (sc["beta"] + P.LAMBDA_2G)
+    a = np.abs(ref["absorbed_rate"])
+    thermal = np.abs(ref["c_mc"] * sc["beta"] * P.n1s_field(spec) * ref["boltzmann"])
+    tol = reion * (2e-3 * a + 2e-6 * a.mean()) + 2e-3 * thermal + 1e-12 * np.abs(ref["ndot_e"]).max()
+    assert (np.abs(nd - ref["ndot_e"]) <= tol).all()
+    mix = f["mix_corr"].cpu().numpy().astype(np.float64)
+    big = orc["A"] > 1e-2 * orc["A"].mean()
+    assert np.allclose(mix[big], ref["mix_corr"][big], rtol=2e-3, atol=0.0)
     st = f["stats"][0]
-    assert st.c_mc == pytest.approx(ref["c_mc"], rel=1e-12)
+    assert st.c_mc == pytest.approx(ref["c_mc"], rel=1e-3)
     assert st.c_mix == pytest.approx(ref["c_mix"], rel=1e-9)
     assert st.x_e_global == pytest.approx(ref["x_e_global"], rel=1e-9)
-    assert st.ndot_e_mean == pytest.approx(ref["ndot_e"].mean(), rel=1e-6)
 
 
 def test_sampled_packets_at_full_256_size():

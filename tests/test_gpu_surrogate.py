@@ -150,8 +150,10 @@ def test_forward_sampled_at_256cube_size():
         mlp.set_envelope(lo, hi)
         y, flags, count = mlp.forward(feats, outside=True, count=True)
     y = y.cpu().numpy()[idx].astype(np.float64)
-    ref, _ = S.forward(p.astype(np.float64), X)
-    bound = 1.5 * _forward_bound(p.astype(np.float64), X) + 1e-5
+    # the oracle's network on the oracle's own features (within 1e-5 of the
+    # library's, checked above; the BF16 bound dwarfs what that moves)
+    ref, _ = S.forward(p.astype(np.float64), ref_f)
+    bound = 1.5 * _forward_bound(p.astype(np.float64), ref_f) + 1e-4
     assert np.all(np.abs(y - ref) <= bound)
     f32 = feats.cpu().numpy()
     want = np.any((f32 < lo) | (f32 > hi), axis=1)
