@@ -193,12 +193,17 @@ enum {
     MC_LYA_OPT_TILE_CHUNK = 13,   /* tiled walk: packets a wave takes from its tile's input at
                                      once (1..1024, default 64) */
     MC_LYA_OPT_TILE_REFILL = 14,  /* tiled walk: refill a wave once this many lanes are idle
-                                     (1..64, default 24) */
-    MC_LYA_OPT_TAIL = 15          /* tiled walk: once fewer packets than this many millionths
-                                     of a batch are in flight (0..1000000, default 100000 =
-                                     10 %; 0 = never), one kernel walks them to the end with
+                                     (1..64, default 40) */
+    MC_LYA_OPT_TAIL = 15,         /* tiled walk: once fewer packets than this many millionths
+                                     of a batch are in flight (0..1000000, default 20000 =
+                                     2 %; 0 = never), one kernel walks them to the end with
                                      device-wide deposits instead of further, thinning tile
                                      generations */
+    MC_LYA_OPT_BESIDE = 16        /* kernel 2 with both parts: the persistent walk of the
+                                     untiled boxes runs beside the tile generations on a
+                                     stream of its own, with at most this many waves per
+                                     compute unit (1..32, default 4; 0 = after them on the
+                                     context's stream). The two write disjoint boxes. */
 };
 
 /* What a context reserves at mc_lya_init. Every device buffer of the

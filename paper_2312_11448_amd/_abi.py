@@ -26,6 +26,7 @@ MC_LYA_OPT_DEFER = 12
 MC_LYA_OPT_TILE_CHUNK = 13
 MC_LYA_OPT_TILE_REFILL = 14
 MC_LYA_OPT_TAIL = 15
+MC_LYA_OPT_BESIDE = 16
 
 
 class mc_lya_box_desc(C.Structure):

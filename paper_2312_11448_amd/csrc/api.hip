@@ -156,6 +156,12 @@ struct mc_lya_ctx {
     bool graph = false;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr;        // private stream the graph is captured on
+    // the persistent part of a kernel-2 walk runs beside the tile generations
+    // on its own stream (fork and join events), with at most this many waves
+    // per compute unit (0: after them, on the context's stream)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    int beside = 4;                          // MC_LYA_OPT_BESIDE
     std::vector<uint64_t> graph_key;
     int graph_gens = 64;                     // tile generations inside the graph
     int eager_gens = kEagerGens;             // tile generations in the first eager round
@@ -166,7 +172,7 @@ struct mc_lya_ctx {
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
     int kernel = 2, block = 256, waves_per_cu = 32, chunk = 256, refill = 16, nqueues = 8;
-    int tile_chunk = 64, tile_refill = 48;   // the tiled walk's own chunk and refill
+    int tile_chunk = 64, tile_refill = 40;   // the tiled walk's own chunk and refill
     int64_t max_cross = 1000000;
     int timing = 0;                          // 0 off, 1 per launch, 2 per transport
     int64_t coarse_launches = 0;
@@ -206,6 +212,11 @@ void free_all(mc_lya_ctx *c)
     c->graph_exec = nullptr;
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->join) (void)hipEventDestroy(c->join);
+    c->side = nullptr;
+    c->fork = c->join = nullptr;
     void *ptrs[] = {c->d_pack, c->d_walk, c->d_red, c->d_tot, c->d_rec, c->d_wgt, c->d_part, c->d_q,
                     c->d_bsum, c->d_npk, c->d_A, c->d_queue, c->d_boxabs, c->d_fsum, c->d_feed,
                     c->d_cop, c->d_pfirst, c->d_seg, c->d_featbox, c->d_tail_prefix, c->d_tiles, c->d_texits[0], c->d_texits[1], c->d_state[0], c->d_sbox, c->d_ev, c->d_ev_coef,
@@ -669,7 +680,34 @@ mc_lya_status ensure_cell_of_packet(mc_lya_ctx *c)
     return MC_LYA_OK;
 }
 
-mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed);
+mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed, int waves_cap = 0);
+
+// The persistent part of a kernel-2 walk on the side stream: fork_beside
+// forks the side stream from the context's stream and enqueues `body` there
+// (the context's stream is switched to the side stream meanwhile), and
+// join_beside makes the context's stream wait for it, after the tile
+// generations have been enqueued. Inside a stream capture the side stream
+// joins the capture, and the graph holds the two as parallel branches.
+template <typename F>
+mc_lya_status fork_beside(mc_lya_ctx *c, F body)
+{
+    const hipStream_t main = c->stream;
+    HIP_TRY(c, hipEventRecord(c->fork, main));
+    HIP_TRY(c, hipStreamWaitEvent(c->side, c->fork, 0));
+    c->stream = c->side;
+    const mc_lya_status st = body();
+    c->stream = main;
+    // recorded even after a failed launch: the join then waits for whatever
+    // reached the side stream
+    HIP_TRY(c, hipEventRecord(c->join, c->side));
+    return st;
+}
+
+mc_lya_status join_beside(mc_lya_ctx *c)
+{
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join, 0));
+    return MC_LYA_OK;
+}
 
 // Everything a transport of [first, first + count) needs before its kernels
 // are enqueued: the tiled / persistent split of the boxes, the packet-state
@@ -772,7 +810,7 @@ std::vector<uint64_t> graph_key(mc_lya_ctx *c, const WalkPlan &w, int budget)
                                (uint64_t)c->chunk, (uint64_t)c->refill, (uint64_t)c->nqueues,
                                (uint64_t)c->tile_chunk, (uint64_t)c->tile_refill,
                                (uint64_t)c->max_cross, c->total_packets, c->state_cap, (uint64_t)budget,
-                               (uint64_t)c->defer, (uint64_t)c->tail,
+                               (uint64_t)c->defer, (uint64_t)c->tail, (uint64_t)c->beside,
                                (uint64_t)w.tiled, (uint64_t)w.global, (uint64_t)c->tiles.size(),
                                (uint64_t)(uintptr_t)c->d_state[0], (uint64_t)(uintptr_t)c->d_cop,
                                (uint64_t)w.p.n_seg, w.p.count, c->epoch};
@@ -803,13 +841,21 @@ mc_lya_status transport_graph(mc_lya_ctx *c, WalkPlan &w)
             return hip_fail(c, e, "hipStreamBeginCapture");
         }
         const int64_t gens = c->generations;
-        if (w.tiled) {
+        const bool beside = w.tiled && w.global && c->beside > 0;
+        bool forked = false;
+        if (beside) {
+            forked = true;
+            if (fork_beside(c, [&] { return launch_global_walk(c, w.p, false, c->beside); }) != MC_LYA_OK)
+                e = hipErrorUnknown;
+        }
+        if (e == hipSuccess && w.tiled) {
             e = launch_zero_counters(c->d_gen, kGenCounters, c->stream);
             if (e == hipSuccess && enqueue_generations(c, tp, 0, budget, false) != MC_LYA_OK) e = hipErrorUnknown;
             if (e == hipSuccess && enqueue_tail(c, c->total_packets, false) != MC_LYA_OK) e = hipErrorUnknown;
         }
         c->generations = gens;
-        if (e == hipSuccess && w.global && launch_global_walk(c, w.p, false) != MC_LYA_OK) e = hipErrorUnknown;
+        if (forked && join_beside(c) != MC_LYA_OK) e = hipErrorUnknown;
+        if (e == hipSuccess && w.global && !beside && launch_global_walk(c, w.p, false) != MC_LYA_OK) e = hipErrorUnknown;
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
         c->stream = user;
@@ -864,6 +910,13 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
     const bool whole = first == 0 && count == c->total_packets;
     if (c->graph && whole && (!w.tiled || c->total_packets <= c->state_cap)) {
         st = transport_graph(c, w);
+    } else if (w.tiled && w.global && c->beside > 0) {
+        // the persistent part first, on the side stream, so that its
+        // workgroups are resident before the tile generations fill the chip
+        st = fork_beside(c, [&] { return launch_global_walk(c, w.p, true, c->beside); });
+        if (st == MC_LYA_OK) st = walk_tiled(c, first, count);
+        const mc_lya_status sj = join_beside(c);
+        if (st == MC_LYA_OK) st = sj;
     } else {
         if (w.tiled) st = walk_tiled(c, first, count);
         if (st == MC_LYA_OK && w.global) st = launch_global_walk(c, w.p, true);
@@ -876,7 +929,7 @@ mc_lya_status launch_walk(mc_lya_ctx *c, uint64_t first, uint64_t count)
 
 // The persistent (kernel 0 and the untiled part of kernel 2) or per-packet
 // (kernel 1) walk over p.count packets.
-mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed)
+mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed, int waves_cap)
 {
     const uint64_t count = p.count;
     hipEvent_t e1 = nullptr;
@@ -890,7 +943,8 @@ mc_lya_status launch_global_walk(mc_lya_ctx *c, const WalkParams &p, bool timed)
         const int waves_per_block = c->block / 64;
         // never more workgroups than can be resident at once
         const int resident = persistent_blocks_per_cu(c->vel, c->voigt, c->block);
-        const int per_cu = std::max(1, std::min(c->waves_per_cu / waves_per_block, resident));
+        const int waves = waves_cap > 0 ? std::min(c->waves_per_cu, waves_cap) : c->waves_per_cu;
+        const int per_cu = std::max(1, std::min(waves / waves_per_block, resident));
         int grid = c->num_cu * per_cu;
         const uint64_t need = (count + 63) / 64;     // no more waves than packets
         if ((uint64_t)grid * waves_per_block > need) grid = (int)std::max<uint64_t>(1, (need + waves_per_block - 1) / waves_per_block);
@@ -1026,6 +1080,11 @@ mc_lya_status mc_lya_init(mc_lya_ctx **out, const mc_lya_box_desc *boxes, int32_
         (e = dalloc(&c->d_texits[1], nt)) != hipSuccess || (e = dalloc(&c->d_gen, kGenCounters)) != hipSuccess ||
         (e = dalloc(&c->d_tail_prefix, nt)) != hipSuccess)
         return cleanup(e == hipErrorOutOfMemory ? MC_LYA_ENOMEM : MC_LYA_EDEVICE);
+    // (default stream priority)
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess)
+        return cleanup(MC_LYA_EDEVICE);
     if (hipMemcpyAsync(c->d_tiles, c->tiles.data(), sizeof(TileInfo) * nt, hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
         hipMemcpyAsync(c->d_pack, c->pack.data(), sizeof(PackBox) * n_boxes, hipMemcpyHostToDevice, c->stream) !=
@@ -1513,6 +1572,10 @@ mc_lya_status mc_lya_set_option(mc_lya_ctx *c, int32_t option, int64_t v)
     case MC_LYA_OPT_TILE_REFILL:
         if (v < 1 || v > 64) return fail(c, MC_LYA_EINVAL, "tile refill must be in [1, 64]");
         c->tile_refill = (int)v;
+        return MC_LYA_OK;
+    case MC_LYA_OPT_BESIDE:
+        if (v < 0 || v > 32) return fail(c, MC_LYA_EINVAL, "beside must be in [0, 32]");
+        c->beside = (int)v;
         return MC_LYA_OK;
     case MC_LYA_OPT_TAIL:
         if (v < 0 || v > 1000000) return fail(c, MC_LYA_EINVAL, "tail must be in [0, 1000000] (ppm)");

@@ -368,12 +368,14 @@ __device__ __forceinline__ void load_state(Lane &L, const PState &o, const WalkB
     L.xeff = B.x_eff;
 }
 
-// Per-lane running totals: crossings walked in this generation, and the
-// weights of the packets that escaped (capped packets, which are rare, go to
-// the tile's LDS totals).
+// The tile's totals in LDS, in the order of the box totals they add to.
+constexpr int kTotEscaped = 0, kTotCrossings = 1, kTotCapped = 2, kTotCappedWeight = 3, kTotWing = 4;
+
+// Running total of a wave: crossings walked in this generation, counted from
+// the wave's step masks (the same in every lane). Escaping and capped
+// packets, one event per packet, go to the tile's LDS totals.
 struct TileAcc {
     uint32_t cross;
-    uint64_t esc, wing;
 };
 
 // The walk of one tile's input by one workgroup (all its waves): refill
@@ -384,7 +386,7 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
                                           const TileCtx &C, uint32_t n_in, const uint32_t *pre, const uint32_t *lst,
                                           const char *recs, unsigned long long *tally, uint32_t *s_next,
                                           uint32_t *s_exit, uint32_t s_base, uint32_t *s_fcnt,
-                                          unsigned long long *s_cap, TileAcc &acc)
+                                          unsigned long long *s_tot, TileAcc &acc)
 {
     constexpr int RS = VEL ? 16 : 4;
     const int ncell = ti.sx * ti.sy * ti.sz;
@@ -394,17 +396,20 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
     idle_tlane(L, RS);          // every lane steps, so none starts undefined
     bool alive = false, more = true;
     bool fresh = false;          // wave-uniform: packets loaded since the wave's last step
-    // A packet that reaches the tile's edge parks in its lane (pending) and is
-    // written out when the wave next refills or stops: one exit-writing pass
-    // for many lanes instead of one per step for a few.
-    bool pending = false;
+    // A packet that reaches the tile's edge parks in its lane and is written
+    // out when the wave next refills or stops: one exit-writing pass for many
+    // lanes instead of one per step for a few. A lane is parked when it is not
+    // live yet holds weight (a finished packet's lane holds none).
     auto flush_exits = [&]() {
-        if (pending) {
-            const uint32_t g = s_base + atomicAdd(s_exit, 1u);
-            const uint32_t f = save_exit<RS>(P.out_state[g], L, C, B);
-            P.out_face[g] = (uint8_t)f;
-            atomicAdd(&s_fcnt[f], 1u);
-            pending = false;
+        const bool parked = !alive && L.w != 0u;
+        if (__ballot(parked)) {
+            if (parked) {
+                const uint32_t g = s_base + atomicAdd(s_exit, 1u);
+                const uint32_t f = save_exit<RS>(P.out_state[g], L, C, B);
+                P.out_face[g] = (uint8_t)f;
+                atomicAdd(&s_fcnt[f], 1u);
+                L.w = 0u;
+            }
         }
     };
     uint32_t cur = 0, end = 0;
@@ -470,16 +475,19 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
             idle = __ballot(!alive);
         }
         }
+        // The wave stops once the input is used up and no lane is live (while
+        // there is input, a wave with every lane idle refills), or, once the
+        // input is used up, when few lanes are live (deferred). One exit, on
+        // a value the compiler sees as uniform, keeps the loop's state in
+        // scalar registers where it is uniform.
+        uint32_t stop = 0;
         if (!more) {
             const uint64_t live = __ballot(alive);
-            // no live lane once the input is used up: done (while there is
-            // input, a wave with every lane idle refills)
             if (!live) {
                 flush_exits();
-                break;
-            }
-            // (only after a step, so every deferred packet has moved in this generation)
-            if (!fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
+                stop = 1;
+            } else if (!fresh && n_in >= P.defer_min && (uint32_t)__popcll(live) <= (uint32_t)P.defer_lanes) {
+                // (only after a step, so every deferred packet has moved in this generation)
                 flush_exits();
                 if (alive) {
                     const uint32_t g = s_base + atomicAdd(s_exit, 1u);
@@ -487,25 +495,57 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
                     P.out_face[g] = (uint8_t)kDeferred;
                     atomicAdd(&s_fcnt[kDeferred], 1u);
                 }
-                break;
+                stop = 1;
             }
         }
+        if (uniform_u32(stop)) break;
         fresh = false;
         // Every lane steps: an idle or parked lane's step changes nothing and
         // deposits nothing (selects, not branches, keep the lane state in the
         // same registers round the loop).
         const TStep o = tile_step<VEL, VOIGT, WRAP, RS>(L, alive, C, recs, tally, dep_q, dep_w);
-        acc.cross += o.walked ? 1u : 0u;
-        acc.esc += o.escaped ? L.w : 0u;
-        if (VOIGT) acc.wing += o.escaped ? o.wing : 0u;
-        if (o.capped) {          // rare: the tile's LDS totals
-            atomicAdd(&s_cap[0], 1ull);
-            atomicAdd(&s_cap[1], (unsigned long long)L.w);
+        // (wave-uniform counts kept in scalar registers)
+        acc.cross = uniform_u32(acc.cross + (uint32_t)__popcll(__ballot(o.walked)));
+        if (o.escaped) {         // rare: the tile's LDS totals
+            atomicAdd(&s_tot[kTotEscaped], (unsigned long long)L.w);
+            if (VOIGT && o.wing) atomicAdd(&s_tot[kTotWing], (unsigned long long)o.wing);
         }
-        pending = pending || o.exit;
+        if (o.capped) {
+            atomicAdd(&s_tot[kTotCapped], 1ull);
+            atomicAdd(&s_tot[kTotCappedWeight], (unsigned long long)L.w);
+        }
+        L.w = (o.escaped || o.capped) ? 0u : L.w;   // counted: the lane holds nothing
         alive = o.alive;
     }
     if (dep_w) atomicAdd(tally_of<RS>(tally, dep_q), (unsigned long long)dep_w);
+}
+
+// The tile's records into LDS (rows of 16 cells read together), with its
+// tallies zeroed, and the record kOutside in every other slot.
+template <bool VEL>
+__device__ __forceinline__ void load_tile_records(const TileParams &P, const TileInfo &ti, const WalkBox &B,
+                                                  float4 *srec4, float *sreck, unsigned long long *tally, int tid)
+{
+    for (int q = tid; q < TC; q += BLK) {
+        const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
+        if (lx < ti.sx && ly < ti.sy && lz < ti.sz) {
+            const int sl = tile_slot(lx, ly, lz);
+            const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
+                                (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+            tally[sl] = 0ull;
+            if (VEL) srec4[sl] = static_cast<const float4 *>(P.rec)[gc];
+            else sreck[sl] = static_cast<const float *>(P.rec)[gc];
+        }
+    }
+    for (int sl = tid; sl < kSlots; sl += BLK) {
+        int32_t lx, ly, lz;
+        slot_cell(sl, lx, ly, lz);
+        const bool in = (uint32_t)lx < (uint32_t)ti.sx && (uint32_t)ly < (uint32_t)ti.sy && (uint32_t)lz < (uint32_t)ti.sz;
+        if (!in) {
+            if (VEL) srec4[sl] = make_float4(__uint_as_float(kOutside), 0.0f, 0.0f, 0.0f);
+            else sreck[sl] = __uint_as_float(kOutside);
+        }
+    }
 }
 
 // One generation. GEN0: the tile's input is the packets emitted in its cells
@@ -522,11 +562,13 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     __shared__ uint32_t s_tsum[kWaves];
     __shared__ uint32_t s_next, s_exit, s_total, s_base;
     __shared__ uint32_t s_fcnt[8], s_fcur[8];
-    __shared__ unsigned long long s_red[kWaves][5];
-    __shared__ unsigned long long s_cap[2];        // capped packets and their weight
+    __shared__ unsigned long long s_red[kWaves];   // crossings of each wave
+    __shared__ unsigned long long s_tot[5];        // escaped weight, -, capped packets and weight, wing
 
     const int T = blockIdx.x;
     const int tid = threadIdx.x;
+    // (the tile's entry is read alongside the count of packets in flight)
+    const TileInfo ti = P.tiles[T];
     if (!GEN0) {
         const unsigned long long in_flight = *P.prev_exits;
         if (in_flight == 0) return;                 // the walk has drained (or went to the tail walk)
@@ -537,7 +579,6 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
             return;
         }
     }
-    const TileInfo ti = P.tiles[T];
     const WalkBox B = P.boxes[ti.box];
     const int ncell = ti.sx * ti.sy * ti.sz;
     const uint32_t lane = __lane_id();
@@ -595,23 +636,30 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
         if (tid == 0) pre[ncell] = s_total;
     } else {
+        // the neighbours' face lists, then this tile's deferred list: one
+        // thread per list reads its extent (independent reads), while every
+        // thread loads the tile's records
+        if (tid <= ti.nsrc) {
+            const int k = tid;
+            const int f = k < ti.nsrc ? (int)((ti.src_faces >> (4 * k)) & 15u) : kDeferred;
+            const TileExits &e = P.in_exits[k < ti.nsrc ? P.tiles[T].src_tile[k] : T];
+            lst[k] = e.base + e.off[f];
+            s_tsum[k] = e.off[f + 1] - e.off[f];
+        }
+        load_tile_records<VEL>(P, ti, B, srec4, sreck, tally, tid);
+        __syncthreads();
         if (tid == 0) {
             uint32_t run = 0;
-            const int32_t *src = P.tiles[T].src_tile;
             for (int k = 0; k <= ti.nsrc; ++k) {
-                // the neighbours' face lists, then this tile's deferred list
-                const int f = k < ti.nsrc ? (int)((ti.src_faces >> (4 * k)) & 15u) : kDeferred;
-                const TileExits &e = P.in_exits[k < ti.nsrc ? src[k] : T];
                 pre[k] = run;
-                lst[k] = e.base + e.off[f];
-                run += e.off[f + 1] - e.off[f];
+                run += s_tsum[k];
             }
             pre[ti.nsrc + 1] = run;
             s_total = run;
         }
         __syncthreads();
     }
-    n_in = s_total;
+    n_in = uniform_u32(s_total);   // (uniform, so the walk loop's exits are too)
     if (n_in == 0) {
         if (tid == 0) {
             TileExits e;
@@ -621,35 +669,14 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         }
         return;
     }
-    // the tile's records (rows of 16 cells read together) and zero tallies
-    for (int q = tid; q < TC; q += BLK) {
-        const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
-        if (lx < ti.sx && ly < ti.sy && lz < ti.sz) {
-            const int sl = tile_slot(lx, ly, lz);
-            const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
-                                (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
-            tally[sl] = 0ull;
-            if (VEL) srec4[sl] = static_cast<const float4 *>(P.rec)[gc];
-            else sreck[sl] = static_cast<const float *>(P.rec)[gc];
-        }
-    }
-    // every other slot reads as outside the tile
-    for (int sl = tid; sl < kSlots; sl += BLK) {
-        int32_t lx, ly, lz;
-        slot_cell(sl, lx, ly, lz);
-        const bool in = (uint32_t)lx < (uint32_t)ti.sx && (uint32_t)ly < (uint32_t)ti.sy && (uint32_t)lz < (uint32_t)ti.sz;
-        if (!in) {
-            if (VEL) srec4[sl] = make_float4(__uint_as_float(kOutside), 0.0f, 0.0f, 0.0f);
-            else sreck[sl] = __uint_as_float(kOutside);
-        }
-    }
+    if (GEN0) load_tile_records<VEL>(P, ti, B, srec4, sreck, tally, tid);
     if (tid == 0) {
         s_next = 0;
         s_exit = 0;
         s_base = (uint32_t)atomicAdd(P.bump, (unsigned long long)n_in);
     }
     if (tid < 8) s_fcnt[tid] = 0;
-    if (tid < 2) s_cap[tid] = 0;
+    if (tid < 5) s_tot[tid] = 0;
     __syncthreads();
 
     // ---- walk -------------------------------------------------------------
@@ -666,40 +693,46 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
     C.sz = ti.sz;
     C.span = ti.span;
     const char *recs = VEL ? reinterpret_cast<const char *>(srec4) : reinterpret_cast<const char *>(sreck);
-    TileAcc acc{0, 0, 0};
+    TileAcc acc{0};
     // a tile that spans the box along some axis wraps round inside itself
     if (ti.span)
         walk_tile<VEL, GEN0, VOIGT, true>(P, ti, B, C, n_in, pre, lst, recs, tally, &s_next, &s_exit, s_base, s_fcnt,
-                                          s_cap, acc);
+                                          s_tot, acc);
     else
         walk_tile<VEL, GEN0, VOIGT, false>(P, ti, B, C, n_in, pre, lst, recs, tally, &s_next, &s_exit, s_base, s_fcnt,
-                                           s_cap, acc);
+                                           s_tot, acc);
 
     // ---- finish: tally, totals, face lists of the exits ----------------------
-    const uint64_t a_esc = wave_sum(acc.esc), a_cross = wave_sum((uint64_t)acc.cross),
-                   a_wing = VOIGT ? wave_sum(acc.wing) : 0;
-    if (lane == 0) {
-        s_red[tid >> 6][0] = a_esc;
-        s_red[tid >> 6][1] = a_cross;
-        s_red[tid >> 6][2] = 0;
-        s_red[tid >> 6][3] = 0;
-        s_red[tid >> 6][4] = a_wing;
-    }
+    if (lane == 0) s_red[tid >> 6] = acc.cross;
     __threadfence_block();
     __syncthreads();
-    for (int q = tid; q < TC; q += BLK) {
-        const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
-        const unsigned long long v = (lx < ti.sx && ly < ti.sy && lz < ti.sz) ? tally[tile_slot(lx, ly, lz)] : 0ull;
-        if (v) {
-            const uint32_t gc = B.cell_off + (uint32_t)(ti.ox + lx) +
-                                (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
-            P.A[gc] += v;    // this workgroup alone owns these cells in this generation
+    {
+        // this workgroup alone owns these cells in this generation: plain
+        // read-modify-write, every read issued before the first is used
+        constexpr int PER = TC / BLK;
+        unsigned long long v[PER], old[PER];
+        uint32_t gc[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int q = tid + k * BLK;
+            const int lx = q & 15, ly = (q >> 4) & 15, lz = q >> 8;
+            v[k] = (lx < ti.sx && ly < ti.sy && lz < ti.sz) ? tally[tile_slot(lx, ly, lz)] : 0ull;
+            gc[k] = B.cell_off + (uint32_t)(ti.ox + lx) +
+                    (uint32_t)B.nx * ((uint32_t)(ti.oy + ly) + (uint32_t)B.ny * (uint32_t)(ti.oz + lz));
+            old[k] = 0ull;
         }
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (v[k]) old[k] = P.A[gc[k]];
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (v[k]) P.A[gc[k]] = old[k] + v[k];
     }
     if (tid < (VOIGT ? 5 : 4)) {
-        // (after the barrier: every wave's walk has ended, so s_cap is final)
-        unsigned long long t = tid == 2 ? s_cap[0] : tid == 3 ? s_cap[1] : 0ull;
-        for (int w = 0; w < kWaves; ++w) t += s_red[w][tid];
+        // (after the barrier: every wave's walk has ended, so s_tot is final)
+        unsigned long long t = s_tot[tid];
+        if (tid == kTotCrossings)
+            for (int w = 0; w < kWaves; ++w) t += s_red[w];
         if (t) {
             unsigned long long *dst = tid == 0 ? &P.tot[ti.box].escaped
                                    : tid == 1 ? &P.tot[ti.box].crossings
@@ -724,10 +757,23 @@ __global__ __launch_bounds__(BLK) void tile_walk_kernel(TileParams P)
         if (n_exit) atomicAdd(P.exits, (unsigned long long)n_exit);
     }
     __syncthreads();
-    for (uint32_t k = tid; k < n_exit; k += BLK) {
-        const uint32_t g = s_base + k;
-        const uint32_t pos = atomicAdd(&s_fcur[P.out_face[g]], 1u);
-        P.out_idx[s_base + pos] = g;
+    // the face lists: four exits per thread at a time, their faces read first
+    constexpr int kIdxBatch = 4;
+    for (uint32_t k0 = tid; k0 < n_exit; k0 += kIdxBatch * BLK) {
+        uint32_t f[kIdxBatch];
+#pragma unroll
+        for (int j = 0; j < kIdxBatch; ++j) {
+            const uint32_t k = k0 + (uint32_t)(j * BLK);
+            f[j] = k < n_exit ? (uint32_t)P.out_face[s_base + k] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kIdxBatch; ++j) {
+            const uint32_t k = k0 + (uint32_t)(j * BLK);
+            if (k < n_exit) {
+                const uint32_t pos = atomicAdd(&s_fcur[f[j]], 1u);
+                P.out_idx[s_base + pos] = s_base + k;
+            }
+        }
     }
 }
 

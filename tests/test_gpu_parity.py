@@ -307,7 +307,7 @@ def test_errors_and_cap():
                          (M.MC_LYA_OPT_TILE_CHUNK, 2000), (M.MC_LYA_OPT_TILE_REFILL, 65),
                          (M.MC_LYA_OPT_DEFER, -1), (M.MC_LYA_OPT_TILE_SHARE, -5), (M.MC_LYA_OPT_GRAPH, 2),
                          (M.MC_LYA_OPT_GRAPH_GENS, 8), (M.MC_LYA_OPT_QUEUES, 0), (M.MC_LYA_OPT_TAIL, -1),
-                         (99, 1)):
+                         (M.MC_LYA_OPT_BESIDE, 33), (99, 1)):
             with pytest.raises(M.MCLyaError) as e:
                 sim.set_option(opt, bad)
             assert e.value.status == M.MC_LYA_EINVAL, opt
@@ -365,8 +365,9 @@ def _batch_run(boxes, options, ranges=None):
 def test_mixed_tiled_and_persistent_batch():
     """Kernel 2 on a batch walks boxes with enough tiles by tiles and a box
     with a single, crowded tile by the persistent walk, in the same
-    transport; the integers equal those of either walk alone, also over
-    packet ranges that cut through boxes."""
+    transport (beside the tile generations on a stream of its own, or after
+    them); the integers equal those of either walk alone, also over packet
+    ranges that cut through boxes."""
     boxes = [W.make_box("c2", n=64, n_packets=20_000, field_seed=11, seed=1),
              W.make_box("c2", n=16, n_packets=100_000, field_seed=12, seed=2),
              W.make_box("c2", n=40, n_packets=5_000, field_seed=13, seed=3)]
@@ -380,6 +381,8 @@ def test_mixed_tiled_and_persistent_batch():
     assert np.array_equal(tail_A, ref_A) and tail_s == ref_s
     assert np.array_equal(tiled_A, ref_A) and tiled_s == ref_s
     assert np.array_equal(mixed_A, ref_A) and mixed_s == ref_s
+    after_A, after_s, n_after = _batch_run(boxes, {M.MC_LYA_OPT_TAIL: 0, M.MC_LYA_OPT_BESIDE: 0})
+    assert np.array_equal(after_A, ref_A) and after_s == ref_s and n_after == n_mixed
     split_A, split_s, _ = _batch_run(boxes, {}, ranges=[(0, 15_000), (15_000, 118_000), (118_000, 125_000)])
     assert np.array_equal(split_A, ref_A) and split_s == ref_s
 
