@@ -191,7 +191,8 @@ enum {
                                      them to the tile's next generation instead of walking on
                                      with idle lanes (tiles that took >= 2048 packets) */
     MC_LYA_OPT_TILE_CHUNK = 13,   /* tiled walk: packets a wave takes from its tile's input at
-                                     once (1..1024, default 64) */
+                                     once (1..1024, default 512; smaller claims near the end
+                                     of the input) */
     MC_LYA_OPT_TILE_REFILL = 14,  /* tiled walk: refill a wave once this many lanes are idle
                                      (1..64, default 40) */
     MC_LYA_OPT_TAIL = 15,         /* tiled walk: once fewer packets than this many millionths

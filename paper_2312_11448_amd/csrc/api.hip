@@ -172,7 +172,7 @@ struct mc_lya_ctx {
     int state = 0;                    // 0 packed, 1 emitted, 2 transported
     // options
     int kernel = 2, block = 256, waves_per_cu = 32, chunk = 256, refill = 16, nqueues = 8;
-    int tile_chunk = 64, tile_refill = 40;   // the tiled walk's own chunk and refill
+    int tile_chunk = 512, tile_refill = 40;  // the tiled walk's own chunk and refill
     int64_t max_cross = 1000000;
     int timing = 0;                          // 0 off, 1 per launch, 2 per transport
     int64_t coarse_launches = 0;
@@ -1617,10 +1617,11 @@ mc_lya_status mc_lya_autotune(mc_lya_ctx *c, int32_t reps, mc_lya_tune_result *r
     // tiled walk (with the persistent walk for crowded boxes) at several tile
     // shares, tile chunks and refill thresholds; the persistent walk alone
     const Opts fixed[] = {
-        {2, 100, 256, 32, 256, 16, 64, 24}, {2, 50, 256, 32, 256, 16, 64, 24}, {2, 25, 256, 32, 256, 16, 64, 24},
-        {2, 100, 256, 32, 256, 16, 32, 24}, {2, 100, 256, 32, 256, 16, 128, 24}, {2, 100, 256, 32, 256, 16, 64, 16},
-        {0, 100, 256, 32, 256, 16, 64, 24}, {0, 100, 256, 16, 256, 16, 64, 24}, {0, 100, 256, 32, 64, 16, 64, 24},
-        {0, 100, 256, 32, 256, 32, 64, 24}, {0, 100, 128, 32, 256, 16, 64, 24},
+        {2, 100, 256, 32, 256, 16, 512, 40}, {2, 50, 256, 32, 256, 16, 512, 40}, {2, 25, 256, 32, 256, 16, 512, 40},
+        {2, 100, 256, 32, 256, 16, 128, 40}, {2, 100, 256, 32, 256, 16, 1024, 40}, {2, 100, 256, 32, 256, 16, 512, 48},
+        {2, 100, 256, 32, 256, 16, 512, 32},
+        {0, 100, 256, 32, 256, 16, 512, 40}, {0, 100, 256, 16, 256, 16, 512, 40}, {0, 100, 256, 32, 64, 16, 512, 40},
+        {0, 100, 256, 32, 256, 32, 512, 40}, {0, 100, 128, 32, 256, 16, 512, 40},
     };
     for (const Opts &o : fixed)
         if (std::find(cand.begin(), cand.end(), o) == cand.end()) cand.push_back(o);

@@ -29,6 +29,7 @@ constexpr int TC = kTileCells;
 constexpr int BLK = kTileBlock;
 static_assert(TC % BLK == 0, "tile cells must be a multiple of the workgroup size");
 constexpr int kWaves = BLK / 64;
+constexpr uint32_t kMinClaim = 8;   // smallest claim on a tile's input
 
 // LDS slots: the tile's cells with a ring of one slot round them, in a
 // (kTileX + 2) x (kTileY + 2) x (kTileZ + 2) layout whatever the tile's extent
@@ -425,15 +426,24 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
         flush_exits();
         while (idle && more) {
             if (cur >= end) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(s_next, chunk);
+                // near the end of the input the claims shrink, so that the
+                // last packets spread over the waves instead of leaving one
+                // wave with a whole chunk while the others are done
+                uint32_t base = 0, want = 0;
+                if (lane == 0) {
+                    const uint32_t seen = __hip_atomic_load(s_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint32_t left = seen < n_in ? n_in - seen : 0u;
+                    want = left < chunk * kWaves ? max(left / kWaves, min(chunk, kMinClaim)) : chunk;
+                    base = atomicAdd(s_next, want);
+                }
                 base = uniform_u32(__shfl(base, 0, 64));
+                want = uniform_u32(__shfl(want, 0, 64));
                 if (base >= n_in) {
                     more = false;
                     break;
                 }
                 cur = base;
-                end = base + chunk < n_in ? base + chunk : n_in;
+                end = base + want < n_in ? base + want : n_in;
             }
             const uint32_t take = min((uint32_t)__popcll(idle), end - cur);
             const uint32_t r = rank_in(idle);
