@@ -81,6 +81,10 @@ def parse():
                          "about 7e4 scatterings per photon)")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=None,
                     help="replay each transport as a captured HIP graph (default 0)")
+    ap.add_argument("--tail", type=int, default=None, metavar="PPM",
+                    help="MC_LYA_OPT_TAIL: the tail walk takes over below this many millionths of the packets in "
+                         "flight (default: the library's 2 % for a single box, 20 % for the batch, whose last "
+                         "generations are held by a few crowded tiles of its low-redshift boxes)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the walk options on the first emission, before the warm-up")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
@@ -518,6 +522,9 @@ def main():
     sim.set_option(M.MC_LYA_OPT_TIMING, 2)
     graph = a.graph if a.graph is not None else 0
     sim.set_option(M.MC_LYA_OPT_GRAPH, graph)
+    tail = a.tail if a.tail is not None else (200000 if a.config == "batch" else None)
+    if tail is not None:
+        sim.set_option(M.MC_LYA_OPT_TAIL, tail)
     seeds, npk = [s.seed for s in specs], [s.n_packets for s in specs]
     tuned = None
     if a.autotune:
@@ -587,7 +594,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload_name(a.config, specs), "cells": sum(x.ncells for x in specs),
-                   "packets": sum(npk), "graph": graph, "autotuned": tuned,
+                   "packets": sum(npk), "graph": graph, "tail_ppm": tail, "autotuned": tuned,
                    "crossings_per_step": cross_per_step,
                    "packets_per_s": sum(npk) * a.steps / dt,
                    "walk_ms": walk_s * 1e3,
