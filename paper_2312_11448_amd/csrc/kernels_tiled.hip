@@ -188,9 +188,9 @@ struct TStep {
 // neighbour's record at the end of the step it was computed in.
 template <bool VEL, bool VOIGT, bool WRAP, int RS>
 __device__ __forceinline__ TStep tile_step(TLane &L, bool act, const TileCtx &C, const char *recs,
-                                           unsigned long long *tally, int32_t &dep_q, uint32_t &dep_w)
+                                           unsigned long long *tally, int32_t &dep_q, uint32_t &dep_w,
+                                           int32_t spare_q)
 {
-    if (dep_w) atomicAdd(tally_of<RS>(tally, dep_q), (unsigned long long)dep_w);
     TStep o;
     const bool gone = VOIGT ? (L.x <= -C.xeff) | (L.x > C.ln.xblue) : L.x <= -C.xeff;
     const bool capped = !gone && L.ncross >= C.max_cross;
@@ -204,8 +204,13 @@ __device__ __forceinline__ TStep tile_step(TLane &L, bool act, const TileCtx &C,
     // the next slot's record, in flight during the profile arithmetic; the
     // ring round the tile holds kOutside
     const Rec nr = rec_at<VEL>(recs, qn);
+    // the last step's deposit, issued after the record read so that waiting
+    // for the record does not wait for it; every lane issues it (a lane with
+    // nothing to deposit adds 0 to a ring slot of its own), so the wait's
+    // count is the same on every path
+    atomicAdd(tally_of<RS>(tally, dep_q), (unsigned long long)dep_w);
     const Segment g = segment<VOIGT>(L.x, (float)(f.tn - L.t), C.delta, C.xeff, L.kap, L.w, walk, C.ln);
-    dep_q = L.q;                 // the deposit goes into the cell being left
+    dep_q = walk ? L.q : spare_q;   // the deposit goes into the cell being left
     dep_w = g.d;
     L.w -= g.d;
     L.ncross += walk ? 1u : 0u;
@@ -418,7 +423,10 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
     // refilling stalls the whole wave on the new packets' loads: wait until
     // this many lanes are idle (1..64; 64 waits for all)
     const uint32_t refill = (uint32_t)min(max(P.refill, 1), 64);
-    int32_t dep_q = 0;           // the last step's deposit, not yet issued
+    // a ring slot of this lane's own (the ring's z = -1 plane has 324 slots),
+    // whose tally is never read: where a lane with nothing to deposit adds 0
+    const int32_t spare_q = tile_slot((int32_t)(lane % kSX) - 1, (int32_t)(lane / kSX) - 1, -1) * RS;
+    int32_t dep_q = spare_q;     // the last step's deposit, not yet issued
     uint32_t dep_w = 0;
     for (;;) {
         uint64_t idle = __ballot(!alive);
@@ -513,7 +521,7 @@ __device__ __forceinline__ void walk_tile(const TileParams &P, const TileInfo &t
         // Every lane steps: an idle or parked lane's step changes nothing and
         // deposits nothing (selects, not branches, keep the lane state in the
         // same registers round the loop).
-        const TStep o = tile_step<VEL, VOIGT, WRAP, RS>(L, alive, C, recs, tally, dep_q, dep_w);
+        const TStep o = tile_step<VEL, VOIGT, WRAP, RS>(L, alive, C, recs, tally, dep_q, dep_w, spare_q);
         // (wave-uniform counts kept in scalar registers)
         acc.cross = uniform_u32(acc.cross + (uint32_t)__popcll(__ballot(o.walked)));
         if (o.escaped) {         // rare: the tile's LDS totals
