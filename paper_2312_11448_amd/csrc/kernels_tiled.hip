@@ -182,10 +182,11 @@ struct TStep {
 // drifted pre-jump frequency and its cell's velocity (save_exit completes the
 // crossing). act = false leaves the lane's state as it is (an idle lane, or
 // one waiting to be written out) and deposits nothing.
-// The deposit of a step is issued at the start of the next one (dep_q, dep_w:
-// the cell's record offset and the weight, 0 for none): its LDS atomic then
-// runs while the step computes, instead of delaying the wait for the
-// neighbour's record at the end of the step it was computed in.
+// The deposit of a step is issued in the next one, right after that step's
+// record read (dep_q, dep_w: the cell's record offset and the weight; a lane
+// that deposited nothing holds its spare slot spare_q and 0): the LDS atomic
+// then runs while the step computes, and waiting for the record does not wait
+// for it.
 template <bool VEL, bool VOIGT, bool WRAP, int RS>
 __device__ __forceinline__ TStep tile_step(TLane &L, bool act, const TileCtx &C, const char *recs,
                                            unsigned long long *tally, int32_t &dep_q, uint32_t &dep_w,
