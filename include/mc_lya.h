@@ -25,7 +25,12 @@
  *     directions. With several boxes, cells and packets are concatenated box
  *     by box ("box-major") in the order the boxes were given.
  *   - "dev" pointers are HIP device memory; "host" pointers are host memory.
- *     All device work is queued on the HIP stream given to mc_lya_init.
+ *     All device work is queued on the HIP stream given to mc_lya_init. The
+ *     one exception is the persistent walk of a kernel-2 transport's untiled
+ *     boxes (MC_LYA_OPT_BESIDE), which runs on a stream the context creates at
+ *     init, forked from that stream and joined back into it before the call
+ *     returns its work to it: work queued afterwards on the context's stream
+ *     waits for both.
  *   - Every call returns a status and never aborts. On failure the context is
  *     left as it was and mc_lya_last_error() describes the failure.
  *   - Call order: init -> [refresh] -> emit -> transport (or transport_range,
@@ -236,7 +241,8 @@ typedef struct mc_lya_limits {
 /* Creates a context for n_boxes boxes, validates and packs their fields
  * (Sec. III.A.1 quantities per cell: n_1s, the true-absorption depth kappa_c
  * of Eq. (<fnu>), the bulk velocity, the emission weight) and allocates every
- * device buffer the context will use (mc_lya_limits states the sizes).
+ * device buffer the context will use (mc_lya_limits states the sizes), and one
+ * stream and two events of its own (default priority; see MC_LYA_OPT_BESIDE).
  *   out      host, receives the context (set to NULL on failure)
  *   boxes    host [n_boxes]; the field pointers must stay valid and unchanged
  *            until mc_lya_destroy, or until they are refreshed
