@@ -2,8 +2,9 @@
 size (16^3 to 96^3), redshift (830 to 1390, the Monte-Carlo redshifts of
 Fig. MCtravel), contrast and temperature T = T0 (1 + z), x_e = 0.1. The
 transport splits the boxes between the tile-decomposed walk and the
-persistent walk (asserted from the per-box stats) and runs as a replayed HIP
-graph, with the default options and again after the autotuner; every box is
+persistent walk (asserted from the per-box stats) and runs eagerly (the
+persistent part beside the tiles or after them) and as a replayed HIP graph,
+with the default options and again after the autotuner; every box is
 compared cell by cell with the oracle run of that box alone, at the stated
 tolerances (per cell 1e-3 relative plus 1e-6 of the mean cell, absorbed
 fraction 1e-5), and its emission counts bit for bit."""
@@ -80,6 +81,23 @@ def test_batch_graph_replay_matches_oracle(batch):
         # the batch took both walks: tiles for some boxes, the persistent walk for others
         assert 1 in kinds and 0 in kinds, kinds
         assert kinds[0] == 1 and kinds[2] == 0
+
+
+@pytest.mark.parametrize("beside", [4, 0])
+def test_batch_eager_matches_oracle(batch, beside):
+    """The eager transport, with the persistent walk of the untiled boxes
+    beside the tile generations on the context's second stream (and after
+    them, beside = 0), and with the batch's tail switch at 20 % in flight."""
+    specs, refs = batch
+    with M.Simulation(specs) as sim:
+        sim.set_option(M.MC_LYA_OPT_BESIDE, beside)
+        sim.set_option(M.MC_LYA_OPT_TAIL, 200_000)
+        sim.emit()
+        sim.transport()
+        t = sim.tally(want_emitted=True)
+        _check(specs, refs, sim, t, f"eager beside={beside}")
+        kinds = [s.tiled for s in t["stats"]]
+        assert 1 in kinds and 0 in kinds, kinds
 
 
 def test_batch_after_autotune_matches_oracle(batch):
