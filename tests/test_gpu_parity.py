@@ -320,12 +320,14 @@ def test_errors_and_cap():
         assert sim.tally()["stats"][0].conserved == 1
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (9, 9, 9), (20, 33, 17), (48, 16, 40), (5, 70, 3)])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (9, 9, 9), (20, 33, 17), (48, 16, 40), (5, 70, 3),
+                                   (1, 33, 40), (40, 1, 1), (1, 1, 1)])
 def test_tiled_walk_equals_global_walk(shape):
     """The tile-decomposed walk (LDS tallies, packets handed between tiles)
     gives the same integers as the walk with device-wide atomics: tiles that
     span an axis and wrap onto themselves, thin last tiles, two tiles along an
-    axis (one neighbour on both sides)."""
+    axis (one neighbour on both sides), axes one cell thick (a packet crossing
+    such a face re-enters its own cell) and a single-cell box."""
     rng = np.random.default_rng(sum(shape))
     od = rng.lognormal(0.0, 0.6, size=shape[::-1]).astype(np.float32)
     vel = rng.normal(0.0, 0.15, size=(3,) + shape[::-1]).astype(np.float32)
@@ -481,16 +483,24 @@ def test_autotune_changes_speed_only():
         assert [s.escaped for s in t["stats"]] == [s.escaped for s in ref["stats"]]
 
 
-@pytest.mark.parametrize("case", ["transparent", "opaque", "single_source_cell"])
+@pytest.mark.parametrize("case", ["transparent", "opaque", "single_source_cell", "one_cell", "one_cell_thick"])
 def test_degenerate_boxes_match_oracle(case):
     """x_e = 1 (no neutral hydrogen: nothing is absorbed, every packet walks
     to -x_eff), a box 100 times more opaque than the paper's (absorption in
-    the emission cell), and all emission in one cell."""
+    the emission cell), all emission in one cell, a box of one cell (every
+    face leads back into it) and a box one cell thick along x."""
     base = W.make_box("c2", n=20, n_packets=40_000, field_seed=8, seed=9)
     if case == "transparent":
         spec = W.BoxSpec(**{**base.__dict__, "x_e_uniform": 1.0})
     elif case == "opaque":
         spec = W.BoxSpec(**{**base.__dict__, "zeta": 0.01})
+    elif case in ("one_cell", "one_cell_thick"):
+        shape = (1, 1, 1) if case == "one_cell" else (1, 24, 24)
+        rng = np.random.default_rng(77)
+        od = rng.lognormal(0.0, 0.5, size=shape[::-1]).astype(np.float32)
+        vel = rng.normal(0.0, 0.1, size=(3,) + shape[::-1]).astype(np.float32)
+        spec = W.BoxSpec(**{**base.__dict__, "n": shape, "overdensity": od, "velocity": vel,
+                            "n_packets": 20_000})
     else:
         src = np.zeros_like(base.overdensity)
         src[7, 3, 11] = 1.0
