@@ -526,7 +526,8 @@ mc_lya_status mc_lya_mlp_set_envelope(mc_lya_mlp *mlp, const float *lo, const fl
  * the last layer (w3, b3) in FP32. Training differentiates this same function.
  *   features  dev [n][8] float
  *   y         dev [n] float
- *   outside   dev [n] uint8 (1 = some feature outside the envelope), or NULL
+ *   outside   dev [n] uint8 (1 = some feature outside the envelope; all 0
+ *             while no envelope is set), or NULL
  *   n_outside host, or NULL: number of such cells (then synchronises)
  * Asynchronous otherwise. Errors: EINVAL, EDEVICE. */
 mc_lya_status mc_lya_mlp_forward(mc_lya_mlp *mlp, const float *features, uint64_t n, float *y,

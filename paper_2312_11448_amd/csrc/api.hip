@@ -1217,6 +1217,7 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
     const int nb = c->n_boxes;
     HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
     c->featbox.resize(nb);
+    uint64_t blocks = 1;
     for (int b = 0; b < nb; ++b) {
         const mc_lya_box_desc &d = c->desc[b];
         FeatBox &f = c->featbox[b];
@@ -1236,10 +1237,17 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
         // the box clumping from the pack's FP64 sums (read back by refresh)
         const double n = (double)f.ncells, m1 = c->red[b].od_sum / n, m2 = c->red[b].od2_sum / n;
         f.ln_clump = m1 > 0.0 ? (float)std::log(m2 / (m1 * m1)) : 0.0f;
+        // four cells per thread where rows hold whole groups of four and the
+        // fields take 16-byte loads (8-byte for FP16 velocities)
+        auto aligned = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; };
+        f.quad = d.nx % 4 == 0 && aligned(d.overdensity, 16) && (!d.x_e || aligned(d.x_e, 16)) &&
+                 (d.vel_dtype == MC_LYA_VEL_NONE || aligned(d.velocity, d.vel_dtype == MC_LYA_VEL_F16 ? 8 : 16));
+        const uint64_t threads = f.quad ? f.ncells / 4u : f.ncells;
+        blocks = std::max<uint64_t>(blocks, (threads + 255) / 256);
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_featbox, c->featbox.data(), sizeof(FeatBox) * nb, hipMemcpyHostToDevice,
                               c->stream));
-    HIP_TRY(c, launch_features(c->d_featbox, nb, c->max_blk, out, c->stream));
+    HIP_TRY(c, launch_features(c->d_featbox, nb, (int)blocks, out, c->stream));
     return MC_LYA_OK;
 }
 

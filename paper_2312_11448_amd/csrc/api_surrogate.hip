@@ -113,7 +113,9 @@ mc_lya_status mc_lya_mlp_create(mc_lya_mlp **out, const float *params, void *str
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cu = prop.multiProcessorCount;
     }
-    m->forward_grid = cu * 8;
+    // one wave per SIMD per resident workgroup, each wave looping over its
+    // tiles: a grid the chip holds at once has no partly filled last round
+    m->forward_grid = cu * mlp_forward_blocks_per_cu();
     *out = m;
     return MC_LYA_OK;
 }

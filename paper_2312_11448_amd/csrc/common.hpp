@@ -342,6 +342,7 @@ struct FeatBox {
     int32_t nx, ny, nz;
     uint32_t cell_off, ncells;
     int32_t vel_dtype;
+    int32_t quad;            // 1: four cells along x per thread (nx % 4 == 0, fields 16-byte aligned)
     const float *od;
     const void *vel;
     const float *xe;
@@ -364,6 +365,8 @@ hipError_t launch_features(const FeatBox *fb_dev, int n_boxes, int max_blk, floa
 hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, float *y, uint8_t *outside,
                               const float *lo, const float *hi, unsigned long long *n_out, int grid,
                               hipStream_t s);
+// workgroups of the inference kernel that one compute unit holds at once
+int mlp_forward_blocks_per_cu();
 // partial: [max_blocks + ceil(max_blocks / 32)][kMlpPartStride] floats of workspace
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,
                                float *partial, int max_blocks, float *grad, hipStream_t s);

@@ -31,34 +31,58 @@ __device__ __forceinline__ float step(float z) { return z > 0.0f ? 1.0f : 0.0f; 
 // ln(<Delta^2> / <Delta>^2) = ln(1 + b) (Sec. II.C, Eq. (clumpingfactor)): in
 // the no-mixing limit M_c = S_c sum(n_1s) / (n_1s,c sum(S)), which carries
 // that box-wide ratio.
-__device__ __forceinline__ float vel_at(const FeatBox &fb, int comp, uint32_t i)
+// A load through the global (not flat) memory path at a byte offset from a
+// base held in scalar registers. With 32-bit offsets (boxes of at most 2^30
+// cells) each neighbour costs one add.
+template <typename T, typename Off>
+__device__ __forceinline__ T load_at(const void *base, Off byte_off)
 {
-    const size_t k = (size_t)comp * fb.ncells + i;
-    if (fb.vel_dtype == MC_LYA_VEL_F32) return static_cast<const float *>(fb.vel)[k];
-    return (float)static_cast<const _Float16 *>(fb.vel)[k];
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) T gT;
+    return *(gT *)((gchar *)base + (uint64_t)byte_off);
 }
 
-__global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict__ fbs, float *__restrict__ out)
+// div U by central differences, from velocity components stored as V
+// (component c starts c * ncells elements in; FP16 elements are half as far
+// apart as the 4-byte offsets given)
+template <typename V, typename Off>
+__device__ __forceinline__ float divergence(const FeatBox &fb, const Off (&xo)[3], const Off (&yo)[3],
+                                            const Off (&zo)[3])
 {
-    const FeatBox fb = fbs[blockIdx.y];
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= fb.ncells) return;
-    const int nx = fb.nx, ny = fb.ny, nz = fb.nz;
-    const int ix = (int)(i % (uint32_t)nx), iy = (int)((i / (uint32_t)nx) % (uint32_t)ny),
-              iz = (int)(i / ((uint32_t)nx * (uint32_t)ny));
-    int xs[3], ys[3], zs[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        xs[d] = ix + d - 1 < 0 ? nx - 1 : (ix + d - 1 == nx ? 0 : ix + d - 1);
-        ys[d] = iy + d - 1 < 0 ? ny - 1 : (iy + d - 1 == ny ? 0 : iy + d - 1);
-        zs[d] = iz + d - 1 < 0 ? nz - 1 : (iz + d - 1 == nz ? 0 : iz + d - 1);
-    }
+    const char *vb = static_cast<const char *>(fb.vel);
+    auto vel = [&](int comp, Off off) -> float {
+        const void *base = vb + (uint64_t)comp * fb.ncells * sizeof(V);
+        return (float)load_at<V>(base, (Off)(off / (4 / sizeof(V))));
+    };
+    return 0.5f * (vel(0, xo[2] + yo[1] + zo[1]) - vel(0, xo[0] + yo[1] + zo[1])) +
+           0.5f * (vel(1, xo[1] + yo[2] + zo[1]) - vel(1, xo[1] + yo[0] + zo[1])) +
+           0.5f * (vel(2, xo[1] + yo[1] + zo[2]) - vel(2, xo[1] + yo[1] + zo[0]));
+}
+
+template <typename Off>
+__device__ __forceinline__ void features_cell(const FeatBox &fb, uint32_t i, float *__restrict__ out)
+{
+    const uint32_t nx = (uint32_t)fb.nx, ny = (uint32_t)fb.ny, nz = (uint32_t)fb.nz;
+    const uint32_t ix = i % nx, r = i / nx, iy = r % ny, iz = r / ny;
+    const Off sx = (Off)nx * 4u, sxy = (Off)nx * ny * 4u;
+    // byte offsets (4-byte elements) of the columns, rows and planes around
+    // the cell, periodic: index 0 is the lower neighbour, 2 the upper
+    Off xo[3], yo[3], zo[3];
+    xo[0] = (Off)(ix == 0 ? nx - 1 : ix - 1) * 4u;
+    xo[1] = (Off)ix * 4u;
+    xo[2] = (Off)(ix + 1 == nx ? 0 : ix + 1) * 4u;
+    yo[0] = (Off)(iy == 0 ? ny - 1 : iy - 1) * sx;
+    yo[1] = (Off)iy * sx;
+    yo[2] = (Off)(iy + 1 == ny ? 0 : iy + 1) * sx;
+    zo[0] = (Off)(iz == 0 ? nz - 1 : iz - 1) * sxy;
+    zo[1] = (Off)iz * sxy;
+    zo[2] = (Off)(iz + 1 == nz ? 0 : iz + 1) * sxy;
     float v[27];
     float s = 0.0f;
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
         const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;
-        v[k] = fb.od[(size_t)xs[dx] + (size_t)nx * ((size_t)ys[dy] + (size_t)ny * (size_t)zs[dz])];
+        v[k] = load_at<float>(fb.od, xo[dx] + yo[dy] + zo[dz]);
         s += v[k];
     }
     const float mean = s / 27.0f;
@@ -66,17 +90,154 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict
 #pragma unroll
     for (int k = 0; k < 27; ++k) ss += (v[k] - mean) * (v[k] - mean);
     float div = 0.0f;
-    if (fb.vel_dtype != MC_LYA_VEL_NONE) {
-        const uint32_t sx = (uint32_t)nx, sxy = (uint32_t)nx * (uint32_t)ny;
-        auto at = [&](int x, int y, int z) { return (uint32_t)x + sx * (uint32_t)y + sxy * (uint32_t)z; };
-        div = 0.5f * (vel_at(fb, 0, at(xs[2], iy, iz)) - vel_at(fb, 0, at(xs[0], iy, iz))) +
-              0.5f * (vel_at(fb, 1, at(ix, ys[2], iz)) - vel_at(fb, 1, at(ix, ys[0], iz))) +
-              0.5f * (vel_at(fb, 2, at(ix, iy, zs[2])) - vel_at(fb, 2, at(ix, iy, zs[0])));
-    }
-    const float xe = fb.xe ? fb.xe[i] : fb.xe_uniform;
+    if (fb.vel_dtype == MC_LYA_VEL_F32)
+        div = divergence<float>(fb, xo, yo, zo);
+    else if (fb.vel_dtype == MC_LYA_VEL_F16)
+        div = divergence<_Float16>(fb, xo, yo, zo);
+    const float xe = fb.xe ? load_at<float>(fb.xe, xo[1] + yo[1] + zo[1]) : fb.xe_uniform;
     float4 *o = reinterpret_cast<float4 *>(out + ((size_t)fb.cell_off + i) * kFeat);
     o[0] = make_float4(logf(v[13]), mean, ss / 27.0f, div);
     o[1] = make_float4(fb.ln_t, xe, fb.z_feat, fb.ln_clump);
+}
+
+// 4 consecutive elements of type V at a byte offset, as float
+template <typename V, typename Off>
+__device__ __forceinline__ void load4(const void *base, Off byte_off, float *o)
+{
+    typedef V v4 __attribute__((ext_vector_type(4)));
+    const v4 a = load_at<v4>(base, byte_off);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = (float)a[e];
+}
+
+// div U of four cells x..x+3 of one row (xm, x0, xp: byte offsets of x - 1,
+// x and x + 4, periodic), with the same central differences as above
+template <typename V, typename Off>
+__device__ __forceinline__ void divergence4(const FeatBox &fb, Off xm, Off x0, Off xp, const Off (&yo)[3],
+                                            const Off (&zo)[3], float (&dv)[4])
+{
+    const char *vb = static_cast<const char *>(fb.vel);
+    const uint64_t comp = (uint64_t)fb.ncells * sizeof(V);
+    constexpr Off div_off = 4 / sizeof(V);
+    const Off row = yo[1] + zo[1];
+    float vx[6], yp[4], ym[4], zp[4], zm[4];
+    vx[0] = (float)load_at<V>(vb, (Off)((row + xm) / div_off));
+    load4<V>(vb, (Off)((row + x0) / div_off), &vx[1]);
+    vx[5] = (float)load_at<V>(vb, (Off)((row + xp) / div_off));
+    load4<V>(vb + comp, (Off)((yo[2] + zo[1] + x0) / div_off), yp);
+    load4<V>(vb + comp, (Off)((yo[0] + zo[1] + x0) / div_off), ym);
+    load4<V>(vb + 2 * comp, (Off)((yo[1] + zo[2] + x0) / div_off), zp);
+    load4<V>(vb + 2 * comp, (Off)((yo[1] + zo[0] + x0) / div_off), zm);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        dv[c] = 0.5f * (vx[c + 2] - vx[c]) + 0.5f * (yp[c] - ym[c]) + 0.5f * (zp[c] - zm[c]);
+}
+
+// The same features for four cells along x (nx a multiple of 4): each of the
+// 9 rows around them is read as one 16-byte load plus the cells beyond its
+// two ends, 27 + 7 loads for four cells where one cell at a time takes 33
+// each. The sums run in the same order as for one cell.
+template <typename Off>
+__device__ __forceinline__ void features_quad(const FeatBox &fb, uint32_t q, float4 *__restrict__ stage)
+{
+    const uint32_t nx = (uint32_t)fb.nx, ny = (uint32_t)fb.ny, nz = (uint32_t)fb.nz;
+    const uint32_t i = 4u * q;
+    const uint32_t ix = i % nx, r = i / nx, iy = r % ny, iz = r / ny;
+    const Off sx = (Off)nx * 4u, sxy = (Off)nx * ny * 4u;
+    const Off xm = (Off)(ix == 0 ? nx - 1 : ix - 1) * 4u, x0 = (Off)ix * 4u,
+              xp = (Off)(ix + 4 == nx ? 0 : ix + 4) * 4u;
+    Off yo[3], zo[3];
+    yo[0] = (Off)(iy == 0 ? ny - 1 : iy - 1) * sx;
+    yo[1] = (Off)iy * sx;
+    yo[2] = (Off)(iy + 1 == ny ? 0 : iy + 1) * sx;
+    zo[0] = (Off)(iz == 0 ? nz - 1 : iz - 1) * sxy;
+    zo[1] = (Off)iz * sxy;
+    zo[2] = (Off)(iz + 1 == nz ? 0 : iz + 1) * sxy;
+    // w[3 dz + dy][j]: Delta at x - 1 + j of the row (dy, dz)
+    float w[9][6];
+#pragma unroll
+    for (int rw = 0; rw < 9; ++rw) {
+        const Off row = yo[rw % 3] + zo[rw / 3];
+        w[rw][0] = load_at<float>(fb.od, row + xm);
+        load4<float>(fb.od, row + x0, &w[rw][1]);
+        w[rw][5] = load_at<float>(fb.od, row + xp);
+    }
+    float dv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (fb.vel_dtype == MC_LYA_VEL_F32)
+        divergence4<float>(fb, xm, x0, xp, yo, zo, dv);
+    else if (fb.vel_dtype == MC_LYA_VEL_F16)
+        divergence4<_Float16>(fb, xm, x0, xp, yo, zo, dv);
+    float xe[4];
+    if (fb.xe)
+        load4<float>(fb.xe, yo[1] + zo[1] + x0, xe);
+    else
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xe[c] = fb.xe_uniform;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float v[27];
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            const int dz = k / 9, dy = (k / 3) % 3, dx = k % 3;
+            v[k] = w[3 * dz + dy][c + dx];
+            s += v[k];
+        }
+        const float mean = s / 27.0f;
+        float ss = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 27; ++k) ss += (v[k] - mean) * (v[k] - mean);
+        stage[2 * c] = make_float4(logf(v[13]), mean, ss / 27.0f, dv[c]);
+        stage[2 * c + 1] = make_float4(fb.ln_t, xe[c], fb.z_feat, fb.ln_clump);
+    }
+}
+
+// One thread per cell, or per four cells along x. Workgroups go round-robin
+// to the chip's 8 XCDs; when a box's block count is a multiple of 8 its
+// blocks are dealt so that each XCD takes a contiguous run of them (a slab of
+// the box), whose neighbour rows and planes its own L2 then holds.
+__global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict__ fbs, float *__restrict__ out)
+{
+    // a wave's 256 cells of output (8 KB), written out contiguously (rows of
+    // 9 for 8 values, so that the lanes' writes spread over the banks)
+    __shared__ float4 s_out[4][64 * 9];
+    const FeatBox fb = fbs[blockIdx.y];
+    const uint32_t threads = fb.quad ? fb.ncells / 4u : fb.ncells;
+    const uint32_t need = (threads + 255u) / 256u, bx = blockIdx.x;
+    if (bx >= need) return;
+    const uint32_t blk = need % 8u == 0 ? (bx % 8u) * (need / 8u) + bx / 8u : bx;
+    const uint32_t t = blk * 256u + threadIdx.x;
+    const bool narrow = fb.ncells <= (1u << 30);
+    if (fb.quad) {
+        const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const uint32_t t0 = t - lane;                  // the wave's first thread
+        if (t0 >= threads) return;
+        if (t < threads) {
+            if (narrow)
+                features_quad<uint32_t>(fb, t, &s_out[wv][9 * lane]);
+            else
+                features_quad<uint64_t>(fb, t, &s_out[wv][9 * lane]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t n16 = 8u * (threads - t0 < 64u ? threads - t0 : 64u);   // 16-byte chunks to write
+        float4 *o = reinterpret_cast<float4 *>(out + ((size_t)fb.cell_off + 4u * (size_t)t0) * kFeat);
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint32_t k = 64u * j + lane;
+            if (k < n16) o[k] = s_out[wv][9 * (k / 8u) + k % 8u];
+        }
+        return;
+    }
+    if (t >= threads) return;
+    {
+        if (narrow)
+            features_cell<uint32_t>(fb, t, out);
+        else
+            features_cell<uint64_t>(fb, t, out);
+    }
 }
 
 // ---- the network on the matrix cores ----------------------------------------
@@ -188,13 +349,34 @@ __device__ __forceinline__ bf16x8 feature_operand(const float (&x)[kFeat], int h
     return ones_pair(true);
 }
 
-// h1 = relu(D1) as the four K steps of layer 2
+// (bf16(a), bf16(b)) in one register, a in the low half
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+// h1 = relu(D1) as the four K steps of layer 2. Rounding to BF16 keeps the
+// sign, so the ReLU is taken after it, on two BF16 values at once read as
+// 16-bit integers (a set sign bit makes a negative integer, which becomes 0):
+// the same values as rounding relu(D1), in half the instructions.
 __device__ __forceinline__ void hidden_operand(const f32x16 (&d1)[2], bf16x8 (&h1)[4])
 {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
+        u32x4 u;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) h1[s][e] = (__bf16)relu(d1[s / 2][l1_reg(s, e)]);
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t v = bf16_pair(d1[s / 2][l1_reg(s, 2 * p)], d1[s / 2][l1_reg(s, 2 * p + 1)]);
+            u[p] = __builtin_bit_cast(uint32_t,
+                                      __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), (s16x2){0, 0}));
+        }
+        h1[s] = __builtin_bit_cast(bf16x8, u);
+    }
 }
 
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restrict__ P, const float *__restrict__ X,
@@ -205,53 +387,75 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
                                                           unsigned long long *__restrict__ n_out)
 {
     __shared__ unsigned long long s_cnt;
+    // w3 in the order of the layer-2 result registers: [T][lane half][r]
+    __shared__ float4 s_w3[2][2][4];
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
     if (threadIdx.x == 0) s_cnt = 0;
+    if (threadIdx.x < 64) {
+        const int T = threadIdx.x >> 5, h = (threadIdx.x >> 4) & 1, r = threadIdx.x & 15;
+        reinterpret_cast<float *>(&s_w3[T][h][0])[r] = P[OFF_W3 + 32 * T + d_row(r, h)];
+    }
     NetOps o;
     load_ops(P, half, col, o);
     const bf16x8 ones = ones_pair(half == 0);
-    float w3r[2][16];
-#pragma unroll
-    for (int T = 0; T < 2; ++T)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) w3r[T][r] = P[OFF_W3 + 32 * T + d_row(r, half)];
     const float b3 = P[OFF_B3];
     float flo[kFeat], fhi[kFeat];
 #pragma unroll
     for (int e = 0; e < kFeat; ++e) {
-        flo[e] = lo ? lo[e] : -3.0e38f;
-        fhi[e] = hi ? hi[e] : 3.0e38f;
+        flo[e] = lo ? lo[e] : 0.0f;
+        fhi[e] = lo ? hi[e] : 0.0f;
     }
     __syncthreads();
+    // the wave's tiles are uniform: the loop and the tile's addresses stay
+    // in scalar registers
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const uint64_t wave =
+        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
     const uint64_t tiles = (n + 31) / 32;
     uint32_t n_outside = 0;
-    // lane half 0 loads the cell's 8 features; the next tile's while this
-    // one is computed
-    auto load = [&](uint64_t tile, float (&x)[kFeat]) {
-        const uint64_t cell = tile * 32 + (uint64_t)col;
-        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
-        if (half == 0 && cell < n) {
-            a = *reinterpret_cast<const float4 *>(X + cell * kFeat);
-            b = *reinterpret_cast<const float4 *>(X + cell * kFeat + 4);
-        }
-        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    // Lane half 0 reads its cell's 8 features through a buffer view of the
+    // tile's rows, which gives 0 for a row past the last cell; half 1 reads
+    // past the view (zeros) and ORs in the pair (1, 1) that meets the b1 pair.
+    // The next tile's features are loaded as soon as this tile's are rounded.
+    const uint32_t voff = half == 0 ? 32u * (uint32_t)col : 1024u;
+    const uint32_t ones_bits = half == 0 ? 0u : 0x3f803f80u;
+    // rows of the tile starting at cell `first` (0 past the end)
+    auto rows_at = [&](uint64_t first) -> uint32_t {
+        return first < n ? (uint32_t)(n - first < 32 ? n - first : 32) : 0u;
     };
-    float next[kFeat];
-    load(wave, next);
-    for (uint64_t tile = wave; tile < tiles; tile += waves) {
-        const uint64_t cell = tile * 32 + (uint64_t)col;
-        const bool valid = cell < n;
-        float x[kFeat];
+    auto load = [&](uint64_t tile, float (&x)[kFeat]) {
+        const uint64_t first = tile * 32;
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(X + first * kFeat), (short)0, (int)(rows_at(first) * 32u), 0x00020000);
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0);
+        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff + 16, 0, 0);
 #pragma unroll
-        for (int e = 0; e < kFeat; ++e) x[e] = next[e];
+        for (int e = 0; e < 4; ++e) {
+            x[e] = __builtin_bit_cast(float, (uint32_t)a[e]);
+            x[4 + e] = __builtin_bit_cast(float, (uint32_t)b[e]);
+        }
+    };
+    // one tile from the features in x, loading those of tile + waves into
+    // `next` (two register sets taken in turn, so nothing is copied)
+    auto step = [&](uint64_t tile, const float (&x)[kFeat], float (&next)[kFeat]) {
+        const uint64_t first = tile * 32;
+        const uint32_t rows = rows_at(first);
+        // the lanes whose features leave the envelope, as a wave mask taken
+        // now, so that the features are not kept to the store (none without
+        // an envelope)
+        uint64_t env = 0;
+        if (lo) {
+            bool out_env = false;
+#pragma unroll
+            for (int e = 0; e < kFeat; ++e) out_env |= (x[e] < flo[e]) | (x[e] > fhi[e]);
+            env = __ballot(out_env);
+        }
+        u32x4 bu;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) bu[p] = bf16_pair(x[2 * p], x[2 * p + 1]);
+        bu[0] |= ones_bits;
+        const bf16x8 bx = __builtin_bit_cast(bf16x8, bu);
         load(tile + waves, next);
-        int out_env = 0;
-#pragma unroll
-        for (int e = 0; e < kFeat; ++e) out_env |= (x[e] < flo[e]) | (x[e] > fhi[e]);
-        const bf16x8 bx = feature_operand(x, half);
         f32x16 d1[2];
 #pragma unroll
         for (int T = 0; T < 2; ++T) d1[T] = mfma16(o.a1[T], bx, zero16());
@@ -268,18 +472,30 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
 #pragma unroll
         for (int T = 0; T < 2; ++T)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) part += w3r[T][r] * relu(d2[T][r]);
+            for (int q = 0; q < 4; ++q) {
+                const float4 w = s_w3[T][half][q];
+                part += w.x * relu(d2[T][4 * q]);
+                part += w.y * relu(d2[T][4 * q + 1]);
+                part += w.z * relu(d2[T][4 * q + 2]);
+                part += w.w * relu(d2[T][4 * q + 3]);
+            }
         part += __shfl_xor(part, 32, 64);
-        if (half == 0 && valid) {
-            y[cell] = part + b3;
-            if (outside) outside[cell] = (uint8_t)out_env;
-            n_outside += (uint32_t)out_env;
+        if (half == 0 && (uint32_t)col < rows) {
+            y[first + (uint32_t)col] = part + b3;
+            if (outside) outside[first + (uint32_t)col] = (uint8_t)((env >> col) & 1u);
         }
+        n_outside += (uint32_t)__popcll(env & (rows < 32 ? (1ull << rows) - 1ull : 0xffffffffull));
+    };
+    float xa[kFeat], xb[kFeat];
+    load(wave, xa);
+    for (uint64_t tile = wave; tile < tiles; tile += 2 * waves) {
+        step(tile, xa, xb);
+        if (tile + waves >= tiles) break;
+        step(tile + waves, xb, xa);
     }
     if (n_out) {
-        unsigned long long c = n_outside;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+        // n_outside is the wave's count
+        const unsigned long long c = n_outside;
         if (lane == 0 && c) atomicAdd(&s_cnt, c);
         __syncthreads();
         if (threadIdx.x == 0 && s_cnt) atomicAdd(n_out, s_cnt);
@@ -642,6 +858,13 @@ hipError_t launch_mlp_forward(const float *params, const float *X, uint64_t n, f
     hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)grid), dim3(256), 0, s, params, X, n, y, outside, lo, hi,
                        n_out);
     return hipGetLastError();
+}
+
+int mlp_forward_blocks_per_cu()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mlp_forward_kernel, 256, 0) != hipSuccess || b < 1) b = 1;
+    return b;
 }
 
 hipError_t launch_mlp_gradient(const float *params, const float *X, const float *t, const float *w, uint64_t n,

@@ -45,11 +45,13 @@ def _box_features_oracle(spec):
     return S.features(spec.overdensity, spec.velocity, np.float32(spec.x_e_uniform), spec.temp_K, spec.z)
 
 
-@pytest.mark.parametrize("shape,vel", [((24, 24, 24), True), ((9, 13, 7), True), ((16, 8, 5), False)])
+@pytest.mark.parametrize("shape,vel", [((24, 24, 24), True), ((9, 13, 7), True), ((16, 8, 5), False),
+                                       ((11, 6, 10), "f16"), ((1, 1, 3), True), ((300, 2, 3), "f16")])
 def test_features_match_oracle(shape, vel):
     rng = np.random.default_rng(sum(shape))
     od = rng.lognormal(0.0, 0.7, size=shape[::-1]).astype(np.float32)
-    v = rng.normal(0.0, 0.2, size=(3,) + shape[::-1]).astype(np.float32) if vel else None
+    v = rng.normal(0.0, 0.2, size=(3,) + shape[::-1]).astype(np.float16 if vel == "f16" else np.float32) \
+        if vel else None
     spec = W.BoxSpec(n=shape, overdensity=od, velocity=v, z=950.0, temp_K=2.7255 * 951, n_packets=1)
     with M.Simulation(spec) as sim:
         f = sim.features().cpu().numpy().astype(np.float64)
@@ -58,6 +60,20 @@ def test_features_match_oracle(shape, vel):
     err = np.abs(f - ref) / scale
     _say(f"  worst feature error / scale: {err.max(axis=0)}")
     assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(13, 5, 9), (12, 5, 9), (4, 1, 1)])
+def test_features_with_a_per_cell_electron_fraction(shape):
+    rng = np.random.default_rng(8)
+    od = rng.lognormal(0.0, 0.5, size=shape[::-1]).astype(np.float32)
+    xe = rng.uniform(0.0, 1.2, size=shape[::-1]).astype(np.float32)
+    v = rng.normal(0.0, 0.2, size=(3,) + shape[::-1]).astype(np.float32)
+    spec = W.BoxSpec(n=shape, overdensity=od, velocity=v, x_e=xe, z=1000.0, temp_K=2.7255 * 1001, n_packets=1)
+    with M.Simulation(spec) as sim:
+        f = sim.features().cpu().numpy().astype(np.float64)
+    ref = S.features(spec.overdensity, spec.velocity, spec.x_e, spec.temp_K, spec.z)
+    assert np.array_equal(f[:, 5], ref[:, 5])            # x_e itself, unchanged
+    assert np.abs(f - ref).max() <= 1e-5 * max(1.0, ref[:, 1].max() ** 2)
 
 
 def test_features_of_a_batch_are_per_box():
@@ -160,6 +176,29 @@ def test_forward_sampled_at_256cube_size():
     got = flags.cpu().numpy().astype(bool)
     assert np.array_equal(got, want) and count == int(want.sum())
     _say(f"  {count} of {spec.ncells} cells outside the envelope")
+
+
+@pytest.mark.parametrize("n", [1, 33, 5000])
+def test_flags_follow_the_envelope_and_its_clearing(n):
+    """No envelope flags nothing; an envelope flags exactly the cells a plain
+    float32 comparison puts outside, ragged tiles included; clearing it
+    flags nothing again. y does not depend on the envelope."""
+    rng = np.random.default_rng(n + 5)
+    X = rng.normal(0.0, 1.0, size=(n, 8)).astype(np.float32)
+    lo = np.full(8, -1.5, np.float32)
+    hi = np.full(8, 1.5, np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    with M.Mlp(_test_params(3)) as mlp:
+        y0, f0, c0 = mlp.forward(Xd, outside=True, count=True)
+        mlp.set_envelope(lo, hi)
+        y1, f1, c1 = mlp.forward(Xd, outside=True, count=True)
+        mlp.set_envelope(None, None)
+        y2, f2, c2 = mlp.forward(Xd, outside=True, count=True)
+    want = np.any((X < lo) | (X > hi), axis=1)
+    assert c0 == 0 and not f0.cpu().numpy().any()
+    assert np.array_equal(f1.cpu().numpy().astype(bool), want) and c1 == int(want.sum())
+    assert c2 == 0 and not f2.cpu().numpy().any()
+    assert torch.equal(y0, y1) and torch.equal(y0, y2)
 
 
 def _train_data(n, seed):
