@@ -149,6 +149,8 @@ struct mc_lya_ctx {
     std::vector<uint64_t> seg_host;          // packet segments of the persistent part: starts, then ids
     std::vector<FeatBox> featbox;            // surrogate features: per-box inputs
     FeatBox *d_featbox = nullptr;
+    bool featbox_stale = true;               // rebuilt and uploaded after each refresh
+    int feat_blocks = 1;                     // grid width of the features launch
     uint64_t *d_seg = nullptr;               // [2 (n_boxes + 1)]
     int tile_share = 100;
     int defer = 16;                          // MC_LYA_OPT_DEFER
@@ -303,6 +305,7 @@ mc_lya_status do_refresh(mc_lya_ctx *c)
                                  c->d_part, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->red.data(), c->d_red, sizeof(BoxRed) * nb, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->featbox_stale = true;                 // the box clumping comes from these sums
     for (int b = 0; b < nb; ++b) {
         const uint32_t f = c->red[b].flags;
         if (f) {
@@ -1209,13 +1212,13 @@ mc_lya_status mc_lya_tally(mc_lya_ctx *c, int64_t *absorbed, int64_t *emitted, m
     return MC_LYA_OK;
 }
 
-mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
+// The per-box table of the features kernel, from the descriptors and the
+// sums of the last refresh; uploaded once per refresh.
+static hipError_t build_featbox(mc_lya_ctx *c)
 {
-    if (!c) return MC_LYA_EINVAL;
-    if (!out) return fail(c, MC_LYA_EINVAL, "out is NULL");
-    if (c->state < 0) return fail(c, MC_LYA_ESTATE, "fields failed validation; call mc_lya_refresh");
     const int nb = c->n_boxes;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));      // the previous table may still be in flight
+    hipError_t e = hipStreamSynchronize(c->stream);      // the previous table may still be in flight
+    if (e != hipSuccess) return e;
     c->featbox.resize(nb);
     uint64_t blocks = 1;
     for (int b = 0; b < nb; ++b) {
@@ -1245,9 +1248,21 @@ mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
         const uint64_t threads = f.quad ? f.ncells / 4u : f.ncells;
         blocks = std::max<uint64_t>(blocks, (threads + 255) / 256);
     }
-    HIP_TRY(c, hipMemcpyAsync(c->d_featbox, c->featbox.data(), sizeof(FeatBox) * nb, hipMemcpyHostToDevice,
-                              c->stream));
-    HIP_TRY(c, launch_features(c->d_featbox, nb, (int)blocks, out, c->stream));
+    e = hipMemcpyAsync(c->d_featbox, c->featbox.data(), sizeof(FeatBox) * nb, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    c->feat_blocks = (int)blocks;
+    c->featbox_stale = false;
+    return hipSuccess;
+}
+
+mc_lya_status mc_lya_features(mc_lya_ctx *c, float *out)
+{
+    if (!c) return MC_LYA_EINVAL;
+    if (!out) return fail(c, MC_LYA_EINVAL, "out is NULL");
+    if (c->state < 0) return fail(c, MC_LYA_ESTATE, "fields failed validation; call mc_lya_refresh");
+    const int nb = c->n_boxes;
+    if (c->featbox_stale) HIP_TRY(c, build_featbox(c));
+    HIP_TRY(c, launch_features(c->d_featbox, nb, c->feat_blocks, out, c->stream));
     return MC_LYA_OK;
 }
 

@@ -59,6 +59,15 @@ __device__ __forceinline__ float divergence(const FeatBox &fb, const Off (&xo)[3
            0.5f * (vel(2, xo[1] + yo[1] + zo[2]) - vel(2, xo[1] + yo[1] + zo[0]));
 }
 
+// A store that streams past the caches: the 32 bytes a cell's features take
+// are read back only by a later kernel, and keeping them out of L2 leaves it
+// to the neighbour rows this kernel reads again and again.
+__device__ __forceinline__ void store_stream(float4 *p, float4 v)
+{
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(__builtin_bit_cast(f32x4, v), reinterpret_cast<f32x4 *>(p));
+}
+
 template <typename Off>
 __device__ __forceinline__ void features_cell(const FeatBox &fb, uint32_t i, float *__restrict__ out)
 {
@@ -96,8 +105,8 @@ __device__ __forceinline__ void features_cell(const FeatBox &fb, uint32_t i, flo
         div = divergence<_Float16>(fb, xo, yo, zo);
     const float xe = fb.xe ? load_at<float>(fb.xe, xo[1] + yo[1] + zo[1]) : fb.xe_uniform;
     float4 *o = reinterpret_cast<float4 *>(out + ((size_t)fb.cell_off + i) * kFeat);
-    o[0] = make_float4(logf(v[13]), mean, ss / 27.0f, div);
-    o[1] = make_float4(fb.ln_t, xe, fb.z_feat, fb.ln_clump);
+    store_stream(&o[0], make_float4(logf(v[13]), mean, ss / 27.0f, div));
+    store_stream(&o[1], make_float4(fb.ln_t, xe, fb.z_feat, fb.ln_clump));
 }
 
 // 4 consecutive elements of type V at a byte offset, as float
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatBox *__restrict
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) {
             const uint32_t k = 64u * j + lane;
-            if (k < n16) o[k] = s_out[wv][9 * (k / 8u) + k % 8u];
+            if (k < n16) store_stream(&o[k], s_out[wv][9 * (k / 8u) + k % 8u]);
         }
         return;
     }

@@ -76,6 +76,29 @@ def test_features_with_a_per_cell_electron_fraction(shape):
     assert np.abs(f - ref).max() <= 1e-5 * max(1.0, ref[:, 1].max() ** 2)
 
 
+def test_features_follow_new_fields_after_a_refresh():
+    """The per-box table (pointers, box clumping) is uploaded once per
+    refresh: features taken twice agree bit for bit, and after new field
+    contents are loaded they are those of the new fields."""
+    shape = (16, 12, 8)
+    rng = np.random.default_rng(21)
+    specs = []
+    for sig in (0.4, 1.1):
+        od = rng.lognormal(0.0, sig, size=shape[::-1]).astype(np.float32)
+        v = rng.normal(0.0, 0.2, size=(3,) + shape[::-1]).astype(np.float32)
+        specs.append(W.BoxSpec(n=shape, overdensity=od, velocity=v, z=1000.0, temp_K=2.7255 * 1001, n_packets=1))
+    with M.Simulation(specs[0]) as sim:
+        f0 = sim.features().cpu().numpy()
+        f0b = sim.features().cpu().numpy()
+        sim.load_fields(specs[1])
+        f1 = sim.features().cpu().numpy().astype(np.float64)
+    assert np.array_equal(f0, f0b)
+    for f, spec in ((f0.astype(np.float64), specs[0]), (f1, specs[1])):
+        ref = _box_features_oracle(spec)
+        assert np.abs(f - ref).max() <= 1e-5 * max(1.0, ref[:, 1].max() ** 2)
+    assert f1[0, 7] != f0[0, 7]          # the box clumping moved with the field
+
+
 def test_features_of_a_batch_are_per_box():
     boxes = [W.make_box("c2", n=12, field_seed=3), W.make_box("c1", n=10)]
     boxes[1].z = 1250.0
