@@ -89,10 +89,20 @@ def train(mlp, data, steps=3000, batch=65536, lr=3e-3, lr_final=3e-4, seed=0, lo
     gen = torch.Generator(device="cpu")
     gen.manual_seed(int(seed))
     n = idx_all.numel()
+    b = min(batch, n)
+    # the draws of many steps at once (the same sequence as one draw per
+    # step), copied from pinned memory without waiting: the steps then queue
+    # on the stream with no synchronisation unless a loss is asked for
+    chunk = max(1, min(steps, (1 << 24) // b))
     losses = []
+    picks = None
     for s in range(steps):
-        pick = torch.randint(0, n, (min(batch, n),), generator=gen).to(idx_all.device)
-        idx = idx_all[pick]
+        if s % chunk == 0:
+            k = min(chunk, steps - s)
+            picks = torch.randint(0, n, (k, b), generator=gen)
+            if idx_all.is_cuda:
+                picks = picks.pin_memory().to(idx_all.device, non_blocking=True)
+        idx = idx_all[picks[s % chunk]]
         X = data["features"][idx].contiguous()
         t = data["y"][idx].contiguous()
         w = data["w"][idx].contiguous()
