@@ -570,6 +570,27 @@ mc_lya_status mc_lya_mlp_train_step(mc_lya_mlp *mlp, const float *features, cons
                                     const float *weights, uint64_t n, const mc_lya_adam *hp,
                                     float *loss);
 
+/* n_steps training steps in one call, each the same as mc_lya_mlp_train_step
+ * on the mini-batch that an index array picks from a training set, queued
+ * step after step with no synchronisation between them (for callers that
+ * would otherwise spend more time issuing the steps than the device takes
+ * to run them).
+ *   features, targets, weights  dev [n_cells][8], [n_cells], [n_cells] float:
+ *             the training set
+ *   idx       dev [n_steps][batch] int64: step s trains on cells
+ *             idx[s][0..batch), each in [0, n_cells)
+ *   lr        host [n_steps] learning rates (> 0); beta1, beta2, eps as in
+ *             mc_lya_adam
+ *   losses    host [n_steps] (each step's loss before its update), or NULL
+ * The object allocates a gather buffer of batch cells (kept, grown when a
+ * larger batch comes). Synchronises once, at the end; an index outside
+ * [0, n_cells) is then reported as EINVAL (the steps have been taken with
+ * such cells read as cell 0). Errors: EINVAL, ENOMEM, EDEVICE. */
+mc_lya_status mc_lya_mlp_train_steps(mc_lya_mlp *mlp, const float *features, const float *targets,
+                                     const float *weights, uint64_t n_cells, const int64_t *idx, uint64_t batch,
+                                     int n_steps, const float *lr, float beta1, float beta2, float eps,
+                                     float *losses);
+
 /* For callers that cannot allocate device memory (work being captured into a
  * HIP graph, tight serving or training loops, harnesses that forbid
  * hipMalloc): mc_lya_mlp_gradient without a network object and without any

@@ -93,7 +93,7 @@ EXPORTS = ["mc_lya_init", "mc_lya_refresh", "mc_lya_emit", "mc_lya_transport",
            "mc_lya_probe_read",
            "mc_lya_destroy", "mc_lya_strerror", "mc_lya_last_error",
            "mc_lya_features", "mc_lya_surrogate_targets", "mc_lya_mlp_create", "mc_lya_mlp_get_params",
-           "mc_lya_mlp_set_envelope", "mc_lya_mlp_forward", "mc_lya_mlp_correction", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_destroy",
+           "mc_lya_mlp_set_envelope", "mc_lya_mlp_forward", "mc_lya_mlp_correction", "mc_lya_mlp_gradient", "mc_lya_mlp_train_step", "mc_lya_mlp_train_steps", "mc_lya_mlp_destroy",
            "mc_lya_mlp_last_error", "mc_lya_mlp_gradient_static", "mc_lya_mlp_static_last_error"]
 # the static workspace of mc_lya_mlp_gradient_static (mc_lya.h)
 MC_LYA_STATIC_MAX_CELLS = (1 << 40) - 1
@@ -162,6 +162,8 @@ def load():
     L.mc_lya_mlp_forward.argtypes = [vp, vp, u64, vp, vp, P(u64)]
     L.mc_lya_mlp_gradient.argtypes = [vp, vp, vp, vp, u64, fp, fp]
     L.mc_lya_mlp_train_step.argtypes = [vp, vp, vp, vp, u64, P(mc_lya_adam), fp]
+    L.mc_lya_mlp_train_steps.argtypes = [vp, vp, vp, vp, u64, vp, u64, C.c_int, fp, C.c_float, C.c_float, C.c_float,
+                                         fp]
     L.mc_lya_mlp_destroy.argtypes = [vp]
     L.mc_lya_mlp_destroy.restype = None
     L.mc_lya_mlp_last_error.argtypes = [vp]
@@ -365,6 +367,16 @@ def mc_lya_mlp_train_step(mlp, feat_ptr, t_ptr, w_ptr, n, lr, beta1=0.9, beta2=0
     _check_mlp(load().mc_lya_mlp_train_step(mlp, feat_ptr, t_ptr, w_ptr, int(n), C.byref(hp),
                                             C.byref(loss) if want_loss else None), mlp)
     return loss.value if want_loss else None
+
+
+def mc_lya_mlp_train_steps(mlp, feat_ptr, t_ptr, w_ptr, n_cells, idx_ptr, batch, lrs, beta1=0.9, beta2=0.999,
+                           eps=1e-8, want_losses=False):
+    k = len(lrs)
+    lr = (C.c_float * max(1, k))(*[float(x) for x in lrs])
+    out = (C.c_float * max(1, k))() if want_losses else None
+    _check_mlp(load().mc_lya_mlp_train_steps(mlp, feat_ptr, t_ptr, w_ptr, int(n_cells), idx_ptr, int(batch), k, lr,
+                                             beta1, beta2, eps, out), mlp)
+    return [float(out[i]) for i in range(k)] if want_losses else None
 
 
 def mc_lya_mlp_destroy(mlp):

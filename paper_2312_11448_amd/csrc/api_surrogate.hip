@@ -6,6 +6,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -21,6 +22,13 @@ struct mc_lya_mlp {
     bool envelope = false;
     int64_t step = 0;
     int forward_grid = 0;
+    // mc_lya_mlp_train_steps: the gathered batch ([cap][8] + [cap] + [cap]),
+    // the index-range flag, and two floats of loss tail per step
+    float *d_batch = nullptr;
+    uint64_t batch_cap = 0;
+    unsigned int *d_bad = nullptr;
+    float *d_tails = nullptr;
+    int tails_cap = 0;
     std::string err;
 };
 
@@ -48,7 +56,8 @@ mc_lya_status mlp_hip(mc_lya_mlp *m, hipError_t e, const char *what)
 
 void mlp_free(mc_lya_mlp *m)
 {
-    void *ptrs[] = {m->d_params, m->d_m, m->d_v, m->d_grad, m->d_part, m->d_env, m->d_count};
+    void *ptrs[] = {m->d_params, m->d_m, m->d_v, m->d_grad, m->d_part, m->d_env, m->d_count, m->d_batch, m->d_bad,
+                    m->d_tails};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -232,6 +241,76 @@ mc_lya_status mc_lya_mlp_train_step(mc_lya_mlp *m, const float *features, const 
         MLP_TRY(m, hipStreamSynchronize(m->stream));
         *loss = tail[1] > 0.0f ? tail[0] / tail[1] : 0.0f;
     }
+    return MC_LYA_OK;
+}
+
+mc_lya_status mc_lya_mlp_train_steps(mc_lya_mlp *m, const float *features, const float *targets,
+                                     const float *weights, uint64_t n_cells, const int64_t *idx, uint64_t batch,
+                                     int n_steps, const float *lr, float beta1, float beta2, float eps,
+                                     float *losses)
+{
+    if (!m) return MC_LYA_EINVAL;
+    mc_lya_status st = check_batch(m, features, n_cells);
+    if (st != MC_LYA_OK) return st;
+    if (n_cells == 0 || !targets || !weights) return mlp_fail(m, MC_LYA_EINVAL, "need cells, targets and weights");
+    if (n_steps < 0 || (n_steps > 0 && (!idx || !lr || batch == 0)))
+        return mlp_fail(m, MC_LYA_EINVAL, "need n_steps >= 0 and, for steps, idx, lr and batch > 0");
+    if (batch > (1ull << 32)) return mlp_fail(m, MC_LYA_EINVAL, "batch must be at most 2^32");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return mlp_fail(m, MC_LYA_EINVAL, "Adam needs beta1 and beta2 in [0, 1), eps > 0");
+    for (int s = 0; s < n_steps; ++s)
+        if (!(lr[s] > 0.0f)) return mlp_fail(m, MC_LYA_EINVAL, "every learning rate must be > 0");
+    if (n_steps == 0) return MC_LYA_OK;
+    if (batch > m->batch_cap) {
+        if (m->d_batch) MLP_TRY(m, hipFree(m->d_batch));
+        m->d_batch = nullptr;
+        m->batch_cap = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&m->d_batch), sizeof(float) * batch * (8 + 2)) != hipSuccess)
+            return mlp_fail(m, MC_LYA_ENOMEM, "device allocation of the gathered batch failed");
+        m->batch_cap = batch;
+    }
+    if (!m->d_bad && hipMalloc(reinterpret_cast<void **>(&m->d_bad), sizeof(unsigned int)) != hipSuccess)
+        return mlp_fail(m, MC_LYA_ENOMEM, "device allocation failed");
+    if (losses && n_steps > m->tails_cap) {
+        if (m->d_tails) MLP_TRY(m, hipFree(m->d_tails));
+        m->d_tails = nullptr;
+        m->tails_cap = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&m->d_tails), sizeof(float) * 2 * (size_t)n_steps) != hipSuccess)
+            return mlp_fail(m, MC_LYA_ENOMEM, "device allocation of the losses failed");
+        m->tails_cap = n_steps;
+    }
+    float *Xb = m->d_batch, *tb = Xb + batch * 8, *wb = tb + batch;    // [batch][8] features, then t, w
+    MLP_TRY(m, hipMemsetAsync(m->d_bad, 0, sizeof(unsigned int), m->stream));
+    for (int s = 0; s < n_steps; ++s) {
+        MLP_TRY(m, launch_mlp_gather(features, targets, weights, n_cells, idx + (size_t)s * batch, batch, Xb, tb, wb,
+                                     m->d_bad, m->stream));
+        MLP_TRY(m, launch_mlp_gradient(m->d_params, Xb, tb, wb, batch, m->d_part, kMlpGradBlocks, m->d_grad,
+                                       m->stream));
+        const int64_t t = m->step + 1;
+        MlpAdam a;
+        a.lr = lr[s];
+        a.beta1 = beta1;
+        a.beta2 = beta2;
+        a.eps = eps;
+        a.bc1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+        a.bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+        MLP_TRY(m, launch_mlp_adam(m->d_params, m->d_m, m->d_v, m->d_grad, a, m->stream));
+        m->step = t;
+        if (losses)
+            MLP_TRY(m, hipMemcpyAsync(m->d_tails + 2 * (size_t)s, m->d_grad + kMlpParams, 2 * sizeof(float),
+                                      hipMemcpyDeviceToDevice, m->stream));
+    }
+    unsigned int bad = 0;
+    std::vector<float> tails(losses ? 2 * (size_t)n_steps : 0);
+    if (losses)
+        MLP_TRY(m, hipMemcpyAsync(tails.data(), m->d_tails, sizeof(float) * tails.size(), hipMemcpyDeviceToHost,
+                                  m->stream));
+    MLP_TRY(m, hipMemcpyAsync(&bad, m->d_bad, sizeof bad, hipMemcpyDeviceToHost, m->stream));
+    MLP_TRY(m, hipStreamSynchronize(m->stream));
+    if (losses)
+        for (int s = 0; s < n_steps; ++s)
+            losses[s] = tails[2 * s + 1] > 0.0f ? tails[2 * s] / tails[2 * s + 1] : 0.0f;
+    if (bad) return mlp_fail(m, MC_LYA_EINVAL, "an index is outside [0, n_cells)");
     return MC_LYA_OK;
 }
 

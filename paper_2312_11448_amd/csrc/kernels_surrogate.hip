@@ -897,6 +897,33 @@ hipError_t launch_mlp_gradient(const float *params, const float *X, const float 
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void mlp_gather_kernel(const float *__restrict__ X, const float *__restrict__ t,
+                                                         const float *__restrict__ w, uint64_t n_cells,
+                                                         const int64_t *__restrict__ idx, uint64_t batch,
+                                                         float *__restrict__ Xb, float *__restrict__ tb,
+                                                         float *__restrict__ wb, unsigned int *__restrict__ bad)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (i >= batch) return;
+    int64_t c = idx[i];
+    if (c < 0 || (uint64_t)c >= n_cells) {
+        atomicOr(bad, 1u);
+        c = 0;
+    }
+#pragma unroll
+    for (int e = 0; e < kFeat; ++e) Xb[i * kFeat + e] = X[(uint64_t)c * kFeat + e];
+    tb[i] = t[c];
+    wb[i] = w[c];
+}
+
+hipError_t launch_mlp_gather(const float *X, const float *t, const float *w, uint64_t n_cells, const int64_t *idx,
+                             uint64_t batch, float *Xb, float *tb, float *wb, unsigned int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_gather_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, X, t, w, n_cells,
+                       idx, batch, Xb, tb, wb, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_correction(const float *y, const uint8_t *outside, const float *fallback, uint64_t n,
                                  float *M, hipStream_t s)
 {

@@ -61,6 +61,19 @@ class Mlp:
         return A.mc_lya_mlp_train_step(self.h, features.data_ptr(), targets.data_ptr(), weights.data_ptr(),
                                        features.shape[0], lr, beta1, beta2, eps, want_loss)
 
+    def train_steps(self, features, targets, weights, idx, lrs, beta1=0.9, beta2=0.999, eps=1e-8,
+                    want_losses=False):
+        """len(lrs) training steps in one call: step s on the cells
+        idx[s] (int64 [steps][batch] device tensor) of the training set.
+        Returns each step's loss if asked."""
+        assert idx.dtype == torch.int64 and idx.dim() == 2 and idx.shape[0] == len(lrs)
+        f = features.contiguous()
+        t = targets.contiguous()
+        w = weights.contiguous()
+        i = idx.contiguous()
+        return A.mc_lya_mlp_train_steps(self.h, f.data_ptr(), t.data_ptr(), w.data_ptr(), f.shape[0], i.data_ptr(),
+                                        i.shape[1], lrs, beta1, beta2, eps, want_losses)
+
     def close(self):
         if self.h:
             A.mc_lya_mlp_destroy(self.h)

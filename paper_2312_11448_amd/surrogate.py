@@ -86,31 +86,24 @@ def train(mlp, data, steps=3000, batch=65536, lr=3e-3, lr_final=3e-4, seed=0, lo
     """Adam on mini-batches drawn (seeded) from the cells with weight > 0;
     the learning rate decays geometrically from lr to lr_final."""
     idx_all = torch.nonzero(data["w"] > 0).squeeze(1)
-    gen = torch.Generator(device="cpu")
+    # batches drawn on the device (a seeded generator there): a host
+    # generator draws 65 536 indices a step far slower than the device
+    # trains on them
+    gen = torch.Generator(device=idx_all.device)
     gen.manual_seed(int(seed))
     n = idx_all.numel()
     b = min(batch, n)
-    # the draws of many steps at once (the same sequence as one draw per
-    # step), copied from pinned memory without waiting: the steps then queue
-    # on the stream with no synchronisation unless a loss is asked for
     chunk = max(1, min(steps, (1 << 24) // b))
     losses = []
-    picks = None
-    for s in range(steps):
-        if s % chunk == 0:
-            k = min(chunk, steps - s)
-            picks = torch.randint(0, n, (k, b), generator=gen)
-            if idx_all.is_cuda:
-                picks = picks.pin_memory().to(idx_all.device, non_blocking=True)
-        idx = idx_all[picks[s % chunk]]
-        X = data["features"][idx].contiguous()
-        t = data["y"][idx].contiguous()
-        w = data["w"][idx].contiguous()
-        rate = lr * (lr_final / lr) ** (s / max(1, steps - 1))
-        want = log_every and (s % log_every == 0 or s == steps - 1)
-        loss = mlp.train_step(X, t, w, rate, want_loss=bool(want))
-        if want:
-            losses.append((s, loss))
+    for s0 in range(0, steps, chunk):
+        k = min(chunk, steps - s0)
+        picks = torch.randint(0, n, (k, b), generator=gen, device=idx_all.device)
+        rates = [lr * (lr_final / lr) ** (s / max(1, steps - 1)) for s in range(s0, s0 + k)]
+        logged = [s for s in range(s0, s0 + k) if log_every and (s % log_every == 0 or s == steps - 1)]
+        # the chunk's steps in one library call (gather, gradient, Adam per step)
+        out = mlp.train_steps(data["features"], data["y"], data["w"], idx_all[picks], rates,
+                              want_losses=bool(logged))
+        losses.extend((s, out[s - s0]) for s in logged)
     return losses
 
 

@@ -35,6 +35,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2312_11448_amd as M  # noqa: E402
+from paper_2312_11448_amd import _abi as A  # noqa: E402
 
 
 def _say(msg):
@@ -222,6 +223,30 @@ def test_flags_follow_the_envelope_and_its_clearing(n):
     assert np.array_equal(f1.cpu().numpy().astype(bool), want) and c1 == int(want.sum())
     assert c2 == 0 and not f2.cpu().numpy().any()
     assert torch.equal(y0, y1) and torch.equal(y0, y2)
+
+
+def test_train_steps_equal_single_steps_bit_for_bit():
+    """Several steps in one call take the same batches, learning rates and
+    Adam step counts as single steps: the same parameters and losses bit for
+    bit. An index outside the set is reported."""
+    X, t, w = _train_data(5000, 4)
+    Xd, td, wd = (torch.from_numpy(a.astype(np.float32)).cuda() for a in (X, t, w))
+    rng = np.random.default_rng(9)
+    idx = torch.from_numpy(rng.integers(0, 5000, size=(7, 1000))).cuda()
+    lrs = [3e-3 * 0.9 ** s for s in range(7)]
+    p0 = _test_params(5)
+    with M.Mlp(p0) as one, M.Mlp(p0) as many:
+        want = [one.train_step(Xd[i].contiguous(), td[i].contiguous(), wd[i].contiguous(), lr, want_loss=True)
+                for i, lr in zip(idx, lrs)]
+        got = many.train_steps(Xd, td, wd, idx[:3], lrs[:3], want_losses=True)
+        got += many.train_steps(Xd, td, wd, idx[3:], lrs[3:], want_losses=True)
+        assert got == want
+        assert np.array_equal(np.array(one.params()), np.array(many.params()))
+        assert many.train_steps(Xd, td, wd, idx[:0], []) is None
+        bad = idx[:1].clone()
+        bad[0, 17] = 5000
+        with pytest.raises(A.MCLyaError, match="outside"):
+            many.train_steps(Xd, td, wd, bad, [1e-3])
 
 
 def _train_data(n, seed):
