@@ -32,6 +32,13 @@ struct mc_lya_mlp {
     std::string err;
 };
 
+namespace mclya {
+// (kernels_surrogate.hip) rows idx[0..batch) of (X [.][8], t, w) into
+// (Xb, tb, wb); an index outside [0, n_cells) reads row 0 and sets *bad
+hipError_t launch_mlp_gather(const float *X, const float *t, const float *w, uint64_t n_cells, const int64_t *idx,
+                             uint64_t batch, float *Xb, float *tb, float *wb, unsigned int *bad, hipStream_t s);
+}  // namespace mclya
+
 namespace {
 
 thread_local std::string g_mlp_init_err;

@@ -374,9 +374,5 @@ hipError_t launch_mlp_normalise(float *grad, hipStream_t s);
 hipError_t launch_mlp_correction(const float *y, const uint8_t *outside, const float *fallback, uint64_t n,
                                  float *M, hipStream_t s);
 hipError_t launch_mlp_adam(float *params, float *m, float *v, float *grad, const MlpAdam &a, hipStream_t s);
-// rows idx[0..batch) of (X [.][8], t, w) into (Xb, tb, wb); an index outside
-// [0, n_cells) reads row 0 and sets *bad
-hipError_t launch_mlp_gather(const float *X, const float *t, const float *w, uint64_t n_cells, const int64_t *idx,
-                             uint64_t batch, float *Xb, float *tb, float *wb, unsigned int *bad, hipStream_t s);
 
 }  // namespace mclya
