@@ -212,24 +212,24 @@ def evaluate(M_pred, ref, ref2):
 
 def time_inference(mlp, sim, reps=5):
     """Seconds per features + inference pass over every cell of `sim`
-    (device time, averaged), with the time of the inference alone."""
+    (device time, averaged over passes queued back to back, with events
+    between the calls), with the time of the inference alone."""
     n = sim.total_cells
     y = None
     for _ in range(2):
         f = sim.features()
         y = mlp.forward(f)
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    tf = ti = 0.0
-    for _ in range(reps):
-        e[0].record()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
+    e[0].record()
+    for r in range(reps):
         f = sim.features()
-        e[1].record()
+        e[2 * r + 1].record()
         y = mlp.forward(f)
-        e[2].record()
-        torch.cuda.synchronize()
-        tf += e[0].elapsed_time(e[1]) / 1e3
-        ti += e[1].elapsed_time(e[2]) / 1e3
+        e[2 * r + 2].record()
+    torch.cuda.synchronize()
+    tf = sum(e[2 * r].elapsed_time(e[2 * r + 1]) for r in range(reps)) / 1e3
+    ti = sum(e[2 * r + 1].elapsed_time(e[2 * r + 2]) for r in range(reps)) / 1e3
     return (tf + ti) / reps, ti / reps, n, y
 
 
