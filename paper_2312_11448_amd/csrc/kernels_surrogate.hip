@@ -363,6 +363,8 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// cache-policy operand of a buffer load: non-temporal (streaming)
+constexpr int kStreamingLoad = 2;
 
 __device__ __forceinline__ uint32_t bf16_pair(float a, float b)
 {
@@ -436,8 +438,10 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
         const uint64_t first = tile * 32;
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(X + first * kFeat), (short)0, (int)(rows_at(first) * 32u), 0x00020000);
-        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0);
-        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff + 16, 0, 0);
+        // (streaming reads: the features are read once, and keeping them out
+        // of the caches leaves those to the fields the features come from)
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, kStreamingLoad);
+        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff + 16, 0, kStreamingLoad);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             x[e] = __builtin_bit_cast(float, (uint32_t)a[e]);
@@ -490,7 +494,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
             }
         part += __shfl_xor(part, 32, 64);
         if (half == 0 && (uint32_t)col < rows) {
-            y[first + (uint32_t)col] = part + b3;
+            __builtin_nontemporal_store(part + b3, &y[first + (uint32_t)col]);
             if (outside) outside[first + (uint32_t)col] = (uint8_t)((env >> col) & 1u);
         }
         n_outside += (uint32_t)__popcll(env & (rows < 32 ? (1ull << rows) - 1ull : 0xffffffffull));
