@@ -99,3 +99,17 @@ def test_null_context_calls():
     assert L.mc_lya_set_option(None, 1, 0) == M.MC_LYA_EINVAL
     assert L.mc_lya_emit(None, None, None) == M.MC_LYA_EINVAL
     L.mc_lya_destroy(None)
+
+
+def test_null_network_calls():
+    """The network's entry points refuse a null handle before any device
+    work (the training entry points included)."""
+    M = _lib()
+    L = M.load()
+    lr = (C.c_float * 1)(1e-3)
+    assert L.mc_lya_mlp_train_steps(None, None, None, None, 0, None, 0, 1, lr, 0.9, 0.999, 1e-8, None) \
+        == M.MC_LYA_EINVAL
+    hp = M.mc_lya_adam(1e-3, 0.9, 0.999, 1e-8)
+    assert L.mc_lya_mlp_train_step(None, None, None, None, 0, C.byref(hp), None) == M.MC_LYA_EINVAL
+    assert L.mc_lya_mlp_forward(None, None, 0, None, None, None) == M.MC_LYA_EINVAL
+    L.mc_lya_mlp_destroy(None)
