@@ -475,12 +475,17 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *__restric
         bf16x8 h1[4];
         hidden_operand(d1, h1);
         f32x16 d2[2];
+        // the wave issues its layer-2 products at raised priority, so that
+        // the matrix cores start on them while the other waves' VALU work
+        // (ReLU, conversions, the last layer) fills the SIMD around them
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int T = 0; T < 2; ++T) {
             d2[T] = mfma16(o.a2[T][4], ones, zero16());
 #pragma unroll
             for (int s = 0; s < 4; ++s) d2[T] = mfma16(o.a2[T][s], h1[s], d2[T]);
         }
+        __builtin_amdgcn_s_setprio(0);
         float part = 0.0f;
 #pragma unroll
         for (int T = 0; T < 2; ++T)
